@@ -1,0 +1,96 @@
+"""Pins of the oracle's density, dipole, Hartree and XC pieces (CPU only)."""
+import numpy as np
+import pytest
+from scipy.special import erf
+
+import workloads as W
+from oracle import scf
+from oracle.mesh import Mesh
+
+
+def _box(lo, hi, nc, p):
+    return Mesh(p, (nc, nc, nc), W.box_vertices(lo, hi, (nc, nc, nc)))
+
+
+def test_gaussian_orbital_charge_and_dipole():
+    # a normalised Gaussian centred at R has charge 1 and dipole R
+    m = _box(-8.0, 8.0, 6, 5)
+    R = np.array([0.7, -0.4, 1.1])
+    s = 1.2
+    d2 = np.sum((m.dof_xyz - R) ** 2, axis=1)
+    psi = (np.pi * s * s) ** -0.75 * np.exp(-d2 / (2 * s * s))
+    rho = scf.density(m, m.m_sqrt * psi)
+    # interpolation error of the Gaussian at h = 2.7, p = 5 is ~1e-5
+    assert abs(scf.charge(m, rho) - 1.0) < 1e-4
+    np.testing.assert_allclose(scf.dipole(m, rho), R, atol=1e-4)
+
+
+def test_occupations_weight_density():
+    m = _box(-4.0, 4.0, 2, 3)
+    X = W.random_block(m.n_dof, 2, 4)
+    r1 = scf.density(m, X, [2.0, 0.5])
+    r2 = 2.0 * scf.density(m, X[:, :1]) + 0.5 * scf.density(m, X[:, 1:])
+    assert np.abs(r1 - r2).max() < 1e-12 * np.abs(r1).max()
+
+
+def test_hartree_of_gaussian_charge_converges():
+    # rho = Q (2 pi s^2)^-3/2 exp(-r^2 / 2 s^2)  =>  V_H = Q erf(r / (sqrt(2) s)) / r,
+    # boundary values Q / r (one "nucleus" of charge Q at the origin)
+    Q, s = 2.0, 1.0
+    errs = []
+    for nc in (4, 6):
+        m = _box(-8.0, 8.0, nc, 6)
+        r = np.linalg.norm(m.quad_xyz, axis=-1)
+        rho = Q * (2 * np.pi * s * s) ** -1.5 * np.exp(-r * r / (2 * s * s))
+        h = scf.Hartree(m, [Q], [np.zeros(3)], tol=1e-13)
+        phi, vh = h.solve(rho)
+        exact = Q * erf(r / (np.sqrt(2) * s)) / r
+        errs.append(np.abs(vh - exact).max())
+        # discrete residual of the interior equations
+        assert h.last_iters > 0
+    assert errs[1] < 2e-4 and errs[1] < errs[0] / 8  # (h_0/h_1)^(p+1) ~ 17
+
+
+def test_pcg_solves_interior_system():
+    from oracle import operators as op
+    m = _box(-3.0, 3.0, 2, 3)
+    rng = np.random.default_rng(1)
+    rho = np.abs(rng.normal(size=(m.n_cell, m.nq ** 3)))
+    h = scf.Hartree(m, [1.0, 2.0], [np.array([0.1, 0, 0]), np.array([0, 0.5, 0])], tol=1e-14)
+    phi, _ = h.solve(rho)
+    K = op.dense_K(m)
+    c = scf.load_vector(m, rho)
+    res = (K @ phi - 4 * np.pi * c)[~m.is_boundary]
+    assert np.linalg.norm(res) < 1e-12 * np.linalg.norm(4 * np.pi * c)
+    np.testing.assert_allclose(phi[m.is_boundary], h.fb[m.is_boundary])
+
+
+def test_exchange_textbook_values():
+    # Dirac exchange at r_s = 1: eps_x = -0.458165 Ha, V_x = 4/3 eps_x = -0.610887 Ha
+    rho = 3.0 / (4.0 * np.pi)
+    assert abs(scf.exchange_energy_density(rho) + 0.4581653) < 1e-6
+    assert abs(scf.exchange_potential(rho) + 0.6108871) < 1e-6
+
+
+@pytest.mark.parametrize("rs", [0.3, 0.8, 1.5, 4.0, 12.0])
+def test_xc_potential_is_derivative_of_energy(rs):
+    # V = d(rho eps)/d rho, checked by a central difference in rho
+    rho = 3.0 / (4.0 * np.pi * rs ** 3)
+    h = rho * 1e-5
+
+    def e(r):
+        rs_ = np.cbrt(3.0 / (4.0 * np.pi * r))
+        return r * (scf.exchange_energy_density(r) + scf.pz_eps_c(rs_))
+
+    fd = (e(rho + h) - e(rho - h)) / (2 * h)
+    v = scf.xc_potential(np.array([rho]), "xc")[0]
+    assert abs(v - fd) < 1e-7 * abs(v)
+
+
+def test_pz81_branches_join_at_rs_1():
+    lo = scf.pz_eps_c(np.array([1.0 - 1e-12]))[0]
+    hi = scf.pz_eps_c(np.array([1.0]))[0]
+    assert abs(lo - hi) < 1e-4
+    assert -0.07 < hi < -0.05
+    # correlation vanishes in the zero-density limit
+    assert scf.correlation_potential(np.array([0.0]))[0] == 0.0
