@@ -1,0 +1,177 @@
+/*
+ * tdfe.h -- C ABI of the MI355X spectral-finite-element real-time TDDFT step.
+ *
+ * Method: Kanungo & Gavini, "Real-time time-dependent density functional
+ * theory using higher-order finite-element methods" (arXiv:1810.13130).
+ * One call of tdfe_magnus_step advances a block of complex Kohn-Sham orbitals
+ * psibar (Loewdin coordinates, Eq. TDKSMatVecStandard) by one second-order
+ * Magnus step (Eqs. ApproxMagnus, PsiTimeDiscrete) whose exponential is
+ * formed by adaptive Lanczos (Eqs. zk, AdaptiveLanczos) on
+ * Hbar = M^-1/2 H M^-1/2 with M the diagonal GLL overlap (Sec. "Higher-order
+ * spectral finite-elements") and H the FE Hamiltonian of
+ * Eq. DiscreteHamiltonian.
+ *
+ * Conventions shared by every call
+ *  - Mesh: a structured logical grid of ncell[0] x ncell[1] x ncell[2]
+ *    hexahedra; cell (cx,cy,cz) is the trilinear image of [-1,1]^3 through
+ *    its 8 corner vertices.  Cells are numbered cx + ncx (cy + ncy cz).
+ *  - Global GLL nodes (I,J,K), 0 <= I <= ncx p, numbered I + Nx (J + Ny K)
+ *    with Nx = ncx p + 1.  The unknowns (DoFs) are the interior nodes
+ *    (homogeneous Dirichlet data, Eq. PsiExpansion), numbered
+ *    lexicographically with x fastest; n_dof = (Nx-2)(Ny-2)(Nz-2).
+ *  - Gauss points: nq = p + 1 per direction (tensor rule); point (a,b,c) of
+ *    a cell has index a + nq (b + nq c).  Per-point arrays are
+ *    [n_cell][nq^3] row-major FP64.
+ *  - Orbitals at the boundary are ALWAYS psibar, complex128 interleaved
+ *    (re, im), row-major [n_dof][n_orb]: element (j, alpha) at
+ *    ((double*)ptr)[2 (j n_orb + alpha) + {0,1}].  Orbital psi = M^-1/2 psibar.
+ *  - All device pointers are owned by the caller.  The library owns only its
+ *    context and small host tables; all device scratch lives in the caller's
+ *    workspace (tdfe_query / tdfe_bind_workspace).  No call frees caller
+ *    memory.
+ *  - All device work is enqueued on the hipStream_t given at setup.  Calls
+ *    that return host values (scalars, reports) synchronise that stream.
+ *  - Every call returns a tdfe_status; arguments are validated on the host
+ *    before any device work.  Nothing aborts or throws across the ABI.  One
+ *    context per stream; a context is not thread-safe.
+ */
+#ifndef TDFE_H
+#define TDFE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int tdfe_status;
+#define TDFE_OK 0
+#define TDFE_EINVAL (-1)     /* bad argument (sizes, nulls, order, tolerances) */
+#define TDFE_ENOMEM (-2)     /* workspace missing or too small */
+#define TDFE_EDEVICE (-3)    /* HIP runtime error; text in tdfe_last_error */
+#define TDFE_ENOCONV (-4)    /* Lanczos reached k_max / PCG reached maxit */
+#define TDFE_ESTATE (-5)     /* call out of order (e.g. apply before potential) */
+#define TDFE_ENONFINITE (-6) /* NaN/Inf detected by an FP64 norm */
+
+typedef struct tdfe_ctx tdfe_ctx;
+
+/* working precision of the cell contractions and Krylov storage */
+#define TDFE_FP64 0       /* everything FP64 (parity path) */
+#define TDFE_MIXED_FP32 1 /* FP32 contractions and Krylov storage; FP64 scalars */
+
+typedef struct {
+  int p;                  /* element order, 1..8 (Sec. spectral FE) */
+  int nq;                 /* Gauss points per direction; must be p + 1 */
+  int ncell[3];           /* logical cells along x, y, z (each >= 1) */
+  const double* vertices; /* HOST, (ncx+1)(ncy+1)(ncz+1) x 3, x fastest */
+  int n_orb_max;          /* largest orbital block passed to any call */
+  int k_max;              /* Krylov dimension cap, 1..1024 */
+  int precision;          /* TDFE_FP64 or TDFE_MIXED_FP32 */
+} tdfe_mesh_desc;
+
+/* fe_mesh_setup: reference element (GLL nodes/weights, Gauss rule, 1D
+ * interpolation/derivative tables) and mesh bookkeeping (Sec. "Higher-order
+ * spectral finite-elements"; Eq. PsiExpansion for the Dirichlet DoFs).
+ * Host-only: no device memory is touched until tdfe_bind_workspace.
+ * hip_stream: hipStream_t (may be 0).  *out receives a new context. */
+tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_ctx** out);
+
+/* sizes of the problem and of the device workspace the caller must provide */
+tdfe_status tdfe_query(const tdfe_ctx* ctx, int64_t* n_dof, int64_t* n_cell, int64_t* n_quad,
+                       size_t* workspace_bytes);
+
+/* binds a caller-owned device buffer of >= workspace_bytes (256-byte aligned)
+ * and computes the device-side geometry and the diagonal overlap
+ * M_jj = sum_e w_i w_j w_k det J_e(node) (GLL quadrature, Sec. spectral FE). */
+tdfe_status tdfe_bind_workspace(tdfe_ctx* ctx, void* dev, size_t bytes);
+
+/* device outputs: DoF coordinates [n_dof][3], Gauss point coordinates
+ * [n_cell][nq^3][3], overlap diagonal M [n_dof] */
+tdfe_status tdfe_dof_coords(tdfe_ctx* ctx, double* dev_xyz);
+tdfe_status tdfe_quad_coords(tdfe_ctx* ctx, double* dev_xyz);
+tdfe_status tdfe_mass_diag(tdfe_ctx* ctx, double* dev_m);
+
+/* set_potential: the static external potential V_ext at the Gauss points,
+ * [n_cell][nq^3] FP64 device (Eq. VKS, local part).  Copied into the
+ * workspace.  Also the total potential used by apply_H until SCF terms are
+ * added by magnus_step. */
+tdfe_status tdfe_set_potential(tdfe_ctx* ctx, const double* dev_v);
+
+#define TDFE_XC_NONE 0
+#define TDFE_XC_X 1   /* LDA exchange */
+#define TDFE_XC_XC 2  /* LDA exchange + Perdew-Zunger 81 correlation */
+
+typedef struct {
+  int hartree;              /* solve K phi = 4 pi c for V_H (Eqs. Poisson, VHDiscretePoisson) */
+  int xc;                   /* TDFE_XC_* (ALDA, Sec. TDKS equations) */
+  int n_nuclei;             /* nuclei giving the Hartree boundary values f = sum Z/|r-R| */
+  const double* Z;          /* HOST [n_nuclei] */
+  const double* R;          /* HOST [n_nuclei][3] */
+  const double* occupation; /* HOST [n_orb] occupations f_alpha, or NULL for all 1 */
+  int n_orb;                /* orbitals the occupations refer to */
+  double pcg_tol;           /* relative residual for curved meshes (box meshes solve exactly) */
+  int pcg_maxit;
+} tdfe_scf_desc;
+
+/* set_scf: density-dependent part of V_KS.  Resets the extrapolation history. */
+tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);
+
+/* apply_H: dev_out = Hbar dev_psibar for n_orb orbitals (both [n_dof][n_orb]
+ * complex128), Hbar = M^-1/2 (1/2 K + V-mass) M^-1/2 with the current total
+ * potential (Eqs. DiscreteHamiltonian, TDKSMatVecStandard).  Gauss quadrature
+ * for every term.  dev_out must not alias dev_psibar. */
+tdfe_status tdfe_apply_H(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, int n_orb);
+
+/* lanczos_expm: psibar <- exp(-i tau Hbar) psibar in place, each orbital with
+ * its own adaptive Krylov space (Eqs. KrylovSubspace, zk, AdaptiveLanczos):
+ * stop at the first k with tau beta_k ||psibar|| |[exp(-i tau T_k)]_{k,1}| <= tol
+ * or on happy breakdown (beta_k <= 1e-14 max|alpha|).  tau < 0 gives the
+ * adjoint direction exp(+i|tau|Hbar).  host_k [n_orb] and host_err [n_orb]
+ * (may be NULL) receive the final dimension and error estimate.
+ * Returns TDFE_ENOCONV (psibar holds the k_max iterate) if k_max is reached. */
+tdfe_status tdfe_lanczos_expm(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double tau, double tol,
+                              int* host_k, double* host_err);
+
+/* density at the Gauss points, rho_q = sum_alpha f_alpha |psi_alpha(x_q)|^2,
+ * psi = M^-1/2 psibar interpolated with the GLL basis (Sec. TDKS equations).
+ * dev_rho_q: [n_cell][nq^3] FP64 device. */
+tdfe_status tdfe_density(tdfe_ctx* ctx, const void* dev_psibar, int n_orb, double* dev_rho_q);
+
+/* dipole mu = sum_q varpi_q detJ_q x_q rho_q (electronic, +int r rho) and the
+ * charge sum_q varpi_q detJ_q rho_q of the given orbitals.  host_mu[3]. */
+tdfe_status tdfe_dipole(tdfe_ctx* ctx, const void* dev_psibar, int n_orb, double* host_mu,
+                        double* host_charge);
+
+typedef struct {
+  int k_pred_max, k_corr_max; /* largest Krylov dimension of the two propagations */
+  int k_pred_sum, k_corr_sum; /* sum over orbitals */
+  double err_max;             /* largest Lanczos error estimate */
+  int poisson_iters;          /* 0 for the exact box solver */
+  double mu[3];               /* dipole of psibar^n */
+  double charge;              /* charge of psibar^n */
+} tdfe_step_report;
+
+/* magnus_step: one second-order Magnus step with the predictor-corrector
+ * midpoint Hamiltonian (Eqs. ApproxMagnus, PsiTimeDiscrete; Sec.
+ * "Approximating the second-order Magnus operator"):
+ *   V_P = V_ext + V_field + 1.25 W_{n-1} - 0.25 W_{n-2}
+ *   psibar^{n-1/2} = exp(-i dt/2 Hbar(V_P)) psibar^{n-1}
+ *   V_C = V_ext + V_field + W[rho(psibar^{n-1/2})]
+ *   psibar^n = exp(-i dt Hbar(V_C)) psibar^{n-1},   W_n = W[rho(psibar^n)]
+ * with W = V_H + V_xc and V_field = -field_E z (Eq. VField), held over the
+ * step.  Without SCF terms the step is one exp(-i dt Hbar) psibar.  The first
+ * call after set_scf computes W_0 from psibar (and W_{-1} := W_0).
+ * psibar is updated in place; rep may be NULL (no synchronisation then). */
+tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double dt, double field_E,
+                             double tol, tdfe_step_report* rep);
+
+/* text of the last error on this context (never NULL) */
+const char* tdfe_last_error(const tdfe_ctx* ctx);
+
+void tdfe_destroy(tdfe_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TDFE_H */

@@ -1,0 +1,594 @@
+// Matrix-free spectral-FE operator on MI355X (gfx950).
+//
+// One workgroup handles CPB cells x CB real columns.  Every thread owns one
+// (line, column) of a cell and keeps a 1D line of N values in registers; the
+// line orientation changes between phases through LDS.  Per cell and column
+// the action of Eq. DiscreteHamiltonian is
+//   y_e = B^T B^T B^T [ V w u_q + sum_d Dg_d^T ( kin G_d w Dg_d u_q ) ]
+// with u_q = (B x B x B) u_e the values at the Gauss points and Dg the
+// collocation derivative on the Gauss points (Dg B = D exactly because
+// nq = p + 1).  Box cells have a diagonal metric G, so each direction's
+// gradient term is finished by the thread owning that direction's line;
+// curved (trilinear) cells compute J, det J and J^-1 J^-T per Gauss point
+// from the 8 cell corners and couple the three gradient components.
+// The element results are added into the output with FP64/FP32 atomics
+// (hardware global_atomic_add), after the M^-1/2 scaling of the Loewdin
+// form (Eq. TDKSMatVecStandard).  The quadratic form u^T H u of every
+// column is accumulated from the quadrature-point fluxes and reduced per
+// workgroup; it equals Re<x, Hbar x> and feeds the Lanczos alpha.
+#include "tdfe_internal.h"
+
+namespace {
+
+template <typename T>
+__device__ __forceinline__ void atomic_add(T* p, T v) {
+  unsafeAtomicAdd(p, v);
+}
+
+__device__ __forceinline__ int remap_block(int p, int G) {
+  // consecutive logical blocks on the same XCD (8 XCDs, round-robin dispatch)
+  if ((G & 7) == 0) return (p & 7) * (G >> 3) + (p >> 3);
+  return p;
+}
+
+template <int N, int CB, int CPB, int GEOM>
+struct ApplyShape {
+  static constexpr int LINES = N * N;
+  static constexpr int THREADS = CPB * LINES * CB;
+  static constexpr int VOL = N * N * N;
+  static constexpr int NARR = GEOM ? 4 : 2;
+};
+
+template <int N, int CB>
+__device__ __forceinline__ int lidx(int slot, int z, int y, int x, int col) {
+  return (((slot * N + z) * N + y) * N + x) * CB + col;
+}
+
+struct KParams {
+  const void* x;
+  void* y;
+  int ld, cols, nchunks;
+  const double* colscale;
+  double kin;
+  const void* vw;
+  const double* minv;
+  const double* cellgeo;
+  const double* corners;
+  const double* tab;
+  double* energy;
+  const int* done;
+  int ncx, ncy, ncz, p, Nx, Ny, Nz;
+  int64_t n_cell;
+  int lowdin, fullgrid;
+  int64_t* groups_out;  // host pointer, set by the launcher
+};
+
+template <typename T, int N, int CB, int CPB, int GEOM>
+__global__ void __launch_bounds__(CPB * N * N * CB)
+    apply_kernel(KParams P) {
+  using S = ApplyShape<N, CB, CPB, GEOM>;
+  constexpr int VOL = S::VOL;
+  __shared__ T sU[CPB * VOL * CB];
+  __shared__ T sR[CPB * VOL * CB];
+  __shared__ T sGY[GEOM ? CPB * VOL * CB : 1];
+  __shared__ T sGZ[GEOM ? CPB * VOL * CB : 1];
+  __shared__ T sGeo[GEOM ? CPB * VOL * 6 : 1];
+  __shared__ T sB[N * N], sDg[N * N], sW3[VOL];
+  __shared__ double sRed[S::THREADS];
+
+  if (P.done && *P.done) return;
+
+  const int t = threadIdx.x;
+  const int L = remap_block(blockIdx.x, gridDim.x);
+  const int chunk = L % P.nchunks;
+  const int group = L / P.nchunks;
+  const int col = t % CB;
+  const int line = (t / CB) % S::LINES;
+  const int slot = t / (CB * S::LINES);
+  const int64_t cell = (int64_t)group * CPB + slot;
+  const bool cell_ok = cell < P.n_cell;
+  const int colg = chunk * CB + col;
+  const bool col_ok = colg < P.cols;
+  const bool act = cell_ok && col_ok;
+
+  for (int i = t; i < N * N; i += S::THREADS) {
+    sB[i] = (T)P.tab[TAB_B + (i / N) * TDFE_MAXN + (i % N)];
+    sDg[i] = (T)P.tab[TAB_DG + (i / N) * TDFE_MAXN + (i % N)];
+  }
+  for (int i = t; i < VOL; i += S::THREADS) sW3[i] = (T)P.tab[TAB_W3Q + i];
+
+  int cx = 0, cy = 0, cz = 0;
+  if (cell_ok) {
+    cx = (int)(cell % P.ncx);
+    cy = (int)((cell / P.ncx) % P.ncy);
+    cz = (int)(cell / ((int64_t)P.ncx * P.ncy));
+  }
+  const T* __restrict__ X = (const T*)P.x;
+  T* __restrict__ Y = (T*)P.y;
+  const T* __restrict__ VW = (const T*)P.vw;
+  T cs = (T)1;
+  if (P.colscale && col_ok) cs = (T)P.colscale[colg >> 1];
+
+  // geometry of curved cells: 6 entries of detJ w J^-1 J^-T at every Gauss point
+  if constexpr (GEOM) {
+    for (int it = t; it < CPB * VOL; it += S::THREADS) {
+      const int sl = it / VOL, q = it % VOL;
+      const int64_t ce = (int64_t)group * CPB + sl;
+      if (ce >= P.n_cell) continue;
+      const int a = q % N, b = (q / N) % N, c = q / (N * N);
+      const double xa = P.tab[TAB_ETA + a], xb = P.tab[TAB_ETA + b], xc = P.tab[TAB_ETA + c];
+      const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
+                              {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
+      const double* C = P.corners + ce * 24;
+      double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int vz = 0; vz < 2; ++vz)
+        for (int vy = 0; vy < 2; ++vy)
+          for (int vx = 0; vx < 2; ++vx) {
+            const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
+            const double sx = vx ? 0.5 : -0.5, sy = vy ? 0.5 : -0.5, sz = vz ? 0.5 : -0.5;
+            const double d0 = sx * f[vy][1] * f[vz][2];
+            const double d1 = f[vx][0] * sy * f[vz][2];
+            const double d2 = f[vx][0] * f[vy][1] * sz;
+            for (int d = 0; d < 3; ++d) {
+              J[d][0] += X3[d] * d0;
+              J[d][1] += X3[d] * d1;
+              J[d][2] += X3[d] * d2;
+            }
+          }
+      // adjugate: J^-1 = adj / det ; det J^-1 J^-T = adj adj^T / det
+      double A[3][3];
+      A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+      const double s = P.tab[TAB_W3Q + q] / det;
+      T* g = sGeo + (sl * VOL + q) * 6;
+      g[0] = (T)(s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]));
+      g[1] = (T)(s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]));
+      g[2] = (T)(s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]));
+      g[3] = (T)(s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]));
+      g[4] = (T)(s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]));
+      g[5] = (T)(s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]));
+    }
+  }
+  __syncthreads();
+
+  const int NxI = P.Nx - 2, NyI = P.Ny - 2;
+  auto node_index = [&](int i, int j, int k, bool& inside) -> int64_t {
+    const int I = cx * P.p + i, J = cy * P.p + j, K = cz * P.p + k;
+    if (P.fullgrid) {
+      inside = true;
+      return (int64_t)I + (int64_t)P.Nx * ((int64_t)J + (int64_t)P.Ny * K);
+    }
+    inside = I > 0 && I < P.Nx - 1 && J > 0 && J < P.Ny - 1 && K > 0 && K < P.Nz - 1;
+    return (int64_t)(I - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (K - 1));
+  };
+
+  double energy = 0.0;
+  T r1[N], r2[N];
+
+  // ---- F1: gather z-lines, interpolate in z -----------------------------------
+  {
+    const int i = line % N, j = line / N;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      T v = (T)0;
+      if (act) {
+        bool inside;
+        const int64_t id = node_index(i, j, k, inside);
+        if (inside) {
+          v = X[id * P.ld + colg] * cs;
+          if (P.lowdin) v *= (T)P.minv[id];
+        }
+      }
+      r1[k] = v;
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T s = 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += sB[c * N + k] * r1[k];
+      sU[lidx<N, CB>(slot, c, j, i, col)] = s;
+    }
+  }
+  __syncthreads();
+  // ---- F2: interpolate in y -------------------------------------------------------
+  {
+    const int i = line % N, c = line / N;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r1[j] = sU[lidx<N, CB>(slot, c, j, i, col)];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      T s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += sB[b * N + j] * r1[j];
+      sU[lidx<N, CB>(slot, c, b, i, col)] = s;
+    }
+  }
+  __syncthreads();
+  // ---- F3: interpolate in x; x-direction flux (box) or x-derivative (curved) -------------
+  const T* vwc = (VW && cell_ok) ? VW + cell * VOL : nullptr;
+  double gx = 0, gy = 0, gz = 0;
+  if constexpr (!GEOM) {
+    if (cell_ok) {
+      gx = P.kin * P.cellgeo[cell * 4 + 0];
+      gy = P.kin * P.cellgeo[cell * 4 + 1];
+      gz = P.kin * P.cellgeo[cell * 4 + 2];
+    }
+  }
+  {
+    const int b = line % N, c = line / N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r1[i] = sU[lidx<N, CB>(slot, c, b, i, col)];
+    T uq[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += sB[a * N + i] * r1[i];
+      uq[a] = s;
+    }
+    T du[N];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T s = 0;
+#pragma unroll
+      for (int q = 0; q < N; ++q) s += sDg[a * N + q] * uq[q];
+      du[a] = s;
+    }
+    if constexpr (!GEOM) {
+      T pot[N], f[N];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const int q = a + N * (b + N * c);
+        pot[a] = vwc ? vwc[q] * uq[a] : (T)0;
+        f[a] = (T)gx * sW3[q] * du[a];
+        energy += (double)f[a] * (double)du[a] + (double)pot[a] * (double)uq[a];
+      }
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T s = pot[a];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[q * N + a] * f[q];
+        sU[lidx<N, CB>(slot, c, b, a, col)] = uq[a];
+        sR[lidx<N, CB>(slot, c, b, a, col)] = s;
+      }
+    } else {
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        sU[lidx<N, CB>(slot, c, b, a, col)] = uq[a];
+        sR[lidx<N, CB>(slot, c, b, a, col)] = du[a];  // x-derivative
+      }
+    }
+  }
+  __syncthreads();
+
+  if constexpr (!GEOM) {
+    // ---- F4: y-direction flux -----------------------------------------------------
+    {
+      const int a = line % N, c = line / N;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        r1[b] = sU[lidx<N, CB>(slot, c, b, a, col)];
+        r2[b] = sR[lidx<N, CB>(slot, c, b, a, col)];
+      }
+      T f[N];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[b * N + q] * r1[q];
+        f[b] = (T)gy * sW3[a + N * (b + N * c)] * s;
+        energy += (double)f[b] * (double)s;
+      }
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T s = r2[b];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[q * N + b] * f[q];
+        sR[lidx<N, CB>(slot, c, b, a, col)] = s;
+      }
+    }
+    __syncthreads();
+    // ---- F5: z-direction flux, then B^T in z ------------------------------------------
+    {
+      const int a = line % N, b = line / N;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        r1[c] = sU[lidx<N, CB>(slot, c, b, a, col)];
+        r2[c] = sR[lidx<N, CB>(slot, c, b, a, col)];
+      }
+      T f[N];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[c * N + q] * r1[q];
+        f[c] = (T)gz * sW3[a + N * (b + N * c)] * s;
+        energy += (double)f[c] * (double)s;
+      }
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T s = r2[c];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[q * N + c] * f[q];
+        r1[c] = s;
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) s += sB[c * N + k] * r1[c];
+        sR[lidx<N, CB>(slot, k, b, a, col)] = s;
+      }
+    }
+    __syncthreads();
+  } else {
+    // ---- F4/F5: y- and z-derivatives of u_q ------------------------------------------
+    {
+      const int a = line % N, c = line / N;
+#pragma unroll
+      for (int b = 0; b < N; ++b) r1[b] = sU[lidx<N, CB>(slot, c, b, a, col)];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[b * N + q] * r1[q];
+        sGY[lidx<N, CB>(slot, c, b, a, col)] = s;
+      }
+    }
+    {
+      const int a = line % N, b = line / N;
+#pragma unroll
+      for (int c = 0; c < N; ++c) r1[c] = sU[lidx<N, CB>(slot, c, b, a, col)];
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T s = 0;
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[c * N + q] * r1[q];
+        sGZ[lidx<N, CB>(slot, c, b, a, col)] = s;
+      }
+    }
+    __syncthreads();
+    // ---- P: pointwise fluxes, x-part of the transposed derivative --------------------
+    {
+      const int b = line % N, c = line / N;
+      T fx[N], pot[N];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        const int q = a + N * (b + N * c);
+        const int li = lidx<N, CB>(slot, c, b, a, col);
+        const T u = sU[li], dx = sR[li], dy = sGY[li], dz = sGZ[li];
+        const T* g = sGeo + (slot * VOL + q) * 6;
+        const T k = (T)P.kin;
+        const T ffx = k * (g[0] * dx + g[1] * dy + g[2] * dz);
+        const T ffy = k * (g[1] * dx + g[3] * dy + g[4] * dz);
+        const T ffz = k * (g[2] * dx + g[4] * dy + g[5] * dz);
+        pot[a] = vwc ? vwc[q] * u : (T)0;
+        energy += (double)ffx * dx + (double)ffy * dy + (double)ffz * dz + (double)pot[a] * u;
+        fx[a] = ffx;
+        sGY[li] = ffy;
+        sGZ[li] = ffz;
+      }
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        T s = pot[a];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[q * N + a] * fx[q];
+        sU[lidx<N, CB>(slot, c, b, a, col)] = s;
+      }
+    }
+    __syncthreads();
+    // ---- B1: y-part of the transposed derivative -----------------------------------
+    {
+      const int a = line % N, c = line / N;
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        r1[b] = sU[lidx<N, CB>(slot, c, b, a, col)];
+        r2[b] = sGY[lidx<N, CB>(slot, c, b, a, col)];
+      }
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        T s = r1[b];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[q * N + b] * r2[q];
+        sU[lidx<N, CB>(slot, c, b, a, col)] = s;
+      }
+    }
+    __syncthreads();
+    // ---- B2: z-part of the transposed derivative, then B^T in z --------------------------
+    {
+      const int a = line % N, b = line / N;
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        r1[c] = sU[lidx<N, CB>(slot, c, b, a, col)];
+        r2[c] = sGZ[lidx<N, CB>(slot, c, b, a, col)];
+      }
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        T s = r1[c];
+#pragma unroll
+        for (int q = 0; q < N; ++q) s += sDg[q * N + c] * r2[q];
+        r1[c] = s;  // reads only r1[c] itself and r2
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        T s = 0;
+#pragma unroll
+        for (int c = 0; c < N; ++c) s += sB[c * N + k] * r1[c];
+        sR[lidx<N, CB>(slot, k, b, a, col)] = s;
+      }
+    }
+    __syncthreads();
+  }
+  // ---- B4: B^T in y ------------------------------------------------------------------------
+  {
+    const int a = line % N, k = line / N;
+#pragma unroll
+    for (int b = 0; b < N; ++b) r1[b] = sR[lidx<N, CB>(slot, k, b, a, col)];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      T s = 0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) s += sB[b * N + j] * r1[b];
+      sR[lidx<N, CB>(slot, k, j, a, col)] = s;
+    }
+  }
+  __syncthreads();
+  // ---- B5: B^T in x and scatter-add -------------------------------------------------------
+  {
+    const int j = line % N, k = line / N;
+#pragma unroll
+    for (int a = 0; a < N; ++a) r1[a] = sR[lidx<N, CB>(slot, k, j, a, col)];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T s = 0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) s += sB[a * N + i] * r1[a];
+      if (act) {
+        bool inside;
+        const int64_t id = node_index(i, j, k, inside);
+        if (inside) {
+          if (P.lowdin) s *= (T)P.minv[id];
+          atomic_add(Y + id * P.ld + colg, s);
+        }
+      }
+    }
+  }
+
+  // ---- per-column quadratic form --------------------------------------------------------------
+  if (P.energy) {
+    sRed[t] = act ? energy : 0.0;
+    __syncthreads();
+    if (t < CB) {
+      double s = 0.0;
+      for (int u = t; u < S::THREADS; u += CB) s += sRed[u];
+      if (chunk * CB + t < P.cols) P.energy[(int64_t)group * P.cols + chunk * CB + t] = s;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// dispatch
+// ---------------------------------------------------------------------------------------------
+template <int N, int CB, int GEOM>
+constexpr int pick_cpb() {
+  // aim for >= 128 threads per block and <= 64 KB of line arrays
+  int cpb = 1;
+  while (cpb * N * N * CB < 128 && cpb < 16) cpb *= 2;
+  return cpb;
+}
+
+template <typename T, int N, int CB, int GEOM>
+tdfe_status launch_t(tdfe_ctx* c, KParams& P, int nchunks) {
+  constexpr int CPB = pick_cpb<N, CB, GEOM>();
+  using S = ApplyShape<N, CB, CPB, GEOM>;
+  static_assert(S::THREADS <= 1024, "block too large");
+  const int64_t groups = (c->n_cell + CPB - 1) / CPB;
+  P.nchunks = nchunks;
+  if (P.groups_out) *P.groups_out = groups;
+  const int64_t grid = groups * nchunks;
+  hipLaunchKernelGGL((apply_kernel<T, N, CB, CPB, GEOM>), dim3((unsigned)grid), dim3(S::THREADS), 0,
+                     c->stream, P);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+template <typename T, int N>
+tdfe_status launch_n(tdfe_ctx* c, KParams& P, bool geom) {
+  // largest column block that keeps the workgroup within 1024 threads and the
+  // line arrays within ~96 KB of LDS
+  const int cols = P.cols;
+  constexpr int VOLB = N * N * N * (int)sizeof(T);
+  int cb;
+  if (cols <= 1) cb = 1;
+  else if (cols <= 2) cb = 2;
+  else if (cols <= 4) cb = 4;
+  else if (cols <= 8) cb = 8;
+  else cb = 16;
+  auto fits = [&](int b) {
+    const int narr = geom ? 4 : 2;
+    return N * N * b <= 1024 && narr * VOLB * b + (geom ? 6 * VOLB : 0) <= 96 * 1024;
+  };
+  while (cb > 1 && !fits(cb)) cb >>= 1;
+  const int nchunks = (cols + cb - 1) / cb;
+#define TDFE_CASE(CBV)                                                                   \
+  case CBV:                                                                              \
+    if constexpr (N * N * CBV <= 1024 && 2 * VOLB * CBV <= 96 * 1024) {                    \
+      if (geom) {                                                                        \
+        if constexpr (4 * VOLB * CBV + 6 * VOLB <= 96 * 1024) return launch_t<T, N, CBV, 1>(c, P, nchunks); \
+      } else                                                                             \
+        return launch_t<T, N, CBV, 0>(c, P, nchunks);                                    \
+    }                                                                                    \
+    break;
+  switch (cb) {
+    TDFE_CASE(1)
+    TDFE_CASE(2)
+    TDFE_CASE(4)
+    TDFE_CASE(8)
+    TDFE_CASE(16)
+  }
+#undef TDFE_CASE
+  return tdfe_fail(c, TDFE_EINVAL, "no operator kernel for n=%d cols=%d", N, cols);
+}
+
+template <typename T>
+tdfe_status launch_p(tdfe_ctx* c, KParams& P, bool geom) {
+  switch (c->n) {
+    case 2: return launch_n<T, 2>(c, P, geom);
+    case 3: return launch_n<T, 3>(c, P, geom);
+    case 4: return launch_n<T, 4>(c, P, geom);
+    case 5: return launch_n<T, 5>(c, P, geom);
+    case 6: return launch_n<T, 6>(c, P, geom);
+    case 7: return launch_n<T, 7>(c, P, geom);
+    case 8: return launch_n<T, 8>(c, P, geom);
+    case 9: return launch_n<T, 9>(c, P, geom);
+  }
+  return tdfe_fail(c, TDFE_EINVAL, "unsupported order p=%d", c->p);
+}
+
+}  // namespace
+
+int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
+  // upper bound on the number of cell groups any launch uses (CPB >= 1)
+  (void)cols;
+  return c->n_cell;
+}
+
+tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
+  KParams P{};
+  P.x = a.x;
+  P.y = a.y;
+  P.ld = a.ld;
+  P.cols = a.cols;
+  P.colscale = a.colscale;
+  P.kin = a.kin;
+  P.vw = a.fp32 ? (const void*)a.vw32 : (const void*)a.vw;
+  P.minv = c->minv;
+  P.cellgeo = c->cellgeo;
+  P.corners = c->corners;
+  P.tab = c->tab;
+  P.energy = a.energy;
+  P.done = a.done_flag;
+  P.ncx = c->ncx;
+  P.ncy = c->ncy;
+  P.ncz = c->ncz;
+  P.p = c->p;
+  P.Nx = c->Nx;
+  P.Ny = c->Ny;
+  P.Nz = c->Nz;
+  P.n_cell = c->n_cell;
+  P.lowdin = a.lowdin;
+  P.fullgrid = a.fullgrid;
+  P.groups_out = a.n_blocks_out;
+  if (a.cols < 1) return tdfe_fail(c, TDFE_EINVAL, "apply: cols < 1");
+  const bool geom = !c->box;
+  if (a.fp32) return launch_p<float>(c, P, geom);
+  return launch_p<double>(c, P, geom);
+}

@@ -1,0 +1,153 @@
+// Internal declarations of the tdfe HIP library (not part of the ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <cstdio>
+#include <string>
+#include <vector>
+
+#include "../../include/tdfe.h"
+
+#define TDFE_MAXN 9  // p <= 8
+
+// one Krylov chunk holds at most this many real columns (2 per orbital)
+#define TDFE_MAX_COLS 64
+
+struct tdfe_ctx {
+  // ---- configuration -------------------------------------------------------
+  int p = 0, n = 0, nq = 0;
+  int ncx = 0, ncy = 0, ncz = 0;
+  int64_t n_cell = 0, n_dof = 0, n_quad = 0, n_nodes = 0;
+  int Nx = 0, Ny = 0, Nz = 0;
+  int n_orb_max = 0, k_max = 0, precision = TDFE_FP64;
+  bool box = false;  // rectilinear grid: axis-aligned cells
+  hipStream_t stream = nullptr;
+  std::string err;
+
+  // ---- host tables ---------------------------------------------------------
+  double xi[TDFE_MAXN], w[TDFE_MAXN];    // GLL nodes / weights
+  double eta[TDFE_MAXN], wq[TDFE_MAXN];  // Gauss points / weights
+  double B[TDFE_MAXN * TDFE_MAXN];       // B[a*n+i] = l_i(eta_a)
+  double D[TDFE_MAXN * TDFE_MAXN];       // D[a*n+i] = l_i'(eta_a)
+  double Dg[TDFE_MAXN * TDFE_MAXN];      // Dg[a*nq+b] = derivative at eta_a of the Gauss-point Lagrange basis b
+  std::vector<double> vertices;          // (ncx+1)(ncy+1)(ncz+1)*3
+  std::vector<double> ax_x, ax_y, ax_z;  // box grids: vertex coordinates along each axis
+
+  // ---- workspace ------------------------------------------------------------
+  char* ws = nullptr;
+  size_t ws_bytes = 0, ws_need = 0;
+  int chunk_orb = 0;  // orbitals per Krylov chunk
+
+  // device pointers into the workspace
+  double* tab = nullptr;      // device copy of the 1D tables (see tab_* offsets)
+  double* minv = nullptr;     // [n_dof] M^-1/2
+  double* mdiag = nullptr;    // [n_dof] M
+  double* dofxyz = nullptr;   // [n_dof][3]
+  double* nodexyz_ptr = nullptr;  // [n_nodes][3]
+  double* cellgeo = nullptr;  // box: [n_cell][4] = {detJ*4/hx^2, .../hy^2, .../hz^2, detJ}
+  double* corners = nullptr;  // [n_cell][8][3] (z-corner slowest, x fastest)
+  double* xq = nullptr;       // [n_cell][nq^3][3]
+  double* wdet = nullptr;     // [n_cell][nq^3] varpi_q detJ_q
+  double* vext = nullptr;     // [n_cell][nq^3]
+  double* vw = nullptr;       // [n_cell][nq^3] weighted total potential used by apply
+  float* vw32 = nullptr;      // FP32 copy for the mixed path
+  double* w1 = nullptr;       // W_{n-1}  (unweighted, [n_cell][nq^3])
+  double* w2 = nullptr;       // W_{n-2}
+  double* wh = nullptr;       // W_{n-1/2}
+  double* rho = nullptr;      // [n_cell][nq^3]
+  double* phi = nullptr;      // [n_nodes] Hartree potential, boundary values included
+  double* cload = nullptr;    // [n_nodes] load vector c_j
+  double* fb = nullptr;       // [n_nodes] boundary values f (0 inside)
+  double* lift = nullptr;     // [n_dof] (K f)_interior
+  double* fdmS = nullptr;     // 1D eigenvector matrices Sx, Sy, Sz (row-major, n1 x n1)
+  double* fdmL = nullptr;     // 1D eigenvalues
+  double* t0 = nullptr;       // [n_dof] scratch
+  double* t1 = nullptr;       // [n_dof] scratch
+  double* pcg = nullptr;      // 5 x [n_nodes] (r, z, p, Ap, x) for curved meshes
+  double* dinvK = nullptr;    // [n_nodes] inverse stiffness diagonal (interior), 0 on boundary
+  void* krylov = nullptr;     // (k_max+1) x [n_dof][cols]
+  void* hq = nullptr;         // [n_dof][cols] apply output
+  void* half = nullptr;       // [n_dof][2 n_orb_max] predictor state (complex128)
+  double* partial = nullptr;  // reduction partials
+  double* scal = nullptr;     // per-orbital Lanczos scalars
+  unsigned* counters = nullptr;
+  int64_t n_partial = 0;
+
+  // host pinned poll buffer
+  int* poll = nullptr;
+  hipEvent_t* evs = nullptr;
+  int n_evs = 0;
+
+  // ---- state -------------------------------------------------------------------
+  bool bound = false, have_potential = false, have_scf = false, scf_init = false;
+  int hartree = 0, xc = 0;
+  std::vector<double> nucZ, nucR, occ, occ_host;
+  double pcg_tol = 1e-13;
+  int pcg_maxit = 5000;
+  int last_poisson_iters = 0;
+};
+
+// error helpers ----------------------------------------------------------------
+tdfe_status tdfe_fail(tdfe_ctx* c, tdfe_status s, const char* fmt, ...);
+#define TDFE_HIP(ctx, call)                                                          \
+  do {                                                                               \
+    hipError_t e_ = (call);                                                          \
+    if (e_ != hipSuccess)                                                            \
+      return tdfe_fail((ctx), TDFE_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+#define TDFE_TRY(x)                      \
+  do {                                   \
+    tdfe_status s_ = (x);                \
+    if (s_ != TDFE_OK) return s_;        \
+  } while (0)
+
+// layout of the device table block ----------------------------------------------
+// tab[TAB_B + a*n + i], tab[TAB_D + ...], tab[TAB_DG + a*nq + b], tab[TAB_W3Q + q]
+#define TAB_B 0
+#define TAB_D (TDFE_MAXN * TDFE_MAXN)
+#define TAB_DG (2 * TDFE_MAXN * TDFE_MAXN)
+#define TAB_ETA (3 * TDFE_MAXN * TDFE_MAXN)
+#define TAB_WQ (TAB_ETA + TDFE_MAXN)
+#define TAB_W3Q (TAB_WQ + TDFE_MAXN)
+#define TAB_SIZE (TAB_W3Q + TDFE_MAXN * TDFE_MAXN * TDFE_MAXN)
+
+// operator launchers (tdfe_apply.hip) ------------------------------------------------
+// y += kin-Laplacian-plus-potential applied to x on the DoF numbering, for
+// `cols` real columns stored [n_dof][ld].  colscale[col/2] (may be NULL)
+// scales the gathered input per orbital pair.  energy (may be NULL) receives
+// per-block partial sums of x^T H x per column (layout [block][cols]).
+struct ApplyArgs {
+  const void* x;
+  void* y;
+  int ld;
+  int cols;
+  const double* colscale;
+  double kin;           // 0.5 for H, 1.0 for K
+  const double* vw;     // weighted potential or NULL
+  const float* vw32;
+  bool lowdin;          // scale by M^-1/2 on gather and scatter
+  bool fullgrid;        // x / y are full node arrays (stiffness mode)
+  double* energy;       // partials or NULL
+  int64_t* n_blocks_out;
+  const int* done_flag; // early-exit flag (device) or NULL
+  bool fp32;            // x, y stored as float
+};
+tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
+
+// vector kernels (tdfe_lanczos.hip)
+tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes);
+tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb,
+                             double tau, double tol, int* k_out, double* err_out, int* kmax_out,
+                             int* ksum_out, double* errmax_out);
+
+// scf kernels (tdfe_scf.hip)
+tdfe_status tdfe_density_dev(tdfe_ctx* c, const void* psibar, int n_orb, double* rho, double* partial3);
+tdfe_status tdfe_dipole_dev(tdfe_ctx* c, const double* rho, double mu[3], double* charge);
+tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, double* w_out,
+                               double* mu, double* charge);
+tdfe_status tdfe_fdm_setup(tdfe_ctx* c);
+tdfe_status tdfe_compute_lift(tdfe_ctx* c);
+
+// workspace carving (tdfe_setup.hip)
+int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols);

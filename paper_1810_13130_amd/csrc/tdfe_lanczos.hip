@@ -1,0 +1,561 @@
+// Adaptive Lanczos exponential exp(-i tau Hbar) psibar on MI355X.
+//
+// Eqs. KrylovSubspace, zk, AdaptiveLanczos: for every orbital its own
+// Lanczos recurrence on the real symmetric Hbar (run on the real and
+// imaginary columns together, the scalars taken as pair sums), the small
+// exponential y = exp(-i tau T_k) e_1 and the a-posteriori error
+// eps_k = |tau| beta_k ||psibar|| |y_k|, checked after every iteration; an
+// orbital is frozen once eps_k <= tol (or on happy breakdown), and the
+// result is z = ||psibar|| sum_j y_j q_j.
+//
+// Device design:
+//  * basis vectors are stored unnormalised (w_j) together with per-orbital
+//    scale factors s_j = 1/beta_{j-1}; every consumer applies s_j on the fly,
+//    which removes the normalisation pass;
+//  * alpha_k = Re<q_k, Hbar q_k> comes from the operator kernel's own
+//    quadrature-point quadratic form (no extra pass over the vectors);
+//  * the three-term update, the zeroing of the operator output and the norm
+//    partials are one streaming kernel;
+//  * all reductions are two-level with a fixed summation order
+//    (deterministic);
+//  * the small exponential is evaluated on the device by the Chebyshev
+//    expansion of exp(-i tau x) on the Gershgorin interval of T_k
+//    (Jacobi-Anger coefficients 2 (-i)^m J_m(tau r), Bessel values by
+//    Miller's backward recurrence), one wavefront per orbital, rows across
+//    lanes.  It gives the same y as an eigendecomposition of T_k to ~1e-15.
+//  * the host enqueues iterations ahead and polls a device "all converged"
+//    flag two iterations behind; iterations enqueued past convergence exit
+//    at their first instruction.
+#include <cmath>
+
+#include "tdfe_internal.h"
+
+namespace {
+
+constexpr int RED_BLOCKS = 1024;  // blocks of the streaming reductions
+constexpr int RED_THREADS = 256;
+constexpr int CHK_THREADS = 64;
+constexpr int MAX_BESSEL = 6144;
+
+// scalar block layout per chunk (doubles), Nc = orbitals in the chunk
+struct Scal {
+  double* alpha;  // [k_max][Nc]
+  double* beta;   // [k_max][Nc]
+  double* scale;  // [k_max+2][Nc]  s_j applied to basis vector j
+  double* nrm;    // [Nc]
+  double* err;    // [Nc]
+  double* y;      // [Nc][k_max][2]
+  int* kconv;     // [Nc]
+  int* status;    // [Nc] 0 active, 1 converged, 2 not converged at k_max, 3 Chebyshev too long
+  int* nconv;     // [1]
+  int* done;      // [1]
+};
+
+Scal carve_scal(tdfe_ctx* c, int Nc) {
+  Scal s;
+  double* p = c->scal;
+  const int K = c->k_max;
+  s.alpha = p;
+  p += (size_t)K * Nc;
+  s.beta = p;
+  p += (size_t)K * Nc;
+  s.scale = p;
+  p += (size_t)(K + 2) * Nc;
+  s.nrm = p;
+  p += Nc;
+  s.err = p;
+  p += Nc;
+  s.y = p;
+  p += (size_t)2 * K * Nc;
+  int* ip = (int*)c->counters;
+  s.kconv = ip;
+  s.status = ip + 64;
+  s.nconv = ip + 128;
+  s.done = ip + 129;
+  return s;
+}
+
+// ---------------------------------------------------------------------------------------------
+// block reduction helper: sums v over threads that share (t % C) -> out[col]
+// ---------------------------------------------------------------------------------------------
+__device__ void block_col_sum(double v, int C, double* sred, double* out) {
+  const int t = threadIdx.x;
+  sred[t] = v;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s >= C; s >>= 1) {
+    if (t < s) sred[t] += sred[t + s];
+    __syncthreads();
+  }
+  if (t < C) out[t] = sred[t];
+}
+
+// copy one orbital chunk of the complex128 input into basis slot 0 (type T)
+// and per-column sum of squares partials
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+    copy_in_kernel(const double* __restrict__ in, int ld_in, int col0, T* __restrict__ w0, int C, int64_t nrows,
+                   double* __restrict__ partial) {
+  __shared__ double sred[RED_THREADS];
+  const int Cp = (C <= 1) ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : (C <= 32 ? 32 : 64)))));
+  const int col = threadIdx.x % Cp;
+  const int rlane = threadIdx.x / Cp;
+  const int rstride = (RED_THREADS / Cp) * gridDim.x;
+  double acc = 0.0;
+  if (col < C) {
+    for (int64_t r = (int64_t)blockIdx.x * (RED_THREADS / Cp) + rlane; r < nrows; r += rstride) {
+      const double v = in[r * ld_in + col0 + col];
+      w0[r * C + col] = (T)v;
+      acc += v * v;
+    }
+  }
+  block_col_sum(acc, Cp, sred, sred);
+  __syncthreads();
+  if (threadIdx.x < C) partial[(int64_t)blockIdx.x * C + threadIdx.x] = sred[threadIdx.x];
+}
+
+// w_k = Hq - alpha s_{k-1} w_{k-1} - beta_{k-2} s_{k-2} w_{k-2}; Hq <- 0; partial ||w_k||^2
+template <typename T>
+__global__ void __launch_bounds__(RED_THREADS)
+    update_kernel(T* __restrict__ hq, const T* __restrict__ wa, const T* __restrict__ wb, T* __restrict__ wn, int C,
+                  int64_t nrows, const double* alpha_k, const double* beta_km1, const double* s_a, const double* s_b,
+                  const int* status, int has_b, double* __restrict__ partial, const int* done) {
+  __shared__ double sred[RED_THREADS];
+  if (*done) return;
+  const int Cp = (C <= 1) ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : (C <= 32 ? 32 : 64)))));
+  const int col = threadIdx.x % Cp;
+  const int rlane = threadIdx.x / Cp;
+  const int rstride = (RED_THREADS / Cp) * gridDim.x;
+  double acc = 0.0;
+  if (col < C) {
+    const int o = col >> 1;
+    const bool live = status[o] == 0;
+    const double ca = live ? alpha_k[o] * s_a[o] : 0.0;
+    const double cb = (live && has_b) ? beta_km1[o] * s_b[o] : 0.0;
+    for (int64_t r = (int64_t)blockIdx.x * (RED_THREADS / Cp) + rlane; r < nrows; r += rstride) {
+      const int64_t i = r * C + col;
+      double v = 0.0;
+      if (live) {
+        v = (double)hq[i] - ca * (double)wa[i];
+        if (has_b) v -= cb * (double)wb[i];
+      }
+      hq[i] = (T)0;
+      const T vt = (T)v;
+      wn[i] = vt;
+      acc += (double)vt * (double)vt;
+    }
+  }
+  block_col_sum(acc, Cp, sred, sred);
+  __syncthreads();
+  if (threadIdx.x < C) partial[(int64_t)blockIdx.x * C + threadIdx.x] = sred[threadIdx.x];
+}
+
+// out[o] = f( sum_b partial[b][2o] + partial[b][2o+1] ), one block per orbital, fixed order.
+// mode 0: plain sum; 1: sqrt; 2: sqrt and also scale0[o] = 1/sqrt (0 if zero)
+__global__ void __launch_bounds__(RED_THREADS)
+    finalize_pairs_kernel(const double* __restrict__ partial, int64_t nblocks, int C, double* out, int mode,
+                          double* scale0, const int* done) {
+  __shared__ double sred[RED_THREADS];
+  if (done && *done) return;
+  const int o = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += RED_THREADS)
+    acc += partial[b * C + 2 * o] + partial[b * C + 2 * o + 1];
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sred[threadIdx.x] += sred[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double v = sred[0];
+    if (mode >= 1) v = sqrt(v);
+    out[o] = v;
+    if (mode == 2) scale0[o] = v > 0.0 ? 1.0 / v : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------------------------------------
+// small exponential and adaptive stop, one wavefront per orbital
+// ---------------------------------------------------------------------------------------------
+constexpr int KCAP = 1024;
+__global__ void __launch_bounds__(CHK_THREADS)
+    check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, int* err_flag) {
+  __shared__ double sJ[MAX_BESSEL + 2];
+  __shared__ double sA[KCAP], sBv[KCAP];  // Chebyshev vectors v_{m-1} / v_m (roles alternate)
+  __shared__ double sa[KCAP], sb[KCAP];
+  __shared__ double syr[KCAP], syi[KCAP];
+  __shared__ double sredlo[CHK_THREADS], sredhi[CHK_THREADS], sredmx[CHK_THREADS];
+  __shared__ int sM;
+  if (*S.done) return;
+  const int o = blockIdx.x;
+  if (S.status[o] != 0) return;
+  const int t = threadIdx.x;
+  for (int j = t; j < k; j += CHK_THREADS) {
+    sa[j] = S.alpha[(size_t)j * Nc + o];
+    sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
+  }
+  __syncthreads();
+  // Gershgorin interval of T_k and max |alpha|
+  double lo = 1e300, hi = -1e300, amax = 0.0;
+  for (int j = t; j < k; j += CHK_THREADS) {
+    double rad = 0.0;
+    if (j > 0) rad += fabs(sb[j - 1]);
+    if (j < k - 1) rad += fabs(sb[j]);
+    lo = fmin(lo, sa[j] - rad);
+    hi = fmax(hi, sa[j] + rad);
+    amax = fmax(amax, fabs(sa[j]));
+  }
+  sredlo[t] = lo;
+  sredhi[t] = hi;
+  sredmx[t] = amax;
+  __syncthreads();
+  for (int s = CHK_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sredlo[t] = fmin(sredlo[t], sredlo[t + s]);
+      sredhi[t] = fmax(sredhi[t], sredhi[t + s]);
+      sredmx[t] = fmax(sredmx[t], sredmx[t + s]);
+    }
+    __syncthreads();
+  }
+  lo = sredlo[0];
+  hi = sredhi[0];
+  amax = sredmx[0];
+  const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
+  const double z = fabs(tau) * rr;
+  // Bessel J_m(z), m = 0..M, by Miller's backward recurrence normalised with
+  // J_0 + 2 sum J_2m = 1 (lane 0)
+  if (t == 0) {
+    int M = 0;
+    if (z > 1e-300) {
+      M = (int)ceil(z + 10.0 * cbrt(z) + 20.0);
+      int ms = M + 20 + (int)(2.0 * sqrt((double)M));
+      ms += ms & 1;
+      if (ms + 1 > MAX_BESSEL) {
+        M = -1;
+      } else {
+        sJ[ms + 1] = 0.0;
+        sJ[ms] = 1e-300;
+        for (int m = ms; m > 0; --m) {
+          const double jm1 = (2.0 * m / z) * sJ[m] - sJ[m + 1];
+          sJ[m - 1] = jm1;
+          if (fabs(jm1) > 1e250)
+            for (int q = m - 1; q <= ms + 1; ++q) sJ[q] *= 1e-250;
+        }
+        double norm = sJ[0];
+        for (int m = 2; m <= ms; m += 2) norm += 2.0 * sJ[m];
+        const double inv = 1.0 / norm;
+        for (int m = 0; m <= M; ++m) sJ[m] *= inv;
+      }
+    } else {
+      sJ[0] = 1.0;
+    }
+    sM = M;
+  }
+  __syncthreads();
+  const int M = sM;
+  if (M < 0) {
+    if (t == 0) {
+      S.status[o] = 3;
+      atomicOr(err_flag, 1);
+      if (atomicAdd(S.nconv, 1) + 1 == Nc) *S.done = 1;
+    }
+    return;
+  }
+  // Chebyshev recurrence v_{m+1} = 2 X v_m - v_{m-1}, X = (T - c)/r, v_0 = e_1
+  const double sgn = tau >= 0.0 ? 1.0 : -1.0;
+  const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
+  for (int j = t; j < k; j += CHK_THREADS) {
+    sA[j] = (j == 0) ? 1.0 : 0.0;  // v_0
+    syr[j] = sJ[0] * sA[j];
+    syi[j] = 0.0;
+  }
+  __syncthreads();
+  double* prev = sA;  // v_{m-1}
+  double* cur = sBv;  // v_m
+  if (M >= 1) {
+    for (int j = t; j < k; j += CHK_THREADS) {
+      double w = (sa[j] - cc) * prev[j];
+      if (j > 0) w += sb[j - 1] * prev[j - 1];
+      if (j < k - 1) w += sb[j] * prev[j + 1];
+      w *= invr;
+      cur[j] = w;                      // v_1 = X e_1
+      syi[j] += -2.0 * sgn * sJ[1] * w;  // 2 (-i sgn) J_1
+    }
+    __syncthreads();
+    for (int mm = 2; mm <= M; ++mm) {
+      const double cj = 2.0 * sJ[mm];
+      const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
+      for (int j = t; j < k; j += CHK_THREADS) {
+        double w = (sa[j] - cc) * cur[j];
+        if (j > 0) w += sb[j - 1] * cur[j - 1];
+        if (j < k - 1) w += sb[j] * cur[j + 1];
+        const double v2 = 2.0 * w * invr - prev[j];
+        prev[j] = v2;  // row j of v_{m-1} is read only by this thread
+        if (ph == 0) syr[j] += cj * v2;
+        else if (ph == 1) syi[j] -= sgn * cj * v2;
+        else if (ph == 2) syr[j] -= cj * v2;
+        else syi[j] += sgn * cj * v2;
+      }
+      __syncthreads();
+      double* tmp = prev;
+      prev = cur;
+      cur = tmp;
+    }
+  }
+  // multiply by exp(-i tau c)
+  const double pr = cos(tau * cc), pim = -sin(tau * cc);
+  for (int j = t; j < k; j += CHK_THREADS) {
+    const double a = syr[j], b = syi[j];
+    syr[j] = a * pr - b * pim;
+    syi[j] = a * pim + b * pr;
+  }
+  __syncthreads();
+  const double bk = sb[k - 1];
+  const double eps = fabs(tau) * bk * S.nrm[o] * sqrt(syr[k - 1] * syr[k - 1] + syi[k - 1] * syi[k - 1]);
+  const bool happy = bk <= 1e-14 * amax;
+  const bool conv = (eps <= tol) || happy;
+  const bool stop = conv || k >= k_max;
+  if (stop) {
+    for (int j = t; j < k; j += CHK_THREADS) {
+      S.y[((size_t)o * k_max + j) * 2 + 0] = syr[j];
+      S.y[((size_t)o * k_max + j) * 2 + 1] = syi[j];
+    }
+  }
+  if (t == 0) {
+    S.err[o] = eps;
+    if (stop) {
+      S.kconv[o] = k;
+      S.status[o] = conv ? 1 : 2;
+      S.scale[(size_t)k * Nc + o] = 0.0;
+      if (atomicAdd(S.nconv, 1) + 1 == Nc) *S.done = 1;
+    } else {
+      S.scale[(size_t)k * Nc + o] = 1.0 / bk;
+    }
+  }
+}
+
+// z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk
+template <typename T>
+__global__ void combine_kernel(const T* __restrict__ W, int64_t stride_vec, int C, int64_t nrows, Scal S, int Nc,
+                               int k_max, double* __restrict__ out, int ld_out, int col0) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int o = (int)(idx % Nc);
+  const int64_t r = idx / Nc;
+  if (r >= nrows) return;
+  const int kc = S.kconv[o];
+  double zr = 0.0, zi = 0.0;
+  for (int j = 0; j < kc; ++j) {
+    const double s = S.scale[(size_t)j * Nc + o];
+    const double ar = S.y[((size_t)o * k_max + j) * 2 + 0] * s;
+    const double ai = S.y[((size_t)o * k_max + j) * 2 + 1] * s;
+    const T* w = W + j * stride_vec + r * C + 2 * o;
+    const double qr = (double)w[0], qi = (double)w[1];
+    zr += ar * qr - ai * qi;
+    zi += ar * qi + ai * qr;
+  }
+  const double nr = S.nrm[o];
+  out[r * ld_out + col0 + 2 * o] = nr * zr;
+  out[r * ld_out + col0 + 2 * o + 1] = nr * zi;
+}
+
+__global__ void init_scal_kernel(Scal S, int Nc) {
+  const int o = threadIdx.x;
+  if (o < Nc) {
+    S.status[o] = 0;
+    S.kconv[o] = 0;
+    S.err[o] = 0.0;
+  }
+  if (o == 0) {
+    *S.nconv = 0;
+    *S.done = 0;
+  }
+}
+
+// orbitals with zero norm are finished before the first iteration
+__global__ void zero_norm_kernel(Scal S, int Nc) {
+  const int o = threadIdx.x;
+  if (o < Nc && !(S.nrm[o] > 0.0)) {
+    S.status[o] = 1;
+    S.kconv[o] = 0;
+    if (atomicAdd(S.nconv, 1) + 1 == Nc) *S.done = 1;
+  }
+}
+
+int pad_cols(int C) {
+  int p = 1;
+  while (p < C) p <<= 1;
+  return p;
+}
+
+template <typename T>
+tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out, int ld, int o0, int Nc,
+                      double tau, double tol, int* k_out, double* err_out, int* status_out) {
+  const int C = 2 * Nc;
+  const int64_t nd = c->n_dof;
+  const int64_t vstride = nd * C;
+  T* W = (T*)c->krylov;
+  T* Hq = (T*)c->hq;
+  Scal S = carve_scal(c, Nc);
+  const int K = c->k_max;
+  int* err_flag = (int*)c->counters + 140;
+
+  hipLaunchKernelGGL(init_scal_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc);
+  TDFE_HIP(c, hipMemsetAsync(Hq, 0, (size_t)vstride * sizeof(T), c->stream));
+  TDFE_HIP(c, hipMemsetAsync(err_flag, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL((copy_in_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, in, ld, 2 * o0, W, C, nd,
+                     c->partial);
+  hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
+                     (int64_t)RED_BLOCKS, C, S.nrm, 2, S.scale, (const int*)nullptr);
+  hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc);
+  TDFE_HIP(c, hipGetLastError());
+
+  const int LOOK = 2;
+  const int RING = 8;
+  if (!c->evs) {
+    c->evs = new hipEvent_t[RING];
+    for (int i = 0; i < RING; ++i) TDFE_HIP(c, hipEventCreateWithFlags(&c->evs[i], hipEventDisableTiming));
+    c->n_evs = RING;
+  }
+  for (int k = 1; k <= K; ++k) {
+    T* wk = W + (int64_t)(k - 1) * vstride;
+    ApplyArgs a{};
+    a.x = wk;
+    a.y = Hq;
+    a.ld = C;
+    a.cols = C;
+    a.colscale = S.scale + (size_t)(k - 1) * Nc;
+    a.kin = 0.5;
+    a.vw = (const double*)vw;
+    a.vw32 = (const float*)vw;
+    a.lowdin = true;
+    a.fullgrid = false;
+    a.energy = c->partial;
+    int64_t groups = 0;
+    a.n_blocks_out = &groups;
+    a.done_flag = S.done;
+    a.fp32 = sizeof(T) == 4;
+    TDFE_TRY(tdfe_launch_apply(c, a));
+    hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial, groups, C,
+                       S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (const int*)S.done);
+    const T* wb = k >= 2 ? W + (int64_t)(k - 2) * vstride : wk;
+    hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, Hq, (const T*)wk, wb,
+                       W + (int64_t)k * vstride, C, nd, S.alpha + (size_t)(k - 1) * Nc,
+                       S.beta + (size_t)(k >= 2 ? k - 2 : 0) * Nc, S.scale + (size_t)(k - 1) * Nc,
+                       S.scale + (size_t)(k >= 2 ? k - 2 : 0) * Nc, (const int*)S.status, k >= 2 ? 1 : 0, c->partial,
+                       (const int*)S.done);
+    hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
+                       (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 1, (double*)nullptr,
+                       (const int*)S.done);
+    hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, err_flag);
+    TDFE_HIP(c, hipGetLastError());
+    TDFE_HIP(c, hipMemcpyAsync(c->poll + (k % RING), S.done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    TDFE_HIP(c, hipEventRecord(c->evs[k % RING], c->stream));
+    if (k > LOOK) {
+      const int kk = k - LOOK;
+      TDFE_HIP(c, hipEventSynchronize(c->evs[kk % RING]));
+      if (c->poll[kk % RING]) break;
+    }
+  }
+  // combination
+  {
+    const int64_t n = nd * Nc;
+    hipLaunchKernelGGL((combine_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)W,
+                       vstride, C, nd, S, Nc, K, out, ld, 2 * o0);
+    TDFE_HIP(c, hipGetLastError());
+  }
+  std::vector<int> kc(Nc), st(Nc);
+  std::vector<double> er(Nc);
+  int ef = 0;
+  TDFE_HIP(c, hipMemcpyAsync(kc.data(), S.kconv, Nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipMemcpyAsync(st.data(), S.status, Nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipMemcpyAsync(er.data(), S.err, Nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipMemcpyAsync(&ef, err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  for (int o = 0; o < Nc; ++o) {
+    k_out[o] = kc[o];
+    err_out[o] = er[o];
+    status_out[o] = st[o];
+  }
+  if (ef) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
+  return TDFE_OK;
+}
+
+}  // namespace
+
+tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes) {
+  TDFE_HIP(c, hipMemsetAsync(p, 0, bytes, c->stream));
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb, double tau,
+                             double tol, int* k_out, double* err_out, int* kmax_out, int* ksum_out,
+                             double* errmax_out) {
+  const int ld = 2 * n_orb;
+  std::vector<int> ks(n_orb), st(n_orb);
+  std::vector<double> es(n_orb);
+  const void* v = c->precision == TDFE_FP64 ? (const void*)vw : (const void*)c->vw32;
+  // when the input is also the output, every chunk must read the input before
+  // any chunk writes: the combination of a chunk only writes that chunk's
+  // columns, and copy_in of a chunk only reads them, so chunk order is safe.
+  for (int o0 = 0; o0 < n_orb; o0 += c->chunk_orb) {
+    const int Nc = std::min(c->chunk_orb, n_orb - o0);
+    tdfe_status s;
+    if (c->precision == TDFE_FP64)
+      s = run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
+                            es.data() + o0, st.data() + o0);
+    else
+      s = run_chunk<float>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
+                           es.data() + o0, st.data() + o0);
+    if (s != TDFE_OK) return s;
+  }
+  int kmax = 0, ksum = 0, bad = 0;
+  double emax = 0.0;
+  for (int o = 0; o < n_orb; ++o) {
+    kmax = std::max(kmax, ks[o]);
+    ksum += ks[o];
+    emax = std::max(emax, es[o]);
+    if (st[o] == 2) bad = 1;
+    if (k_out) k_out[o] = ks[o];
+    if (err_out) err_out[o] = es[o];
+  }
+  if (kmax_out) *kmax_out = kmax;
+  if (ksum_out) *ksum_out = ksum;
+  if (errmax_out) *errmax_out = emax;
+  if (bad) return tdfe_fail(c, TDFE_ENOCONV, "Lanczos reached k_max=%d without eps <= %g", c->k_max, tol);
+  return TDFE_OK;
+}
+
+extern "C" {
+
+tdfe_status tdfe_apply_H(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int n_orb) {
+  if (!c || !dev_psibar || !dev_out) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "apply_H: n_orb out of range");
+  if (dev_psibar == dev_out) return tdfe_fail(c, TDFE_EINVAL, "apply_H: output aliases input");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "apply_H before bind_workspace");
+  if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "apply_H before set_potential");
+  const int cols = 2 * n_orb;
+  TDFE_HIP(c, hipMemsetAsync(dev_out, 0, (size_t)c->n_dof * cols * sizeof(double), c->stream));
+  ApplyArgs a{};
+  a.x = dev_psibar;
+  a.y = dev_out;
+  a.ld = cols;
+  a.cols = cols;
+  a.kin = 0.5;
+  a.vw = c->vw;
+  a.lowdin = true;
+  a.fp32 = false;
+  return tdfe_launch_apply(c, a);
+}
+
+tdfe_status tdfe_lanczos_expm(tdfe_ctx* c, void* dev_psibar, int n_orb, double tau, double tol, int* host_k,
+                              double* host_err) {
+  if (!c || !dev_psibar) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "lanczos_expm: n_orb out of range");
+  if (!(tol > 0.0) || !std::isfinite(tau)) return tdfe_fail(c, TDFE_EINVAL, "lanczos_expm: bad tau/tol");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "lanczos_expm before bind_workspace");
+  if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "lanczos_expm before set_potential");
+  return tdfe_lanczos_run(c, c->vw, dev_psibar, dev_psibar, n_orb, tau, tol, host_k, host_err, nullptr, nullptr,
+                          nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,863 @@
+// Density, dipole, Hartree/XC potential and the Magnus step (tdfe C ABI).
+//
+// * density: rho_q = sum_alpha f_alpha |psi_alpha(x_q)|^2 with
+//   psi = M^-1/2 psibar interpolated to the Gauss points (Sec. TDKS
+//   equations, Eq. TDKSMatVecStandard);
+// * dipole mu = sum_q varpi_q detJ_q x_q rho_q, charge = sum_q varpi_q detJ_q rho_q;
+// * Hartree: K phi = 4 pi c, c_j = int rho N_j, phi = f on the boundary with
+//   f = sum_I Z_I / |x - R_I| at the boundary nodes (Eqs. Poisson,
+//   VHDiscretePoisson; the appendix's boundary interpolant).  On a
+//   rectilinear grid with Gauss quadrature the interior stiffness is exactly
+//   the Kronecker sum Kx(x)My(x)Mz + Mx(x)Ky(x)Mz + Mx(x)My(x)Kz of 1D
+//   matrices, so it is inverted exactly by the fast diagonalisation method
+//   (1D generalised eigenvectors S with S^T M S = I, S^T K S = Lambda):
+//   K^-1 = (S x S x S) diag(1/(lx+ly+lz)) (S x S x S)^T.  Curved meshes use
+//   Jacobi-preconditioned conjugate gradients.
+// * ALDA exchange (and Perdew-Zunger 81 correlation) at the Gauss points.
+// * magnus_step: the predictor-corrector second-order Magnus step.
+#include <algorithm>
+#include <cmath>
+
+#include "tdfe_internal.h"
+
+namespace {
+
+constexpr int EW = 256;  // elementwise block size
+
+inline unsigned nblk(int64_t n, int b = EW) { return (unsigned)((n + b - 1) / b); }
+
+constexpr int pow2_floor(int x) {
+  int p = 1;
+  while (p * 2 <= x) p *= 2;
+  return p;
+}
+
+__device__ __forceinline__ int64_t dof_of(int I, int J, int K, int Nx, int Ny) {
+  return (int64_t)(I - 1) + (int64_t)(Nx - 2) * ((int64_t)(J - 1) + (int64_t)(Ny - 2) * (K - 1));
+}
+
+// ------------------------------------------------------------------------------------------------
+// density: per cell, all orbitals; rho at the Gauss points and dipole partials
+// ------------------------------------------------------------------------------------------------
+struct DensParams {
+  const double* psi;  // [n_dof][2 n_orb]
+  int cols;           // 2 n_orb
+  const double* occ;  // [n_orb]
+  const double* minv;
+  const double* tab;
+  const double* wdet;
+  const double* xq;
+  double* rho;
+  double* partial;  // [block][4]
+  int ncx, ncy, ncz, p, Nx, Ny, Nz;
+  int64_t n_cell;
+};
+
+template <int N, int CB>
+__global__ void __launch_bounds__(N* N* CB) density_kernel(DensParams P) {
+  constexpr int VOL = N * N * N;
+  constexpr int T = N * N * CB;
+  __shared__ double sU[VOL * CB];
+  __shared__ double sB[N * N];
+  __shared__ double sred[T];
+  const int t = threadIdx.x;
+  const int col = t % CB, line = t / CB;
+  const int64_t cell = blockIdx.x;
+  for (int i = t; i < N * N; i += T) sB[i] = P.tab[TAB_B + (i / N) * TDFE_MAXN + (i % N)];
+  const int cx = (int)(cell % P.ncx), cy = (int)((cell / P.ncx) % P.ncy), cz = (int)(cell / ((int64_t)P.ncx * P.ncy));
+  double racc[N];
+#pragma unroll
+  for (int a = 0; a < N; ++a) racc[a] = 0.0;
+  __syncthreads();
+  auto L = [&](int z, int y, int x) { return ((z * N + y) * N + x) * CB + col; };
+  for (int c0 = 0; c0 < P.cols; c0 += CB) {
+    const int cg = c0 + col;
+    const bool ok = cg < P.cols;
+    double r1[N];
+    {
+      const int i = line % N, j = line / N;
+      const int I = cx * P.p + i, J = cy * P.p + j;
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const int K = cz * P.p + k;
+        double v = 0.0;
+        if (ok && I > 0 && I < P.Nx - 1 && J > 0 && J < P.Ny - 1 && K > 0 && K < P.Nz - 1) {
+          const int64_t d = dof_of(I, J, K, P.Nx, P.Ny);
+          v = P.psi[d * P.cols + cg] * P.minv[d];
+        }
+        r1[k] = v;
+      }
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        double s = 0;
+#pragma unroll
+        for (int k = 0; k < N; ++k) s += sB[c * N + k] * r1[k];
+        sU[L(c, j, i)] = s;
+      }
+    }
+    __syncthreads();
+    {
+      const int i = line % N, c = line / N;
+#pragma unroll
+      for (int j = 0; j < N; ++j) r1[j] = sU[L(c, j, i)];
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        double s = 0;
+#pragma unroll
+        for (int j = 0; j < N; ++j) s += sB[b * N + j] * r1[j];
+        sU[L(c, b, i)] = s;
+      }
+    }
+    __syncthreads();
+    {
+      const int b = line % N, c = line / N;
+#pragma unroll
+      for (int i = 0; i < N; ++i) r1[i] = sU[L(c, b, i)];
+      const double f = ok ? P.occ[cg >> 1] : 0.0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        double s = 0;
+#pragma unroll
+        for (int i = 0; i < N; ++i) s += sB[a * N + i] * r1[i];
+        racc[a] += f * s * s;
+      }
+    }
+    __syncthreads();
+  }
+  // sum over the column lanes of each x-line
+  {
+    const int b = line % N, c = line / N;
+#pragma unroll
+    for (int a = 0; a < N; ++a) sU[L(c, b, a)] = racc[a];
+  }
+  __syncthreads();
+  double ch = 0, mx = 0, my = 0, mz = 0;
+  for (int q = t; q < VOL; q += T) {
+    double s = 0.0;
+    for (int cc = 0; cc < CB; ++cc) s += sU[q * CB + cc];
+    const int64_t g = cell * VOL + q;
+    P.rho[g] = s;
+    const double w = P.wdet[g] * s;
+    ch += w;
+    mx += w * P.xq[g * 3 + 0];
+    my += w * P.xq[g * 3 + 1];
+    mz += w * P.xq[g * 3 + 2];
+  }
+  double vals[4] = {ch, mx, my, mz};
+  constexpr int PW = pow2_floor(T);
+  for (int v = 0; v < 4; ++v) {
+    sred[t] = vals[v];
+    __syncthreads();
+    if (t < T - PW) sred[t] += sred[t + PW];  // fold the part beyond the largest power of two
+    __syncthreads();
+    for (int s = PW / 2; s > 0; s >>= 1) {
+      if (t < s) sred[t] += sred[t + s];
+      __syncthreads();
+    }
+    if (t == 0) P.partial[cell * 4 + v] = sred[0];
+    __syncthreads();
+  }
+}
+
+// sum of [nblocks][4] partials in a fixed order
+__global__ void finalize4_kernel(const double* partial, int64_t nblocks, double* out) {
+  __shared__ double sred[256];
+  for (int v = 0; v < 4; ++v) {
+    double acc = 0.0;
+    for (int64_t b = threadIdx.x; b < nblocks; b += 256) acc += partial[b * 4 + v];
+    sred[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (threadIdx.x < s) sred[threadIdx.x] += sred[threadIdx.x + s];
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) out[v] = sred[0];
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// load vector c_j = sum_e sum_q varpi_q detJ_q rho_q N_j(x_q), all nodes (full grid)
+// ------------------------------------------------------------------------------------------------
+template <int N>
+__global__ void __launch_bounds__(N* N) load_kernel(const double* rho, const double* wdet, const double* tab,
+                                                     double* cload, int ncx, int ncy, int p, int Nx, int Ny) {
+  constexpr int VOL = N * N * N;
+  __shared__ double sU[VOL];
+  __shared__ double sB[N * N];
+  const int t = threadIdx.x;
+  const int64_t cell = blockIdx.x;
+  if (t < N * N) sB[t] = tab[TAB_B + (t / N) * TDFE_MAXN + (t % N)];
+  __syncthreads();
+  const int cx = (int)(cell % ncx), cy = (int)((cell / ncx) % ncy), cz = (int)(cell / ((int64_t)ncx * ncy));
+  double r1[N];
+  {
+    const int a = t % N, b = t / N;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const int64_t g = cell * VOL + a + N * (b + N * c);
+      r1[c] = wdet[g] * rho[g];
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      double s = 0;
+#pragma unroll
+      for (int c = 0; c < N; ++c) s += tab[TAB_B + c * TDFE_MAXN + k] * r1[c];
+      sU[(k * N + b) * N + a] = s;
+    }
+  }
+  __syncthreads();
+  {
+    const int a = t % N, k = t / N;
+#pragma unroll
+    for (int b = 0; b < N; ++b) r1[b] = sU[(k * N + b) * N + a];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      double s = 0;
+#pragma unroll
+      for (int b = 0; b < N; ++b) s += sB[b * N + j] * r1[b];
+      sU[(k * N + j) * N + a] = s;
+    }
+  }
+  __syncthreads();
+  {
+    const int j = t % N, k = t / N;
+#pragma unroll
+    for (int a = 0; a < N; ++a) r1[a] = sU[(k * N + j) * N + a];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      double s = 0;
+#pragma unroll
+      for (int a = 0; a < N; ++a) s += sB[a * N + i] * r1[a];
+      const int64_t node = (int64_t)(cx * p + i) + (int64_t)Nx * ((int64_t)(cy * p + j) + (int64_t)Ny * (cz * p + k));
+      unsafeAtomicAdd(cload + node, s);
+    }
+  }
+}
+
+// ------------------------------------------------------------------------------------------------
+// nodal field (full grid) -> Gauss points, fused with the XC potential:
+//   W_q = phi(x_q) + V_xc(rho_q)
+// ------------------------------------------------------------------------------------------------
+__device__ double vxc(double rho, int mode) {
+  if (mode == TDFE_XC_NONE || !(rho > 1e-300)) return 0.0;
+  double v = -cbrt(3.0 * rho / M_PI);
+  if (mode == TDFE_XC_XC) {
+    const double rs = cbrt(3.0 / (4.0 * M_PI * rho));
+    if (rs >= 1.0) {
+      const double g = -0.1423, b1 = 1.0529, b2 = 0.3334;
+      const double sq = sqrt(rs);
+      const double den = 1.0 + b1 * sq + b2 * rs;
+      v += g * (1.0 + 7.0 / 6.0 * b1 * sq + 4.0 / 3.0 * b2 * rs) / (den * den);
+    } else {
+      const double A = 0.0311, B = -0.048, C = 0.0020, D = -0.0116;
+      const double lr = log(rs);
+      v += A * lr + (B - A / 3.0) + 2.0 / 3.0 * C * rs * lr + (2.0 * D - C) / 3.0 * rs;
+    }
+  }
+  return v;
+}
+
+template <int N>
+__global__ void __launch_bounds__(N* N) interp_xc_kernel(const double* phi, const double* rho, const double* tab,
+                                                          double* W, int hartree, int xcmode, int ncx, int ncy, int p,
+                                                          int Nx, int Ny) {
+  constexpr int VOL = N * N * N;
+  __shared__ double sU[VOL];
+  __shared__ double sB[N * N];
+  const int t = threadIdx.x;
+  const int64_t cell = blockIdx.x;
+  if (t < N * N) sB[t] = tab[TAB_B + (t / N) * TDFE_MAXN + (t % N)];
+  __syncthreads();
+  const int cx = (int)(cell % ncx), cy = (int)((cell / ncx) % ncy), cz = (int)(cell / ((int64_t)ncx * ncy));
+  double r1[N];
+  {
+    const int i = t % N, j = t / N;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      const int64_t node = (int64_t)(cx * p + i) + (int64_t)Nx * ((int64_t)(cy * p + j) + (int64_t)Ny * (cz * p + k));
+      r1[k] = hartree ? phi[node] : 0.0;
+    }
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      double s = 0;
+#pragma unroll
+      for (int k = 0; k < N; ++k) s += sB[c * N + k] * r1[k];
+      sU[(c * N + j) * N + i] = s;
+    }
+  }
+  __syncthreads();
+  {
+    const int i = t % N, c = t / N;
+#pragma unroll
+    for (int j = 0; j < N; ++j) r1[j] = sU[(c * N + j) * N + i];
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      double s = 0;
+#pragma unroll
+      for (int j = 0; j < N; ++j) s += sB[b * N + j] * r1[j];
+      sU[(c * N + b) * N + i] = s;
+    }
+  }
+  __syncthreads();
+  {
+    const int b = t % N, c = t / N;
+#pragma unroll
+    for (int i = 0; i < N; ++i) r1[i] = sU[(c * N + b) * N + i];
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      double s = 0;
+#pragma unroll
+      for (int i = 0; i < N; ++i) s += sB[a * N + i] * r1[i];
+      const int64_t g = cell * VOL + a + N * (b + N * c);
+      W[g] = s + vxc(rho[g], xcmode);
+    }
+  }
+}
+
+// vw = wdet * (vext - E z + ca * A + cb * B)   (A, B may be null)
+__global__ void assemble_vw_kernel(const double* vext, const double* xq, const double* wdet, const double* A, double ca,
+                                   const double* Bv, double cb, double E, double* vw, float* vw32, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = vext[i] - E * xq[i * 3 + 2];
+  if (A) v += ca * A[i];
+  if (Bv) v += cb * Bv[i];
+  const double x = wdet[i] * v;
+  vw[i] = x;
+  if (vw32) vw32[i] = (float)x;
+}
+
+// ------------------------------------------------------------------------------------------------
+// Poisson: boundary data, right-hand side, fast diagonalisation
+// ------------------------------------------------------------------------------------------------
+__global__ void boundary_values_kernel(const double* nodexyz, const double* ZR, int nnuc, double* fb, double* phi,
+                                       int Nx, int Ny, int Nz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)Nx * Ny * Nz;
+  if (idx >= nn) return;
+  const int I = (int)(idx % Nx), J = (int)((idx / Nx) % Ny), K = (int)(idx / ((int64_t)Nx * Ny));
+  const bool bnd = I == 0 || I == Nx - 1 || J == 0 || J == Ny - 1 || K == 0 || K == Nz - 1;
+  double f = 0.0;
+  if (bnd) {
+    for (int a = 0; a < nnuc; ++a) {
+      const double dx = nodexyz[idx * 3 + 0] - ZR[a * 4 + 1];
+      const double dy = nodexyz[idx * 3 + 1] - ZR[a * 4 + 2];
+      const double dz = nodexyz[idx * 3 + 2] - ZR[a * 4 + 3];
+      f += ZR[a * 4 + 0] / sqrt(dx * dx + dy * dy + dz * dz);
+    }
+  }
+  fb[idx] = f;
+  phi[idx] = f;
+}
+
+// interior entries of a full-grid array -> DoF numbering, out = s * full[node] - sub[dof]
+__global__ void gather_interior_kernel(const double* full, const double* sub, double s, double* out, int Nx, int Ny,
+                                       int Nz) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nd = (int64_t)(Nx - 2) * (Ny - 2) * (Nz - 2);
+  if (d >= nd) return;
+  const int i = (int)(d % (Nx - 2)), j = (int)((d / (Nx - 2)) % (Ny - 2)), k = (int)(d / ((int64_t)(Nx - 2) * (Ny - 2)));
+  const int64_t node = (int64_t)(i + 1) + (int64_t)Nx * ((int64_t)(j + 1) + (int64_t)Ny * (k + 1));
+  out[d] = s * full[node] - (sub ? sub[d] : 0.0);
+}
+
+__global__ void scatter_interior_kernel(const double* in, double* full, int Nx, int Ny, int Nz) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nd = (int64_t)(Nx - 2) * (Ny - 2) * (Nz - 2);
+  if (d >= nd) return;
+  const int i = (int)(d % (Nx - 2)), j = (int)((d / (Nx - 2)) % (Ny - 2)), k = (int)(d / ((int64_t)(Nx - 2) * (Ny - 2)));
+  const int64_t node = (int64_t)(i + 1) + (int64_t)Nx * ((int64_t)(j + 1) + (int64_t)Ny * (k + 1));
+  full[node] = in[d];
+}
+
+// one 1D transform of the interior grid along `axis`:
+//   trans = 1: out[.., m', ..] = sum_m S[m][m'] in[.., m, ..]   (S^T)
+//   trans = 0: out[.., m', ..] = sum_m S[m'][m] in[.., m, ..]   (S)
+// if lam != null the result is divided by lx_i + ly_j + lz_k.
+constexpr int FDM_TL = 16;
+__global__ void __launch_bounds__(256) fdm_axis_kernel(const double* in, double* out, const double* S, int n1x, int n1y,
+                                                       int n1z, int axis, int trans, const double* lx, const double* ly,
+                                                       const double* lz) {
+  extern __shared__ double tile[];  // [n_ax][FDM_TL]
+  const int nax = axis == 0 ? n1x : (axis == 1 ? n1y : n1z);
+  const int64_t nlines = (int64_t)n1x * n1y * n1z / nax;
+  const int64_t l0 = (int64_t)blockIdx.x * FDM_TL;
+  auto base_stride = [&](int64_t line, int64_t& base, int64_t& stride) {
+    if (axis == 0) {
+      base = line * n1x;
+      stride = 1;
+    } else if (axis == 1) {
+      const int64_t i = line % n1x, k = line / n1x;
+      base = i + k * (int64_t)n1x * n1y;
+      stride = n1x;
+    } else {
+      base = line;
+      stride = (int64_t)n1x * n1y;
+    }
+  };
+  for (int idx = threadIdx.x; idx < nax * FDM_TL; idx += blockDim.x) {
+    int m, l;
+    if (axis == 0) {
+      l = idx / nax;
+      m = idx % nax;
+    } else {
+      m = idx / FDM_TL;
+      l = idx % FDM_TL;
+    }
+    const int64_t line = l0 + l;
+    double v = 0.0;
+    if (line < nlines) {
+      int64_t b, s;
+      base_stride(line, b, s);
+      v = in[b + m * s];
+    }
+    tile[m * FDM_TL + l] = v;
+  }
+  __syncthreads();
+  for (int idx = threadIdx.x; idx < nax * FDM_TL; idx += blockDim.x) {
+    int mp, l;
+    if (axis == 0) {
+      l = idx / nax;
+      mp = idx % nax;
+    } else {
+      mp = idx / FDM_TL;
+      l = idx % FDM_TL;
+    }
+    const int64_t line = l0 + l;
+    if (line >= nlines) continue;
+    double s = 0.0;
+    if (trans)
+      for (int m = 0; m < nax; ++m) s += S[(int64_t)m * nax + mp] * tile[m * FDM_TL + l];
+    else
+      for (int m = 0; m < nax; ++m) s += S[(int64_t)mp * nax + m] * tile[m * FDM_TL + l];
+    int64_t b, st;
+    base_stride(line, b, st);
+    const int64_t o = b + mp * st;
+    if (lx) {
+      const int64_t i = o % n1x, j = (o / n1x) % n1y, k = o / ((int64_t)n1x * n1y);
+      s /= (lx[i] + ly[j] + lz[k]);
+    }
+    out[o] = s;
+  }
+}
+
+// ---- host linear algebra for the 1D fast-diagonalisation tables ------------------------------
+void cholesky(std::vector<double>& A, int n) {  // lower, in place
+  for (int j = 0; j < n; ++j) {
+    double s = A[j * n + j];
+    for (int k = 0; k < j; ++k) s -= A[j * n + k] * A[j * n + k];
+    A[j * n + j] = std::sqrt(s);
+    for (int i = j + 1; i < n; ++i) {
+      double t = A[i * n + j];
+      for (int k = 0; k < j; ++k) t -= A[i * n + k] * A[j * n + k];
+      A[i * n + j] = t / A[j * n + j];
+    }
+    for (int k = j + 1; k < n; ++k) A[j * n + k] = 0.0;
+  }
+}
+
+// cyclic Jacobi eigenvalue algorithm for a symmetric matrix: A = U diag(lam) U^T
+void jacobi_eigen(std::vector<double> A, int n, std::vector<double>& lam, std::vector<double>& U) {
+  U.assign((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) U[(size_t)i * n + i] = 1.0;
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0.0, tot = 0.0;
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        const double v = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+        tot += v;
+        if (i != j) off += v;
+      }
+    if (off <= 1e-32 * tot) break;
+    for (int p = 0; p < n - 1; ++p)
+      for (int q = p + 1; q < n; ++q) {
+        const double apq = A[(size_t)p * n + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+        const double theta = (aqq - app) / (2.0 * apq);
+        const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+        const double cs = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * cs;
+        for (int k = 0; k < n; ++k) {  // columns p, q
+          const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+          A[(size_t)k * n + p] = cs * akp - sn * akq;
+          A[(size_t)k * n + q] = sn * akp + cs * akq;
+        }
+        for (int k = 0; k < n; ++k) {  // rows p, q
+          const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+          A[(size_t)p * n + k] = cs * apk - sn * aqk;
+          A[(size_t)q * n + k] = sn * apk + cs * aqk;
+        }
+        for (int k = 0; k < n; ++k) {
+          const double ukp = U[(size_t)k * n + p], ukq = U[(size_t)k * n + q];
+          U[(size_t)k * n + p] = cs * ukp - sn * ukq;
+          U[(size_t)k * n + q] = sn * ukp + cs * ukq;
+        }
+      }
+  }
+  lam.resize(n);
+  for (int i = 0; i < n; ++i) lam[i] = A[(size_t)i * n + i];
+}
+
+// 1D interior stiffness and mass of one axis; returns S (row-major, S[m][mode]) and lambda
+void fdm_axis(const tdfe_ctx* c, const std::vector<double>& ax, std::vector<double>& S, std::vector<double>& lam) {
+  const int p = c->p, n = c->n, nq = c->nq;
+  const int ncell = (int)ax.size() - 1;
+  const int nn = ncell * p + 1;
+  std::vector<double> K((size_t)nn * nn, 0.0), M((size_t)nn * nn, 0.0);
+  for (int e = 0; e < ncell; ++e) {
+    const double h = ax[e + 1] - ax[e];
+    for (int i = 0; i < n; ++i)
+      for (int j = 0; j < n; ++j) {
+        double kk = 0.0, mm = 0.0;
+        for (int a = 0; a < nq; ++a) {
+          kk += c->wq[a] * c->D[a * TDFE_MAXN + i] * c->D[a * TDFE_MAXN + j];
+          mm += c->wq[a] * c->B[a * TDFE_MAXN + i] * c->B[a * TDFE_MAXN + j];
+        }
+        const int I = e * p + i, J = e * p + j;
+        K[(size_t)I * nn + J] += kk * 2.0 / h;
+        M[(size_t)I * nn + J] += mm * h / 2.0;
+      }
+  }
+  const int m = nn - 2;
+  std::vector<double> Ki((size_t)m * m), Mi((size_t)m * m);
+  for (int i = 0; i < m; ++i)
+    for (int j = 0; j < m; ++j) {
+      Ki[(size_t)i * m + j] = K[(size_t)(i + 1) * nn + (j + 1)];
+      Mi[(size_t)i * m + j] = M[(size_t)(i + 1) * nn + (j + 1)];
+    }
+  cholesky(Mi, m);  // Mi = L L^T
+  // C = L^-1 K L^-T
+  std::vector<double> X = Ki;  // solve L X = K  (columns)
+  for (int col = 0; col < m; ++col)
+    for (int i = 0; i < m; ++i) {
+      double s = X[(size_t)i * m + col];
+      for (int k = 0; k < i; ++k) s -= Mi[(size_t)i * m + k] * X[(size_t)k * m + col];
+      X[(size_t)i * m + col] = s / Mi[(size_t)i * m + i];
+    }
+  std::vector<double> Cm((size_t)m * m);  // C = X L^-T  ->  solve L C^T = X^T
+  for (int row = 0; row < m; ++row)
+    for (int i = 0; i < m; ++i) {
+      double s = X[(size_t)row * m + i];
+      for (int k = 0; k < i; ++k) s -= Mi[(size_t)i * m + k] * Cm[(size_t)row * m + k];
+      Cm[(size_t)row * m + i] = s / Mi[(size_t)i * m + i];
+    }
+  for (int i = 0; i < m; ++i)  // symmetrise rounding
+    for (int j = i + 1; j < m; ++j) {
+      const double v = 0.5 * (Cm[(size_t)i * m + j] + Cm[(size_t)j * m + i]);
+      Cm[(size_t)i * m + j] = Cm[(size_t)j * m + i] = v;
+    }
+  std::vector<double> U;
+  jacobi_eigen(Cm, m, lam, U);
+  // S = L^-T U  (back substitution with L^T)
+  S.assign((size_t)m * m, 0.0);
+  for (int col = 0; col < m; ++col)
+    for (int i = m - 1; i >= 0; --i) {
+      double s = U[(size_t)i * m + col];
+      for (int k = i + 1; k < m; ++k) s -= Mi[(size_t)k * m + i] * S[(size_t)k * m + col];
+      S[(size_t)i * m + col] = s / Mi[(size_t)i * m + i];
+    }
+}
+
+tdfe_status fdm_solve(tdfe_ctx* c) {
+  // rhs = 4 pi c_interior - (K f)_interior ; phi_interior = K^-1 rhs
+  const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
+  const int64_t nd = c->n_dof;
+  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->cload, c->lift, 4.0 * M_PI,
+                     c->t0, c->Nx, c->Ny, c->Nz);
+  const double* Sx = c->fdmS;
+  const double* Sy = Sx + (size_t)n1x * n1x;
+  const double* Sz = Sy + (size_t)n1y * n1y;
+  const double* lx = c->fdmL;
+  const double* ly = lx + n1x;
+  const double* lz = ly + n1y;
+  auto pass = [&](const double* in, double* out, int axis, int trans, bool scale) -> tdfe_status {
+    const int nax = axis == 0 ? n1x : (axis == 1 ? n1y : n1z);
+    const int64_t nlines = nd / nax;
+    const double* S = axis == 0 ? Sx : (axis == 1 ? Sy : Sz);
+    const size_t shm = (size_t)nax * FDM_TL * sizeof(double);
+    hipLaunchKernelGGL(fdm_axis_kernel, dim3((unsigned)((nlines + FDM_TL - 1) / FDM_TL)), dim3(256), shm, c->stream, in,
+                       out, S, n1x, n1y, n1z, axis, trans, scale ? lx : nullptr, ly, lz);
+    TDFE_HIP(c, hipGetLastError());
+    return TDFE_OK;
+  };
+  TDFE_TRY(pass(c->t0, c->t1, 0, 1, false));
+  TDFE_TRY(pass(c->t1, c->t0, 1, 1, false));
+  TDFE_TRY(pass(c->t0, c->t1, 2, 1, true));
+  TDFE_TRY(pass(c->t1, c->t0, 2, 0, false));
+  TDFE_TRY(pass(c->t0, c->t1, 1, 0, false));
+  TDFE_TRY(pass(c->t1, c->t0, 0, 0, false));
+  hipLaunchKernelGGL(scatter_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->t0, c->phi, c->Nx, c->Ny,
+                     c->Nz);
+  TDFE_HIP(c, hipGetLastError());
+  c->last_poisson_iters = 0;
+  return TDFE_OK;
+}
+
+template <int N>
+tdfe_status launch_density_n(tdfe_ctx* c, DensParams& P) {
+  constexpr int CB = (N * N * 16 <= 1024 && N <= 6) ? 16 : ((N * N * 8 <= 1024) ? 8 : 4);
+  hipLaunchKernelGGL((density_kernel<N, CB>), dim3((unsigned)c->n_cell), dim3(N * N * CB), 0, c->stream, P);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+template <int N>
+tdfe_status launch_load_interp(tdfe_ctx* c, int which, double* Wout) {
+  if (which == 0) {
+    hipLaunchKernelGGL((load_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, c->rho, c->wdet, c->tab,
+                       c->cload, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
+  } else {
+    hipLaunchKernelGGL((interp_xc_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, c->phi, c->rho,
+                       c->tab, Wout, c->hartree, c->xc, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
+  }
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+#define TDFE_DISPATCH_N(FN, ...)                        \
+  switch (c->n) {                                      \
+    case 2: return FN<2>(__VA_ARGS__);                 \
+    case 3: return FN<3>(__VA_ARGS__);                 \
+    case 4: return FN<4>(__VA_ARGS__);                 \
+    case 5: return FN<5>(__VA_ARGS__);                 \
+    case 6: return FN<6>(__VA_ARGS__);                 \
+    case 7: return FN<7>(__VA_ARGS__);                 \
+    case 8: return FN<8>(__VA_ARGS__);                 \
+    case 9: return FN<9>(__VA_ARGS__);                 \
+  }                                                    \
+  return tdfe_fail(c, TDFE_EINVAL, "unsupported order");
+
+tdfe_status density_launch(tdfe_ctx* c, DensParams& P) { TDFE_DISPATCH_N(launch_density_n, c, P) }
+tdfe_status load_launch(tdfe_ctx* c) { TDFE_DISPATCH_N(launch_load_interp, c, 0, nullptr) }
+tdfe_status interp_launch(tdfe_ctx* c, double* W) { TDFE_DISPATCH_N(launch_load_interp, c, 1, W) }
+
+tdfe_status upload_occ(tdfe_ctx* c, int n_orb, double** dev) {
+  // occupations live in the scalar block's tail
+  double* occ = c->scal + (size_t)(8 * c->k_max + 32) * c->n_orb_max - c->n_orb_max;
+  // persistent host copy: the asynchronous upload may still read it after return
+  c->occ_host.assign(c->n_orb_max, 1.0);
+  for (int o = 0; o < n_orb && o < (int)c->occ.size(); ++o) c->occ_host[o] = c->occ[o];
+  TDFE_HIP(c, hipMemcpyAsync(occ, c->occ_host.data(), n_orb * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  *dev = occ;
+  return TDFE_OK;
+}
+
+}  // namespace
+
+// density at the Gauss points into rho (device) and 4 partial sums per cell
+tdfe_status tdfe_density_dev(tdfe_ctx* c, const void* psibar, int n_orb, double* rho, double* partial4) {
+  DensParams P{};
+  P.psi = (const double*)psibar;
+  P.cols = 2 * n_orb;
+  TDFE_TRY(upload_occ(c, n_orb, (double**)&P.occ));
+  P.minv = c->minv;
+  P.tab = c->tab;
+  P.wdet = c->wdet;
+  P.xq = c->xq;
+  P.rho = rho;
+  P.partial = partial4;
+  P.ncx = c->ncx;
+  P.ncy = c->ncy;
+  P.ncz = c->ncz;
+  P.p = c->p;
+  P.Nx = c->Nx;
+  P.Ny = c->Ny;
+  P.Nz = c->Nz;
+  P.n_cell = c->n_cell;
+  return density_launch(c, P);
+}
+
+// W = V_H[rho] + V_xc[rho] at the Gauss points for the orbitals psibar;
+// mu/charge (host, may be null) receive the dipole and charge of rho
+tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, double* W, double* mu, double* charge) {
+  TDFE_TRY(tdfe_density_dev(c, psibar, n_orb, c->rho, c->partial));
+  double* red = c->partial + c->n_cell * 4;
+  hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
+  TDFE_HIP(c, hipGetLastError());
+  if (c->hartree) {
+    TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
+    TDFE_TRY(load_launch(c));
+    if (c->box) {
+      TDFE_TRY(fdm_solve(c));
+    } else {
+      return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
+    }
+  }
+  TDFE_TRY(interp_launch(c, W));
+  if (mu || charge) {
+    double h[4];
+    TDFE_HIP(c, hipMemcpyAsync(h, red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    TDFE_HIP(c, hipStreamSynchronize(c->stream));
+    if (charge) *charge = h[0];
+    if (mu) {
+      mu[0] = h[1];
+      mu[1] = h[2];
+      mu[2] = h[3];
+    }
+  }
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_fdm_setup(tdfe_ctx* c) {
+  std::vector<double> Sx, Sy, Sz, lx, ly, lz;
+  fdm_axis(c, c->ax_x, Sx, lx);
+  fdm_axis(c, c->ax_y, Sy, ly);
+  fdm_axis(c, c->ax_z, Sz, lz);
+  std::vector<double> S, L;
+  S.insert(S.end(), Sx.begin(), Sx.end());
+  S.insert(S.end(), Sy.begin(), Sy.end());
+  S.insert(S.end(), Sz.begin(), Sz.end());
+  L.insert(L.end(), lx.begin(), lx.end());
+  L.insert(L.end(), ly.begin(), ly.end());
+  L.insert(L.end(), lz.begin(), lz.end());
+  TDFE_HIP(c, hipMemcpy(c->fdmS, S.data(), S.size() * sizeof(double), hipMemcpyHostToDevice));
+  TDFE_HIP(c, hipMemcpy(c->fdmL, L.data(), L.size() * sizeof(double), hipMemcpyHostToDevice));
+  return TDFE_OK;
+}
+
+// lift = (K f)_interior with f the boundary data (interior zero)
+tdfe_status tdfe_compute_lift(tdfe_ctx* c) {
+  TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
+  ApplyArgs a{};
+  a.x = c->fb;
+  a.y = c->cload;
+  a.ld = 1;
+  a.cols = 1;
+  a.kin = 1.0;
+  a.lowdin = false;
+  a.fullgrid = true;
+  TDFE_TRY(tdfe_launch_apply(c, a));
+  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(c->n_dof)), dim3(EW), 0, c->stream, c->cload, (const double*)nullptr,
+                     1.0, c->lift, c->Nx, c->Ny, c->Nz);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+extern "C" {
+
+tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
+  if (!c || !s) return TDFE_EINVAL;
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "set_scf before bind_workspace");
+  if (s->xc < TDFE_XC_NONE || s->xc > TDFE_XC_XC) return tdfe_fail(c, TDFE_EINVAL, "set_scf: bad xc mode");
+  if (s->n_nuclei < 0 || (s->n_nuclei > 0 && (!s->Z || !s->R))) return tdfe_fail(c, TDFE_EINVAL, "set_scf: nuclei");
+  if (s->n_orb < 0 || s->n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "set_scf: n_orb");
+  if (s->hartree && !c->box && !(s->pcg_tol > 0.0)) return tdfe_fail(c, TDFE_EINVAL, "set_scf: pcg_tol");
+  c->hartree = s->hartree ? 1 : 0;
+  c->xc = s->xc;
+  c->nucZ.assign(s->Z, s->Z + s->n_nuclei);
+  c->nucR.assign(s->R, s->R + 3 * s->n_nuclei);
+  c->occ.assign(s->n_orb, 1.0);
+  if (s->occupation)
+    for (int o = 0; o < s->n_orb; ++o) c->occ[o] = s->occupation[o];
+  c->pcg_tol = s->pcg_tol;
+  c->pcg_maxit = s->pcg_maxit;
+  if (c->hartree) {
+    if (!c->box) return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
+    std::vector<double> zr(4 * std::max(1, s->n_nuclei));
+    for (int a = 0; a < s->n_nuclei; ++a) {
+      zr[a * 4 + 0] = s->Z[a];
+      zr[a * 4 + 1] = s->R[a * 3 + 0];
+      zr[a * 4 + 2] = s->R[a * 3 + 1];
+      zr[a * 4 + 3] = s->R[a * 3 + 2];
+    }
+    double* dzr = c->partial;  // staging
+    TDFE_HIP(c, hipMemcpyAsync(dzr, zr.data(), zr.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    hipLaunchKernelGGL(boundary_values_kernel, dim3(nblk(c->n_nodes)), dim3(EW), 0, c->stream, c->nodexyz_ptr,
+                       (const double*)dzr, s->n_nuclei, c->fb, c->phi, c->Nx, c->Ny, c->Nz);
+    TDFE_HIP(c, hipGetLastError());
+    TDFE_TRY(tdfe_compute_lift(c));
+    TDFE_HIP(c, hipStreamSynchronize(c->stream));
+    TDFE_TRY(tdfe_fdm_setup(c));
+  }
+  c->have_scf = c->hartree || c->xc != TDFE_XC_NONE;
+  c->scf_init = false;
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_density(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* dev_rho_q) {
+  if (!c || !dev_psibar || !dev_rho_q) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "density: n_orb out of range");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "density before bind_workspace");
+  return tdfe_density_dev(c, dev_psibar, n_orb, dev_rho_q, c->partial);
+}
+
+tdfe_status tdfe_dipole(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* host_mu, double* host_charge) {
+  if (!c || !dev_psibar || !host_mu) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "dipole: n_orb out of range");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "dipole before bind_workspace");
+  TDFE_TRY(tdfe_density_dev(c, dev_psibar, n_orb, c->rho, c->partial));
+  double* red = c->partial + c->n_cell * 4;
+  hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
+  TDFE_HIP(c, hipGetLastError());
+  double h[4];
+  TDFE_HIP(c, hipMemcpyAsync(h, red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  host_mu[0] = h[1];
+  host_mu[1] = h[2];
+  host_mu[2] = h[3];
+  if (host_charge) *host_charge = h[0];
+  if (!std::isfinite(h[0])) return tdfe_fail(c, TDFE_ENONFINITE, "dipole: non-finite density");
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt, double field_E, double tol,
+                             tdfe_step_report* rep) {
+  if (!c || !dev_psibar) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "magnus_step: n_orb out of range");
+  if (!(dt > 0.0) || !std::isfinite(dt) || !(tol > 0.0) || !std::isfinite(field_E))
+    return tdfe_fail(c, TDFE_EINVAL, "magnus_step: dt, tol or field");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "magnus_step before bind_workspace");
+  if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "magnus_step before set_potential");
+  const int64_t nqd = c->n_quad;
+  float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
+  tdfe_step_report r{};
+  tdfe_status st = TDFE_OK, s2;
+  if (!c->have_scf) {
+    hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
+                       (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, field_E, c->vw, v32, nqd);
+    TDFE_HIP(c, hipGetLastError());
+    st = tdfe_lanczos_run(c, c->vw, dev_psibar, dev_psibar, n_orb, dt, tol, nullptr, nullptr, &r.k_corr_max,
+                          &r.k_corr_sum, &r.err_max);
+    if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
+    if (rep) {
+      s2 = tdfe_dipole(c, dev_psibar, n_orb, r.mu, &r.charge);
+      if (s2 != TDFE_OK) return s2;
+    }
+  } else {
+    if (!c->scf_init) {
+      TDFE_TRY(tdfe_scf_potential(c, dev_psibar, n_orb, c->w1, nullptr, nullptr));
+      TDFE_HIP(c, hipMemcpyAsync(c->w2, c->w1, nqd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      c->scf_init = true;
+    }
+    // predictor: W(t + dt/4) ~ 1.25 W_{n-1} - 0.25 W_{n-2}
+    hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
+                       (const double*)c->w1, 1.25, (const double*)c->w2, -0.25, field_E, c->vw, v32, nqd);
+    TDFE_HIP(c, hipGetLastError());
+    double eh = 0.0;
+    st = tdfe_lanczos_run(c, c->vw, dev_psibar, c->half, n_orb, 0.5 * dt, tol, nullptr, nullptr, &r.k_pred_max,
+                          &r.k_pred_sum, &eh);
+    if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
+    TDFE_TRY(tdfe_scf_potential(c, c->half, n_orb, c->wh, nullptr, nullptr));
+    // corrector with the midpoint potential
+    hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
+                       (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, field_E, c->vw, v32, nqd);
+    TDFE_HIP(c, hipGetLastError());
+    s2 = tdfe_lanczos_run(c, c->vw, dev_psibar, dev_psibar, n_orb, dt, tol, nullptr, nullptr, &r.k_corr_max,
+                          &r.k_corr_sum, &r.err_max);
+    if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
+    if (s2 == TDFE_ENOCONV) st = s2;
+    r.err_max = std::max(r.err_max, eh);
+    // history: W_{n-2} <- W_{n-1}, W_{n-1} <- W[rho(psibar^n)]
+    std::swap(c->w1, c->w2);
+    TDFE_TRY(tdfe_scf_potential(c, dev_psibar, n_orb, c->w1, rep ? r.mu : nullptr, rep ? &r.charge : nullptr));
+  }
+  r.poisson_iters = c->last_poisson_iters;
+  if (rep) {
+    *rep = r;
+    if (!std::isfinite(r.charge)) return tdfe_fail(c, TDFE_ENONFINITE, "magnus_step: non-finite density");
+  }
+  return st;
+}
+
+}  // extern "C"

@@ -1,0 +1,247 @@
+"""Thin Python binding of the tdfe C ABI (include/tdfe.h).
+
+Argument marshalling only: every step of the method runs in the HIP library
+``libtdfe.so`` built from ``csrc/``.  PyTorch supplies device memory and the
+HIP stream.  There is no fallback: if the library is missing, loading fails.
+
+Function names match the C ABI without the ``tdfe_`` prefix; ``Context``
+bundles a context with its torch-owned workspace.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtdfe.so")
+
+OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
+FP64, MIXED_FP32 = 0, 1
+XC_NONE, XC_X, XC_XC = 0, 1, 2
+_NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "ESTATE", -6: "ENONFINITE"}
+
+
+class TdfeError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"tdfe status {status} ({_NAMES.get(status, '?')}): {msg}")
+        self.status = status
+
+
+class MeshDesc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("nq", ctypes.c_int), ("ncell", ctypes.c_int * 3),
+                ("vertices", ctypes.POINTER(ctypes.c_double)), ("n_orb_max", ctypes.c_int),
+                ("k_max", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
+class ScfDesc(ctypes.Structure):
+    _fields_ = [("hartree", ctypes.c_int), ("xc", ctypes.c_int), ("n_nuclei", ctypes.c_int),
+                ("Z", ctypes.POINTER(ctypes.c_double)), ("R", ctypes.POINTER(ctypes.c_double)),
+                ("occupation", ctypes.POINTER(ctypes.c_double)), ("n_orb", ctypes.c_int),
+                ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int)]
+
+
+class StepReport(ctypes.Structure):
+    _fields_ = [("k_pred_max", ctypes.c_int), ("k_corr_max", ctypes.c_int), ("k_pred_sum", ctypes.c_int),
+                ("k_corr_sum", ctypes.c_int), ("err_max", ctypes.c_double), ("poisson_iters", ctypes.c_int),
+                ("mu", ctypes.c_double * 3), ("charge", ctypes.c_double)]
+
+    def as_dict(self):
+        return {"k_pred_max": self.k_pred_max, "k_corr_max": self.k_corr_max, "k_pred_sum": self.k_pred_sum,
+                "k_corr_sum": self.k_corr_sum, "err_max": self.err_max, "poisson_iters": self.poisson_iters,
+                "mu": np.array(self.mu[:]), "charge": self.charge}
+
+
+_P = ctypes.c_void_p
+_I64P = ctypes.POINTER(ctypes.c_int64)
+_DP = ctypes.POINTER(ctypes.c_double)
+_IP = ctypes.POINTER(ctypes.c_int)
+SIGNATURES = {
+    "tdfe_fe_mesh_setup": [ctypes.POINTER(MeshDesc), _P, ctypes.POINTER(_P)],
+    "tdfe_query": [_P, _I64P, _I64P, _I64P, ctypes.POINTER(ctypes.c_size_t)],
+    "tdfe_bind_workspace": [_P, _P, ctypes.c_size_t],
+    "tdfe_dof_coords": [_P, _P],
+    "tdfe_quad_coords": [_P, _P],
+    "tdfe_mass_diag": [_P, _P],
+    "tdfe_set_potential": [_P, _P],
+    "tdfe_set_scf": [_P, ctypes.POINTER(ScfDesc)],
+    "tdfe_apply_H": [_P, _P, _P, ctypes.c_int],
+    "tdfe_lanczos_expm": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _IP, _DP],
+    "tdfe_density": [_P, _P, ctypes.c_int, _P],
+    "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
+    "tdfe_magnus_step": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                         ctypes.POINTER(StepReport)],
+    "tdfe_last_error": [_P],
+    "tdfe_destroy": [_P],
+}
+
+_lib = None
+
+
+def load(path=LIB_PATH):
+    """Load libtdfe.so and declare every exported function; raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libtdfe.so not built at {path}; run __graft_entry__.build()")
+    lib = ctypes.CDLL(path)
+    for name, args in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = ctypes.c_int
+    lib.tdfe_last_error.restype = ctypes.c_char_p
+    lib.tdfe_destroy.restype = None
+    _lib = lib
+    return lib
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def _stream_handle():
+    import torch
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class Context:
+    """One tdfe context plus its torch-owned workspace on the current device."""
+
+    def __init__(self, p, ncell, vertices, n_orb_max, k_max=128, precision=FP64, nq=None, stream=None):
+        import torch
+        self.lib = load()
+        v = np.ascontiguousarray(np.asarray(vertices, dtype=np.float64).reshape(-1))
+        self._vert = v
+        d = MeshDesc()
+        d.p = p
+        d.nq = p + 1 if nq is None else nq
+        d.ncell[0], d.ncell[1], d.ncell[2] = ncell
+        d.vertices = v.ctypes.data_as(_DP)
+        d.n_orb_max = n_orb_max
+        d.k_max = k_max
+        d.precision = precision
+        self._stream = stream if stream is not None else _stream_handle()
+        h = ctypes.c_void_p()
+        s = self.lib.tdfe_fe_mesh_setup(ctypes.byref(d), self._stream, ctypes.byref(h))
+        if s != OK:
+            raise TdfeError(s, "fe_mesh_setup rejected the mesh description")
+        self.h = h
+        self.n_dof, self.n_cell, self.n_quad, self.ws_bytes = self.query()
+        self.p, self.nq = p, d.nq
+        self.n_orb_max = n_orb_max
+        self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
+        base = self.workspace.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.tdfe_bind_workspace(self.h, ctypes.c_void_p(base + off), self.ws_bytes))
+
+    # -- plumbing ---------------------------------------------------------------
+    def _check(self, s):
+        if s != OK:
+            raise TdfeError(s, self.lib.tdfe_last_error(self.h).decode())
+        return s
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.tdfe_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- ABI calls (same names as the C functions) -----------------------------------
+    def query(self):
+        nd, nc, nq = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        ws = ctypes.c_size_t()
+        self._check(self.lib.tdfe_query(self.h, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(nq),
+                                        ctypes.byref(ws)))
+        return nd.value, nc.value, nq.value, ws.value
+
+    def dof_coords(self):
+        import torch
+        out = torch.empty((self.n_dof, 3), dtype=torch.float64, device="cuda")
+        self._check(self.lib.tdfe_dof_coords(self.h, _ptr(out)))
+        return out
+
+    def quad_coords(self):
+        import torch
+        out = torch.empty((self.n_cell, self.n_quad // self.n_cell, 3), dtype=torch.float64, device="cuda")
+        self._check(self.lib.tdfe_quad_coords(self.h, _ptr(out)))
+        return out
+
+    def mass_diag(self):
+        import torch
+        out = torch.empty(self.n_dof, dtype=torch.float64, device="cuda")
+        self._check(self.lib.tdfe_mass_diag(self.h, _ptr(out)))
+        return out
+
+    def set_potential(self, v):
+        assert v.dtype.is_floating_point and v.numel() == self.n_quad and v.is_contiguous()
+        self._check(self.lib.tdfe_set_potential(self.h, _ptr(v)))
+
+    def set_scf(self, hartree=False, xc=XC_NONE, Z=(), R=(), occupation=None, n_orb=0, pcg_tol=1e-13,
+                pcg_maxit=5000):
+        s = ScfDesc()
+        s.hartree = int(bool(hartree))
+        s.xc = xc
+        Zc = np.ascontiguousarray(np.asarray(Z, dtype=np.float64).reshape(-1))
+        Rc = np.ascontiguousarray(np.asarray(R, dtype=np.float64).reshape(-1))
+        self._scf_keep = [Zc, Rc]
+        s.n_nuclei = len(Zc)
+        s.Z = Zc.ctypes.data_as(_DP)
+        s.R = Rc.ctypes.data_as(_DP)
+        if occupation is not None:
+            oc = np.ascontiguousarray(np.asarray(occupation, dtype=np.float64))
+            self._scf_keep.append(oc)
+            s.occupation = oc.ctypes.data_as(_DP)
+            s.n_orb = len(oc)
+        else:
+            s.n_orb = n_orb
+        s.pcg_tol = pcg_tol
+        s.pcg_maxit = pcg_maxit
+        self._check(self.lib.tdfe_set_scf(self.h, ctypes.byref(s)))
+
+    @staticmethod
+    def _orb(psi):
+        import torch
+        assert psi.dtype == torch.complex128 and psi.is_contiguous() and psi.is_cuda
+        return psi.shape[1]
+
+    def apply_H(self, psibar, out=None):
+        import torch
+        n = self._orb(psibar)
+        if out is None:
+            out = torch.empty_like(psibar)
+        self._check(self.lib.tdfe_apply_H(self.h, _ptr(psibar), _ptr(out), n))
+        return out
+
+    def lanczos_expm(self, psibar, tau, tol):
+        n = self._orb(psibar)
+        ks = (ctypes.c_int * n)()
+        es = (ctypes.c_double * n)()
+        self._check(self.lib.tdfe_lanczos_expm(self.h, _ptr(psibar), n, tau, tol, ks, es))
+        return list(ks), list(es)
+
+    def density(self, psibar, out=None):
+        import torch
+        n = self._orb(psibar)
+        if out is None:
+            out = torch.empty((self.n_cell, self.n_quad // self.n_cell), dtype=torch.float64, device="cuda")
+        self._check(self.lib.tdfe_density(self.h, _ptr(psibar), n, _ptr(out)))
+        return out
+
+    def dipole(self, psibar):
+        n = self._orb(psibar)
+        mu = (ctypes.c_double * 3)()
+        ch = ctypes.c_double()
+        self._check(self.lib.tdfe_dipole(self.h, _ptr(psibar), n, mu, ctypes.byref(ch)))
+        return np.array(mu[:]), ch.value
+
+    def magnus_step(self, psibar, dt, field_E=0.0, tol=1e-10, report=True):
+        n = self._orb(psibar)
+        rep = StepReport()
+        self._check(self.lib.tdfe_magnus_step(self.h, _ptr(psibar), n, dt, field_E, tol,
+                                              ctypes.byref(rep) if report else None))
+        return rep.as_dict() if report else None
