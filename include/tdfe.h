@@ -123,6 +123,11 @@ tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);
  * for every term.  dev_out must not alias dev_psibar. */
 tdfe_status tdfe_apply_H(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, int n_orb);
 
+/* apply_H_add: dev_out += Hbar dev_psibar (same operator as apply_H, no
+ * zeroing of dev_out): exactly one launch of the operator kernel, for
+ * composite operators and for timing that kernel alone. */
+tdfe_status tdfe_apply_H_add(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, int n_orb);
+
 /* lanczos_expm: psibar <- exp(-i tau Hbar) psibar in place, each orbital with
  * its own adaptive Krylov space (Eqs. KrylovSubspace, zk, AdaptiveLanczos):
  * stop at the first k with tau beta_k ||psibar|| |[exp(-i tau T_k)]_{k,1}| <= tol

@@ -1,0 +1,544 @@
+// Operator kernel for rectilinear (box) cells: "plane" sum factorisation.
+//
+// Same operator as tdfe_apply.hip (Eq. DiscreteHamiltonian in the Loewdin
+// form, Eq. TDKSMatVecStandard), organised for the register file of CDNA4:
+// each thread owns one column and an n x n plane of a cell's values.
+//
+//   A  (plane at fixed y node j):  gather u(i,k); x: B u, D u; z: B on both
+//   -- LDS transpose of the two arrays -->
+//   B  (plane at fixed x point a): y: B on both -> u_q, d_x u_q; then in
+//      registers d_y u_q, d_z u_q by the Gauss collocation derivative,
+//      the box fluxes (diagonal metric), the potential term, the y and z
+//      transposed derivatives and the transposed y interpolation of the two
+//      results (s, s_x)
+//   -- LDS transpose of the two arrays -->
+//   C  (plane at fixed y node j):  x: B^T s + D^T s_x; z: B^T; scatter-add.
+//
+// Only the y direction crosses threads, so the cell data make four LDS
+// round trips (two arrays each way) instead of fifteen.  Every 1D contraction
+// uses the reflection symmetry of the GLL nodes and Gauss points
+// (B[n-1-a][n-1-i] = B[a][i], D and Dg antisymmetric): even/odd folding halves
+// the multiply-adds.  The folded tables are kernel arguments, so they are
+// uniform (scalar registers / scalar cache) and take no vector registers.
+#include "tdfe_internal.h"
+
+namespace {
+
+constexpr int EO_MAX_H = 5;  // (9 + 1) / 2
+
+// folded form of one N x N matrix with reflection symmetry S (+1 or -1)
+struct Folded {
+  double E[EO_MAX_H * EO_MAX_H];  // (A[a][i] + A[a][N-1-i]) / 2, a, i < H
+  double O[EO_MAX_H * EO_MAX_H];  // (A[a][i] - A[a][N-1-i]) / 2
+  double mc[EO_MAX_H];            // A[a][H] (odd N)
+  double mr[EO_MAX_H + 1];        // A[H][i], i <= H (odd N)
+};
+
+struct PlaneParams {
+  const void* x;
+  void* y;
+  int ld, cols, nchunks;
+  const double* colscale;
+  double kin;
+  const void* vw;
+  const double* minv;
+  const double* m1x;  // separable M^-1/2 factors of a box mesh: minv(I,J,K) = m1x[I] m1y[J] m1z[K]
+  const double* m1y;
+  const double* m1z;
+  const double* cellgeo;
+  double* energy;
+  const int* done;
+  int ncx, ncy, ncz, p, Nx, Ny, Nz;
+  int64_t n_cell;
+  int lowdin, fullgrid;
+  double wq[TDFE_MAXN];
+  Folded fB, fBt, fD, fDt, fG, fGt;  // B, B^T, D, D^T, Dg, Dg^T
+};
+
+__device__ __forceinline__ int remap_block(int p, int G) {
+  if ((G & 7) == 0) return (p & 7) * (G >> 3) + (p >> 3);
+  return p;
+}
+
+// out[a] = sum_i A[a][i] in[i] by even/odd folding; A given folded, symmetry S
+template <typename T, int N, int S>
+__device__ __forceinline__ void eo(const Folded& F, const T* in, T* out) {
+  constexpr int H = N / 2;
+  T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
+#pragma unroll
+  for (int i = 0; i < H; ++i) {
+    e[i] = in[i] + in[N - 1 - i];
+    o[i] = in[i] - in[N - 1 - i];
+  }
+#pragma unroll
+  for (int a = 0; a < H; ++a) {
+    T Pv = 0, Qv = 0;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      Pv += (T)F.E[a * EO_MAX_H + i] * e[i];
+      Qv += (T)F.O[a * EO_MAX_H + i] * o[i];
+    }
+    if constexpr (N & 1) Pv += (T)F.mc[a] * in[H];
+    out[a] = Pv + Qv;
+    out[N - 1 - a] = S > 0 ? Pv - Qv : Qv - Pv;
+  }
+  if constexpr (N & 1) {
+    T m = 0;
+    if constexpr (S > 0) {
+#pragma unroll
+      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * e[i];
+      m += (T)F.mr[H] * in[H];
+    } else {
+#pragma unroll
+      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * o[i];
+    }
+    out[H] = m;
+  }
+}
+
+// two matrices on the same input line share the fold
+template <typename T, int N, int S1, int S2>
+__device__ __forceinline__ void eo2(const Folded& F1, const Folded& F2, const T* in, T* out1, T* out2) {
+  eo<T, N, S1>(F1, in, out1);
+  eo<T, N, S2>(F2, in, out2);
+}
+
+// occupancy target: FP64 planes of n >= 6 need more than 256 registers per
+// lane, so they run one wave per SIMD and use the accumulation registers
+template <typename T, int N>
+constexpr int plane_wpe() {
+  return (sizeof(T) == 8 && N >= 6) ? 1 : 2;
+}
+
+template <typename T, int N, int CB, int CPB>
+__global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_eu(plane_wpe<T, N>())))
+    plane_kernel(PlaneParams P) {
+  constexpr int VOL = N * N * N;
+  constexpr int THREADS = CPB * N * CB;
+  __shared__ T sX[CPB * VOL * CB];
+  __shared__ T sV[CPB * VOL];  // weighted potential of the block's cells
+  __shared__ double sRed[THREADS];
+  if (P.done && *P.done) return;
+
+  const int t = threadIdx.x;
+  const int L = remap_block(blockIdx.x, gridDim.x);
+  const int chunk = L % P.nchunks;
+  const int group = L / P.nchunks;
+  const int col = t % CB;
+  const int pl = (t / CB) % N;
+  const int slot = t / (CB * N);
+  const int64_t cell = (int64_t)group * CPB + slot;
+  const bool cell_ok = cell < P.n_cell;
+  const int colg = chunk * CB + col;
+  const bool act = cell_ok && colg < P.cols;
+
+  int cx = 0, cy = 0, cz = 0;
+  if (cell_ok) {
+    cx = (int)(cell % P.ncx);
+    cy = (int)((cell / P.ncx) % P.ncy);
+    cz = (int)(cell / ((int64_t)P.ncx * P.ncy));
+  }
+  const T* __restrict__ X = (const T*)P.x;
+  T* __restrict__ Y = (T*)P.y;
+  T cs = (T)1;
+  if (P.colscale && act) cs = (T)P.colscale[colg >> 1];
+
+  // weighted potential of the block's cells -> LDS (read per line in phase B)
+  if (P.vw) {
+    const int64_t c0 = (int64_t)group * CPB;
+    for (int q = t; q < CPB * VOL; q += THREADS) {
+      const int64_t ce = c0 + q / VOL;
+      sV[q] = ce < P.n_cell ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
+    }
+  }
+  // LDS index: slot, y index, x index, z index, column
+  auto sidx = [&](int y, int x, int z) { return (((slot * N + y) * N + x) * N + z) * CB + col; };
+  const int NxI = P.Nx - 2, NyI = P.Ny - 2;
+
+  // ---------------- A: plane j = pl, values (i, k) -------------------------------------
+  T tu[N][N], tx[N][N];  // [x][z]
+  {
+    const int j = pl;
+    const int J = cy * P.p + j;
+    T u[N][N];  // [i][k]
+    // node (I, J, K) -> element offset; all loads are issued unconditionally
+    // from a valid address (masked entries read element 0 and are zeroed)
+    const bool jok = P.fullgrid ? true : (J > 0 && J < P.Ny - 1);
+    unsigned imask = 0, kmask = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int I = cx * P.p + q, K = cz * P.p + q;
+      if (P.fullgrid || (I > 0 && I < P.Nx - 1)) imask |= 1u << q;
+      if (P.fullgrid || (K > 0 && K < P.Nz - 1)) kmask |= 1u << q;
+    }
+    if (!act || !jok) imask = 0;
+    // element index of (i, k): e0 + i * ld + k * kstride
+    int64_t e0, kstride;
+    if (P.fullgrid) {
+      e0 = ((int64_t)cx * P.p + (int64_t)P.Nx * ((int64_t)J + (int64_t)P.Ny * cz * P.p)) * P.ld + colg;
+      kstride = (int64_t)P.Nx * P.Ny * P.ld;
+    } else {
+      e0 = ((int64_t)(cx * P.p - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (cz * P.p - 1))) * P.ld + colg;
+      kstride = (int64_t)NxI * NyI * P.ld;
+    }
+    T my = (T)1;
+    if (P.lowdin && imask) my = (T)P.m1y[J] * cs;
+    else my = cs;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
+        const int64_t e = ok ? e0 + (int64_t)i * P.ld + (int64_t)k * kstride : 0;
+        const T val = X[e];
+        u[i][k] = ok ? val : (T)0;
+      }
+    }
+    if (P.lowdin) {
+      T fx[N], fz[N];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        fx[q] = ((imask >> q) & 1u) ? (T)P.m1x[cx * P.p + q] : (T)0;
+        fz[q] = ((kmask >> q) & 1u) ? (T)P.m1z[cz * P.p + q] : (T)0;
+      }
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int i = 0; i < N; ++i) u[i][k] *= fx[i] * fz[k] * my;
+    } else {
+#pragma unroll
+      for (int k = 0; k < N; ++k)
+#pragma unroll
+        for (int i = 0; i < N; ++i) u[i][k] *= my;
+    }
+    // x: interpolation and nodal derivative at the Gauss points, per z line
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      T line[N], o1[N], o2[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) line[i] = u[i][k];
+      eo2<T, N, 1, -1>(P.fB, P.fD, line, o1, o2);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        tu[a][k] = o1[a];
+        tx[a][k] = o2[a];
+      }
+    }
+    // z: interpolation of both, per x point
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T o1[N], o2[N];
+      eo<T, N, 1>(P.fB, tu[a], o1);
+      eo<T, N, 1>(P.fB, tx[a], o2);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        tu[a][c] = o1[c];
+        tx[a][c] = o2[c];
+      }
+    }
+  }
+  // ---------------- transpose: (j; a, c) -> (a; j, c) ------------------------------------
+  T v[N][N], w[N][N];  // [y][z] at x point a = pl
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tu[a][c];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[j][c] = sX[sidx(j, pl, c)];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tx[a][c];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int c = 0; c < N; ++c) w[j][c] = sX[sidx(j, pl, c)];
+  __syncthreads();
+
+  // ---------------- B: plane a = pl, quadrature values (b, c) --------------------------------
+  double energy = 0.0;
+  T gx = 0, gy = 0, gz = 0;
+  const bool havev = P.vw != nullptr;
+  if (cell_ok) {
+    const T wa = (T)P.wq[pl];
+    gx = (T)(P.kin * P.cellgeo[cell * 4 + 0]) * wa;
+    gy = (T)(P.kin * P.cellgeo[cell * 4 + 1]) * wa;
+    gz = (T)(P.kin * P.cellgeo[cell * 4 + 2]) * wa;
+  }
+  // B1: x flux from w, transposed y interpolation, straight into the transpose
+  // buffer (free: every thread has finished reading w)
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    T l[N], o[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) l[j] = w[j][c];
+    eo<T, N, 1>(P.fB, l, o);  // u_x at (pl, b, c)
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      const T f = gx * (T)(P.wq[b] * P.wq[c]) * o[b];
+      energy += (double)f * (double)o[b];
+      o[b] = f;
+    }
+    eo<T, N, 1>(P.fBt, o, l);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sX[sidx(j, pl, c)] = l[j];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // B2: u_q, potential, y and z fluxes, transposed y interpolation
+  T s[N][N];  // [j][c]
+  {
+    T uq[N][N], acc[N][N];
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T l[N], o[N];
+#pragma unroll
+      for (int j = 0; j < N; ++j) l[j] = v[j][c];
+      eo<T, N, 1>(P.fB, l, o);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        uq[b][c] = o[b];
+        const T pot = havev ? sV[slot * VOL + pl + N * (b + N * c)] * o[b] : (T)0;
+        energy += (double)pot * (double)o[b];
+        acc[b][c] = pot;
+      }
+      // keep the potential reads of later lines from being hoisted here
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    // z flux, per y line
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      T d[N], r[N];
+      eo<T, N, -1>(P.fG, uq[b], d);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        const T f = gz * (T)(P.wq[b] * P.wq[c]) * d[c];
+        energy += (double)f * (double)d[c];
+        d[c] = f;
+      }
+      eo<T, N, -1>(P.fGt, d, r);
+#pragma unroll
+      for (int c = 0; c < N; ++c) acc[b][c] += r[c];
+    }
+    // y flux and transposed y interpolation, per z line
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T l[N], d[N], r[N];
+#pragma unroll
+      for (int b = 0; b < N; ++b) l[b] = uq[b][c];
+      eo<T, N, -1>(P.fG, l, d);
+#pragma unroll
+      for (int b = 0; b < N; ++b) {
+        const T f = gy * (T)(P.wq[b] * P.wq[c]) * d[b];
+        energy += (double)f * (double)d[b];
+        d[b] = f;
+      }
+      eo<T, N, -1>(P.fGt, d, r);
+#pragma unroll
+      for (int b = 0; b < N; ++b) r[b] += acc[b][c];
+      eo<T, N, 1>(P.fBt, r, l);
+#pragma unroll
+      for (int j = 0; j < N; ++j) s[j][c] = l[j];
+    }
+  }
+  // ---------------- transposes: (a; j, c) -> (j; a, c) ----------------------------------------
+  // the quadratic form is parked in LDS here, unconditionally: otherwise the
+  // compiler sinks its whole accumulation chain into the final reduction and
+  // keeps every partial product alive across phase C
+  sRed[t] = act ? energy : 0.0;
+  T s2[N][N], sx2[N][N];  // [x point a][z point c] at node plane j = pl
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sx2[a][c] = sX[sidx(pl, a, c)];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sX[sidx(j, pl, c)] = s[j][c];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) s2[a][c] = sX[sidx(pl, a, c)];
+
+  // ---------------- C: plane j = pl: x then z transposed, scatter ------------------------------
+  {
+    const int j = pl;
+    T h[N][N];  // [i][c]
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T l1[N], l2[N], o1[N], o2[N];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        l1[a] = s2[a][c];
+        l2[a] = sx2[a][c];
+      }
+      eo<T, N, 1>(P.fBt, l1, o1);
+      eo<T, N, -1>(P.fDt, l2, o2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) h[i][c] = o1[i] + o2[i];
+    }
+    const int J = cy * P.p + j;
+    const bool jok = P.fullgrid ? true : (J > 0 && J < P.Ny - 1);
+    unsigned imask = 0, kmask = 0;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      const int I = cx * P.p + q, K = cz * P.p + q;
+      if (P.fullgrid || (I > 0 && I < P.Nx - 1)) imask |= 1u << q;
+      if (P.fullgrid || (K > 0 && K < P.Nz - 1)) kmask |= 1u << q;
+    }
+    if (!act || !jok) imask = 0;
+    int64_t e0, kstride;
+    if (P.fullgrid) {
+      e0 = ((int64_t)cx * P.p + (int64_t)P.Nx * ((int64_t)J + (int64_t)P.Ny * cz * P.p)) * P.ld + colg;
+      kstride = (int64_t)P.Nx * P.Ny * P.ld;
+    } else {
+      e0 = ((int64_t)(cx * P.p - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (cz * P.p - 1))) * P.ld + colg;
+      kstride = (int64_t)NxI * NyI * P.ld;
+    }
+    T fx[N], fz[N];
+    T my = (T)1;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+      fx[q] = (T)1;
+      fz[q] = (T)1;
+    }
+    if (P.lowdin && imask) {
+      my = (T)P.m1y[J];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        if ((imask >> q) & 1u) fx[q] = (T)P.m1x[cx * P.p + q];
+        if ((kmask >> q) & 1u) fz[q] = (T)P.m1z[cz * P.p + q];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T o[N];
+      eo<T, N, 1>(P.fBt, h[i], o);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        if (((imask >> i) & (kmask >> k) & 1u) != 0)
+          unsafeAtomicAdd(Y + (e0 + (int64_t)i * P.ld + (int64_t)k * kstride), o[k] * fx[i] * fz[k] * my);
+      }
+    }
+  }
+  // ---------------- per-column quadratic form -------------------------------------------------
+  if (P.energy) {
+    __syncthreads();
+    if (t < CB) {
+      double acc = 0.0;
+      for (int u = t; u < THREADS; u += CB) acc += sRed[u];
+      if (chunk * CB + t < P.cols) P.energy[(int64_t)group * P.cols + chunk * CB + t] = acc;
+    }
+  }
+}
+
+// ----------------------------------------------------------------------------------------------
+// host side
+// ----------------------------------------------------------------------------------------------
+void fold(const double* A, int N, int S, bool transpose, Folded& F) {
+  auto at = [&](int a, int i) { return transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i]; };
+  const int H = N / 2;
+  for (int a = 0; a < H; ++a)
+    for (int i = 0; i < H; ++i) {
+      F.E[a * EO_MAX_H + i] = 0.5 * (at(a, i) + at(a, N - 1 - i));
+      F.O[a * EO_MAX_H + i] = 0.5 * (at(a, i) - at(a, N - 1 - i));
+    }
+  if (N & 1) {
+    for (int a = 0; a < H; ++a) F.mc[a] = at(a, H);
+    for (int i = 0; i <= H; ++i) F.mr[i] = at(H, i);
+    if (S < 0) F.mr[H] = 0.0;
+  }
+}
+
+template <int N, int CB>
+constexpr int plane_cpb() {
+  int cpb = 1;
+  while (cpb * 2 * N * CB <= 512 && (cpb * 2) * N * N * N * CB * 8 <= 64 * 1024) cpb *= 2;
+  return cpb;
+}
+
+template <typename T, int N, int CB>
+tdfe_status launch_plane(tdfe_ctx* c, PlaneParams& P, int64_t* groups_out) {
+  constexpr int CPB = plane_cpb<N, CB>();
+  const int64_t groups = (c->n_cell + CPB - 1) / CPB;
+  P.nchunks = (P.cols + CB - 1) / CB;
+  if (groups_out) *groups_out = groups;
+  hipLaunchKernelGGL((plane_kernel<T, N, CB, CPB>), dim3((unsigned)(groups * P.nchunks)), dim3(CPB * N * CB), 0,
+                     c->stream, P);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+template <typename T, int N>
+tdfe_status launch_plane_n(tdfe_ctx* c, PlaneParams& P, int64_t* g) {
+  if (P.cols <= 1) return launch_plane<T, N, 1>(c, P, g);
+  if (P.cols <= 2) return launch_plane<T, N, 2>(c, P, g);
+  if (P.cols <= 4) return launch_plane<T, N, 4>(c, P, g);
+  if (P.cols <= 8) return launch_plane<T, N, 8>(c, P, g);
+  return launch_plane<T, N, 16>(c, P, g);
+}
+
+template <typename T>
+tdfe_status launch_plane_p(tdfe_ctx* c, PlaneParams& P, int64_t* g) {
+  switch (c->n) {
+    case 2: return launch_plane_n<T, 2>(c, P, g);
+    case 3: return launch_plane_n<T, 3>(c, P, g);
+    case 4: return launch_plane_n<T, 4>(c, P, g);
+    case 5: return launch_plane_n<T, 5>(c, P, g);
+    case 6: return launch_plane_n<T, 6>(c, P, g);
+    case 7: return launch_plane_n<T, 7>(c, P, g);
+    case 8: return launch_plane_n<T, 8>(c, P, g);
+  }
+  return tdfe_fail(c, TDFE_EINVAL, "box operator: unsupported order p=%d", c->p);
+}
+
+}  // namespace
+
+// true if the box kernel handles this context (rectilinear mesh, p <= 7)
+bool tdfe_box_kernel_ok(const tdfe_ctx* c) { return c->box && c->n <= 8; }
+
+tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a) {
+  PlaneParams P{};
+  P.x = a.x;
+  P.y = a.y;
+  P.ld = a.ld;
+  P.cols = a.cols;
+  P.colscale = a.colscale;
+  P.kin = a.kin;
+  P.vw = a.fp32 ? (const void*)a.vw32 : (const void*)a.vw;
+  P.minv = c->minv;
+  P.m1x = c->m1x;
+  P.m1y = c->m1y;
+  P.m1z = c->m1z;
+  P.cellgeo = c->cellgeo;
+  P.energy = a.energy;
+  P.done = a.done_flag;
+  P.ncx = c->ncx;
+  P.ncy = c->ncy;
+  P.ncz = c->ncz;
+  P.p = c->p;
+  P.Nx = c->Nx;
+  P.Ny = c->Ny;
+  P.Nz = c->Nz;
+  P.n_cell = c->n_cell;
+  P.lowdin = a.lowdin;
+  P.fullgrid = a.fullgrid;
+  const int N = c->n;
+  for (int i = 0; i < N; ++i) P.wq[i] = c->wq[i];
+  fold(c->B, N, 1, false, P.fB);
+  fold(c->B, N, 1, true, P.fBt);
+  fold(c->D, N, -1, false, P.fD);
+  fold(c->D, N, -1, true, P.fDt);
+  fold(c->Dg, N, -1, false, P.fG);
+  fold(c->Dg, N, -1, true, P.fGt);
+  if (a.cols < 1) return tdfe_fail(c, TDFE_EINVAL, "apply: cols < 1");
+  if (a.fp32) return launch_plane_p<float>(c, P, a.n_blocks_out);
+  return launch_plane_p<double>(c, P, a.n_blocks_out);
+}

@@ -22,6 +22,7 @@ struct tdfe_ctx {
   int Nx = 0, Ny = 0, Nz = 0;
   int n_orb_max = 0, k_max = 0, precision = TDFE_FP64;
   bool box = false;  // rectilinear grid: axis-aligned cells
+  bool force_line_kernel = false;  // use the line-ownership operator kernel on box meshes too
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -45,6 +46,9 @@ struct tdfe_ctx {
   double* mdiag = nullptr;    // [n_dof] M
   double* dofxyz = nullptr;   // [n_dof][3]
   double* nodexyz_ptr = nullptr;  // [n_nodes][3]
+  double* m1x = nullptr;      // box: 1D M^-1/2 factors [Nx], [Ny], [Nz]
+  double* m1y = nullptr;
+  double* m1z = nullptr;
   double* cellgeo = nullptr;  // box: [n_cell][4] = {detJ*4/hx^2, .../hy^2, .../hz^2, detJ}
   double* corners = nullptr;  // [n_cell][8][3] (z-corner slowest, x fastest)
   double* xq = nullptr;       // [n_cell][nq^3][3]
@@ -134,6 +138,9 @@ struct ApplyArgs {
   bool fp32;            // x, y stored as float
 };
 tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
+// rectilinear-cell variant (tdfe_apply_box.hip), used by tdfe_launch_apply
+bool tdfe_box_kernel_ok(const tdfe_ctx* c);
+tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a);
 
 // vector kernels (tdfe_lanczos.hip)
 tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes);

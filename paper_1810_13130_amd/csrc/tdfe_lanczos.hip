@@ -527,14 +527,14 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
 
 extern "C" {
 
-tdfe_status tdfe_apply_H(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int n_orb) {
+static tdfe_status apply_checked(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int n_orb, bool zero) {
   if (!c || !dev_psibar || !dev_out) return TDFE_EINVAL;
   if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "apply_H: n_orb out of range");
   if (dev_psibar == dev_out) return tdfe_fail(c, TDFE_EINVAL, "apply_H: output aliases input");
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "apply_H before bind_workspace");
   if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "apply_H before set_potential");
   const int cols = 2 * n_orb;
-  TDFE_HIP(c, hipMemsetAsync(dev_out, 0, (size_t)c->n_dof * cols * sizeof(double), c->stream));
+  if (zero) TDFE_HIP(c, hipMemsetAsync(dev_out, 0, (size_t)c->n_dof * cols * sizeof(double), c->stream));
   ApplyArgs a{};
   a.x = dev_psibar;
   a.y = dev_out;
@@ -545,6 +545,14 @@ tdfe_status tdfe_apply_H(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int
   a.lowdin = true;
   a.fp32 = false;
   return tdfe_launch_apply(c, a);
+}
+
+tdfe_status tdfe_apply_H(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int n_orb) {
+  return apply_checked(c, dev_psibar, dev_out, n_orb, true);
+}
+
+tdfe_status tdfe_apply_H_add(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int n_orb) {
+  return apply_checked(c, dev_psibar, dev_out, n_orb, false);
 }
 
 tdfe_status tdfe_lanczos_expm(tdfe_ctx* c, void* dev_psibar, int n_orb, double tau, double tol, int* host_k,

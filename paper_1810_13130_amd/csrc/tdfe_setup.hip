@@ -9,6 +9,7 @@
 // geometry and M are computed on the device.
 #include <cmath>
 #include <cstdarg>
+#include <cstdlib>
 #include <cstring>
 
 #include "tdfe_internal.h"
@@ -267,6 +268,9 @@ void carve(tdfe_ctx* c, char* base) {
   c->dofxyz = k.take<double>(3 * nd);
   double* nodexyz = k.take<double>(3 * nn);
   (void)nodexyz;
+  c->m1x = k.take<double>(c->Nx);
+  c->m1y = k.take<double>(c->Ny);
+  c->m1z = k.take<double>(c->Nz);
   c->cellgeo = k.take<double>(4 * ne);
   c->corners = k.take<double>(24 * ne);
   c->xq = k.take<double>(3 * nqd);
@@ -383,6 +387,10 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
       if (!(c->ax_z[i] > c->ax_z[i - 1])) box = false;
   }
   c->box = box;
+  {
+    const char* v = std::getenv("TDFE_APPLY_VARIANT");
+    c->force_line_kernel = v && std::strcmp(v, "line") == 0;
+  }
 
   // Krylov chunk: as many orbitals as fit in 48 GB of basis storage
   const size_t eb = c->precision == TDFE_FP64 ? 8 : 4;
@@ -457,6 +465,24 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
           geo[e * 4 + 3] = det;
         }
       }
+  // box meshes: the GLL-lumped overlap factorises, M(I,J,K) = mx[I] my[J] mz[K] with
+  // m[I] = sum over the 1D cells containing node I of w_i h / 2
+  std::vector<double> f1[3];
+  if (c->box) {
+    const std::vector<double>* axs[3] = {&c->ax_x, &c->ax_y, &c->ax_z};
+    for (int d = 0; d < 3; ++d) {
+      const auto& ax = *axs[d];
+      const int nc = (int)ax.size() - 1;
+      std::vector<double> m(nc * c->p + 1, 0.0);
+      for (int e = 0; e < nc; ++e)
+        for (int i = 0; i <= c->p; ++i) m[e * c->p + i] += c->w[i] * 0.5 * (ax[e + 1] - ax[e]);
+      f1[d].resize(m.size());
+      for (size_t i = 0; i < m.size(); ++i) f1[d][i] = 1.0 / std::sqrt(m[i]);
+    }
+    TDFE_HIP(c, hipMemcpyAsync(c->m1x, f1[0].data(), f1[0].size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    TDFE_HIP(c, hipMemcpyAsync(c->m1y, f1[1].data(), f1[1].size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    TDFE_HIP(c, hipMemcpyAsync(c->m1z, f1[2].data(), f1[2].size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
   TDFE_HIP(c, hipMemcpyAsync(c->corners, cor.data(), cor.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   TDFE_HIP(c, hipMemcpyAsync(c->cellgeo, geo.data(), geo.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
   TDFE_HIP(c, hipMemsetAsync(c->counters, 0, 256 * sizeof(unsigned), c->stream));

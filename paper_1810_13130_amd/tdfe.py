@@ -65,6 +65,7 @@ SIGNATURES = {
     "tdfe_set_potential": [_P, _P],
     "tdfe_set_scf": [_P, ctypes.POINTER(ScfDesc)],
     "tdfe_apply_H": [_P, _P, _P, ctypes.c_int],
+    "tdfe_apply_H_add": [_P, _P, _P, ctypes.c_int],
     "tdfe_lanczos_expm": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _IP, _DP],
     "tdfe_density": [_P, _P, ctypes.c_int, _P],
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
@@ -215,6 +216,11 @@ class Context:
         if out is None:
             out = torch.empty_like(psibar)
         self._check(self.lib.tdfe_apply_H(self.h, _ptr(psibar), _ptr(out), n))
+        return out
+
+    def apply_H_add(self, psibar, out):
+        n = self._orb(psibar)
+        self._check(self.lib.tdfe_apply_H_add(self.h, _ptr(psibar), _ptr(out), n))
         return out
 
     def lanczos_expm(self, psibar, tau, tol):
