@@ -93,6 +93,7 @@ def main():
     ap.add_argument("--config", type=int, default=2)
     ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -114,73 +115,112 @@ def main():
         torch.cuda.synchronize()
     cfg = W.CONFIGS[args.config]
     n_orb = cfg.n_orb
-    ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=n_orb, k_max=cfg.k_max)
-    xq = ctx.quad_coords().cpu().numpy()
-    ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
-    if cfg.hartree or cfg.xc != "none":
-        Z, R = W.atoms(cfg)
-        ctx.set_scf(hartree=cfg.hartree, xc={"none": 0, "x": 1, "xc": 2}[cfg.xc], Z=Z, R=R, n_orb=n_orb)
-    psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
-                                            ctx.mass_diag().cpu().numpy())).cuda()
 
-    for _ in range(args.warmup):
-        ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
-    torch.cuda.synchronize()
-    ks_total = 0
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        rep = ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
-        ks_total += rep["k_pred_sum"] + rep["k_corr_sum"]
-    torch.cuda.synchronize()
-    dt_wall = time.perf_counter() - t0
+    def make(precision):
+        ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=n_orb, k_max=cfg.k_max,
+                           precision=precision)
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
+        if cfg.hartree or cfg.xc != "none":
+            Z, R = W.atoms(cfg)
+            ctx.set_scf(hartree=cfg.hartree, xc={"none": 0, "x": 1, "xc": 2}[cfg.xc], Z=Z, R=R, n_orb=n_orb)
+        psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
+                                                ctx.mass_diag().cpu().numpy())).cuda()
+        return ctx, psi
+
+    def run(precision):
+        ctx, psi = make(precision)
+        mus = []
+        for _ in range(args.warmup):
+            mus.append(ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)["mu"])
+        torch.cuda.synchronize()
+        ks = 0
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            rep = ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+            ks += rep["k_pred_sum"] + rep["k_corr_sum"]
+            mus.append(rep["mu"])
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        return ctx, wall, ks, np.array(mus)
+
+    def time_apply(ctx, fp32):
+        dt_ = torch.complex64 if fp32 else torch.complex128
+        x = torch.randn(ctx.n_dof, n_orb, dtype=dt_, device="cuda")
+        y = torch.zeros_like(x)
+        f = ctx.apply_H_add_f32 if fp32 else ctx.apply_H_add
+        for _ in range(5):
+            f(x, y)
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(args.apply_reps):
+            f(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / 1e3 / args.apply_reps
+
+    def roofline(ctx, t_apply, elem_bytes, alu_peak, label):
+        by, fl = apply_work(cfg.p + 1, cfg.nq, ctx.n_cell, ctx.n_dof, n_orb, elem_bytes)
+        t_hbm = by / (HBM_PEAK_GBS * 1e9)
+        t_alu = fl / (alu_peak * 1e12)
+        if t_alu >= t_hbm:
+            roof = {"bound": "alu", "achieved": fl / t_apply / 1e12, "peak": alu_peak, "unit": "TFLOP/s"}
+        else:
+            roof = {"bound": "hbm", "achieved": by / t_apply / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
+        roof["frac"] = roof["achieved"] / roof["peak"]
+        roof["traffic"] = None
+        roof["kernel"] = label
+        roof["launch_us"] = t_apply * 1e6
+        roof["algorithmic_bytes"] = by
+        roof["algorithmic_flops"] = fl
+        roof["hbm_frac"] = (by / t_apply / 1e9) / HBM_PEAK_GBS
+        roof["alu_frac"] = (fl / t_apply / 1e12) / alu_peak
+        return roof
+
+    ctx, dt_wall, ks_total, mu64 = run(tdfe.FP64)
     steps_per_s = args.steps / dt_wall
-
-    # operator kernel alone: HIP events on the library's stream around back-to-back launches
-    x = torch.randn(ctx.n_dof, n_orb, dtype=torch.complex128, device="cuda")
-    y = torch.zeros_like(x)
-    for _ in range(5):
-        ctx.apply_H_add(x, y)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(args.apply_reps):
-        ctx.apply_H_add(x, y)
-    e1.record()
-    torch.cuda.synchronize()
-    t_apply = e0.elapsed_time(e1) / 1e3 / args.apply_reps
-    n = cfg.p + 1
-    by, fl = apply_work(n, cfg.nq, ctx.n_cell, ctx.n_dof, n_orb)
+    t_apply = time_apply(ctx, False)
+    roof = roofline(ctx, t_apply, 8, FP64_VECTOR_PEAK_TFLOPS, "plane_kernel<double,6,16,2> (Hbar, 16^3 p=5, 8 orbitals)")
     gdof = ctx.n_dof * n_orb / t_apply / 1e9
-    t_hbm = by / (HBM_PEAK_GBS * 1e9)
-    t_alu = fl / (FP64_VECTOR_PEAK_TFLOPS * 1e12)
-    if t_alu >= t_hbm:
-        roof = {"bound": "alu", "achieved": fl / t_apply / 1e12, "peak": FP64_VECTOR_PEAK_TFLOPS,
-                "unit": "TFLOP/s"}
-    else:
-        roof = {"bound": "hbm", "achieved": by / t_apply / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-    roof["frac"] = roof["achieved"] / roof["peak"]
-    roof["traffic"] = None
-    roof["kernel"] = "apply_kernel<double,6,16,1,0> (Hbar on 8 orbitals)"
-    roof["launch_us"] = t_apply * 1e6
-    roof["hbm_frac"] = (by / t_apply / 1e9) / HBM_PEAK_GBS
-    roof["alu_frac"] = (fl / t_apply / 1e12) / FP64_VECTOR_PEAK_TFLOPS
+    n_dof, n_cell = ctx.n_dof, ctx.n_cell
+    ctx.close()
+    del ctx
+    torch.cuda.empty_cache()
+
+    mixed = None
+    if not args.no_mixed:
+        ctxm, wall_m, ks_m, mu32 = run(tdfe.MIXED_FP32)
+        t_apply_m = time_apply(ctxm, True)
+        err = float(np.abs(mu32 - mu64).max() / np.abs(mu64).max())
+        dmu = mu64 - mu64[0]
+        err_induced = float(np.abs(mu32 - mu64).max() / max(np.abs(dmu).max(), 1e-300))
+        mixed = {"value": args.steps / wall_m, "unit": "Magnus steps/s", "ms_per_step": 1e3 * wall_m / args.steps,
+                 "dtype": "f32 operator + Krylov storage, f64 scalars/orbitals",
+                 "speedup_vs_f64": (args.steps / wall_m) / steps_per_s,
+                 "dipole_rel_err": err, "dipole_err_rel_induced": err_induced,
+                 "steps_compared": len(mu64), "krylov_its_per_step": ks_m / args.steps,
+                 "apply_H_gdof_orb_per_s": ctxm.n_dof * n_orb / t_apply_m / 1e9,
+                 "roofline": roofline(ctxm, t_apply_m, 4, FP32_VECTOR_PEAK_TFLOPS,
+                                      "plane_kernel<float,6,16,4> (Hbar, 16^3 p=5, 8 orbitals)")}
+        ctxm.close()
 
     out = {
         "metric": "Magnus steps/sec and apply_H GDoF-orbitals/s, FP64 vs mixed at dipole err<=1e-5",
         "value": steps_per_s, "unit": "Magnus steps/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": 1e3 * dt_wall / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": cfg.name, "n_dof": ctx.n_dof, "n_cell": ctx.n_cell, "p": cfg.p,
+        "config": {"workload": cfg.name, "n_dof": n_dof, "n_cell": n_cell, "p": cfg.p,
                    "n_orb": n_orb, "dt": cfg.dt, "tol": cfg.tol, "krylov_its_per_step": ks_total / args.steps,
                    "hartree": "fast diagonalisation (exact)", "xc": cfg.xc},
         "apply_H_gdof_orb_per_s": gdof,
         "roofline": roof,
+        "mixed": mixed,
     }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_baseline(cfg, int(round(ks_total / args.steps)))
     print(json.dumps(out), flush=True)
-    ctx.close()
 
 
 if __name__ == "__main__":

@@ -128,6 +128,12 @@ tdfe_status tdfe_apply_H(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, i
  * composite operators and for timing that kernel alone. */
 tdfe_status tdfe_apply_H_add(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, int n_orb);
 
+/* apply_H_add_f32: dev_out += Hbar dev_psibar in FP32 (the mixed-precision
+ * operator kernel): both arrays complex64 interleaved [n_dof][n_orb]; the
+ * potential is the FP32 copy of the current total potential.  Requires a
+ * context created with TDFE_MIXED_FP32. */
+tdfe_status tdfe_apply_H_add_f32(tdfe_ctx* ctx, const void* dev_psibar_c64, void* dev_out_c64, int n_orb);
+
 /* lanczos_expm: psibar <- exp(-i tau Hbar) psibar in place, each orbital with
  * its own adaptive Krylov space (Eqs. KrylovSubspace, zk, AdaptiveLanczos):
  * stop at the first k with tau beta_k ||psibar|| |[exp(-i tau T_k)]_{k,1}| <= tol

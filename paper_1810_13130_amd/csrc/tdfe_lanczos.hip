@@ -555,6 +555,25 @@ tdfe_status tdfe_apply_H_add(tdfe_ctx* c, const void* dev_psibar, void* dev_out,
   return apply_checked(c, dev_psibar, dev_out, n_orb, false);
 }
 
+tdfe_status tdfe_apply_H_add_f32(tdfe_ctx* c, const void* dev_psibar, void* dev_out, int n_orb) {
+  if (!c || !dev_psibar || !dev_out) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32: n_orb out of range");
+  if (dev_psibar == dev_out) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32: output aliases input");
+  if (c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32 needs a mixed-precision context");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "apply_H_f32 before bind_workspace");
+  if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "apply_H_f32 before set_potential");
+  ApplyArgs a{};
+  a.x = dev_psibar;
+  a.y = dev_out;
+  a.ld = 2 * n_orb;
+  a.cols = 2 * n_orb;
+  a.kin = 0.5;
+  a.vw32 = c->vw32;
+  a.lowdin = true;
+  a.fp32 = true;
+  return tdfe_launch_apply(c, a);
+}
+
 tdfe_status tdfe_lanczos_expm(tdfe_ctx* c, void* dev_psibar, int n_orb, double tau, double tol, int* host_k,
                               double* host_err) {
   if (!c || !dev_psibar) return TDFE_EINVAL;

@@ -66,6 +66,7 @@ SIGNATURES = {
     "tdfe_set_scf": [_P, ctypes.POINTER(ScfDesc)],
     "tdfe_apply_H": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add": [_P, _P, _P, ctypes.c_int],
+    "tdfe_apply_H_add_f32": [_P, _P, _P, ctypes.c_int],
     "tdfe_lanczos_expm": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _IP, _DP],
     "tdfe_density": [_P, _P, ctypes.c_int, _P],
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
@@ -221,6 +222,12 @@ class Context:
     def apply_H_add(self, psibar, out):
         n = self._orb(psibar)
         self._check(self.lib.tdfe_apply_H_add(self.h, _ptr(psibar), _ptr(out), n))
+        return out
+
+    def apply_H_add_f32(self, psibar, out):
+        import torch
+        assert psibar.dtype == torch.complex64 and out.dtype == torch.complex64
+        self._check(self.lib.tdfe_apply_H_add_f32(self.h, _ptr(psibar), _ptr(out), psibar.shape[1]))
         return out
 
     def lanczos_expm(self, psibar, tau, tol):
