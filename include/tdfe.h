@@ -177,6 +177,40 @@ typedef struct {
 tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double dt, double field_E,
                              double tol, tdfe_step_report* rep);
 
+/* gradient_query: device workspace bytes that tdfe_dipole_gradient needs for
+ * n_orb orbitals, n_steps steps, a state checkpoint every checkpoint_every
+ * steps and Krylov bases of up to k_store vectors (a multiple of 8, at most
+ * k_max).  Memory grows as
+ *   (n_steps/checkpoint_every + checkpoint_every + 8) states of n_dof x n_orb complex128
+ *   + n_steps Gauss-point arrays + 3 k_store n_orb complex Gauss-point arrays. */
+tdfe_status tdfe_gradient_query(tdfe_ctx* ctx, int n_orb, int n_steps, int checkpoint_every, int k_store,
+                                size_t* bytes);
+
+/* dipole_gradient: L = mu_z(psibar^N) after n_steps magnus_step steps from
+ * dev_psibar0 with the field amplitudes host_E[n_steps] (V_field = -E_n z on
+ * step n, Eq. VField; Magnus step as in tdfe_magnus_step, Eqs. ApproxMagnus,
+ * PsiTimeDiscrete), and host_grad[n] = dL/dE_n of that discrete scheme
+ * (reverse mode: exact adjoints of the density, Hartree, exchange and
+ * extrapolation steps; the exponential's Frechet derivative is taken in the
+ * Krylov spaces of the forward and adjoint Lanczos runs, exactly for their
+ * tridiagonal matrices).  The paper propagates forward only; this is an
+ * extension for optimal-control uses of the same step.
+ *  - dev_psibar0 [n_dof][n_orb] complex128 is read, never written; the SCF
+ *    history used by tdfe_magnus_step is left untouched (this call starts
+ *    from W_{-1} = W_0 = W[rho(psibar0)]), and the operator potential is the
+ *    external one again on return.
+ *  - dev_work: >= tdfe_gradient_query bytes, 256-byte aligned, caller-owned.
+ *  - n_orb must fit one Lanczos chunk (every n_orb <= n_orb_max does unless
+ *    the mesh exceeds ~48 GB of Krylov storage); Hartree needs a box mesh;
+ *    XC must be none or LDA exchange.
+ *  - TDFE_EINVAL if a Lanczos run needs more than k_store vectors,
+ *    TDFE_ENOCONV if one does not converge within k_max.
+ *  Synchronises the stream. */
+tdfe_status tdfe_dipole_gradient(tdfe_ctx* ctx, const void* dev_psibar0, int n_orb, int n_steps,
+                                 const double* host_E, double dt, double tol, int checkpoint_every,
+                                 int k_store, void* dev_work, size_t work_bytes, double* host_L,
+                                 double* host_grad);
+
 /* text of the last error on this context (never NULL) */
 const char* tdfe_last_error(const tdfe_ctx* ctx);
 

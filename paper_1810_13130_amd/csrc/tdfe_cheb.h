@@ -1,0 +1,132 @@
+// Chebyshev evaluation of y = exp(-i s T) e_1 for a real symmetric tridiagonal
+// T (k x k; diagonal sa[0..k), off-diagonal sb[0..k-1)), on one workgroup of
+// TDFE_CHEB_THREADS lanes: Gershgorin interval [c - r, c + r], Jacobi-Anger
+// coefficients 2 (-i sgn(s))^m J_m(|s| r), Bessel values by Miller's backward
+// recurrence normalised with J_0 + 2 sum J_2m = 1, and the three-term
+// recurrence v_{m+1} = 2 X v_m - v_{m-1}, X = (T - c)/r, v_0 = e_1, rows across
+// lanes.  Every thread of the workgroup must call it.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#define TDFE_CHEB_THREADS 64
+#define TDFE_MAX_BESSEL 6144
+#define TDFE_KCAP 1024
+
+struct ChebLds {
+  double J[TDFE_MAX_BESSEL + 2];
+  double bufA[TDFE_KCAP], bufB[TDFE_KCAP];
+  double yr[TDFE_KCAP], yi[TDFE_KCAP];
+  double red[3 * TDFE_CHEB_THREADS];
+  int M;
+};
+
+// returns the number of terms M (>= 0) or -1 if |s| r exceeds the Bessel table;
+// *amax receives max_j |sa[j]|
+__device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, double s, ChebLds& L, double* amax) {
+  const int t = threadIdx.x;
+  double lo = 1e300, hi = -1e300, am = 0.0;
+  for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
+    double rad = 0.0;
+    if (j > 0) rad += fabs(sb[j - 1]);
+    if (j < k - 1) rad += fabs(sb[j]);
+    lo = fmin(lo, sa[j] - rad);
+    hi = fmax(hi, sa[j] + rad);
+    am = fmax(am, fabs(sa[j]));
+  }
+  L.red[t] = lo;
+  L.red[TDFE_CHEB_THREADS + t] = hi;
+  L.red[2 * TDFE_CHEB_THREADS + t] = am;
+  __syncthreads();
+  for (int w = TDFE_CHEB_THREADS / 2; w > 0; w >>= 1) {
+    if (t < w) {
+      L.red[t] = fmin(L.red[t], L.red[t + w]);
+      L.red[TDFE_CHEB_THREADS + t] = fmax(L.red[TDFE_CHEB_THREADS + t], L.red[TDFE_CHEB_THREADS + t + w]);
+      L.red[2 * TDFE_CHEB_THREADS + t] = fmax(L.red[2 * TDFE_CHEB_THREADS + t], L.red[2 * TDFE_CHEB_THREADS + t + w]);
+    }
+    __syncthreads();
+  }
+  lo = L.red[0];
+  hi = L.red[TDFE_CHEB_THREADS];
+  *amax = L.red[2 * TDFE_CHEB_THREADS];
+  const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
+  const double z = fabs(s) * rr;
+  if (t == 0) {
+    int M = 0;
+    if (z > 1e-300) {
+      M = (int)ceil(z + 10.0 * cbrt(z) + 20.0);
+      int ms = M + 20 + (int)(2.0 * sqrt((double)M));
+      ms += ms & 1;
+      if (ms + 1 > TDFE_MAX_BESSEL) {
+        M = -1;
+      } else {
+        L.J[ms + 1] = 0.0;
+        L.J[ms] = 1e-300;
+        const double tz = 2.0 / z;
+        for (int m = ms; m > 0; --m) {
+          const double jm1 = (m * tz) * L.J[m] - L.J[m + 1];
+          L.J[m - 1] = jm1;
+          if (fabs(jm1) > 1e250)
+            for (int q = m - 1; q <= ms + 1; ++q) L.J[q] *= 1e-250;
+        }
+        double norm = L.J[0];
+        for (int m = 2; m <= ms; m += 2) norm += 2.0 * L.J[m];
+        const double inv = 1.0 / norm;
+        for (int m = 0; m <= M; ++m) L.J[m] *= inv;
+      }
+    } else {
+      L.J[0] = 1.0;
+    }
+    L.M = M;
+  }
+  __syncthreads();
+  const int M = L.M;
+  if (M < 0) return -1;
+  const double sgn = s >= 0.0 ? 1.0 : -1.0;
+  const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
+  for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
+    L.bufA[j] = (j == 0) ? 1.0 : 0.0;
+    L.yr[j] = L.J[0] * L.bufA[j];
+    L.yi[j] = 0.0;
+  }
+  __syncthreads();
+  double* prev = L.bufA;
+  double* cur = L.bufB;
+  if (M >= 1) {
+    for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
+      double w = (sa[j] - cc) * prev[j];
+      if (j > 0) w += sb[j - 1] * prev[j - 1];
+      if (j < k - 1) w += sb[j] * prev[j + 1];
+      w *= invr;
+      cur[j] = w;
+      L.yi[j] += -2.0 * sgn * L.J[1] * w;
+    }
+    __syncthreads();
+    for (int mm = 2; mm <= M; ++mm) {
+      const double cj = 2.0 * L.J[mm];
+      const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
+      for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
+        double w = (sa[j] - cc) * cur[j];
+        if (j > 0) w += sb[j - 1] * cur[j - 1];
+        if (j < k - 1) w += sb[j] * cur[j + 1];
+        const double v2 = 2.0 * w * invr - prev[j];
+        prev[j] = v2;
+        if (ph == 0) L.yr[j] += cj * v2;
+        else if (ph == 1) L.yi[j] -= sgn * cj * v2;
+        else if (ph == 2) L.yr[j] -= cj * v2;
+        else L.yi[j] += sgn * cj * v2;
+      }
+      __syncthreads();
+      double* tmp = prev;
+      prev = cur;
+      cur = tmp;
+    }
+  }
+  const double pr = cos(s * cc), pim = -sin(s * cc);
+  for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
+    const double a = L.yr[j], b = L.yi[j];
+    L.yr[j] = a * pr - b * pim;
+    L.yi[j] = a * pim + b * pr;
+  }
+  __syncthreads();
+  return M;
+}

@@ -144,9 +144,18 @@ tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a);
 
 // vector kernels (tdfe_lanczos.hip)
 tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes);
+// called once per orbital chunk after the adaptive loop (before the combination):
+// W = basis storage (k_max+1 vectors of vstride elements, float if fp32),
+// scale[j*Nc+o] = 1/beta_{j}, kconv/alpha/beta/nrm as in the Lanczos scalar block
+struct LanczosHook {
+  virtual tdfe_status after_loop(tdfe_ctx* c, const void* W, int64_t vstride, int Nc, int o0, const double* scale,
+                                 const int* kconv, const double* alpha, const double* beta, const double* nrm,
+                                 int k_enqueued, bool fp32) = 0;
+  virtual ~LanczosHook() {}
+};
 tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb,
                              double tau, double tol, int* k_out, double* err_out, int* kmax_out,
-                             int* ksum_out, double* errmax_out);
+                             int* ksum_out, double* errmax_out, LanczosHook* hook = nullptr);
 
 // scf kernels (tdfe_scf.hip)
 tdfe_status tdfe_density_dev(tdfe_ctx* c, const void* psibar, int n_orb, double* rho, double* partial3);
@@ -155,6 +164,18 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
                                double* mu, double* charge);
 tdfe_status tdfe_fdm_setup(tdfe_ctx* c);
 tdfe_status tdfe_compute_lift(tdfe_ctx* c);
+// c->cload = sum_e I^T (w f), w = varpi detJ if weighted else 1 (full grid, zeroed first)
+tdfe_status tdfe_load_vector(tdfe_ctx* c, const double* f, bool weighted);
+// interior of phi_full <- K00^-1 (4 pi c_interior [- lift]); boundary entries untouched
+tdfe_status tdfe_fdm_solve_into(tdfe_ctx* c, bool with_lift, double* phi_full);
+// out_q = phi(x_q) [+ V_xc(rho_q)] for a full-grid nodal field phi
+tdfe_status tdfe_interp_field(tdfe_ctx* c, const double* phi_full, const double* rho, int xcmode, double* out);
+// device array of the occupations f_alpha for n_orb orbitals
+tdfe_status tdfe_occ_dev(tdfe_ctx* c, int n_orb, const double** dev);
+// c->vw (and c->vw32 in mixed contexts) = wdet (vext - E z + ca A + cb B); A, B may be null
+tdfe_status tdfe_assemble_vw(tdfe_ctx* c, const double* A, double ca, const double* B, double cb, double E);
+// host symmetric eigen-decomposition A = U diag(lam) U^T (row-major n x n, U[i*n+k] = k-th vector)
+void tdfe_sym_eigen(const std::vector<double>& A, int n, std::vector<double>& lam, std::vector<double>& U);
 
 // workspace carving (tdfe_setup.hip)
 int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols);

@@ -28,14 +28,14 @@
 //    at their first instruction.
 #include <cmath>
 
+#include "tdfe_cheb.h"
 #include "tdfe_internal.h"
 
 namespace {
 
 constexpr int RED_BLOCKS = 1024;  // blocks of the streaming reductions
 constexpr int RED_THREADS = 256;
-constexpr int CHK_THREADS = 64;
-constexpr int MAX_BESSEL = 6144;
+constexpr int CHK_THREADS = TDFE_CHEB_THREADS;
 
 // scalar block layout per chunk (doubles), Nc = orbitals in the chunk
 struct Scal {
@@ -177,15 +177,10 @@ __global__ void __launch_bounds__(RED_THREADS)
 // ---------------------------------------------------------------------------------------------
 // small exponential and adaptive stop, one wavefront per orbital
 // ---------------------------------------------------------------------------------------------
-constexpr int KCAP = 1024;
 __global__ void __launch_bounds__(CHK_THREADS)
     check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, int* err_flag) {
-  __shared__ double sJ[MAX_BESSEL + 2];
-  __shared__ double sA[KCAP], sBv[KCAP];  // Chebyshev vectors v_{m-1} / v_m (roles alternate)
-  __shared__ double sa[KCAP], sb[KCAP];
-  __shared__ double syr[KCAP], syi[KCAP];
-  __shared__ double sredlo[CHK_THREADS], sredhi[CHK_THREADS], sredmx[CHK_THREADS];
-  __shared__ int sM;
+  __shared__ ChebLds L;
+  __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
   if (*S.done) return;
   const int o = blockIdx.x;
   if (S.status[o] != 0) return;
@@ -195,64 +190,8 @@ __global__ void __launch_bounds__(CHK_THREADS)
     sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
   }
   __syncthreads();
-  // Gershgorin interval of T_k and max |alpha|
-  double lo = 1e300, hi = -1e300, amax = 0.0;
-  for (int j = t; j < k; j += CHK_THREADS) {
-    double rad = 0.0;
-    if (j > 0) rad += fabs(sb[j - 1]);
-    if (j < k - 1) rad += fabs(sb[j]);
-    lo = fmin(lo, sa[j] - rad);
-    hi = fmax(hi, sa[j] + rad);
-    amax = fmax(amax, fabs(sa[j]));
-  }
-  sredlo[t] = lo;
-  sredhi[t] = hi;
-  sredmx[t] = amax;
-  __syncthreads();
-  for (int s = CHK_THREADS / 2; s > 0; s >>= 1) {
-    if (t < s) {
-      sredlo[t] = fmin(sredlo[t], sredlo[t + s]);
-      sredhi[t] = fmax(sredhi[t], sredhi[t + s]);
-      sredmx[t] = fmax(sredmx[t], sredmx[t + s]);
-    }
-    __syncthreads();
-  }
-  lo = sredlo[0];
-  hi = sredhi[0];
-  amax = sredmx[0];
-  const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
-  const double z = fabs(tau) * rr;
-  // Bessel J_m(z), m = 0..M, by Miller's backward recurrence normalised with
-  // J_0 + 2 sum J_2m = 1 (lane 0)
-  if (t == 0) {
-    int M = 0;
-    if (z > 1e-300) {
-      M = (int)ceil(z + 10.0 * cbrt(z) + 20.0);
-      int ms = M + 20 + (int)(2.0 * sqrt((double)M));
-      ms += ms & 1;
-      if (ms + 1 > MAX_BESSEL) {
-        M = -1;
-      } else {
-        sJ[ms + 1] = 0.0;
-        sJ[ms] = 1e-300;
-        for (int m = ms; m > 0; --m) {
-          const double jm1 = (2.0 * m / z) * sJ[m] - sJ[m + 1];
-          sJ[m - 1] = jm1;
-          if (fabs(jm1) > 1e250)
-            for (int q = m - 1; q <= ms + 1; ++q) sJ[q] *= 1e-250;
-        }
-        double norm = sJ[0];
-        for (int m = 2; m <= ms; m += 2) norm += 2.0 * sJ[m];
-        const double inv = 1.0 / norm;
-        for (int m = 0; m <= M; ++m) sJ[m] *= inv;
-      }
-    } else {
-      sJ[0] = 1.0;
-    }
-    sM = M;
-  }
-  __syncthreads();
-  const int M = sM;
+  double amax = 0.0;
+  const int M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
   if (M < 0) {
     if (t == 0) {
       S.status[o] = 3;
@@ -261,64 +200,15 @@ __global__ void __launch_bounds__(CHK_THREADS)
     }
     return;
   }
-  // Chebyshev recurrence v_{m+1} = 2 X v_m - v_{m-1}, X = (T - c)/r, v_0 = e_1
-  const double sgn = tau >= 0.0 ? 1.0 : -1.0;
-  const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
-  for (int j = t; j < k; j += CHK_THREADS) {
-    sA[j] = (j == 0) ? 1.0 : 0.0;  // v_0
-    syr[j] = sJ[0] * sA[j];
-    syi[j] = 0.0;
-  }
-  __syncthreads();
-  double* prev = sA;  // v_{m-1}
-  double* cur = sBv;  // v_m
-  if (M >= 1) {
-    for (int j = t; j < k; j += CHK_THREADS) {
-      double w = (sa[j] - cc) * prev[j];
-      if (j > 0) w += sb[j - 1] * prev[j - 1];
-      if (j < k - 1) w += sb[j] * prev[j + 1];
-      w *= invr;
-      cur[j] = w;                      // v_1 = X e_1
-      syi[j] += -2.0 * sgn * sJ[1] * w;  // 2 (-i sgn) J_1
-    }
-    __syncthreads();
-    for (int mm = 2; mm <= M; ++mm) {
-      const double cj = 2.0 * sJ[mm];
-      const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
-      for (int j = t; j < k; j += CHK_THREADS) {
-        double w = (sa[j] - cc) * cur[j];
-        if (j > 0) w += sb[j - 1] * cur[j - 1];
-        if (j < k - 1) w += sb[j] * cur[j + 1];
-        const double v2 = 2.0 * w * invr - prev[j];
-        prev[j] = v2;  // row j of v_{m-1} is read only by this thread
-        if (ph == 0) syr[j] += cj * v2;
-        else if (ph == 1) syi[j] -= sgn * cj * v2;
-        else if (ph == 2) syr[j] -= cj * v2;
-        else syi[j] += sgn * cj * v2;
-      }
-      __syncthreads();
-      double* tmp = prev;
-      prev = cur;
-      cur = tmp;
-    }
-  }
-  // multiply by exp(-i tau c)
-  const double pr = cos(tau * cc), pim = -sin(tau * cc);
-  for (int j = t; j < k; j += CHK_THREADS) {
-    const double a = syr[j], b = syi[j];
-    syr[j] = a * pr - b * pim;
-    syi[j] = a * pim + b * pr;
-  }
-  __syncthreads();
   const double bk = sb[k - 1];
-  const double eps = fabs(tau) * bk * S.nrm[o] * sqrt(syr[k - 1] * syr[k - 1] + syi[k - 1] * syi[k - 1]);
+  const double eps = fabs(tau) * bk * S.nrm[o] * sqrt(L.yr[k - 1] * L.yr[k - 1] + L.yi[k - 1] * L.yi[k - 1]);
   const bool happy = bk <= 1e-14 * amax;
   const bool conv = (eps <= tol) || happy;
   const bool stop = conv || k >= k_max;
   if (stop) {
     for (int j = t; j < k; j += CHK_THREADS) {
-      S.y[((size_t)o * k_max + j) * 2 + 0] = syr[j];
-      S.y[((size_t)o * k_max + j) * 2 + 1] = syi[j];
+      S.y[((size_t)o * k_max + j) * 2 + 0] = L.yr[j];
+      S.y[((size_t)o * k_max + j) * 2 + 1] = L.yi[j];
     }
   }
   if (t == 0) {
@@ -389,7 +279,7 @@ int pad_cols(int C) {
 
 template <typename T>
 tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out, int ld, int o0, int Nc,
-                      double tau, double tol, int* k_out, double* err_out, int* status_out) {
+                      double tau, double tol, int* k_out, double* err_out, int* status_out, LanczosHook* hook) {
   const int C = 2 * Nc;
   const int64_t nd = c->n_dof;
   const int64_t vstride = nd * C;
@@ -416,7 +306,9 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     for (int i = 0; i < RING; ++i) TDFE_HIP(c, hipEventCreateWithFlags(&c->evs[i], hipEventDisableTiming));
     c->n_evs = RING;
   }
+  int k_enq = 0;
   for (int k = 1; k <= K; ++k) {
+    k_enq = k;
     T* wk = W + (int64_t)(k - 1) * vstride;
     ApplyArgs a{};
     a.x = wk;
@@ -456,6 +348,8 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
       if (c->poll[kk % RING]) break;
     }
   }
+  if (hook)
+    TDFE_TRY(hook->after_loop(c, W, vstride, Nc, o0, S.scale, S.kconv, S.alpha, S.beta, S.nrm, k_enq, sizeof(T) == 4));
   // combination
   {
     const int64_t n = nd * Nc;
@@ -489,7 +383,7 @@ tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes) {
 
 tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb, double tau,
                              double tol, int* k_out, double* err_out, int* kmax_out, int* ksum_out,
-                             double* errmax_out) {
+                             double* errmax_out, LanczosHook* hook) {
   const int ld = 2 * n_orb;
   std::vector<int> ks(n_orb), st(n_orb);
   std::vector<double> es(n_orb);
@@ -502,10 +396,10 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
     tdfe_status s;
     if (c->precision == TDFE_FP64)
       s = run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
-                            es.data() + o0, st.data() + o0);
+                            es.data() + o0, st.data() + o0, hook);
     else
       s = run_chunk<float>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
-                           es.data() + o0, st.data() + o0);
+                           es.data() + o0, st.data() + o0, hook);
     if (s != TDFE_OK) return s;
   }
   int kmax = 0, ksum = 0, bad = 0;

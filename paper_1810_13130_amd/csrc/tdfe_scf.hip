@@ -181,7 +181,7 @@ __global__ void finalize4_kernel(const double* partial, int64_t nblocks, double*
 // ------------------------------------------------------------------------------------------------
 template <int N>
 __global__ void __launch_bounds__(N* N) load_kernel(const double* rho, const double* wdet, const double* tab,
-                                                     double* cload, int ncx, int ncy, int p, int Nx, int Ny) {
+                                                     double* cload, int ncx, int ncy, int p, int Nx, int Ny, int weighted) {
   constexpr int VOL = N * N * N;
   __shared__ double sU[VOL];
   __shared__ double sB[N * N];
@@ -196,7 +196,7 @@ __global__ void __launch_bounds__(N* N) load_kernel(const double* rho, const dou
 #pragma unroll
     for (int c = 0; c < N; ++c) {
       const int64_t g = cell * VOL + a + N * (b + N * c);
-      r1[c] = wdet[g] * rho[g];
+      r1[c] = weighted ? wdet[g] * rho[g] : rho[g];
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -310,7 +310,7 @@ __global__ void __launch_bounds__(N* N) interp_xc_kernel(const double* phi, cons
 #pragma unroll
       for (int i = 0; i < N; ++i) s += sB[a * N + i] * r1[i];
       const int64_t g = cell * VOL + a + N * (b + N * c);
-      W[g] = s + vxc(rho[g], xcmode);
+      W[g] = s + (rho != nullptr ? vxc(rho[g], xcmode) : 0.0);
     }
   }
 }
@@ -559,12 +559,12 @@ void fdm_axis(const tdfe_ctx* c, const std::vector<double>& ax, std::vector<doub
     }
 }
 
-tdfe_status fdm_solve(tdfe_ctx* c) {
+tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
   // rhs = 4 pi c_interior - (K f)_interior ; phi_interior = K^-1 rhs
   const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
   const int64_t nd = c->n_dof;
-  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->cload, c->lift, 4.0 * M_PI,
-                     c->t0, c->Nx, c->Ny, c->Nz);
+  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->cload,
+                     with_lift ? (const double*)c->lift : (const double*)nullptr, 4.0 * M_PI, c->t0, c->Nx, c->Ny, c->Nz);
   const double* Sx = c->fdmS;
   const double* Sy = Sx + (size_t)n1x * n1x;
   const double* Sz = Sy + (size_t)n1y * n1y;
@@ -587,7 +587,7 @@ tdfe_status fdm_solve(tdfe_ctx* c) {
   TDFE_TRY(pass(c->t1, c->t0, 2, 0, false));
   TDFE_TRY(pass(c->t0, c->t1, 1, 0, false));
   TDFE_TRY(pass(c->t1, c->t0, 0, 0, false));
-  hipLaunchKernelGGL(scatter_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->t0, c->phi, c->Nx, c->Ny,
+  hipLaunchKernelGGL(scatter_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->t0, phi_full, c->Nx, c->Ny,
                      c->Nz);
   TDFE_HIP(c, hipGetLastError());
   c->last_poisson_iters = 0;
@@ -603,13 +603,13 @@ tdfe_status launch_density_n(tdfe_ctx* c, DensParams& P) {
 }
 
 template <int N>
-tdfe_status launch_load_interp(tdfe_ctx* c, int which, double* Wout) {
+tdfe_status launch_load_interp(tdfe_ctx* c, int which, const double* in, const double* rho, int flag, double* out) {
   if (which == 0) {
-    hipLaunchKernelGGL((load_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, c->rho, c->wdet, c->tab,
-                       c->cload, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
+    hipLaunchKernelGGL((load_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, in, c->wdet, c->tab,
+                       out, c->ncx, c->ncy, c->p, c->Nx, c->Ny, flag);
   } else {
-    hipLaunchKernelGGL((interp_xc_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, c->phi, c->rho,
-                       c->tab, Wout, c->hartree, c->xc, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
+    hipLaunchKernelGGL((interp_xc_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, in, rho,
+                       c->tab, out, in != nullptr ? 1 : 0, flag, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
   }
   TDFE_HIP(c, hipGetLastError());
   return TDFE_OK;
@@ -629,8 +629,16 @@ tdfe_status launch_load_interp(tdfe_ctx* c, int which, double* Wout) {
   return tdfe_fail(c, TDFE_EINVAL, "unsupported order");
 
 tdfe_status density_launch(tdfe_ctx* c, DensParams& P) { TDFE_DISPATCH_N(launch_density_n, c, P) }
-tdfe_status load_launch(tdfe_ctx* c) { TDFE_DISPATCH_N(launch_load_interp, c, 0, nullptr) }
-tdfe_status interp_launch(tdfe_ctx* c, double* W) { TDFE_DISPATCH_N(launch_load_interp, c, 1, W) }
+tdfe_status load_launch(tdfe_ctx* c) { TDFE_DISPATCH_N(launch_load_interp, c, 0, c->rho, nullptr, 1, c->cload) }
+tdfe_status interp_launch(tdfe_ctx* c, double* W) {
+  TDFE_DISPATCH_N(launch_load_interp, c, 1, c->hartree ? c->phi : nullptr, c->rho, c->xc, W)
+}
+tdfe_status load_launch_f(tdfe_ctx* c, const double* f, int weighted) {
+  TDFE_DISPATCH_N(launch_load_interp, c, 0, f, nullptr, weighted, c->cload)
+}
+tdfe_status interp_launch_f(tdfe_ctx* c, const double* phi, const double* rho, int xcmode, double* out) {
+  TDFE_DISPATCH_N(launch_load_interp, c, 1, phi, rho, xcmode, out)
+}
 
 tdfe_status upload_occ(tdfe_ctx* c, int n_orb, double** dev) {
   // occupations live in the scalar block's tail
@@ -679,7 +687,7 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
     TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
     TDFE_TRY(load_launch(c));
     if (c->box) {
-      TDFE_TRY(fdm_solve(c));
+      TDFE_TRY(fdm_solve(c, true, c->phi));
     } else {
       return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
     }
@@ -731,6 +739,40 @@ tdfe_status tdfe_compute_lift(tdfe_ctx* c) {
   hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(c->n_dof)), dim3(EW), 0, c->stream, c->cload, (const double*)nullptr,
                      1.0, c->lift, c->Nx, c->Ny, c->Nz);
   TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_load_vector(tdfe_ctx* c, const double* f, bool weighted) {
+  TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
+  return load_launch_f(c, f, weighted ? 1 : 0);
+}
+
+tdfe_status tdfe_fdm_solve_into(tdfe_ctx* c, bool with_lift, double* phi_full) {
+  if (!c->box) return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
+  return fdm_solve(c, with_lift, phi_full);
+}
+
+tdfe_status tdfe_interp_field(tdfe_ctx* c, const double* phi_full, const double* rho, int xcmode, double* out) {
+  return interp_launch_f(c, phi_full, rho, xcmode, out);
+}
+
+void tdfe_sym_eigen(const std::vector<double>& A, int n, std::vector<double>& lam, std::vector<double>& U) {
+  jacobi_eigen(A, n, lam, U);
+}
+
+tdfe_status tdfe_assemble_vw(tdfe_ctx* c, const double* A, double ca, const double* B, double cb, double E) {
+  const int64_t nqd = c->n_quad;
+  float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
+  hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet, A, ca, B, cb,
+                     E, c->vw, v32, nqd);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_occ_dev(tdfe_ctx* c, int n_orb, const double** dev) {
+  double* d = nullptr;
+  TDFE_TRY(upload_occ(c, n_orb, &d));
+  *dev = d;
   return TDFE_OK;
 }
 

@@ -72,6 +72,10 @@ SIGNATURES = {
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
     "tdfe_magnus_step": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                          ctypes.POINTER(StepReport)],
+    "tdfe_gradient_query": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                            ctypes.POINTER(ctypes.c_size_t)],
+    "tdfe_dipole_gradient": [_P, _P, ctypes.c_int, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_double,
+                             ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _DP, _DP],
     "tdfe_last_error": [_P],
     "tdfe_destroy": [_P],
 }
@@ -258,3 +262,64 @@ class Context:
         self._check(self.lib.tdfe_magnus_step(self.h, _ptr(psibar), n, dt, field_E, tol,
                                               ctypes.byref(rep) if report else None))
         return rep.as_dict() if report else None
+
+    def gradient_query(self, n_orb, n_steps, checkpoint_every, k_store):
+        b = ctypes.c_size_t()
+        self._check(self.lib.tdfe_gradient_query(self.h, n_orb, n_steps, checkpoint_every, k_store, ctypes.byref(b)))
+        return b.value
+
+    def dipole_gradient(self, psibar0, E, dt, tol=1e-10, checkpoint_every=None, k_store=64):
+        """(L, dL/dE) for L = mu_z after len(E) Magnus steps with fields E (numpy, float64)."""
+        import torch
+        n = self._orb(psibar0)
+        E = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1))
+        N = len(E)
+        ck = N if checkpoint_every is None else int(checkpoint_every)
+        nb = self.gradient_query(n, N, ck, k_store)
+        work = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+        base = work.data_ptr()
+        off = (-base) % 256
+        L = ctypes.c_double()
+        g = np.zeros(N, dtype=np.float64)
+        self._check(self.lib.tdfe_dipole_gradient(self.h, _ptr(psibar0), n, N, E.ctypes.data_as(_DP), dt, tol, ck,
+                                                  k_store, ctypes.c_void_p(base + off), nb, ctypes.byref(L),
+                                                  g.ctypes.data_as(_DP)))
+        del work
+        return L.value, g
+
+
+def _dipole_function():
+    import torch
+
+    class DipoleOfField(torch.autograd.Function):
+        """L = mu_z(t_N) as a differentiable function of the field amplitudes.
+
+        forward(E, ctx, psibar0, dt, tol, checkpoint_every, k_store): E is a
+        float64 tensor of per-step amplitudes; the reverse sweep runs in the
+        same library call as the forward one, so backward only scales the
+        stored gradient.
+        """
+
+        @staticmethod
+        def forward(fctx, E, ctx, psibar0, dt, tol=1e-10, checkpoint_every=None, k_store=64):
+            L, g = ctx.dipole_gradient(psibar0, E.detach().cpu().numpy(), dt, tol, checkpoint_every, k_store)
+            fctx.save_for_backward(torch.from_numpy(g).to(E.device))
+            return torch.tensor(L, dtype=torch.float64, device=E.device)
+
+        @staticmethod
+        def backward(fctx, gL):
+            (g,) = fctx.saved_tensors
+            return gL * g, None, None, None, None, None, None
+
+    return DipoleOfField
+
+
+_DIPOLE_FN = None
+
+
+def dipole_of_field(E, ctx, psibar0, dt, tol=1e-10, checkpoint_every=None, k_store=64):
+    """Autograd entry: returns L (0-d tensor); L.backward() fills E.grad with dL/dE."""
+    global _DIPOLE_FN
+    if _DIPOLE_FN is None:
+        _DIPOLE_FN = _dipole_function()
+    return _DIPOLE_FN.apply(E, ctx, psibar0, dt, tol, checkpoint_every, k_store)

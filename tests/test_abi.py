@@ -91,6 +91,13 @@ def test_query_sizes_and_call_order(lib):
     assert lib.tdfe_magnus_step(h, buf, 1, -0.1, 0.0, 1e-8, None) == tdfe.EINVAL
     assert lib.tdfe_magnus_step(h, buf, 1, 0.1, 0.0, 1e-8, None) == tdfe.ESTATE
     assert b"before" in lib.tdfe_last_error(h)
+    nb = ctypes.c_size_t()
+    assert lib.tdfe_gradient_query(h, 1, 4, 2, 8, ctypes.byref(nb)) == tdfe.ESTATE
+    assert lib.tdfe_gradient_query(h, 1, 4, 2, 8, None) == tdfe.EINVAL
+    E = (ctypes.c_double * 4)()
+    L, g = ctypes.c_double(), (ctypes.c_double * 4)()
+    assert lib.tdfe_dipole_gradient(h, None, 1, 4, E, 0.1, 1e-8, 2, 8, buf, 1 << 20, ctypes.byref(L), g) == tdfe.EINVAL
+    assert lib.tdfe_dipole_gradient(h, buf, 1, 4, E, 0.1, 1e-8, 2, 8, buf, 1 << 20, ctypes.byref(L), g) == tdfe.ESTATE
     assert lib.tdfe_bind_workspace(h, None, 0) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, ctypes.c_void_p(4096 + 8), ws.value) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, ctypes.c_void_p(4096), ws.value - 1) == tdfe.ENOMEM

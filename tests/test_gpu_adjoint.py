@@ -1,0 +1,150 @@
+"""GPU parity of the field gradient dL/dE_n of L = mu_z(t_N).
+
+Tiny meshes: the library's gradient (Krylov adjoint on the GPU) against the
+oracle's dense-exponential adjoint (itself pinned by finite differences and
+the Taylor remainder in the CPU tests).  Full size (16^3 cells, p = 5,
+8 orbitals): properties that hold at any size -- checkpoint invariance,
+central finite differences of the GPU forward map on sampled components,
+the autograd wrapper."""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import gpu_context, gpu_initial_state, rel
+
+pytestmark = pytest.mark.gpu
+
+
+def _tiny(scf_on, n_orb=2):
+    cfg = W.scaled(W.CONFIGS[5], ncell=(3, 3, 3), p=3, n_orb=n_orb)
+    return cfg
+
+
+def _gpu(cfg, scf_on, precision=0):
+    ctx = gpu_context(cfg, precision=precision)
+    if scf_on:
+        Z, R = W.atoms(cfg)
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=cfg.n_orb)
+    return ctx, gpu_initial_state(ctx, cfg)
+
+
+@pytest.mark.parametrize("scf_on", [False, True])
+def test_gradient_matches_dense_oracle(scf_on):
+    from oracle.adjoint import DenseAdjointSystem
+    from oracle.mesh import Mesh
+    cfg = _tiny(scf_on)
+    E = W.field_amplitudes(4) * 50.0
+    m = Mesh(cfg.p, cfg.ncell, W.vertices(cfg), cfg.nq)
+    Z, R = W.atoms(cfg)
+    sysd = DenseAdjointSystem(m, W.external_potential(cfg, m.quad_xyz), Z, R,
+                              xc="x" if scf_on else "none", hartree=scf_on)
+    L_ref, g_ref = sysd.gradient(W.initial_psibar(cfg, m.dof_xyz, m.M), E, cfg.dt)
+    ctx, psi = _gpu(cfg, scf_on)
+    psi_in = psi.clone()
+    L, g = ctx.dipole_gradient(psi, E, cfg.dt, tol=1e-13, k_store=64)
+    print(f"scf={scf_on} L {L:.12e} ref {L_ref:.12e} grad rel err {rel(g, g_ref):.3e}", flush=True)
+    assert abs(L - L_ref) <= 1e-10 * max(abs(L_ref), 1e-3)
+    assert rel(g, g_ref) < 1e-8
+    assert (psi == psi_in).all()  # the initial state is read only
+    ctx.close()
+
+
+def test_gradient_single_step_and_three_orbitals():
+    from oracle.adjoint import DenseAdjointSystem
+    from oracle.mesh import Mesh
+    cfg = _tiny(True, n_orb=3)
+    E = np.array([0.7])
+    m = Mesh(cfg.p, cfg.ncell, W.vertices(cfg), cfg.nq)
+    Z, R = W.atoms(cfg)
+    sysd = DenseAdjointSystem(m, W.external_potential(cfg, m.quad_xyz), Z, R, xc="x", hartree=True)
+    L_ref, g_ref = sysd.gradient(W.initial_psibar(cfg, m.dof_xyz, m.M), E, cfg.dt)
+    ctx, psi = _gpu(cfg, True)
+    L, g = ctx.dipole_gradient(psi, E, cfg.dt, tol=1e-13, k_store=64)
+    assert abs(L - L_ref) <= 1e-10 * max(abs(L_ref), 1e-3)
+    assert rel(g, g_ref) < 1e-8
+    ctx.close()
+
+
+def test_checkpointing_does_not_change_the_gradient():
+    cfg = _tiny(True)
+    E = W.field_amplitudes(7) * 50.0
+    ctx, psi = _gpu(cfg, True)
+    L0, g0 = ctx.dipole_gradient(psi, E, cfg.dt, tol=1e-12, checkpoint_every=None)
+    for ck in (1, 3):
+        L1, g1 = ctx.dipole_gradient(psi, E, cfg.dt, tol=1e-12, checkpoint_every=ck)
+        assert abs(L1 - L0) <= 1e-13 * max(abs(L0), 1.0)
+        assert rel(g1, g0) < 1e-11, ck
+    ctx.close()
+
+
+def test_gradient_leaves_magnus_history_and_potential_alone():
+    cfg = _tiny(True)
+    ctx, psi = _gpu(cfg, True)
+    a = psi.clone()
+    b = psi.clone()
+    ctx.magnus_step(a, cfg.dt, 0.3, 1e-12)
+    ctx.magnus_step(a, cfg.dt, 0.3, 1e-12)
+    ctx.dipole_gradient(psi, [0.1, -0.2], cfg.dt, tol=1e-12)
+    # apply_H sees the external potential again
+    ctx3 = gpu_context(cfg)
+    assert rel(ctx.apply_H(psi).cpu().numpy(), ctx3.apply_H(psi).cpu().numpy()) < 1e-13
+    # and the extrapolation history of magnus_step is intact
+    ctx.magnus_step(a, cfg.dt, 0.3, 1e-12)
+    ctx2, _ = _gpu(cfg, True)
+    for _ in range(3):
+        ctx2.magnus_step(b, cfg.dt, 0.3, 1e-12)
+    assert rel(a.cpu().numpy(), b.cpu().numpy()) < 1e-12
+    for c in (ctx, ctx2, ctx3):
+        c.close()
+
+
+def test_k_store_too_small_is_reported():
+    from paper_1810_13130_amd import tdfe
+    cfg = _tiny(True)
+    ctx, psi = _gpu(cfg, True)
+    with pytest.raises(tdfe.TdfeError) as e:
+        ctx.dipole_gradient(psi, [0.1], 1.0, tol=1e-12, k_store=8)
+    assert e.value.status == tdfe.EINVAL and "basis vectors" in str(e.value)
+    ctx.close()
+
+
+def test_autograd_function():
+    import torch
+    from paper_1810_13130_amd import tdfe
+    cfg = _tiny(True)
+    ctx, psi = _gpu(cfg, True)
+    E = torch.tensor(W.field_amplitudes(3) * 50.0, dtype=torch.float64, requires_grad=True)
+    L = tdfe.dipole_of_field(E, ctx, psi, cfg.dt, tol=1e-12)
+    (3.0 * L).backward()
+    L2, g = ctx.dipole_gradient(psi, E.detach().numpy(), cfg.dt, tol=1e-12)
+    assert abs(float(L.detach()) - L2) <= 1e-13 * max(abs(L2), 1.0)
+    assert rel(E.grad.numpy(), 3.0 * g) < 1e-11
+    ctx.close()
+
+
+def test_full_size_gradient_against_finite_differences():
+    """16^3 cells, p = 5, 8 orbitals, Hartree + exchange: sampled components
+    of the gradient against central differences of the GPU forward map."""
+    cfg = W.CONFIGS[5]
+    n = 4
+    E = W.field_amplitudes(n) * 5.0
+    ctx, psi = _gpu(cfg, True)
+    L, g = ctx.dipole_gradient(psi, E, cfg.dt, tol=1e-12, checkpoint_every=2)
+
+    def forward(Ev):
+        x = psi.clone()
+        ctx.set_scf(hartree=True, xc=1, Z=W.atoms(cfg)[0], R=W.atoms(cfg)[1], n_orb=cfg.n_orb)  # reset history
+        for e in Ev:
+            ctx.magnus_step(x, cfg.dt, float(e), 1e-12, report=False)
+        return ctx.dipole(x)[0][2]
+
+    assert abs(forward(E) - L) <= 1e-10 * max(abs(L), 1e-3)
+    h = 1e-2
+    for k in (0, n - 1):
+        ep, em = E.copy(), E.copy()
+        ep[k] += h
+        em[k] -= h
+        fd = (forward(ep) - forward(em)) / (2 * h)
+        print(f"component {k}: adjoint {g[k]:.10e} fd {fd:.10e}", flush=True)
+        assert abs(fd - g[k]) <= 1e-5 * np.abs(g).max()
+    ctx.close()
