@@ -70,6 +70,7 @@ struct tdfe_ctx {
   double* t1 = nullptr;       // [n_dof] scratch
   double* pcg = nullptr;      // 5 x [n_nodes] (r, z, p, Ap, x) for curved meshes
   double* dinvK = nullptr;    // [n_nodes] inverse stiffness diagonal (interior), 0 on boundary
+  double* pcgs = nullptr;     // [16] CG scalars (rz, rr, bb, alpha, beta, pAp)
   void* krylov = nullptr;     // (k_max+1) x [n_dof][cols]
   void* hq = nullptr;         // [n_dof][cols] apply output
   void* half = nullptr;       // [n_dof][2 n_orb_max] predictor state (complex128)
@@ -141,6 +142,10 @@ tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
 // rectilinear-cell variant (tdfe_apply_box.hip), used by tdfe_launch_apply
 bool tdfe_box_kernel_ok(const tdfe_ctx* c);
 tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a);
+
+// events for the host's look-ahead polling of device convergence flags (created once per context)
+#define TDFE_N_EVENTS 16
+tdfe_status tdfe_poll_events(tdfe_ctx* c);
 
 // vector kernels (tdfe_lanczos.hip)
 tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes);

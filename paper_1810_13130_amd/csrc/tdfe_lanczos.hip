@@ -301,11 +301,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
 
   const int LOOK = 2;
   const int RING = 8;
-  if (!c->evs) {
-    c->evs = new hipEvent_t[RING];
-    for (int i = 0; i < RING; ++i) TDFE_HIP(c, hipEventCreateWithFlags(&c->evs[i], hipEventDisableTiming));
-    c->n_evs = RING;
-  }
+  TDFE_TRY(tdfe_poll_events(c));
   int k_enq = 0;
   for (int k = 1; k <= K; ++k) {
     k_enq = k;
@@ -375,6 +371,17 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
 }
 
 }  // namespace
+
+tdfe_status tdfe_poll_events(tdfe_ctx* c) {
+  if (c->evs) return TDFE_OK;
+  c->evs = new hipEvent_t[TDFE_N_EVENTS];
+  c->n_evs = 0;
+  for (int i = 0; i < TDFE_N_EVENTS; ++i) {
+    TDFE_HIP(c, hipEventCreateWithFlags(&c->evs[i], hipEventDisableTiming));
+    c->n_evs = i + 1;
+  }
+  return TDFE_OK;
+}
 
 tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes) {
   TDFE_HIP(c, hipMemsetAsync(p, 0, bytes, c->stream));

@@ -651,6 +651,346 @@ tdfe_status upload_occ(tdfe_ctx* c, int n_orb, double** dev) {
   return TDFE_OK;
 }
 
+// ------------------------------------------------------------------------------------------------
+// curved meshes: Hartree by Jacobi-preconditioned conjugate gradients on the interior nodes
+// (K_00 phi_0 = 4 pi c_0 - (K f)_0, Eqs. Poisson, VHDiscretePoisson), warm-started from the
+// previous solution.  Vectors are full-grid arrays with zero boundary entries so that the
+// operator kernel's stiffness mode applies K directly; p^T K p comes from that kernel's own
+// quadrature-point quadratic form.  Reductions are two-level in a fixed order.
+// ------------------------------------------------------------------------------------------------
+constexpr int PCG_BLOCKS = 512;
+constexpr int PCG_DONE = 160, PCG_ITERS = 161, PCG_FAIL = 162;  // int slots in c->counters
+
+__device__ __forceinline__ bool interior_node(int64_t idx, int Nx, int Ny, int Nz) {
+  const int I = (int)(idx % Nx), J = (int)((idx / Nx) % Ny), K = (int)(idx / ((int64_t)Nx * Ny));
+  return I > 0 && I < Nx - 1 && J > 0 && J < Ny - 1 && K > 0 && K < Nz - 1;
+}
+
+// diag(K) over all nodes: sum over cells and Gauss points of w detJ (grad_xi N)^T J^-1 J^-T (grad_xi N)
+template <int N>
+__global__ void __launch_bounds__(N* N* N) stiffness_diag_kernel(const double* corners, const double* tab,
+                                                                  double* diag, int ncx, int ncy, int p, int Nx,
+                                                                  int Ny) {
+  constexpr int VOL = N * N * N;
+  __shared__ double sG[VOL * 6];
+  __shared__ double sB[N * N], sD[N * N];
+  const int t = threadIdx.x;
+  const int64_t cell = blockIdx.x;
+  if (t < N * N) {
+    sB[t] = tab[TAB_B + (t / N) * TDFE_MAXN + (t % N)];
+    sD[t] = tab[TAB_D + (t / N) * TDFE_MAXN + (t % N)];
+  }
+  {
+    const int a = t % N, b = (t / N) % N, cq = t / (N * N);
+    const double xa = tab[TAB_ETA + a], xb = tab[TAB_ETA + b], xc = tab[TAB_ETA + cq];
+    const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
+                            {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
+    const double* C = corners + cell * 24;
+    double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+    for (int vz = 0; vz < 2; ++vz)
+      for (int vy = 0; vy < 2; ++vy)
+        for (int vx = 0; vx < 2; ++vx) {
+          const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
+          const double d0 = (vx ? 0.5 : -0.5) * f[vy][1] * f[vz][2];
+          const double d1 = f[vx][0] * (vy ? 0.5 : -0.5) * f[vz][2];
+          const double d2 = f[vx][0] * f[vy][1] * (vz ? 0.5 : -0.5);
+          for (int d = 0; d < 3; ++d) {
+            J[d][0] += X3[d] * d0;
+            J[d][1] += X3[d] * d1;
+            J[d][2] += X3[d] * d2;
+          }
+        }
+    double A[3][3];  // adjugate rows: J^-1 = A / det
+    A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+    A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+    A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+    A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+    A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+    A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+    A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+    A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+    A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+    const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+    const double s = tab[TAB_W3Q + t] / det;
+    double* g = sG + t * 6;
+    g[0] = s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]);
+    g[1] = s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]);
+    g[2] = s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]);
+    g[3] = s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]);
+    g[4] = s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]);
+    g[5] = s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]);
+  }
+  __syncthreads();
+  const int i = t % N, j = (t / N) % N, k = t / (N * N);
+  double acc = 0.0;
+  for (int cq = 0; cq < N; ++cq)
+    for (int b = 0; b < N; ++b)
+      for (int a = 0; a < N; ++a) {
+        const double bi = sB[a * N + i], bj = sB[b * N + j], bk = sB[cq * N + k];
+        const double g0 = sD[a * N + i] * bj * bk, g1 = bi * sD[b * N + j] * bk, g2 = bi * bj * sD[cq * N + k];
+        const double* G = sG + (a + N * (b + N * cq)) * 6;
+        acc += G[0] * g0 * g0 + G[3] * g1 * g1 + G[5] * g2 * g2 +
+               2.0 * (G[1] * g0 * g1 + G[2] * g0 * g2 + G[4] * g1 * g2);
+      }
+  const int cx = (int)(cell % ncx), cy = (int)((cell / ncx) % ncy), cz = (int)(cell / ((int64_t)ncx * ncy));
+  const int64_t node = (int64_t)(cx * p + i) + (int64_t)Nx * ((int64_t)(cy * p + j) + (int64_t)Ny * (cz * p + k));
+  unsafeAtomicAdd(diag + node, acc);
+}
+
+// in place: d <- 1/d inside, 0 on the boundary
+__global__ void invert_diag_kernel(double* d, int Nx, int Ny, int Nz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Nx * Ny * Nz) return;
+  d[idx] = interior_node(idx, Nx, Ny, Nz) ? 1.0 / d[idx] : 0.0;
+}
+
+// b <- 4 pi c - lift inside, 0 on the boundary (in place on the load vector); x <- interior of phi
+__global__ void pcg_rhs_kernel(double* b, const double* lift, const double* phi, double* x, int Nx, int Ny, int Nz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Nx * Ny * Nz) return;
+  const int I = (int)(idx % Nx), J = (int)((idx / Nx) % Ny), K = (int)(idx / ((int64_t)Nx * Ny));
+  const bool in = I > 0 && I < Nx - 1 && J > 0 && J < Ny - 1 && K > 0 && K < Nz - 1;
+  if (in) {
+    const int64_t d = (int64_t)(I - 1) + (int64_t)(Nx - 2) * ((int64_t)(J - 1) + (int64_t)(Ny - 2) * (K - 1));
+    b[idx] = 4.0 * M_PI * b[idx] - lift[d];
+    x[idx] = phi[idx];
+  } else {
+    b[idx] = 0.0;
+    x[idx] = 0.0;
+  }
+}
+
+__device__ void block_sum3(double v0, double v1, double v2, double* out) {
+  __shared__ double sred[3][EW];
+  const int t = threadIdx.x;
+  sred[0][t] = v0;
+  sred[1][t] = v1;
+  sred[2][t] = v2;
+  __syncthreads();
+  for (int s = EW / 2; s > 0; s >>= 1) {
+    if (t < s) {
+      sred[0][t] += sred[0][t + s];
+      sred[1][t] += sred[1][t + s];
+      sred[2][t] += sred[2][t + s];
+    }
+    __syncthreads();
+  }
+  if (t == 0) {
+    out[0] = sred[0][0];
+    out[1] = sred[1][0];
+    out[2] = sred[2][0];
+  }
+}
+
+// r = b - Ap (interior), z = D^-1 r, p = z, Ap = 0; partials of r.z, r.r, b.b
+__global__ void __launch_bounds__(EW) pcg_start_kernel(const double* b, double* r, double* z, double* pv, double* Ap,
+                                                       const double* dinv, int64_t n, double* partial) {
+  double rz = 0, rr = 0, bb = 0;
+  for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < n; i += (int64_t)gridDim.x * EW) {
+    const double di = dinv[i];
+    const double ri = di != 0.0 ? b[i] - Ap[i] : 0.0;  // dinv is 0 exactly on the boundary
+    const double zi = di * ri;
+    r[i] = ri;
+    z[i] = zi;
+    pv[i] = zi;
+    Ap[i] = 0.0;
+    rz += ri * zi;
+    rr += ri * ri;
+    bb += b[i] * b[i];
+  }
+  block_sum3(rz, rr, bb, partial + blockIdx.x * 3);
+}
+
+// x += alpha p, r -= alpha Ap (interior), z = D^-1 r, Ap = 0; partials of r.z, r.r
+__global__ void __launch_bounds__(EW) pcg_update_kernel(double* x, double* r, double* z, const double* pv, double* Ap,
+                                                        const double* dinv, const double* S, int64_t n,
+                                                        double* partial, const int* done) {
+  if (*done) return;
+  const double alpha = S[3];
+  double rz = 0, rr = 0;
+  for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < n; i += (int64_t)gridDim.x * EW) {
+    const double di = dinv[i];
+    const double pi = pv[i];
+    x[i] += alpha * pi;
+    const double ri = di != 0.0 ? r[i] - alpha * Ap[i] : 0.0;
+    const double zi = di * ri;
+    r[i] = ri;
+    z[i] = zi;
+    Ap[i] = 0.0;
+    rz += ri * zi;
+    rr += ri * ri;
+  }
+  block_sum3(rz, rr, 0.0, partial + blockIdx.x * 3);
+}
+
+// p = z + beta p
+__global__ void pcg_direction_kernel(const double* z, double* pv, const double* S, int64_t n, const int* done) {
+  if (*done) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  pv[i] = z[i] + S[4] * pv[i];
+}
+
+// mode 0 (start): S[0]=rz, S[1]=rr, S[2]=bb, done if converged
+// mode 1 (alpha): S[5]=pAp from the operator partials [nb][1]; S[3] = rz / pAp
+// mode 2 (beta):  rz_new, rr -> S[4] = rz_new / rz, S[0] = rz_new, S[1] = rr; iteration count, stop test
+__global__ void __launch_bounds__(EW) pcg_scalar_kernel(const double* partial, int64_t nb, int stride, int mode,
+                                                        double* S, int* flags, double tol, int maxit) {
+  if (mode != 0 && flags[0]) return;
+  __shared__ double sred[3][EW];
+  const int t = threadIdx.x;
+  double v[3] = {0, 0, 0};
+  for (int64_t b = t; b < nb; b += EW)
+    for (int u = 0; u < stride; ++u) v[u] += partial[b * stride + u];
+  for (int u = 0; u < 3; ++u) sred[u][t] = v[u];
+  __syncthreads();
+  for (int s = EW / 2; s > 0; s >>= 1) {
+    if (t < s)
+      for (int u = 0; u < 3; ++u) sred[u][t] += sred[u][t + s];
+    __syncthreads();
+  }
+  if (t != 0) return;
+  if (mode == 0) {
+    S[0] = sred[0][0];
+    S[1] = sred[1][0];
+    S[2] = sred[2][0];
+    flags[1] = 0;
+    flags[2] = 0;
+    flags[0] = (S[2] == 0.0 || sqrt(S[1]) <= tol * sqrt(S[2])) ? 1 : 0;
+  } else if (mode == 1) {
+    const double pAp = sred[0][0];
+    S[5] = pAp;
+    if (!(pAp > 0.0)) {
+      flags[2] = 2;
+      flags[0] = 1;
+      return;
+    }
+    S[3] = S[0] / pAp;
+  } else {
+    const double rz = sred[0][0], rr = sred[1][0];
+    S[4] = rz / S[0];
+    S[0] = rz;
+    S[1] = rr;
+    flags[1] += 1;
+    if (sqrt(rr) <= tol * sqrt(S[2])) {
+      flags[0] = 1;
+    } else if (flags[1] >= maxit) {
+      flags[2] = 1;
+      flags[0] = 1;
+    }
+  }
+}
+
+// phi <- x inside (boundary values stay)
+__global__ void pcg_store_kernel(const double* x, double* phi, int Nx, int Ny, int Nz) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (int64_t)Nx * Ny * Nz) return;
+  if (interior_node(idx, Nx, Ny, Nz)) phi[idx] = x[idx];
+}
+
+template <int N>
+tdfe_status launch_stiffness_diag_n(tdfe_ctx* c) {
+  hipLaunchKernelGGL((stiffness_diag_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N * N), 0, c->stream, c->corners,
+                     c->tab, c->dinvK, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+tdfe_status stiffness_diag(tdfe_ctx* c) {
+  TDFE_HIP(c, hipMemsetAsync(c->dinvK, 0, c->n_nodes * sizeof(double), c->stream));
+  tdfe_status s;
+  switch (c->n) {
+    case 2: s = launch_stiffness_diag_n<2>(c); break;
+    case 3: s = launch_stiffness_diag_n<3>(c); break;
+    case 4: s = launch_stiffness_diag_n<4>(c); break;
+    case 5: s = launch_stiffness_diag_n<5>(c); break;
+    case 6: s = launch_stiffness_diag_n<6>(c); break;
+    case 7: s = launch_stiffness_diag_n<7>(c); break;
+    case 8: s = launch_stiffness_diag_n<8>(c); break;
+    case 9: s = launch_stiffness_diag_n<9>(c); break;
+    default: return tdfe_fail(c, TDFE_EINVAL, "unsupported order");
+  }
+  if (s != TDFE_OK) return s;
+  hipLaunchKernelGGL(invert_diag_kernel, dim3(nblk(c->n_nodes)), dim3(EW), 0, c->stream, c->dinvK, c->Nx, c->Ny,
+                     c->Nz);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+// solves for the interior of c->phi from the load vector in c->cload (overwritten)
+tdfe_status pcg_solve(tdfe_ctx* c) {
+  const int64_t nn = c->n_nodes;
+  double* r = c->pcg;
+  double* z = r + nn;
+  double* pv = z + nn;
+  double* Ap = pv + nn;
+  double* x = Ap + nn;
+  double* S = c->pcgs;
+  int* flags = (int*)c->counters + PCG_DONE;
+  // past the density/dipole partials (n_cell x 4 + 4), which are read after the solve
+  double* part = c->partial + ((c->n_cell * 4 + 8 + 63) / 64) * 64;
+  auto apply_K = [&](const double* in, bool energy, int64_t* groups) -> tdfe_status {
+    ApplyArgs a{};
+    a.x = in;
+    a.y = Ap;
+    a.ld = 1;
+    a.cols = 1;
+    a.kin = 1.0;
+    a.lowdin = false;
+    a.fullgrid = true;
+    a.energy = energy ? part : nullptr;
+    a.n_blocks_out = groups;
+    a.done_flag = energy ? flags : nullptr;
+    return tdfe_launch_apply(c, a);
+  };
+  hipLaunchKernelGGL(pcg_rhs_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, c->cload, (const double*)c->lift,
+                     (const double*)c->phi, x, c->Nx, c->Ny, c->Nz);
+  TDFE_HIP(c, hipMemsetAsync(Ap, 0, nn * sizeof(double), c->stream));
+  TDFE_TRY(apply_K(x, false, nullptr));
+  hipLaunchKernelGGL(pcg_start_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, (const double*)c->cload, r, z, pv, Ap,
+                     (const double*)c->dinvK, nn, part);
+  hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, (int64_t)PCG_BLOCKS, 3,
+                     0, S, flags, c->pcg_tol, c->pcg_maxit);
+  TDFE_HIP(c, hipGetLastError());
+  const int LOOK = 4, RING = TDFE_N_EVENTS, POLL0 = 64;
+  TDFE_TRY(tdfe_poll_events(c));
+  TDFE_HIP(c, hipMemcpyAsync(c->poll + POLL0, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  if (!c->poll[POLL0]) {
+    for (int it = 1; it <= c->pcg_maxit; ++it) {
+      int64_t groups = 0;
+      TDFE_TRY(apply_K(pv, true, &groups));
+      hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, groups, 1, 1, S,
+                         flags, c->pcg_tol, c->pcg_maxit);
+      hipLaunchKernelGGL(pcg_update_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, x, r, z, (const double*)pv, Ap,
+                         (const double*)c->dinvK, (const double*)S, nn, part, (const int*)flags);
+      hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, (int64_t)PCG_BLOCKS,
+                         3, 2, S, flags, c->pcg_tol, c->pcg_maxit);
+      hipLaunchKernelGGL(pcg_direction_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, (const double*)z, pv,
+                         (const double*)S, nn, (const int*)flags);
+      TDFE_HIP(c, hipGetLastError());
+      TDFE_HIP(c, hipMemcpyAsync(c->poll + POLL0 + (it % RING), flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+      TDFE_HIP(c, hipEventRecord(c->evs[it % RING], c->stream));
+      if (it > LOOK) {
+        const int kk = it - LOOK;
+        TDFE_HIP(c, hipEventSynchronize(c->evs[kk % RING]));
+        if (c->poll[POLL0 + (kk % RING)]) break;
+      }
+    }
+  }
+  hipLaunchKernelGGL(pcg_store_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, (const double*)x, c->phi, c->Nx, c->Ny,
+                     c->Nz);
+  TDFE_HIP(c, hipGetLastError());
+  int fl[3];
+  TDFE_HIP(c, hipMemcpyAsync(fl, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  c->last_poisson_iters = fl[1];
+  if (fl[2] == 2) return tdfe_fail(c, TDFE_ENONFINITE, "Hartree CG: p^T K p <= 0");
+  if (fl[2] == 1 || !fl[0])
+    return tdfe_fail(c, TDFE_ENOCONV, "Hartree CG did not reach %g in %d iterations", c->pcg_tol, c->pcg_maxit);
+  return TDFE_OK;
+}
+
 }  // namespace
 
 // density at the Gauss points into rho (device) and 4 partial sums per cell
@@ -689,7 +1029,7 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
     if (c->box) {
       TDFE_TRY(fdm_solve(c, true, c->phi));
     } else {
-      return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
+      TDFE_TRY(pcg_solve(c));
     }
   }
   TDFE_TRY(interp_launch(c, W));
@@ -795,7 +1135,6 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   c->pcg_tol = s->pcg_tol;
   c->pcg_maxit = s->pcg_maxit;
   if (c->hartree) {
-    if (!c->box) return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
     std::vector<double> zr(4 * std::max(1, s->n_nuclei));
     for (int a = 0; a < s->n_nuclei; ++a) {
       zr[a * 4 + 0] = s->Z[a];
@@ -810,7 +1149,10 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
     TDFE_HIP(c, hipGetLastError());
     TDFE_TRY(tdfe_compute_lift(c));
     TDFE_HIP(c, hipStreamSynchronize(c->stream));
-    TDFE_TRY(tdfe_fdm_setup(c));
+    if (c->box)
+      TDFE_TRY(tdfe_fdm_setup(c));
+    else
+      TDFE_TRY(stiffness_diag(c));
   }
   c->have_scf = c->hartree || c->xc != TDFE_XC_NONE;
   c->scf_init = false;

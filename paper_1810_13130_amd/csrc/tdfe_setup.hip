@@ -293,6 +293,7 @@ void carve(tdfe_ctx* c, char* base) {
   c->fdmL = k.take<double>((size_t)n1x + n1y + n1z);
   c->pcg = c->box ? k.take<double>(1) : k.take<double>(5 * nn);
   c->dinvK = c->box ? k.take<double>(1) : k.take<double>(nn);
+  c->pcgs = k.take<double>(16);
   const int cols = 2 * c->chunk_orb;
   c->krylov = k.take<char>((size_t)(c->k_max + 1) * nd * cols * elem_bytes(c));
   c->hq = k.take<char>((size_t)nd * cols * elem_bytes(c));
@@ -570,6 +571,10 @@ const char* tdfe_last_error(const tdfe_ctx* c) {
 
 void tdfe_destroy(tdfe_ctx* c) {
   if (!c) return;
+  // pending copies into the pinned poll buffer must land before it is freed
+  if (c->bound) (void)hipStreamSynchronize(c->stream);
+  for (int i = 0; i < c->n_evs; ++i) (void)hipEventDestroy(c->evs[i]);
+  delete[] c->evs;
   if (c->poll) (void)hipHostFree(c->poll);
   delete c;
 }

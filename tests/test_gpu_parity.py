@@ -145,6 +145,39 @@ def test_magnus_scf_predictor_corrector_matches_oracle(n_orb):
     assert rel(g.cpu().numpy(), st.psibar) < 1e-10
 
 
+@pytest.mark.parametrize("xc", ["x", "xc"])
+def test_magnus_scf_on_graded_mesh_matches_oracle(xc):
+    """Curved (trilinear) cells: Hartree by the GPU's Jacobi-PCG, exchange or
+    exchange + PZ81 correlation, predictor-corrector steps."""
+    cfg = _cfg3_small(n_orb=3)
+    ctx = gpu_context(cfg, n_orb=3)
+    Z, R = W.atoms(cfg)
+    ctx.set_scf(hartree=True, xc={"x": 1, "xc": 2}[xc], Z=Z, R=R, n_orb=3, pcg_tol=1e-14, pcg_maxit=5000)
+    g = gpu_initial_state(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    sysm = System(m, vq, hartree=True, xc=xc, Z=Z, R=R, tol=1e-12, pcg_tol=1e-14)
+    st = State(sysm, W.initial_psibar(cfg, m.dof_xyz, m.M))
+    for n in range(3):
+        rep = ctx.magnus_step(g, cfg.dt, 0.0, 1e-12)
+        ref = magnus_step(sysm, st, cfg.dt)
+        assert rep["poisson_iters"] > 0
+        assert np.abs(rep["mu"] - ref["dipole"]).max() < 1e-10 * np.abs(ref["dipole"]).max()
+        assert abs(rep["charge"] - ref["charge"]) < 1e-10 * abs(ref["charge"])
+    assert rel(g.cpu().numpy(), st.psibar) < 1e-10
+
+
+def test_pcg_not_converging_is_reported():
+    from paper_1810_13130_amd import tdfe
+    cfg = _cfg3_small(n_orb=2)
+    ctx = gpu_context(cfg, n_orb=2)
+    Z, R = W.atoms(cfg)
+    ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=2, pcg_tol=1e-14, pcg_maxit=3)
+    g = gpu_initial_state(ctx, cfg)
+    with pytest.raises(tdfe.TdfeError) as e:
+        ctx.magnus_step(g, cfg.dt, 0.0, 1e-12)
+    assert e.value.status == tdfe.ENOCONV and "CG" in str(e.value)
+
+
 def test_magnus_with_field_matches_oracle():
     cfg = _cfg2_small(n_orb=2)
     ctx = gpu_context(cfg, n_orb=2)
