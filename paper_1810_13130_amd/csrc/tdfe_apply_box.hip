@@ -26,14 +26,17 @@ namespace {
 
 constexpr int EO_MAX_H = 5;  // (9 + 1) / 2
 
-// folded form of one N x N matrix with reflection symmetry S (+1 or -1)
+// folded form of one N x N matrix with reflection symmetry S (+1 or -1), in the
+// kernel's working precision (no conversions at the point of use)
+template <typename T>
 struct Folded {
-  double E[EO_MAX_H * EO_MAX_H];  // (A[a][i] + A[a][N-1-i]) / 2, a, i < H
-  double O[EO_MAX_H * EO_MAX_H];  // (A[a][i] - A[a][N-1-i]) / 2
-  double mc[EO_MAX_H];            // A[a][H] (odd N)
-  double mr[EO_MAX_H + 1];        // A[H][i], i <= H (odd N)
+  T E[EO_MAX_H * EO_MAX_H];  // (A[a][i] + A[a][N-1-i]) / 2, a, i < H
+  T O[EO_MAX_H * EO_MAX_H];  // (A[a][i] - A[a][N-1-i]) / 2
+  T mc[EO_MAX_H];            // A[a][H] (odd N)
+  T mr[EO_MAX_H + 1];        // A[H][i], i <= H (odd N)
 };
 
+template <typename T>
 struct PlaneParams {
   const void* x;
   void* y;
@@ -52,8 +55,32 @@ struct PlaneParams {
   int64_t n_cell;
   int lowdin, fullgrid;
   double wq[TDFE_MAXN];
-  Folded fB, fBt, fD, fDt, fG, fGt;  // B, B^T, D, D^T, Dg, Dg^T
+  T w2[sizeof(T) == 4 ? TDFE_MAXN * TDFE_MAXN : 1];  // wq[b] wq[c] (FP32 kernels)
+  Folded<T> fB, fBt, fD, fDt, fG, fGt;               // B, B^T, D, D^T, Dg, Dg^T
 };
+
+// quadratic form: FP32 kernels sum each line in FP32 and promote the line
+// sums; FP64 kernels accumulate directly
+template <typename T>
+__device__ __forceinline__ void acc_energy(double& e, T& line, T v) {
+  if constexpr (sizeof(T) == 4)
+    line += v;
+  else
+    e += v;
+}
+template <typename T>
+__device__ __forceinline__ void flush_energy(double& e, T line) {
+  if constexpr (sizeof(T) == 4) e += (double)line;
+}
+
+// product of two 1D Gauss weights in the kernel's precision
+template <typename T>
+__device__ __forceinline__ T wprod(const PlaneParams<T>& P, int b, int c) {
+  if constexpr (sizeof(T) == 4)
+    return P.w2[b * TDFE_MAXN + c];
+  else
+    return P.wq[b] * P.wq[c];
+}
 
 __device__ __forceinline__ int remap_block(int p, int G) {
   if ((G & 7) == 0) return (p & 7) * (G >> 3) + (p >> 3);
@@ -62,7 +89,7 @@ __device__ __forceinline__ int remap_block(int p, int G) {
 
 // out[a] = sum_i A[a][i] in[i] by even/odd folding; A given folded, symmetry S
 template <typename T, int N, int S>
-__device__ __forceinline__ void eo(const Folded& F, const T* in, T* out) {
+__device__ __forceinline__ void eo(const Folded<T>& F, const T* in, T* out) {
   constexpr int H = N / 2;
   T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
 #pragma unroll
@@ -75,10 +102,10 @@ __device__ __forceinline__ void eo(const Folded& F, const T* in, T* out) {
     T Pv = 0, Qv = 0;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      Pv += (T)F.E[a * EO_MAX_H + i] * e[i];
-      Qv += (T)F.O[a * EO_MAX_H + i] * o[i];
+      Pv += F.E[a * EO_MAX_H + i] * e[i];
+      Qv += F.O[a * EO_MAX_H + i] * o[i];
     }
-    if constexpr (N & 1) Pv += (T)F.mc[a] * in[H];
+    if constexpr (N & 1) Pv += F.mc[a] * in[H];
     out[a] = Pv + Qv;
     out[N - 1 - a] = S > 0 ? Pv - Qv : Qv - Pv;
   }
@@ -86,11 +113,11 @@ __device__ __forceinline__ void eo(const Folded& F, const T* in, T* out) {
     T m = 0;
     if constexpr (S > 0) {
 #pragma unroll
-      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * e[i];
-      m += (T)F.mr[H] * in[H];
+      for (int i = 0; i < H; ++i) m += F.mr[i] * e[i];
+      m += F.mr[H] * in[H];
     } else {
 #pragma unroll
-      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * o[i];
+      for (int i = 0; i < H; ++i) m += F.mr[i] * o[i];
     }
     out[H] = m;
   }
@@ -98,7 +125,7 @@ __device__ __forceinline__ void eo(const Folded& F, const T* in, T* out) {
 
 // two matrices on the same input line share the fold
 template <typename T, int N, int S1, int S2>
-__device__ __forceinline__ void eo2(const Folded& F1, const Folded& F2, const T* in, T* out1, T* out2) {
+__device__ __forceinline__ void eo2(const Folded<T>& F1, const Folded<T>& F2, const T* in, T* out1, T* out2) {
   eo<T, N, S1>(F1, in, out1);
   eo<T, N, S2>(F2, in, out2);
 }
@@ -107,15 +134,25 @@ __device__ __forceinline__ void eo2(const Folded& F1, const Folded& F2, const T*
 // lane, so they run one wave per SIMD and use the accumulation registers
 template <typename T, int N>
 constexpr int plane_wpe() {
-  return (sizeof(T) == 8 && N >= 6) ? 1 : 2;
+  return sizeof(T) == 4 ? (N == 5 || N == 6 ? 3 : 2) : (N >= 6 ? 1 : 2);
+}
+
+// hold both transposed arrays in LDS at once (fewer barriers) instead of
+// passing them through one buffer in turn; measured slower on both precisions
+// at n = 6 (more live registers), kept selectable
+template <typename T, int N>
+constexpr bool plane_two_buffers() {
+  return false;
 }
 
 template <typename T, int N, int CB, int CPB>
 __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_eu(plane_wpe<T, N>())))
-    plane_kernel(PlaneParams P) {
+    plane_kernel(PlaneParams<T> P) {
   constexpr int VOL = N * N * N;
   constexpr int THREADS = CPB * N * CB;
+  constexpr bool TWO = plane_two_buffers<T, N>();
   __shared__ T sX[CPB * VOL * CB];
+  __shared__ T sY[TWO ? CPB * VOL * CB : 1];
   __shared__ T sV[CPB * VOL];  // weighted potential of the block's cells
   __shared__ double sRed[THREADS];
   if (P.done && *P.done) return;
@@ -239,26 +276,45 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   }
   // ---------------- transpose: (j; a, c) -> (a; j, c) ------------------------------------
   T v[N][N], w[N][N];  // [y][z] at x point a = pl
+  if constexpr (TWO) {
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tu[a][c];
-  __syncthreads();
+      for (int c = 0; c < N; ++c) {
+        sX[sidx(pl, a, c)] = tu[a][c];
+        sY[sidx(pl, a, c)] = tx[a][c];
+      }
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < N; ++j)
+    for (int j = 0; j < N; ++j)
 #pragma unroll
-    for (int c = 0; c < N; ++c) v[j][c] = sX[sidx(j, pl, c)];
-  __syncthreads();
+      for (int c = 0; c < N; ++c) {
+        v[j][c] = sX[sidx(j, pl, c)];
+        w[j][c] = sY[sidx(j, pl, c)];
+      }
+    __syncthreads();
+  } else {
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tx[a][c];
-  __syncthreads();
+      for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tu[a][c];
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < N; ++j)
+    for (int j = 0; j < N; ++j)
 #pragma unroll
-    for (int c = 0; c < N; ++c) w[j][c] = sX[sidx(j, pl, c)];
-  __syncthreads();
+      for (int c = 0; c < N; ++c) v[j][c] = sX[sidx(j, pl, c)];
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < N; ++a)
+#pragma unroll
+      for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tx[a][c];
+    __syncthreads();
+#pragma unroll
+    for (int j = 0; j < N; ++j)
+#pragma unroll
+      for (int c = 0; c < N; ++c) w[j][c] = sX[sidx(j, pl, c)];
+    __syncthreads();
+  }
 
   // ---------------- B: plane a = pl, quadrature values (b, c) --------------------------------
   double energy = 0.0;
@@ -278,12 +334,14 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int j = 0; j < N; ++j) l[j] = w[j][c];
     eo<T, N, 1>(P.fB, l, o);  // u_x at (pl, b, c)
+    T le = 0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      const T f = gx * (T)(P.wq[b] * P.wq[c]) * o[b];
-      energy += (double)f * (double)o[b];
+      const T f = gx * wprod(P, b, c) * o[b];
+      acc_energy<T>(energy, le, f * o[b]);
       o[b] = f;
     }
+    flush_energy<T>(energy, le);
     eo<T, N, 1>(P.fBt, o, l);
 #pragma unroll
     for (int j = 0; j < N; ++j) sX[sidx(j, pl, c)] = l[j];
@@ -299,13 +357,15 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int j = 0; j < N; ++j) l[j] = v[j][c];
       eo<T, N, 1>(P.fB, l, o);
+      T le = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
         uq[b][c] = o[b];
         const T pot = havev ? sV[slot * VOL + pl + N * (b + N * c)] * o[b] : (T)0;
-        energy += (double)pot * (double)o[b];
+        acc_energy<T>(energy, le, pot * o[b]);
         acc[b][c] = pot;
       }
+      flush_energy<T>(energy, le);
       // keep the potential reads of later lines from being hoisted here
       __builtin_amdgcn_sched_barrier(0);
     }
@@ -314,12 +374,14 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     for (int b = 0; b < N; ++b) {
       T d[N], r[N];
       eo<T, N, -1>(P.fG, uq[b], d);
+      T le = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        const T f = gz * (T)(P.wq[b] * P.wq[c]) * d[c];
-        energy += (double)f * (double)d[c];
+        const T f = gz * wprod(P, b, c) * d[c];
+        acc_energy<T>(energy, le, f * d[c]);
         d[c] = f;
       }
+      flush_energy<T>(energy, le);
       eo<T, N, -1>(P.fGt, d, r);
 #pragma unroll
       for (int c = 0; c < N; ++c) acc[b][c] += r[c];
@@ -331,18 +393,25 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int b = 0; b < N; ++b) l[b] = uq[b][c];
       eo<T, N, -1>(P.fG, l, d);
+      T le = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        const T f = gy * (T)(P.wq[b] * P.wq[c]) * d[b];
-        energy += (double)f * (double)d[b];
+        const T f = gy * wprod(P, b, c) * d[b];
+        acc_energy<T>(energy, le, f * d[b]);
         d[b] = f;
       }
+      flush_energy<T>(energy, le);
       eo<T, N, -1>(P.fGt, d, r);
 #pragma unroll
       for (int b = 0; b < N; ++b) r[b] += acc[b][c];
       eo<T, N, 1>(P.fBt, r, l);
+      if constexpr (TWO) {
 #pragma unroll
-      for (int j = 0; j < N; ++j) s[j][c] = l[j];
+        for (int j = 0; j < N; ++j) sY[sidx(j, pl, c)] = l[j];
+      } else {
+#pragma unroll
+        for (int j = 0; j < N; ++j) s[j][c] = l[j];
+      }
     }
   }
   // ---------------- transposes: (a; j, c) -> (j; a, c) ----------------------------------------
@@ -350,22 +419,24 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   // compiler sinks its whole accumulation chain into the final reduction and
   // keeps every partial product alive across phase C
   sRed[t] = act ? energy : 0.0;
-  T s2[N][N], sx2[N][N];  // [x point a][z point c] at node plane j = pl
+  T s2[N][N], sx2[N][N];  // [x point a][z point c] at node plane j = pl (one-buffer blocks)
   __syncthreads();
+  if constexpr (!TWO) {
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int c = 0; c < N; ++c) sx2[a][c] = sX[sidx(pl, a, c)];
-  __syncthreads();
+      for (int c = 0; c < N; ++c) sx2[a][c] = sX[sidx(pl, a, c)];
+    __syncthreads();
 #pragma unroll
-  for (int j = 0; j < N; ++j)
+    for (int j = 0; j < N; ++j)
 #pragma unroll
-    for (int c = 0; c < N; ++c) sX[sidx(j, pl, c)] = s[j][c];
-  __syncthreads();
+      for (int c = 0; c < N; ++c) sX[sidx(j, pl, c)] = s[j][c];
+    __syncthreads();
 #pragma unroll
-  for (int a = 0; a < N; ++a)
+    for (int a = 0; a < N; ++a)
 #pragma unroll
-    for (int c = 0; c < N; ++c) s2[a][c] = sX[sidx(pl, a, c)];
+      for (int c = 0; c < N; ++c) s2[a][c] = sX[sidx(pl, a, c)];
+  }
 
   // ---------------- C: plane j = pl: x then z transposed, scatter ------------------------------
   {
@@ -376,8 +447,13 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       T l1[N], l2[N], o1[N], o2[N];
 #pragma unroll
       for (int a = 0; a < N; ++a) {
-        l1[a] = s2[a][c];
-        l2[a] = sx2[a][c];
+        if constexpr (TWO) {
+          l1[a] = sY[sidx(pl, a, c)];
+          l2[a] = sX[sidx(pl, a, c)];
+        } else {
+          l1[a] = s2[a][c];
+          l2[a] = sx2[a][c];
+        }
       }
       eo<T, N, 1>(P.fBt, l1, o1);
       eo<T, N, -1>(P.fDt, l2, o2);
@@ -442,31 +518,44 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 // ----------------------------------------------------------------------------------------------
 // host side
 // ----------------------------------------------------------------------------------------------
-void fold(const double* A, int N, int S, bool transpose, Folded& F) {
+template <typename T>
+void fold(const double* A, int N, int S, bool transpose, Folded<T>& F) {
   auto at = [&](int a, int i) { return transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i]; };
   const int H = N / 2;
   for (int a = 0; a < H; ++a)
     for (int i = 0; i < H; ++i) {
-      F.E[a * EO_MAX_H + i] = 0.5 * (at(a, i) + at(a, N - 1 - i));
-      F.O[a * EO_MAX_H + i] = 0.5 * (at(a, i) - at(a, N - 1 - i));
+      F.E[a * EO_MAX_H + i] = (T)(0.5 * (at(a, i) + at(a, N - 1 - i)));
+      F.O[a * EO_MAX_H + i] = (T)(0.5 * (at(a, i) - at(a, N - 1 - i)));
     }
   if (N & 1) {
-    for (int a = 0; a < H; ++a) F.mc[a] = at(a, H);
-    for (int i = 0; i <= H; ++i) F.mr[i] = at(H, i);
-    if (S < 0) F.mr[H] = 0.0;
+    for (int a = 0; a < H; ++a) F.mc[a] = (T)at(a, H);
+    for (int i = 0; i <= H; ++i) F.mr[i] = (T)at(H, i);
+    if (S < 0) F.mr[H] = (T)0;
   }
 }
 
-template <int N, int CB>
+// LDS bytes of one block of cpb cells
+template <typename T, int N, int CB>
+constexpr int plane_lds(int cpb) {
+  constexpr int VOL = N * N * N;
+  return cpb * VOL * CB * (int)sizeof(T) * (plane_two_buffers<T, N>() ? 2 : 1) + cpb * VOL * (int)sizeof(T) +
+         cpb * N * CB * 8;
+}
+
+// cells per block: at most 512 threads, and LDS small enough for the
+// occupancy plane_wpe asks for (an FP64 block must also fit one CU at one wave
+// per SIMD: at most four waves)
+template <typename T, int N, int CB>
 constexpr int plane_cpb() {
+  constexpr int budget = sizeof(T) == 8 ? 64 * 1024 : 40 * 1024;
   int cpb = 1;
-  while (cpb * 2 * N * CB <= 512 && (cpb * 2) * N * N * N * CB * 8 <= 64 * 1024) cpb *= 2;
+  while (cpb * 2 * N * CB <= 512 && plane_lds<T, N, CB>(cpb * 2) <= budget) cpb *= 2;
   return cpb;
 }
 
 template <typename T, int N, int CB>
-tdfe_status launch_plane(tdfe_ctx* c, PlaneParams& P, int64_t* groups_out) {
-  constexpr int CPB = plane_cpb<N, CB>();
+tdfe_status launch_plane(tdfe_ctx* c, PlaneParams<T>& P, int64_t* groups_out) {
+  constexpr int CPB = plane_cpb<T, N, CB>();
   const int64_t groups = (c->n_cell + CPB - 1) / CPB;
   P.nchunks = (P.cols + CB - 1) / CB;
   if (groups_out) *groups_out = groups;
@@ -477,7 +566,7 @@ tdfe_status launch_plane(tdfe_ctx* c, PlaneParams& P, int64_t* groups_out) {
 }
 
 template <typename T, int N>
-tdfe_status launch_plane_n(tdfe_ctx* c, PlaneParams& P, int64_t* g) {
+tdfe_status launch_plane_n(tdfe_ctx* c, PlaneParams<T>& P, int64_t* g) {
   if (P.cols <= 1) return launch_plane<T, N, 1>(c, P, g);
   if (P.cols <= 2) return launch_plane<T, N, 2>(c, P, g);
   if (P.cols <= 4) return launch_plane<T, N, 4>(c, P, g);
@@ -486,7 +575,7 @@ tdfe_status launch_plane_n(tdfe_ctx* c, PlaneParams& P, int64_t* g) {
 }
 
 template <typename T>
-tdfe_status launch_plane_p(tdfe_ctx* c, PlaneParams& P, int64_t* g) {
+tdfe_status launch_plane_p(tdfe_ctx* c, PlaneParams<T>& P, int64_t* g) {
   switch (c->n) {
     case 2: return launch_plane_n<T, 2>(c, P, g);
     case 3: return launch_plane_n<T, 3>(c, P, g);
@@ -499,13 +588,11 @@ tdfe_status launch_plane_p(tdfe_ctx* c, PlaneParams& P, int64_t* g) {
   return tdfe_fail(c, TDFE_EINVAL, "box operator: unsupported order p=%d", c->p);
 }
 
-}  // namespace
 
-// true if the box kernel handles this context (rectilinear mesh, p <= 7)
-bool tdfe_box_kernel_ok(const tdfe_ctx* c) { return c->box && c->n <= 8; }
-
-tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a) {
-  PlaneParams P{};
+template <typename T>
+tdfe_status launch_box(tdfe_ctx* c, const ApplyArgs& a) {
+  static_assert(sizeof(PlaneParams<T>) <= 4096, "kernel arguments exceed 4 KB");
+  PlaneParams<T> P{};
   P.x = a.x;
   P.y = a.y;
   P.ld = a.ld;
@@ -532,13 +619,24 @@ tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a) {
   P.fullgrid = a.fullgrid;
   const int N = c->n;
   for (int i = 0; i < N; ++i) P.wq[i] = c->wq[i];
+  if constexpr (sizeof(T) == 4)
+    for (int b = 0; b < N; ++b)
+      for (int q = 0; q < N; ++q) P.w2[b * TDFE_MAXN + q] = (T)(c->wq[b] * c->wq[q]);
   fold(c->B, N, 1, false, P.fB);
   fold(c->B, N, 1, true, P.fBt);
   fold(c->D, N, -1, false, P.fD);
   fold(c->D, N, -1, true, P.fDt);
   fold(c->Dg, N, -1, false, P.fG);
   fold(c->Dg, N, -1, true, P.fGt);
+  return launch_plane_p<T>(c, P, a.n_blocks_out);
+}
+
+}  // namespace
+
+// true if the box kernel handles this context (rectilinear mesh, p <= 7)
+bool tdfe_box_kernel_ok(const tdfe_ctx* c) { return c->box && c->n <= 8; }
+
+tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a) {
   if (a.cols < 1) return tdfe_fail(c, TDFE_EINVAL, "apply: cols < 1");
-  if (a.fp32) return launch_plane_p<float>(c, P, a.n_blocks_out);
-  return launch_plane_p<double>(c, P, a.n_blocks_out);
+  return a.fp32 ? launch_box<float>(c, a) : launch_box<double>(c, a);
 }

@@ -17,8 +17,106 @@ struct ChebLds {
   double bufA[TDFE_KCAP], bufB[TDFE_KCAP];
   double yr[TDFE_KCAP], yi[TDFE_KCAP];
   double red[3 * TDFE_CHEB_THREADS];
+  double inv;  // normalisation of the Bessel table
   int M;
 };
+
+// Bessel values J_0..J_M(z) into J (by the calling lane); returns M or -1.
+// Miller's backward recurrence runs in registers (the table is only written);
+// the values are left unnormalised and *inv receives 1 / (J_0 + 2 sum J_2m),
+// which callers apply to the Chebyshev coefficients.
+__device__ inline int cheb_bessel(double z, double* J, double* inv) {
+  int M = 0;
+  if (z > 1e-300) {
+    M = (int)ceil(z + 10.0 * cbrt(z) + 20.0);
+    int ms = M + 20 + (int)(2.0 * sqrt((double)M));
+    ms += ms & 1;
+    if (ms + 1 > TDFE_MAX_BESSEL) return -1;
+    double jp = 0.0, jc = 1e-300;  // J_{m+1}, J_m
+    J[ms + 1] = jp;
+    J[ms] = jc;
+    double even = jc;  // sum of J_2m for 2m >= 2 (ms is even)
+    const double tz = 2.0 / z;
+    for (int m = ms; m > 0; --m) {
+      const double jm1 = (m * tz) * jc - jp;
+      J[m - 1] = jm1;
+      if (((m - 1) & 1) == 0 && m - 1 > 0) even += jm1;
+      jp = jc;
+      jc = jm1;
+      if (fabs(jm1) > 1e250) {  // rescale what has been produced so far
+        for (int q = m - 1; q <= ms + 1; ++q) J[q] *= 1e-250;
+        jp *= 1e-250;
+        jc *= 1e-250;
+        even *= 1e-250;
+      }
+    }
+    *inv = 1.0 / (jc + 2.0 * even);  // jc = J_0
+  } else {
+    J[0] = 1.0;
+    *inv = 1.0;
+  }
+  return M;
+}
+
+// Same result for k <= TDFE_CHEB_THREADS, one row per lane of a single
+// wavefront: the Chebyshev vectors stay in registers and the tridiagonal
+// neighbours come from cross-lane shuffles, so a term costs no LDS round trip.
+// Lane j returns row j of y in (yr, yi) (zero for j >= k).
+__device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* sb, double s, ChebLds& L, double& yr,
+                                        double& yi, double* amax) {
+  const int t = threadIdx.x;
+  const bool row = t < k;
+  const double a = row ? sa[t] : 0.0;
+  const double bl = (row && t > 0) ? sb[t - 1] : 0.0;
+  const double br = (row && t < k - 1) ? sb[t] : 0.0;
+  double lo = row ? a - fabs(bl) - fabs(br) : 1e300;
+  double hi = row ? a + fabs(bl) + fabs(br) : -1e300;
+  double am = row ? fabs(a) : 0.0;
+  for (int off = TDFE_CHEB_THREADS / 2; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    am = fmax(am, __shfl_xor(am, off));
+  }
+  *amax = am;
+  const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
+  const double z = fabs(s) * rr;
+  if (t == 0) L.M = cheb_bessel(z, L.J, &L.inv);
+  __syncthreads();
+  const int M = L.M;
+  const double jn = L.inv;
+  yr = 0.0;
+  yi = 0.0;
+  if (M < 0) return -1;
+  const double sgn = s >= 0.0 ? 1.0 : -1.0;
+  const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
+  const double ac = row ? a - cc : 0.0;
+  double vp = (t == 0) ? 1.0 : 0.0;
+  yr = jn * L.J[0] * vp;
+  if (M >= 1) {
+    double left = __shfl_up(vp, 1), right = __shfl_down(vp, 1);
+    double vc = (ac * vp + bl * left + br * right) * invr;
+    yi += -2.0 * sgn * jn * L.J[1] * vc;
+    for (int mm = 2; mm <= M; ++mm) {
+      left = __shfl_up(vc, 1);
+      right = __shfl_down(vc, 1);
+      const double w = ac * vc + bl * left + br * right;
+      const double vn = 2.0 * w * invr - vp;
+      vp = vc;
+      vc = vn;
+      const double cj = 2.0 * jn * L.J[mm];
+      const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
+      if (ph == 0) yr += cj * vn;
+      else if (ph == 1) yi -= sgn * cj * vn;
+      else if (ph == 2) yr -= cj * vn;
+      else yi += sgn * cj * vn;
+    }
+  }
+  const double pr = cos(s * cc), pim = -sin(s * cc);
+  const double a0 = yr, b0 = yi;
+  yr = a0 * pr - b0 * pim;
+  yi = a0 * pim + b0 * pr;
+  return M;
+}
 
 // returns the number of terms M (>= 0) or -1 if |s| r exceeds the Bessel table;
 // *amax receives max_j |sa[j]|
@@ -50,42 +148,16 @@ __device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, do
   *amax = L.red[2 * TDFE_CHEB_THREADS];
   const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
   const double z = fabs(s) * rr;
-  if (t == 0) {
-    int M = 0;
-    if (z > 1e-300) {
-      M = (int)ceil(z + 10.0 * cbrt(z) + 20.0);
-      int ms = M + 20 + (int)(2.0 * sqrt((double)M));
-      ms += ms & 1;
-      if (ms + 1 > TDFE_MAX_BESSEL) {
-        M = -1;
-      } else {
-        L.J[ms + 1] = 0.0;
-        L.J[ms] = 1e-300;
-        const double tz = 2.0 / z;
-        for (int m = ms; m > 0; --m) {
-          const double jm1 = (m * tz) * L.J[m] - L.J[m + 1];
-          L.J[m - 1] = jm1;
-          if (fabs(jm1) > 1e250)
-            for (int q = m - 1; q <= ms + 1; ++q) L.J[q] *= 1e-250;
-        }
-        double norm = L.J[0];
-        for (int m = 2; m <= ms; m += 2) norm += 2.0 * L.J[m];
-        const double inv = 1.0 / norm;
-        for (int m = 0; m <= M; ++m) L.J[m] *= inv;
-      }
-    } else {
-      L.J[0] = 1.0;
-    }
-    L.M = M;
-  }
+  if (t == 0) L.M = cheb_bessel(z, L.J, &L.inv);
   __syncthreads();
   const int M = L.M;
+  const double jn = L.inv;
   if (M < 0) return -1;
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
   for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
     L.bufA[j] = (j == 0) ? 1.0 : 0.0;
-    L.yr[j] = L.J[0] * L.bufA[j];
+    L.yr[j] = jn * L.J[0] * L.bufA[j];
     L.yi[j] = 0.0;
   }
   __syncthreads();
@@ -98,11 +170,11 @@ __device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, do
       if (j < k - 1) w += sb[j] * prev[j + 1];
       w *= invr;
       cur[j] = w;
-      L.yi[j] += -2.0 * sgn * L.J[1] * w;
+      L.yi[j] += -2.0 * sgn * jn * L.J[1] * w;
     }
     __syncthreads();
     for (int mm = 2; mm <= M; ++mm) {
-      const double cj = 2.0 * L.J[mm];
+      const double cj = 2.0 * jn * L.J[mm];
       const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
       for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
         double w = (sa[j] - cc) * cur[j];

@@ -64,7 +64,7 @@ struct tdfe_ctx {
   double* cload = nullptr;    // [n_nodes] load vector c_j
   double* fb = nullptr;       // [n_nodes] boundary values f (0 inside)
   double* lift = nullptr;     // [n_dof] (K f)_interior
-  double* fdmS = nullptr;     // 1D eigenvector matrices Sx, Sy, Sz (row-major, n1 x n1)
+  double* fdmS = nullptr;     // 1D eigenvector matrices Sx, Sy, Sz (row-major, n1 x n1), then their transposes
   double* fdmL = nullptr;     // 1D eigenvalues
   double* t0 = nullptr;       // [n_dof] scratch
   double* t1 = nullptr;       // [n_dof] scratch
@@ -81,7 +81,7 @@ struct tdfe_ctx {
 
   // host pinned poll buffer
   int* poll = nullptr;
-  hipEvent_t* evs = nullptr;
+  hipEvent_t* evs = nullptr;  // [TDFE_N_EVENTS] look-ahead polling points
   int n_evs = 0;
 
   // ---- state -------------------------------------------------------------------

@@ -178,49 +178,77 @@ __global__ void __launch_bounds__(RED_THREADS)
 // small exponential and adaptive stop, one wavefront per orbital
 // ---------------------------------------------------------------------------------------------
 __global__ void __launch_bounds__(CHK_THREADS)
-    check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, int* err_flag) {
+    check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, int* err_flag, int* host_flag) {
   __shared__ ChebLds L;
   __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
-  if (*S.done) return;
   const int o = blockIdx.x;
-  if (S.status[o] != 0) return;
   const int t = threadIdx.x;
+  if (*S.done || S.status[o] != 0) return;
   for (int j = t; j < k; j += CHK_THREADS) {
     sa[j] = S.alpha[(size_t)j * Nc + o];
     sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
   }
   __syncthreads();
   double amax = 0.0;
-  const int M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
+  double ylr = 0.0, yli = 0.0, yr = 0.0, yi = 0.0;
+  int M;
+  if (k <= CHK_THREADS) {
+    M = cheb_expm_e1_wave(k, sa, sb, tau, L, yr, yi, &amax);
+    ylr = __shfl(yr, k - 1);
+    yli = __shfl(yi, k - 1);
+  } else {
+    M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
+    ylr = L.yr[k - 1];
+    yli = L.yi[k - 1];
+  }
+  int fin = 0;
   if (M < 0) {
     if (t == 0) {
       S.status[o] = 3;
       atomicOr(err_flag, 1);
-      if (atomicAdd(S.nconv, 1) + 1 == Nc) *S.done = 1;
+      if (atomicAdd(S.nconv, 1) + 1 == Nc) {
+        *S.done = 1;
+        fin = 1;
+      }
     }
-    return;
-  }
-  const double bk = sb[k - 1];
-  const double eps = fabs(tau) * bk * S.nrm[o] * sqrt(L.yr[k - 1] * L.yr[k - 1] + L.yi[k - 1] * L.yi[k - 1]);
-  const bool happy = bk <= 1e-14 * amax;
-  const bool conv = (eps <= tol) || happy;
-  const bool stop = conv || k >= k_max;
-  if (stop) {
-    for (int j = t; j < k; j += CHK_THREADS) {
-      S.y[((size_t)o * k_max + j) * 2 + 0] = L.yr[j];
-      S.y[((size_t)o * k_max + j) * 2 + 1] = L.yi[j];
-    }
-  }
-  if (t == 0) {
-    S.err[o] = eps;
+  } else {
+    const double bk = sb[k - 1];
+    const double eps = fabs(tau) * bk * S.nrm[o] * sqrt(ylr * ylr + yli * yli);
+    const bool happy = bk <= 1e-14 * amax;
+    const bool conv = (eps <= tol) || happy;
+    const bool stop = conv || k >= k_max;
     if (stop) {
-      S.kconv[o] = k;
-      S.status[o] = conv ? 1 : 2;
-      S.scale[(size_t)k * Nc + o] = 0.0;
-      if (atomicAdd(S.nconv, 1) + 1 == Nc) *S.done = 1;
-    } else {
-      S.scale[(size_t)k * Nc + o] = 1.0 / bk;
+      if (k <= CHK_THREADS) {
+        if (t < k) {
+          S.y[((size_t)o * k_max + t) * 2 + 0] = yr;
+          S.y[((size_t)o * k_max + t) * 2 + 1] = yi;
+        }
+      } else {
+        for (int j = t; j < k; j += CHK_THREADS) {
+          S.y[((size_t)o * k_max + j) * 2 + 0] = L.yr[j];
+          S.y[((size_t)o * k_max + j) * 2 + 1] = L.yi[j];
+        }
+      }
     }
+    if (t == 0) {
+      S.err[o] = eps;
+      if (stop) {
+        S.kconv[o] = k;
+        S.status[o] = conv ? 1 : 2;
+        S.scale[(size_t)k * Nc + o] = 0.0;  // freezes the orbital in later operator passes
+        if (atomicAdd(S.nconv, 1) + 1 == Nc) {
+          *S.done = 1;
+          fin = 1;
+        }
+      }
+    }
+  }
+  // the orbital that completes the set raises the host-visible flag (pinned
+  // memory, cleared by the host before the run); the host reads it once an
+  // iteration's event has completed
+  if (fin && host_flag) {
+    *host_flag = 1;
+    __threadfence_system();
   }
 }
 
@@ -262,12 +290,16 @@ __global__ void init_scal_kernel(Scal S, int Nc) {
 }
 
 // orbitals with zero norm are finished before the first iteration
-__global__ void zero_norm_kernel(Scal S, int Nc) {
+__global__ void zero_norm_kernel(Scal S, int Nc, int* host_flag) {
   const int o = threadIdx.x;
   if (o < Nc && !(S.nrm[o] > 0.0)) {
     S.status[o] = 1;
     S.kconv[o] = 0;
-    if (atomicAdd(S.nconv, 1) + 1 == Nc) *S.done = 1;
+    if (atomicAdd(S.nconv, 1) + 1 == Nc) {
+      *S.done = 1;
+      *host_flag = 1;
+      __threadfence_system();
+    }
   }
 }
 
@@ -296,7 +328,13 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                      c->partial);
   hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
                      (int64_t)RED_BLOCKS, C, S.nrm, 2, S.scale, (const int*)nullptr);
-  hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc);
+  // host-visible copy of the done flag (pinned memory; all earlier work on the
+  // stream has completed, so nothing else writes it now)
+  volatile int* hflag = c->poll + 32;
+  *hflag = 0;
+  int* dflag = nullptr;
+  TDFE_HIP(c, hipHostGetDevicePointer((void**)&dflag, (void*)(c->poll + 32), 0));
+  hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc, dflag);
   TDFE_HIP(c, hipGetLastError());
 
   const int LOOK = 2;
@@ -331,17 +369,18 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                        S.beta + (size_t)(k >= 2 ? k - 2 : 0) * Nc, S.scale + (size_t)(k - 1) * Nc,
                        S.scale + (size_t)(k >= 2 ? k - 2 : 0) * Nc, (const int*)S.status, k >= 2 ? 1 : 0, c->partial,
                        (const int*)S.done);
+    // beta_k and the scale 1/beta_k of the next basis vector
     hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
-                       (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 1, (double*)nullptr,
+                       (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 2, S.scale + (size_t)k * Nc,
                        (const int*)S.done);
-    hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, err_flag);
+    hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, err_flag,
+                       dflag);
     TDFE_HIP(c, hipGetLastError());
-    TDFE_HIP(c, hipMemcpyAsync(c->poll + (k % RING), S.done, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     TDFE_HIP(c, hipEventRecord(c->evs[k % RING], c->stream));
     if (k > LOOK) {
       const int kk = k - LOOK;
       TDFE_HIP(c, hipEventSynchronize(c->evs[kk % RING]));
-      if (c->poll[kk % RING]) break;
+      if (*hflag) break;
     }
   }
   if (hook)
@@ -377,7 +416,9 @@ tdfe_status tdfe_poll_events(tdfe_ctx* c) {
   c->evs = new hipEvent_t[TDFE_N_EVENTS];
   c->n_evs = 0;
   for (int i = 0; i < TDFE_N_EVENTS; ++i) {
-    TDFE_HIP(c, hipEventCreateWithFlags(&c->evs[i], hipEventDisableTiming));
+    // host-side completion only: the flags the host reads are written by the
+    // kernels themselves with a system-scope fence
+    TDFE_HIP(c, hipEventCreateWithFlags(&c->evs[i], hipEventDisableTiming | hipEventDisableSystemFence));
     c->n_evs = i + 1;
   }
   return TDFE_OK;

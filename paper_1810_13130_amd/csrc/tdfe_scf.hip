@@ -144,18 +144,35 @@ __global__ void __launch_bounds__(N* N* CB) density_kernel(DensParams P) {
     mz += w * P.xq[g * 3 + 2];
   }
   double vals[4] = {ch, mx, my, mz};
-  constexpr int PW = pow2_floor(T);
-  for (int v = 0; v < 4; ++v) {
-    sred[t] = vals[v];
+  if constexpr (T % 64 == 0) {
+    // whole wavefronts: lane shuffles, then one pass over the block's waves (fixed order)
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      for (int off = 32; off > 0; off >>= 1) vals[v] += __shfl_xor(vals[v], off);
+    constexpr int NW = T / 64;
+    if ((t & 63) == 0)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sred[(t >> 6) * 4 + v] = vals[v];
     __syncthreads();
-    if (t < T - PW) sred[t] += sred[t + PW];  // fold the part beyond the largest power of two
-    __syncthreads();
-    for (int s = PW / 2; s > 0; s >>= 1) {
-      if (t < s) sred[t] += sred[t + s];
+    if (t < 4) {
+      double acc = 0.0;
+      for (int w = 0; w < NW; ++w) acc += sred[w * 4 + t];
+      P.partial[cell * 4 + t] = acc;
+    }
+  } else {
+    constexpr int PW = pow2_floor(T);
+    for (int v = 0; v < 4; ++v) {
+      sred[t] = vals[v];
+      __syncthreads();
+      if (t < T - PW) sred[t] += sred[t + PW];  // fold the part beyond the largest power of two
+      __syncthreads();
+      for (int s = PW / 2; s > 0; s >>= 1) {
+        if (t < s) sred[t] += sred[t + s];
+        __syncthreads();
+      }
+      if (t == 0) P.partial[cell * 4 + v] = sred[0];
       __syncthreads();
     }
-    if (t == 0) P.partial[cell * 4 + v] = sred[0];
-    __syncthreads();
   }
 }
 
@@ -371,6 +388,131 @@ __global__ void scatter_interior_kernel(const double* in, double* full, int Nx, 
   full[node] = in[d];
 }
 
+// Register-tiled form of the same transform: a block stages FDM_TB lines and
+// the whole 1D matrix R (R = S for the transposed product, S^T otherwise) in
+// LDS; wavefront g (of FDM_G) owns output modes [g MPT, g MPT + MPT) and sweeps
+// the input modes once, reading row m of R at a wave-uniform address (an LDS
+// broadcast).  lam scaling is supported along z only.
+constexpr int FDM_TB = 64, FDM_G = 4;
+// rows of R are padded with zeros to FDM_G * MPT entries, so the inner loop needs no bounds test
+inline size_t fdm_tile_lds(int nax, int mpt) {
+  return ((size_t)nax * FDM_G * mpt + (size_t)nax * FDM_TB) * sizeof(double);
+}
+template <int MPT>
+__global__ void __launch_bounds__(FDM_TB* FDM_G) fdm_tile_kernel(const double* __restrict__ in, double* __restrict__ out,
+                                                                 const double* __restrict__ R, int n1x, int n1y,
+                                                                 int n1z, int axis, const double* lx, const double* ly,
+                                                                 const double* lz) {
+  extern __shared__ double lds[];
+  const int nax = axis == 0 ? n1x : (axis == 1 ? n1y : n1z);
+  constexpr int RP = FDM_G * MPT;
+  double* sR = lds;                        // [nax][RP], zero beyond column nax
+  double* tile = lds + (size_t)nax * RP;   // [nax][FDM_TB]; reused as [FDM_TB][nax] for x-line output
+  const int64_t nlines = (int64_t)n1x * n1y * n1z / nax;
+  const int64_t l0 = (int64_t)blockIdx.x * FDM_TB;
+  const int t = threadIdx.x;
+  auto base_stride = [&](int64_t line, int64_t& base, int64_t& stride) {
+    if (axis == 0) {
+      base = line * n1x;
+      stride = 1;
+    } else if (axis == 1) {
+      const int64_t i = line % n1x, k = line / n1x;
+      base = i + k * (int64_t)n1x * n1y;
+      stride = n1x;
+    } else {
+      base = line;
+      stride = (int64_t)n1x * n1y;
+    }
+  };
+  // staging: eight loads in flight per thread before their LDS stores
+  constexpr int NT = FDM_TB * FDM_G, UNR = 8;
+  for (int i0 = t; i0 < nax * RP; i0 += NT * UNR) {
+    double v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = i0 + u * NT;
+      const int m = idx / RP, mp = idx % RP;
+      v[u] = (idx < nax * RP && mp < nax) ? R[m * nax + mp] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = i0 + u * NT;
+      if (idx < nax * RP) sR[idx] = v[u];
+    }
+  }
+  for (int i0 = t; i0 < nax * FDM_TB; i0 += NT * UNR) {
+    double v[UNR];
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = i0 + u * NT;
+      v[u] = 0.0;
+      if (idx < nax * FDM_TB) {
+        int m, l;
+        if (axis == 0) {
+          l = idx / nax;
+          m = idx % nax;
+        } else {
+          m = idx / FDM_TB;
+          l = idx % FDM_TB;
+        }
+        const int64_t line = l0 + l;
+        if (line < nlines) {
+          int64_t b, st;
+          base_stride(line, b, st);
+          v[u] = in[b + m * st];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < UNR; ++u) {
+      const int idx = i0 + u * NT;
+      if (idx < nax * FDM_TB) {
+        const int m = axis == 0 ? idx % nax : idx / FDM_TB;
+        const int l = axis == 0 ? idx / nax : idx % FDM_TB;
+        tile[m * FDM_TB + l] = v[u];
+      }
+    }
+  }
+  __syncthreads();
+  const int l = t % FDM_TB;
+  const int g = t / FDM_TB;  // one wavefront per group
+  const int mp0 = g * MPT;
+  double acc[MPT];
+#pragma unroll
+  for (int q = 0; q < MPT; ++q) acc[q] = 0.0;
+  if (mp0 < nax) {
+    for (int m = 0; m < nax; ++m) {
+      const double v = tile[m * FDM_TB + l];
+      const double* Rm = sR + m * RP + mp0;
+#pragma unroll
+      for (int q = 0; q < MPT; ++q) acc[q] += Rm[q] * v;
+    }
+  }
+  const int64_t line = l0 + l;
+  if (axis == 0) {
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < MPT; ++q)
+      if (mp0 + q < nax) tile[l * nax + mp0 + q] = acc[q];
+    __syncthreads();
+    for (int idx = t; idx < nax * FDM_TB; idx += FDM_TB * FDM_G) {
+      const int ll = idx / nax, mp = idx % nax;
+      if (l0 + ll < nlines) out[(l0 + ll) * n1x + mp] = tile[ll * nax + mp];
+    }
+    return;
+  }
+  if (line >= nlines) return;
+  int64_t b, st;
+  base_stride(line, b, st);
+  double lxy = 0.0;
+  if (lx) lxy = lx[line % n1x] + ly[line / n1x];  // axis 2: line = i + n1x j
+#pragma unroll
+  for (int q = 0; q < MPT; ++q) {
+    const int mp = mp0 + q;
+    if (mp < nax) out[b + (int64_t)mp * st] = lx ? acc[q] / (lxy + lz[mp]) : acc[q];
+  }
+}
+
 // one 1D transform of the interior grid along `axis`:
 //   trans = 1: out[.., m', ..] = sum_m S[m][m'] in[.., m, ..]   (S^T)
 //   trans = 0: out[.., m', ..] = sum_m S[m'][m] in[.., m, ..]   (S)
@@ -571,13 +713,51 @@ tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
   const double* lx = c->fdmL;
   const double* ly = lx + n1x;
   const double* lz = ly + n1y;
+  const size_t nS = (size_t)n1x * n1x + (size_t)n1y * n1y + (size_t)n1z * n1z;
   auto pass = [&](const double* in, double* out, int axis, int trans, bool scale) -> tdfe_status {
     const int nax = axis == 0 ? n1x : (axis == 1 ? n1y : n1z);
     const int64_t nlines = nd / nax;
     const double* S = axis == 0 ? Sx : (axis == 1 ? Sy : Sz);
-    const size_t shm = (size_t)nax * FDM_TL * sizeof(double);
-    hipLaunchKernelGGL(fdm_axis_kernel, dim3((unsigned)((nlines + FDM_TL - 1) / FDM_TL)), dim3(256), shm, c->stream, in,
-                       out, S, n1x, n1y, n1z, axis, trans, scale ? lx : nullptr, ly, lz);
+    const double* St = S + nS;  // transposed copy
+    const double* sl = scale ? lx : nullptr;
+    int mpt = (nax + FDM_G - 1) / FDM_G;
+    for (int cand : {4, 8, 12, 16, 20, 24, 32})
+      if (mpt <= cand) {
+        mpt = cand;
+        break;
+      }
+    const size_t shm_t = fdm_tile_lds(nax, mpt);
+    const unsigned gt = (unsigned)((nlines + FDM_TB - 1) / FDM_TB);
+    const double* Rm = trans ? S : St;
+#define TDFE_FDM_TILE(M)                                                                                       \
+  do {                                                                                                          \
+    TDFE_HIP(c, hipFuncSetAttribute((const void*)fdm_tile_kernel<M>, hipFuncAttributeMaxDynamicSharedMemorySize, \
+                                    (int)shm_t));                                                              \
+    hipLaunchKernelGGL((fdm_tile_kernel<M>), dim3(gt), dim3(FDM_TB * FDM_G), shm_t, c->stream, in, out, Rm, n1x, \
+                       n1y, n1z, axis, sl, ly, lz);                                                            \
+  } while (0)
+    if (shm_t > 160 * 1024 || mpt > 32)
+      mpt = 1 << 30;  // matrix does not fit LDS: line-tiled kernel below
+    if (mpt <= 4)
+      TDFE_FDM_TILE(4);
+    else if (mpt <= 8)
+      TDFE_FDM_TILE(8);
+    else if (mpt <= 12)
+      TDFE_FDM_TILE(12);
+    else if (mpt <= 16)
+      TDFE_FDM_TILE(16);
+    else if (mpt <= 20)
+      TDFE_FDM_TILE(20);
+    else if (mpt <= 24)
+      TDFE_FDM_TILE(24);
+    else if (mpt <= 32)
+      TDFE_FDM_TILE(32);
+#undef TDFE_FDM_TILE
+    else {
+      const size_t shm = (size_t)nax * FDM_TL * sizeof(double);
+      hipLaunchKernelGGL(fdm_axis_kernel, dim3((unsigned)((nlines + FDM_TL - 1) / FDM_TL)), dim3(256), shm, c->stream,
+                         in, out, S, n1x, n1y, n1z, axis, trans, sl, ly, lz);
+    }
     TDFE_HIP(c, hipGetLastError());
     return TDFE_OK;
   };
@@ -834,8 +1014,41 @@ __global__ void pcg_direction_kernel(const double* z, double* pv, const double* 
 // mode 0 (start): S[0]=rz, S[1]=rr, S[2]=bb, done if converged
 // mode 1 (alpha): S[5]=pAp from the operator partials [nb][1]; S[3] = rz / pAp
 // mode 2 (beta):  rz_new, rr -> S[4] = rz_new / rz, S[0] = rz_new, S[1] = rr; iteration count, stop test
+__device__ void pcg_scalars(int mode, double v0, double v1, double v2, double* S, int* flags, double tol, int maxit) {
+  if (mode == 0) {
+    S[0] = v0;
+    S[1] = v1;
+    S[2] = v2;
+    flags[1] = 0;
+    flags[2] = 0;
+    flags[0] = (S[2] == 0.0 || sqrt(S[1]) <= tol * sqrt(S[2])) ? 1 : 0;
+  } else if (mode == 1) {
+    const double pAp = v0;
+    S[5] = pAp;
+    if (!(pAp > 0.0)) {
+      flags[2] = 2;
+      flags[0] = 1;
+      return;
+    }
+    S[3] = S[0] / pAp;
+  } else {
+    const double rz = v0, rr = v1;
+    S[4] = rz / S[0];
+    S[0] = rz;
+    S[1] = rr;
+    flags[1] += 1;
+    if (sqrt(rr) <= tol * sqrt(S[2])) {
+      flags[0] = 1;
+    } else if (flags[1] >= maxit) {
+      flags[2] = 1;
+      flags[0] = 1;
+    }
+  }
+}
+
 __global__ void __launch_bounds__(EW) pcg_scalar_kernel(const double* partial, int64_t nb, int stride, int mode,
-                                                        double* S, int* flags, double tol, int maxit) {
+                                                        double* S, int* flags, double tol, int maxit,
+                                                        int* host_flag) {
   if (mode != 0 && flags[0]) return;
   __shared__ double sred[3][EW];
   const int t = threadIdx.x;
@@ -850,34 +1063,10 @@ __global__ void __launch_bounds__(EW) pcg_scalar_kernel(const double* partial, i
     __syncthreads();
   }
   if (t != 0) return;
-  if (mode == 0) {
-    S[0] = sred[0][0];
-    S[1] = sred[1][0];
-    S[2] = sred[2][0];
-    flags[1] = 0;
-    flags[2] = 0;
-    flags[0] = (S[2] == 0.0 || sqrt(S[1]) <= tol * sqrt(S[2])) ? 1 : 0;
-  } else if (mode == 1) {
-    const double pAp = sred[0][0];
-    S[5] = pAp;
-    if (!(pAp > 0.0)) {
-      flags[2] = 2;
-      flags[0] = 1;
-      return;
-    }
-    S[3] = S[0] / pAp;
-  } else {
-    const double rz = sred[0][0], rr = sred[1][0];
-    S[4] = rz / S[0];
-    S[0] = rz;
-    S[1] = rr;
-    flags[1] += 1;
-    if (sqrt(rr) <= tol * sqrt(S[2])) {
-      flags[0] = 1;
-    } else if (flags[1] >= maxit) {
-      flags[2] = 1;
-      flags[0] = 1;
-    }
+  pcg_scalars(mode, sred[0][0], sred[1][0], sred[2][0], S, flags, tol, maxit);
+  if (flags[0]) {
+    *host_flag = 1;  // pinned memory the host polls; cleared by the host before the solve
+    __threadfence_system();
   }
 }
 
@@ -949,32 +1138,33 @@ tdfe_status pcg_solve(tdfe_ctx* c) {
   TDFE_TRY(apply_K(x, false, nullptr));
   hipLaunchKernelGGL(pcg_start_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, (const double*)c->cload, r, z, pv, Ap,
                      (const double*)c->dinvK, nn, part);
+  volatile int* hflag = c->poll + 40;  // nothing on the stream writes it now
+  *hflag = 0;
+  int* dflag = nullptr;
+  TDFE_HIP(c, hipHostGetDevicePointer((void**)&dflag, (void*)(c->poll + 40), 0));
   hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, (int64_t)PCG_BLOCKS, 3,
-                     0, S, flags, c->pcg_tol, c->pcg_maxit);
+                     0, S, flags, c->pcg_tol, c->pcg_maxit, dflag);
   TDFE_HIP(c, hipGetLastError());
-  const int LOOK = 4, RING = TDFE_N_EVENTS, POLL0 = 64;
+  const int LOOK = 4, RING = TDFE_N_EVENTS;
   TDFE_TRY(tdfe_poll_events(c));
-  TDFE_HIP(c, hipMemcpyAsync(c->poll + POLL0, flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
-  if (!c->poll[POLL0]) {
+  if (!*hflag) {
     for (int it = 1; it <= c->pcg_maxit; ++it) {
       int64_t groups = 0;
       TDFE_TRY(apply_K(pv, true, &groups));
       hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, groups, 1, 1, S,
-                         flags, c->pcg_tol, c->pcg_maxit);
+                         flags, c->pcg_tol, c->pcg_maxit, dflag);
       hipLaunchKernelGGL(pcg_update_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, x, r, z, (const double*)pv, Ap,
                          (const double*)c->dinvK, (const double*)S, nn, part, (const int*)flags);
       hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, (int64_t)PCG_BLOCKS,
-                         3, 2, S, flags, c->pcg_tol, c->pcg_maxit);
+                         3, 2, S, flags, c->pcg_tol, c->pcg_maxit, dflag);
       hipLaunchKernelGGL(pcg_direction_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, (const double*)z, pv,
                          (const double*)S, nn, (const int*)flags);
       TDFE_HIP(c, hipGetLastError());
-      TDFE_HIP(c, hipMemcpyAsync(c->poll + POLL0 + (it % RING), flags, sizeof(int), hipMemcpyDeviceToHost, c->stream));
       TDFE_HIP(c, hipEventRecord(c->evs[it % RING], c->stream));
       if (it > LOOK) {
-        const int kk = it - LOOK;
-        TDFE_HIP(c, hipEventSynchronize(c->evs[kk % RING]));
-        if (c->poll[POLL0 + (kk % RING)]) break;
+        TDFE_HIP(c, hipEventSynchronize(c->evs[(it - LOOK) % RING]));
+        if (*hflag) break;
       }
     }
   }
@@ -1056,6 +1246,11 @@ tdfe_status tdfe_fdm_setup(tdfe_ctx* c) {
   S.insert(S.end(), Sx.begin(), Sx.end());
   S.insert(S.end(), Sy.begin(), Sy.end());
   S.insert(S.end(), Sz.begin(), Sz.end());
+  for (const std::vector<double>* M : {&Sx, &Sy, &Sz}) {
+    const int m = (int)std::lround(std::sqrt((double)M->size()));
+    for (int a = 0; a < m; ++a)
+      for (int b = 0; b < m; ++b) S.push_back((*M)[(size_t)b * m + a]);
+  }
   L.insert(L.end(), lx.begin(), lx.end());
   L.insert(L.end(), ly.begin(), ly.end());
   L.insert(L.end(), lz.begin(), lz.end());

@@ -289,7 +289,7 @@ void carve(tdfe_ctx* c, char* base) {
   c->t0 = k.take<double>(nd);
   c->t1 = k.take<double>(nd);
   const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
-  c->fdmS = k.take<double>((size_t)n1x * n1x + (size_t)n1y * n1y + (size_t)n1z * n1z);
+  c->fdmS = k.take<double>(2 * ((size_t)n1x * n1x + (size_t)n1y * n1y + (size_t)n1z * n1z));
   c->fdmL = k.take<double>((size_t)n1x + n1y + n1z);
   c->pcg = c->box ? k.take<double>(1) : k.take<double>(5 * nn);
   c->dinvK = c->box ? k.take<double>(1) : k.take<double>(nn);
