@@ -198,6 +198,7 @@ def main():
         err_induced = float(np.abs(mu32 - mu64).max() / max(np.abs(dmu).max(), 1e-300))
         mixed = {"value": args.steps / wall_m, "unit": "Magnus steps/s", "ms_per_step": 1e3 * wall_m / args.steps,
                  "dtype": "f32 operator + Krylov storage, f64 scalars/orbitals",
+                 "lanczos_tol": f"max({cfg.tol:g}, 16 * 2^-24 * ||psibar_alpha||) per orbital (FP32 storage floor)",
                  "speedup_vs_f64": (args.steps / wall_m) / steps_per_s,
                  "dipole_rel_err": err, "dipole_err_rel_induced": err_induced,
                  "steps_compared": len(mu64), "krylov_its_per_step": ks_m / args.steps,

@@ -58,12 +58,29 @@ __device__ inline int cheb_bessel(double z, double* J, double* inv) {
   return M;
 }
 
+// whole-wavefront neighbour exchange by DPP row shifts (the value of lane t-1,
+// resp. t+1; 0 at the ends): no LDS traffic
+__device__ __forceinline__ double lane_prev(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x138, 0xf, 0xf, false);  // wave_shr:1
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x138, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ double lane_next(double v) {
+  const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), 0x130, 0xf, 0xf, false);  // wave_shl:1
+  const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), 0x130, 0xf, 0xf, false);
+  return __hiloint2double(hi, lo);
+}
+
 // Same result for k <= TDFE_CHEB_THREADS, one row per lane of a single
 // wavefront: the Chebyshev vectors stay in registers and the tridiagonal
-// neighbours come from cross-lane shuffles, so a term costs no LDS round trip.
-// Lane j returns row j of y in (yr, yi) (zero for j >= k).
-__device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* sb, double s, ChebLds& L, double& yr,
-                                        double& yi, double* amax) {
+// neighbours come from DPP lane shifts, so a term costs no LDS round trip.
+// Lane j returns row j of y in (yr, yi) (zero for j >= k).  J is an LDS
+// table of TDFE_MAX_BESSEL + 2 entries, Ms / invs LDS scalars.  WAVE_ONLY: the
+// calling wavefront is the only one left in its workgroup, so lane 0's table
+// is published with a wavefront-scope fence instead of a workgroup barrier.
+template <bool WAVE_ONLY = false>
+__device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* sb, double s, double* J, int* Ms,
+                                        double* invs, double& yr, double& yi, double* amax) {
   const int t = threadIdx.x;
   const bool row = t < k;
   const double a = row ? sa[t] : 0.0;
@@ -80,10 +97,16 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   *amax = am;
   const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
   const double z = fabs(s) * rr;
-  if (t == 0) L.M = cheb_bessel(z, L.J, &L.inv);
-  __syncthreads();
-  const int M = L.M;
-  const double jn = L.inv;
+  if (t == 0) *Ms = cheb_bessel(z, J, invs);
+  if constexpr (WAVE_ONLY) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+  const int M = *Ms;
+  const double jn = *invs;
   yr = 0.0;
   yi = 0.0;
   if (M < 0) return -1;
@@ -91,19 +114,19 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
   const double ac = row ? a - cc : 0.0;
   double vp = (t == 0) ? 1.0 : 0.0;
-  yr = jn * L.J[0] * vp;
+  yr = jn * J[0] * vp;
   if (M >= 1) {
-    double left = __shfl_up(vp, 1), right = __shfl_down(vp, 1);
+    double left = lane_prev(vp), right = lane_next(vp);
     double vc = (ac * vp + bl * left + br * right) * invr;
-    yi += -2.0 * sgn * jn * L.J[1] * vc;
+    yi += -2.0 * sgn * jn * J[1] * vc;
     for (int mm = 2; mm <= M; ++mm) {
-      left = __shfl_up(vc, 1);
-      right = __shfl_down(vc, 1);
+      left = lane_prev(vc);
+      right = lane_next(vc);
       const double w = ac * vc + bl * left + br * right;
       const double vn = 2.0 * w * invr - vp;
       vp = vc;
       vc = vn;
-      const double cj = 2.0 * jn * L.J[mm];
+      const double cj = 2.0 * jn * J[mm];
       const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
       if (ph == 0) yr += cj * vn;
       else if (ph == 1) yi -= sgn * cj * vn;

@@ -143,6 +143,10 @@ tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
 bool tdfe_box_kernel_ok(const tdfe_ctx* c);
 tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a);
 
+// mixed precision: floor of the Lanczos stop tolerance relative to ||psibar||
+// (16 units of FP32 roundoff)
+#define TDFE_MIXED_TOL_FLOOR (16.0 / 16777216.0)
+
 // events for the host's look-ahead polling of device convergence flags (created once per context)
 #define TDFE_N_EVENTS 16
 tdfe_status tdfe_poll_events(tdfe_ctx* c);

@@ -177,30 +177,13 @@ __global__ void __launch_bounds__(RED_THREADS)
 // ---------------------------------------------------------------------------------------------
 // small exponential and adaptive stop, one wavefront per orbital
 // ---------------------------------------------------------------------------------------------
-__global__ void __launch_bounds__(CHK_THREADS)
-    check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, int* err_flag, int* host_flag) {
-  __shared__ ChebLds L;
-  __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
-  const int o = blockIdx.x;
+// stop decision of orbital o after the small exponential (one wavefront, or
+// the whole block for the LDS path): error estimate, y at convergence, status
+__device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int M,
+                          double amax,
+                          double bk, double ylr, double yli, double yr, double yi, const double* Lyr,
+                          const double* Lyi, int nthreads, int* err_flag, int* host_flag) {
   const int t = threadIdx.x;
-  if (*S.done || S.status[o] != 0) return;
-  for (int j = t; j < k; j += CHK_THREADS) {
-    sa[j] = S.alpha[(size_t)j * Nc + o];
-    sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
-  }
-  __syncthreads();
-  double amax = 0.0;
-  double ylr = 0.0, yli = 0.0, yr = 0.0, yi = 0.0;
-  int M;
-  if (k <= CHK_THREADS) {
-    M = cheb_expm_e1_wave(k, sa, sb, tau, L, yr, yi, &amax);
-    ylr = __shfl(yr, k - 1);
-    yli = __shfl(yi, k - 1);
-  } else {
-    M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
-    ylr = L.yr[k - 1];
-    yli = L.yi[k - 1];
-  }
   int fin = 0;
   if (M < 0) {
     if (t == 0) {
@@ -212,21 +195,21 @@ __global__ void __launch_bounds__(CHK_THREADS)
       }
     }
   } else {
-    const double bk = sb[k - 1];
     const double eps = fabs(tau) * bk * S.nrm[o] * sqrt(ylr * ylr + yli * yli);
     const bool happy = bk <= 1e-14 * amax;
-    const bool conv = (eps <= tol) || happy;
+    // mixed precision: no tighter than the storage precision of the basis allows
+    const bool conv = (eps <= fmax(tol, tol_rel * S.nrm[o])) || happy;
     const bool stop = conv || k >= k_max;
     if (stop) {
-      if (k <= CHK_THREADS) {
+      if (Lyr == nullptr) {
         if (t < k) {
           S.y[((size_t)o * k_max + t) * 2 + 0] = yr;
           S.y[((size_t)o * k_max + t) * 2 + 1] = yi;
         }
       } else {
-        for (int j = t; j < k; j += CHK_THREADS) {
-          S.y[((size_t)o * k_max + j) * 2 + 0] = L.yr[j];
-          S.y[((size_t)o * k_max + j) * 2 + 1] = L.yi[j];
+        for (int j = t; j < k; j += nthreads) {
+          S.y[((size_t)o * k_max + j) * 2 + 0] = Lyr[j];
+          S.y[((size_t)o * k_max + j) * 2 + 1] = Lyi[j];
         }
       }
     }
@@ -250,6 +233,76 @@ __global__ void __launch_bounds__(CHK_THREADS)
     *host_flag = 1;
     __threadfence_system();
   }
+}
+
+__global__ void __launch_bounds__(CHK_THREADS)
+    check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int* err_flag,
+                 int* host_flag) {
+  __shared__ ChebLds L;
+  __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
+  const int o = blockIdx.x;
+  const int t = threadIdx.x;
+  if (*S.done || S.status[o] != 0) return;
+  for (int j = t; j < k; j += CHK_THREADS) {
+    sa[j] = S.alpha[(size_t)j * Nc + o];
+    sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
+  }
+  __syncthreads();
+  double amax = 0.0;
+  if (k <= CHK_THREADS) {
+    double yr = 0.0, yi = 0.0;
+    const int M = cheb_expm_e1_wave(k, sa, sb, tau, L.J, &L.M, &L.inv, yr, yi, &amax);
+    const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
+    stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], ylr, yli, yr, yi, nullptr, nullptr,
+              CHK_THREADS, err_flag, host_flag);
+  } else {
+    const int M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
+    stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], L.yr[k - 1], L.yi[k - 1], 0.0, 0.0, L.yr,
+              L.yi, CHK_THREADS, err_flag, host_flag);
+  }
+}
+
+// beta_k = ||w_k|| from the update partials, the scale 1/beta_k of the next
+// basis vector, and -- for k <= one wavefront -- the stop test of the same
+// orbital in the same launch (the first wavefront; the others leave after the
+// reduction)
+__global__ void __launch_bounds__(RED_THREADS)
+    beta_check_kernel(const double* __restrict__ partial, int64_t nblocks, int C, Scal S, int Nc, int k, int k_max,
+                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag) {
+  __shared__ double sred[RED_THREADS];
+  __shared__ double J[TDFE_MAX_BESSEL + 2];
+  __shared__ double sa[CHK_THREADS], sb[CHK_THREADS];
+  __shared__ int Ms;
+  __shared__ double invs;
+  if (*S.done) return;
+  const int o = blockIdx.x;
+  const int t = threadIdx.x;
+  double acc = 0.0;
+  for (int64_t b = t; b < nblocks; b += RED_THREADS) acc += partial[b * C + 2 * o] + partial[b * C + 2 * o + 1];
+  sred[t] = acc;
+  __syncthreads();
+  for (int s = RED_THREADS / 2; s > 0; s >>= 1) {
+    if (t < s) sred[t] += sred[t + s];
+    __syncthreads();
+  }
+  const double bk = sqrt(sred[0]);
+  if (t == 0) {
+    S.beta[(size_t)(k - 1) * Nc + o] = bk;
+    S.scale[(size_t)k * Nc + o] = bk > 0.0 ? 1.0 / bk : 0.0;
+  }
+  if (S.status[o] != 0 || t >= CHK_THREADS) return;
+  if (t < k) {
+    sa[t] = S.alpha[(size_t)t * Nc + o];
+    sb[t] = t < k - 1 ? S.beta[(size_t)t * Nc + o] : bk;
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double amax = 0.0, yr = 0.0, yi = 0.0;
+  const int M = cheb_expm_e1_wave<true>(k, sa, sb, tau, J, &Ms, &invs, yr, yi, &amax);
+  const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
+  stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, bk, ylr, yli, yr, yi, nullptr, nullptr, CHK_THREADS,
+            err_flag, host_flag);
 }
 
 // z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk
@@ -320,6 +373,9 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   Scal S = carve_scal(c, Nc);
   const int K = c->k_max;
   int* err_flag = (int*)c->counters + 140;
+  // FP32 basis vectors carry rounding of 2^-24 relative: a Krylov error
+  // estimate below a small multiple of that (times ||psibar||) buys nothing
+  const double tol_rel = sizeof(T) == 4 ? TDFE_MIXED_TOL_FLOOR : 0.0;
 
   hipLaunchKernelGGL(init_scal_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc);
   TDFE_HIP(c, hipMemsetAsync(Hq, 0, (size_t)vstride * sizeof(T), c->stream));
@@ -369,12 +425,17 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                        S.beta + (size_t)(k >= 2 ? k - 2 : 0) * Nc, S.scale + (size_t)(k - 1) * Nc,
                        S.scale + (size_t)(k >= 2 ? k - 2 : 0) * Nc, (const int*)S.status, k >= 2 ? 1 : 0, c->partial,
                        (const int*)S.done);
-    // beta_k and the scale 1/beta_k of the next basis vector
-    hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
-                       (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 2, S.scale + (size_t)k * Nc,
-                       (const int*)S.done);
-    hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, err_flag,
-                       dflag);
+    // beta_k, the scale 1/beta_k of the next basis vector and the stop test
+    if (k <= CHK_THREADS) {
+      hipLaunchKernelGGL(beta_check_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial,
+                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag);
+    } else {
+      hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
+                         (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 2, S.scale + (size_t)k * Nc,
+                         (const int*)S.done);
+      hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
+                         err_flag, dflag);
+    }
     TDFE_HIP(c, hipGetLastError());
     TDFE_HIP(c, hipEventRecord(c->evs[k % RING], c->stream));
     if (k > LOOK) {
