@@ -42,6 +42,87 @@ def apply_work(n, nq, n_cell, n_dof, n_orb, elem_bytes=8):
     return bytes_, flops
 
 
+def profiled_traffic(label):
+    """HBM bytes per operator launch from the committed rocprofv3 counter summary,
+    or None when the operator source has changed since the counters were taken."""
+    import hashlib
+    prof = os.path.join(ROOT, "profiles", "plane_kernel_16x16x16_p5_8orb_hbm_bytes.md")
+    src = os.path.join(ROOT, "paper_1810_13130_amd", "csrc", "tdfe_apply_box.hip")
+    try:
+        text = open(prof).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        if "=" in line and not line.startswith("|"):
+            k, v = (x.strip() for x in line.split("=", 1))
+            vals[k] = v
+    if vals.get("source_sha256_prefix") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+        return None
+    v = vals.get(f"traffic_bytes_per_launch.{label}")
+    return float(v) if v is not None else None
+
+
+def adjoint_rate(n_steps=20):
+    """Field gradient dmu_z(t_N)/dE_n on the adjoint workload (16^3 p=5, 8 orbitals,
+    Hartree + exchange, no kick): forward sweep + checkpointed reverse sweep."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[5]
+    ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=cfg.n_orb, k_max=cfg.k_max)
+    xq = ctx.quad_coords().cpu().numpy()
+    ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
+    Z, R = W.atoms(cfg)
+    ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=cfg.n_orb)
+    psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
+                                            ctx.mass_diag().cpu().numpy())).cuda()
+    E = W.field_amplitudes(n_steps)
+    ctx.dipole_gradient(psi, E[:2], cfg.dt, cfg.tol)  # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    L, g = ctx.dipole_gradient(psi, E, cfg.dt, cfg.tol, checkpoint_every=n_steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t
+    ctx.close()
+    return {"workload": cfg.name, "steps": n_steps, "value": n_steps / wall,
+            "unit": "Magnus steps/s (forward + reverse, gradient w.r.t. every E_n)",
+            "wall_s": wall, "L": L, "grad_norm": float(np.linalg.norm(g))}
+
+
+def graded_apply(reps=3):
+    """Operator on curved (trilinear) cells: the graded workload (31^3 cells, p = 6,
+    6,331,625 DoFs, 32 orbitals), FP64 and FP32 launches."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[3]
+    out = {"workload": cfg.name}
+    for prec, name in ((tdfe.FP64, "f64"), (tdfe.MIXED_FP32, "f32")):
+        ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=cfg.n_orb, k_max=4, precision=prec)
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
+        dt_ = torch.complex128 if prec == tdfe.FP64 else torch.complex64
+        f = ctx.apply_H_add if prec == tdfe.FP64 else ctx.apply_H_add_f32
+        x = torch.randn(ctx.n_dof, cfg.n_orb, dtype=dt_, device="cuda")
+        y = torch.zeros_like(x)
+        f(x, y)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            f(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[name + "_launch_ms"] = ms
+        out[name + "_gdof_orb_per_s"] = ctx.n_dof * cfg.n_orb / (ms * 1e-3) / 1e9
+        del x, y
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_oracle_baseline(cfg, ks_total):
     """Bounded sample of the CPU oracle on this host, scaled to steps/s."""
     import threadpoolctl
@@ -94,6 +175,8 @@ def main():
     ap.add_argument("--apply-reps", type=int, default=100)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-graded", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -170,7 +253,8 @@ def main():
         else:
             roof = {"bound": "hbm", "achieved": by / t_apply / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
         roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = None
+        roof["traffic"] = profiled_traffic("fp64" if elem_bytes == 8 else "fp32")
+        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
         roof["kernel"] = label
         roof["launch_us"] = t_apply * 1e6
         roof["algorithmic_bytes"] = by
@@ -219,6 +303,10 @@ def main():
         "roofline": roof,
         "mixed": mixed,
     }
+    if not args.no_adjoint:
+        out["adjoint"] = adjoint_rate()
+    if not args.no_graded:
+        out["graded_apply"] = graded_apply()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_baseline(cfg, int(round(ks_total / args.steps)))
     print(json.dumps(out), flush=True)
