@@ -288,7 +288,7 @@ def main():
                  "steps_compared": len(mu64), "krylov_its_per_step": ks_m / args.steps,
                  "apply_H_gdof_orb_per_s": ctxm.n_dof * n_orb / t_apply_m / 1e9,
                  "roofline": roofline(ctxm, t_apply_m, 4, FP32_VECTOR_PEAK_TFLOPS,
-                                      "plane_kernel<float,6,16,4> (Hbar, 16^3 p=5, 8 orbitals)")}
+                                      "plane_kernel<float,6,16,2> (Hbar, 16^3 p=5, 8 orbitals)")}
         ctxm.close()
 
     out = {
