@@ -102,6 +102,45 @@ def test_lanczos_zero_orbital_and_ragged_block():
     assert rel(out[:, [0, 2]], z) < 1e-10
 
 
+def test_lanczos_tau_zero_is_identity():
+    cfg = _cfg2_small(n_orb=2, nc=3, p=3)
+    ctx = gpu_context(cfg, n_orb=2)
+    m, _ = oracle_mesh(cfg)
+    x = W.random_block(m.n_dof, 2, 3)
+    g = torch.from_numpy(x).cuda()
+    ks, errs = ctx.lanczos_expm(g, 0.0, 1e-12)
+    assert ks == [1, 1] and max(errs) == 0.0
+    assert rel(g.cpu().numpy(), x) < 1e-14
+
+
+def test_lanczos_eigenvector_stops_at_k1():
+    """A discrete eigenvector of Hbar: happy breakdown (or eps_1 below tol) at
+    k = 1 and the exact phase exp(-i tau lambda)."""
+    cfg = _cfg2_small(n_orb=1, nc=3, p=3)
+    ctx = gpu_context(cfg, n_orb=1)
+    m, vq = oracle_mesh(cfg)
+    lam, U = np.linalg.eigh(op.dense_Hbar(m, vq))
+    for idx in (0, 7):
+        v = U[:, idx].astype(np.complex128)[:, None]
+        g = torch.from_numpy(np.ascontiguousarray(v)).cuda()
+        tau = 0.3
+        ks, _ = ctx.lanczos_expm(g, tau, 1e-12)
+        assert ks == [1]
+        assert rel(g.cpu().numpy(), np.exp(-1j * tau * lam[idx]) * v) < 1e-11
+
+
+@pytest.mark.slow
+def test_graded_full_size_operator_matches_oracle():
+    """Curved cells at the graded workload's full size (31^3 cells, p = 6,
+    6,331,625 DoFs), two orbitals, every output compared with the oracle."""
+    cfg = W.scaled(W.CONFIGS[3], n_orb=2)
+    ctx = gpu_context(cfg, n_orb=2, k_max=4)
+    m, vq = oracle_mesh(cfg)
+    x = W.random_block(m.n_dof, 2, 11)
+    y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(y, op.apply_Hbar(m, vq, x)) < 1e-12
+
+
 def test_lanczos_not_converged_reports_enoconv():
     from paper_1810_13130_amd import tdfe
     cfg = W.CONFIGS[1]
