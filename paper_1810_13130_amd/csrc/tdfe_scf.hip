@@ -390,10 +390,11 @@ __global__ void scatter_interior_kernel(const double* in, double* full, int Nx, 
 
 // Register-tiled form of the same transform: a block stages FDM_TB lines and
 // the whole 1D matrix R (R = S for the transposed product, S^T otherwise) in
-// LDS; wavefront g (of FDM_G) owns output modes [g MPT, g MPT + MPT) and sweeps
-// the input modes once, reading row m of R at a wave-uniform address (an LDS
-// broadcast).  lam scaling is supported along z only.
-constexpr int FDM_TB = 64, FDM_G = 4;
+// LDS; the FDM_G groups of FDM_TB lanes each own output modes
+// [g MPT, g MPT + MPT) of every line and sweep the input modes once (a row
+// of R is read at one address per group: LDS broadcasts in distinct banks).
+// lam scaling is supported along z only.
+constexpr int FDM_TB = 16, FDM_G = 16;
 // rows of R are padded with zeros to FDM_G * MPT entries, so the inner loop needs no bounds test
 inline size_t fdm_tile_lds(int nax, int mpt) {
   return ((size_t)nax * FDM_G * mpt + (size_t)nax * FDM_TB) * sizeof(double);
@@ -475,7 +476,7 @@ __global__ void __launch_bounds__(FDM_TB* FDM_G) fdm_tile_kernel(const double* _
   }
   __syncthreads();
   const int l = t % FDM_TB;
-  const int g = t / FDM_TB;  // one wavefront per group
+  const int g = t / FDM_TB;
   const int mp0 = g * MPT;
   double acc[MPT];
 #pragma unroll
@@ -721,7 +722,7 @@ tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
     const double* St = S + nS;  // transposed copy
     const double* sl = scale ? lx : nullptr;
     int mpt = (nax + FDM_G - 1) / FDM_G;
-    for (int cand : {4, 8, 12, 16, 20, 24, 32})
+    for (int cand : {1, 2, 3, 4, 5, 6, 8})
       if (mpt <= cand) {
         mpt = cand;
         break;
@@ -736,22 +737,22 @@ tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
     hipLaunchKernelGGL((fdm_tile_kernel<M>), dim3(gt), dim3(FDM_TB * FDM_G), shm_t, c->stream, in, out, Rm, n1x, \
                        n1y, n1z, axis, sl, ly, lz);                                                            \
   } while (0)
-    if (shm_t > 160 * 1024 || mpt > 32)
+    if (shm_t > 160 * 1024 || mpt > 8)
       mpt = 1 << 30;  // matrix does not fit LDS: line-tiled kernel below
-    if (mpt <= 4)
+    if (mpt <= 1)
+      TDFE_FDM_TILE(1);
+    else if (mpt <= 2)
+      TDFE_FDM_TILE(2);
+    else if (mpt <= 3)
+      TDFE_FDM_TILE(3);
+    else if (mpt <= 4)
       TDFE_FDM_TILE(4);
+    else if (mpt <= 5)
+      TDFE_FDM_TILE(5);
+    else if (mpt <= 6)
+      TDFE_FDM_TILE(6);
     else if (mpt <= 8)
       TDFE_FDM_TILE(8);
-    else if (mpt <= 12)
-      TDFE_FDM_TILE(12);
-    else if (mpt <= 16)
-      TDFE_FDM_TILE(16);
-    else if (mpt <= 20)
-      TDFE_FDM_TILE(20);
-    else if (mpt <= 24)
-      TDFE_FDM_TILE(24);
-    else if (mpt <= 32)
-      TDFE_FDM_TILE(32);
 #undef TDFE_FDM_TILE
     else {
       const size_t shm = (size_t)nax * FDM_TL * sizeof(double);
