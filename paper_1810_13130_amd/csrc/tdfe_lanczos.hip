@@ -41,7 +41,8 @@ constexpr int CHK_THREADS = TDFE_CHEB_THREADS;
 struct Scal {
   double* alpha;  // [k_max][Nc]
   double* beta;   // [k_max][Nc]
-  double* scale;  // [k_max+2][Nc]  s_j applied to basis vector j
+  double* scale;  // [k_max+2][Nc]  s_j applied to basis vector j (q_j = s_j w_j)
+  double* cs;     // [k_max+2][Nc]  input scale of operator pass j: s_0, then s_j^2
   double* nrm;    // [Nc]
   double* err;    // [Nc]
   double* y;      // [Nc][k_max][2]
@@ -60,6 +61,8 @@ Scal carve_scal(tdfe_ctx* c, int Nc) {
   s.beta = p;
   p += (size_t)K * Nc;
   s.scale = p;
+  p += (size_t)(K + 2) * Nc;
+  s.cs = p;
   p += (size_t)(K + 2) * Nc;
   s.nrm = p;
   p += Nc;
@@ -113,12 +116,16 @@ __global__ void __launch_bounds__(RED_THREADS)
   if (threadIdx.x < C) partial[(int64_t)blockIdx.x * C + threadIdx.x] = sred[threadIdx.x];
 }
 
-// w_k = Hq - alpha s_{k-1} w_{k-1} - beta_{k-2} s_{k-2} w_{k-2}; Hq <- 0; partial ||w_k||^2
+// Three-term step in two reads.  The operator pass of vector j accumulates
+// s_j^2 Hbar w_j (s_0 Hbar w_0 for j = 0) onto a buffer that this kernel
+// seeded with -q_{j-1}, so that on entry Hq = (Hbar q_j - beta_{j-1} q_{j-1}) / m_j
+// with m_j = beta_{j-1} (m_0 = 1).  Then
+//   w_{j+1} = m_j Hq - alpha_j s_j w_j,   Hq <- -q_j = -s_j w_j,   partial ||w_{j+1}||^2.
 template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
-    update_kernel(T* __restrict__ hq, const T* __restrict__ wa, const T* __restrict__ wb, T* __restrict__ wn, int C,
-                  int64_t nrows, const double* alpha_k, const double* beta_km1, const double* s_a, const double* s_b,
-                  const int* status, int has_b, double* __restrict__ partial, const int* done) {
+    update_kernel(T* __restrict__ hq, const T* __restrict__ wa, T* __restrict__ wn, int C, int64_t nrows,
+                  const double* alpha_j, const double* s_j, const double* m_j, const int* status,
+                  double* __restrict__ partial, const int* done) {
   __shared__ double sred[RED_THREADS];
   if (*done) return;
   const int Cp = (C <= 1) ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : (C <= 32 ? 32 : 64)))));
@@ -129,16 +136,14 @@ __global__ void __launch_bounds__(RED_THREADS)
   if (col < C) {
     const int o = col >> 1;
     const bool live = status[o] == 0;
-    const double ca = live ? alpha_k[o] * s_a[o] : 0.0;
-    const double cb = (live && has_b) ? beta_km1[o] * s_b[o] : 0.0;
+    const double s = live ? s_j[o] : 0.0;
+    const double ca = live ? alpha_j[o] * s : 0.0;
+    const double cm = live ? (m_j ? m_j[o] : 1.0) : 0.0;
     for (int64_t r = (int64_t)blockIdx.x * (RED_THREADS / Cp) + rlane; r < nrows; r += rstride) {
       const int64_t i = r * C + col;
-      double v = 0.0;
-      if (live) {
-        v = (double)hq[i] - ca * (double)wa[i];
-        if (has_b) v -= cb * (double)wb[i];
-      }
-      hq[i] = (T)0;
+      const double a = (double)wa[i];
+      const double v = cm * (double)hq[i] - ca * a;
+      hq[i] = (T)(-s * a);
       const T vt = (T)v;
       wn[i] = vt;
       acc += (double)vt * (double)vt;
@@ -150,10 +155,12 @@ __global__ void __launch_bounds__(RED_THREADS)
 }
 
 // out[o] = f( sum_b partial[b][2o] + partial[b][2o+1] ), one block per orbital, fixed order.
-// mode 0: plain sum; 1: sqrt; 2: sqrt and also scale0[o] = 1/sqrt (0 if zero)
+// mode 0: plain sum, times mult[o]^2 if mult is given (alpha from the quadratic form of the
+//         scaled operator input); 2: sqrt, scale0[o] = 1/sqrt and cs0[o] = scale0[o] (0 if
+//         zero); 3: as 2 with cs0[o] = scale0[o]^2
 __global__ void __launch_bounds__(RED_THREADS)
     finalize_pairs_kernel(const double* __restrict__ partial, int64_t nblocks, int C, double* out, int mode,
-                          double* scale0, const int* done) {
+                          double* scale0, double* cs0, const double* mult, const int* done) {
   __shared__ double sred[RED_THREADS];
   if (done && *done) return;
   const int o = blockIdx.x;
@@ -168,9 +175,14 @@ __global__ void __launch_bounds__(RED_THREADS)
   }
   if (threadIdx.x == 0) {
     double v = sred[0];
+    if (mode == 0 && mult) v *= mult[o] * mult[o];
     if (mode >= 1) v = sqrt(v);
     out[o] = v;
-    if (mode == 2) scale0[o] = v > 0.0 ? 1.0 / v : 0.0;
+    if (mode >= 2) {
+      const double sc = v > 0.0 ? 1.0 / v : 0.0;
+      scale0[o] = sc;
+      if (cs0) cs0[o] = mode == 3 ? sc * sc : sc;
+    }
   }
 }
 
@@ -219,6 +231,7 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
         S.kconv[o] = k;
         S.status[o] = conv ? 1 : 2;
         S.scale[(size_t)k * Nc + o] = 0.0;  // freezes the orbital in later operator passes
+        S.cs[(size_t)k * Nc + o] = 0.0;
         if (atomicAdd(S.nconv, 1) + 1 == Nc) {
           *S.done = 1;
           fin = 1;
@@ -287,8 +300,10 @@ __global__ void __launch_bounds__(RED_THREADS)
   }
   const double bk = sqrt(sred[0]);
   if (t == 0) {
+    const double sc = bk > 0.0 ? 1.0 / bk : 0.0;
     S.beta[(size_t)(k - 1) * Nc + o] = bk;
-    S.scale[(size_t)k * Nc + o] = bk > 0.0 ? 1.0 / bk : 0.0;
+    S.scale[(size_t)k * Nc + o] = sc;
+    S.cs[(size_t)k * Nc + o] = sc * sc;
   }
   if (S.status[o] != 0 || t >= CHK_THREADS) return;
   if (t < k) {
@@ -383,7 +398,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   hipLaunchKernelGGL((copy_in_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, in, ld, 2 * o0, W, C, nd,
                      c->partial);
   hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
-                     (int64_t)RED_BLOCKS, C, S.nrm, 2, S.scale, (const int*)nullptr);
+                     (int64_t)RED_BLOCKS, C, S.nrm, 2, S.scale, S.cs, (const double*)nullptr, (const int*)nullptr);
   // host-visible copy of the done flag (pinned memory; all earlier work on the
   // stream has completed, so nothing else writes it now)
   volatile int* hflag = c->poll + 32;
@@ -405,7 +420,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     a.y = Hq;
     a.ld = C;
     a.cols = C;
-    a.colscale = S.scale + (size_t)(k - 1) * Nc;
+    a.colscale = S.cs + (size_t)(k - 1) * Nc;
     a.kin = 0.5;
     a.vw = (const double*)vw;
     a.vw32 = (const float*)vw;
@@ -417,13 +432,13 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     a.done_flag = S.done;
     a.fp32 = sizeof(T) == 4;
     TDFE_TRY(tdfe_launch_apply(c, a));
+    // m = beta_{k-2} for k >= 2 (the operator input was scaled by s^2, not s), 1 for k = 1
+    const double* m = k >= 2 ? S.beta + (size_t)(k - 2) * Nc : (const double*)nullptr;
     hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial, groups, C,
-                       S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (const int*)S.done);
-    const T* wb = k >= 2 ? W + (int64_t)(k - 2) * vstride : wk;
-    hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, Hq, (const T*)wk, wb,
-                       W + (int64_t)k * vstride, C, nd, S.alpha + (size_t)(k - 1) * Nc,
-                       S.beta + (size_t)(k >= 2 ? k - 2 : 0) * Nc, S.scale + (size_t)(k - 1) * Nc,
-                       S.scale + (size_t)(k >= 2 ? k - 2 : 0) * Nc, (const int*)S.status, k >= 2 ? 1 : 0, c->partial,
+                       S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (double*)nullptr, m, (const int*)S.done);
+    hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, Hq, (const T*)wk,
+                       W + (int64_t)k * vstride, C, nd, (const double*)(S.alpha + (size_t)(k - 1) * Nc),
+                       (const double*)(S.scale + (size_t)(k - 1) * Nc), m, (const int*)S.status, c->partial,
                        (const int*)S.done);
     // beta_k, the scale 1/beta_k of the next basis vector and the stop test
     if (k <= CHK_THREADS) {
@@ -431,8 +446,8 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                          (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag);
     } else {
       hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
-                         (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 2, S.scale + (size_t)k * Nc,
-                         (const int*)S.done);
+                         (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 3, S.scale + (size_t)k * Nc,
+                         S.cs + (size_t)k * Nc, (const double*)nullptr, (const int*)S.done);
       hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
                          err_flag, dflag);
     }
