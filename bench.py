@@ -181,7 +181,7 @@ def main():
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; multi-GPU sharding is a design note only",
+        print(json.dumps({"error": "runs on one GPU: the orbital-sharded multi-GPU layout is described, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
 

@@ -1284,7 +1284,7 @@ tdfe_status tdfe_load_vector(tdfe_ctx* c, const double* f, bool weighted) {
 }
 
 tdfe_status tdfe_fdm_solve_into(tdfe_ctx* c, bool with_lift, double* phi_full) {
-  if (!c->box) return tdfe_fail(c, TDFE_EINVAL, "Hartree on curved meshes is not available in this build");
+  if (!c->box) return tdfe_fail(c, TDFE_EINVAL, "Hartree adjoint: needs a box mesh (exact inverse)");
   return fdm_solve(c, with_lift, phi_full);
 }
 
