@@ -138,8 +138,10 @@ tdfe_status tdfe_apply_H_add_f32(tdfe_ctx* ctx, const void* dev_psibar_c64, void
  * its own adaptive Krylov space (Eqs. KrylovSubspace, zk, AdaptiveLanczos):
  * stop at the first k with tau beta_k ||psibar|| |[exp(-i tau T_k)]_{k,1}| <= tol
  * or on happy breakdown (beta_k <= 1e-14 max|alpha|).  tau < 0 gives the
- * adjoint direction exp(+i|tau|Hbar).  host_k [n_orb] and host_err [n_orb]
- * (may be NULL) receive the final dimension and error estimate.
+ * adjoint direction exp(+i|tau|Hbar).  In a TDFE_MIXED_FP32 context the
+ * stop tolerance of orbital alpha is max(tol, 16 * 2^-24 * ||psibar_alpha||):
+ * FP32 basis vectors cannot support a tighter estimate.  host_k [n_orb] and
+ * host_err [n_orb] (may be NULL) receive the final dimension and error estimate.
  * Returns TDFE_ENOCONV (psibar holds the k_max iterate) if k_max is reached. */
 tdfe_status tdfe_lanczos_expm(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double tau, double tol,
                               int* host_k, double* host_err);
@@ -201,7 +203,7 @@ tdfe_status tdfe_gradient_query(tdfe_ctx* ctx, int n_orb, int n_steps, int check
  *    external one again on return.
  *  - dev_work: >= tdfe_gradient_query bytes, 256-byte aligned, caller-owned.
  *  - n_orb must fit one Lanczos chunk (every n_orb <= n_orb_max does unless
- *    the mesh exceeds ~48 GB of Krylov storage); Hartree needs a box mesh;
+ *    the mesh exceeds ~128 GB of Krylov storage); Hartree needs a box mesh;
  *    XC must be none or LDA exchange.
  *  - TDFE_EINVAL if a Lanczos run needs more than k_store vectors,
  *    TDFE_ENOCONV if one does not converge within k_max.

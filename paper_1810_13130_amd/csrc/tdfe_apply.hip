@@ -563,6 +563,7 @@ int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
 
 tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
   if (tdfe_box_kernel_ok(c) && !c->force_line_kernel) return tdfe_launch_apply_box(c, a);
+  if (tdfe_curved_kernel_ok(c, a.fp32) && !c->force_line_kernel) return tdfe_launch_apply_curved(c, a);
   KParams P{};
   P.x = a.x;
   P.y = a.y;

@@ -20,21 +20,9 @@
 // (B[n-1-a][n-1-i] = B[a][i], D and Dg antisymmetric): even/odd folding halves
 // the multiply-adds.  The folded tables are kernel arguments, so they are
 // uniform (scalar registers / scalar cache) and take no vector registers.
-#include "tdfe_internal.h"
+#include "tdfe_fold.h"
 
 namespace {
-
-constexpr int EO_MAX_H = 5;  // (9 + 1) / 2
-
-// folded form of one N x N matrix with reflection symmetry S (+1 or -1), in the
-// kernel's working precision (no conversions at the point of use)
-template <typename T>
-struct Folded {
-  T E[EO_MAX_H * EO_MAX_H];  // (A[a][i] + A[a][N-1-i]) / 2, a, i < H
-  T O[EO_MAX_H * EO_MAX_H];  // (A[a][i] - A[a][N-1-i]) / 2
-  T mc[EO_MAX_H];            // A[a][H] (odd N)
-  T mr[EO_MAX_H + 1];        // A[H][i], i <= H (odd N)
-};
 
 template <typename T>
 struct PlaneParams {
@@ -59,20 +47,6 @@ struct PlaneParams {
   Folded<T> fB, fBt, fD, fDt, fG, fGt;               // B, B^T, D, D^T, Dg, Dg^T
 };
 
-// quadratic form: FP32 kernels sum each line in FP32 and promote the line
-// sums; FP64 kernels accumulate directly
-template <typename T>
-__device__ __forceinline__ void acc_energy(double& e, T& line, T v) {
-  if constexpr (sizeof(T) == 4)
-    line += v;
-  else
-    e += v;
-}
-template <typename T>
-__device__ __forceinline__ void flush_energy(double& e, T line) {
-  if constexpr (sizeof(T) == 4) e += (double)line;
-}
-
 // product of two 1D Gauss weights in the kernel's precision
 template <typename T>
 __device__ __forceinline__ T wprod(const PlaneParams<T>& P, int b, int c) {
@@ -80,54 +54,6 @@ __device__ __forceinline__ T wprod(const PlaneParams<T>& P, int b, int c) {
     return P.w2[b * TDFE_MAXN + c];
   else
     return P.wq[b] * P.wq[c];
-}
-
-__device__ __forceinline__ int remap_block(int p, int G) {
-  if ((G & 7) == 0) return (p & 7) * (G >> 3) + (p >> 3);
-  return p;
-}
-
-// out[a] = sum_i A[a][i] in[i] by even/odd folding; A given folded, symmetry S
-template <typename T, int N, int S>
-__device__ __forceinline__ void eo(const Folded<T>& F, const T* in, T* out) {
-  constexpr int H = N / 2;
-  T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
-#pragma unroll
-  for (int i = 0; i < H; ++i) {
-    e[i] = in[i] + in[N - 1 - i];
-    o[i] = in[i] - in[N - 1 - i];
-  }
-#pragma unroll
-  for (int a = 0; a < H; ++a) {
-    T Pv = 0, Qv = 0;
-#pragma unroll
-    for (int i = 0; i < H; ++i) {
-      Pv += F.E[a * EO_MAX_H + i] * e[i];
-      Qv += F.O[a * EO_MAX_H + i] * o[i];
-    }
-    if constexpr (N & 1) Pv += F.mc[a] * in[H];
-    out[a] = Pv + Qv;
-    out[N - 1 - a] = S > 0 ? Pv - Qv : Qv - Pv;
-  }
-  if constexpr (N & 1) {
-    T m = 0;
-    if constexpr (S > 0) {
-#pragma unroll
-      for (int i = 0; i < H; ++i) m += F.mr[i] * e[i];
-      m += F.mr[H] * in[H];
-    } else {
-#pragma unroll
-      for (int i = 0; i < H; ++i) m += F.mr[i] * o[i];
-    }
-    out[H] = m;
-  }
-}
-
-// two matrices on the same input line share the fold
-template <typename T, int N, int S1, int S2>
-__device__ __forceinline__ void eo2(const Folded<T>& F1, const Folded<T>& F2, const T* in, T* out1, T* out2) {
-  eo<T, N, S1>(F1, in, out1);
-  eo<T, N, S2>(F2, in, out2);
 }
 
 // occupancy target: FP64 planes of n >= 6 need more than 256 registers per
@@ -518,21 +444,6 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 // ----------------------------------------------------------------------------------------------
 // host side
 // ----------------------------------------------------------------------------------------------
-template <typename T>
-void fold(const double* A, int N, int S, bool transpose, Folded<T>& F) {
-  auto at = [&](int a, int i) { return transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i]; };
-  const int H = N / 2;
-  for (int a = 0; a < H; ++a)
-    for (int i = 0; i < H; ++i) {
-      F.E[a * EO_MAX_H + i] = (T)(0.5 * (at(a, i) + at(a, N - 1 - i)));
-      F.O[a * EO_MAX_H + i] = (T)(0.5 * (at(a, i) - at(a, N - 1 - i)));
-    }
-  if (N & 1) {
-    for (int a = 0; a < H; ++a) F.mc[a] = (T)at(a, H);
-    for (int i = 0; i <= H; ++i) F.mr[i] = (T)at(H, i);
-    if (S < 0) F.mr[H] = (T)0;
-  }
-}
 
 // LDS bytes of one block of cpb cells
 template <typename T, int N, int CB>

@@ -1,0 +1,464 @@
+// Operator kernel for trilinear (curved) cells in the plane layout of the box
+// kernel (Eq. DiscreteHamiltonian in the Loewdin form, Eq. TDKSMatVecStandard).
+//
+// A thread owns an n x n plane of one column of one cell:
+//   A  (plane at node y = j): gather u(i,k) (x M^-1/2); x: B u, D u; z: B on both
+//   -- LDS transpose of the two arrays -->
+//   B  (plane at Gauss x = a): y: B on both -> u_q, d_x u_q; d_y u_q and d_z u_q
+//      by the Gauss collocation derivative; the full metric
+//      G = w detJ J^-1 J^-T (6 values per Gauss point, from the 8 cell corners,
+//      staged in LDS per block) gives the three fluxes; V u_q; the y and z
+//      transposed derivatives; transposed y interpolation of (V u_q + ...) and of
+//      the x flux
+//   -- LDS transpose of the two arrays -->
+//   C  (plane at node y = j): x: B^T s + D^T s_x; z: B^T; scatter-add (x M^-1/2).
+// The x derivative is taken on the nodes (D = Dg B along x) so that x never
+// crosses threads; only y does.  Contractions use the even/odd folded tables.
+#include "tdfe_fold.h"
+
+namespace {
+
+template <typename T>
+struct CurvedParams {
+  const void* x;
+  void* y;
+  int ld, cols, nchunks;
+  const double* colscale;
+  double kin;
+  const void* vw;
+  const double* minv;
+  const double* corners;  // [n_cell][2][2][2][3]
+  double* energy;
+  const int* done;
+  int ncx, ncy, ncz, p, Nx, Ny, Nz;
+  int64_t n_cell;
+  int lowdin, fullgrid;
+  double eta[TDFE_MAXN];  // Gauss points on [-1, 1]
+  double wq[TDFE_MAXN];   // Gauss weights
+  Folded<T> fB, fBt, fD, fDt, fG, fGt;
+};
+
+template <typename T, int N>
+constexpr int cplane_wpe() {
+  return sizeof(T) == 4 ? 2 : 1;
+}
+
+template <typename T, int N, int CB, int CPB>
+__global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_eu(cplane_wpe<T, N>())))
+    cplane_kernel(CurvedParams<T> P) {
+  constexpr int VOL = N * N * N;
+  constexpr int THREADS = CPB * N * CB;
+  __shared__ T sX[CPB * VOL * CB];
+  __shared__ T sV[CPB * VOL];
+  __shared__ T sG[CPB * VOL * 6];
+  __shared__ double sRed[THREADS];
+  if (P.done && *P.done) return;
+
+  const int t = threadIdx.x;
+  const int L = remap_block(blockIdx.x, gridDim.x);
+  const int chunk = L % P.nchunks;
+  const int group = L / P.nchunks;
+  const int col = t % CB;
+  const int pl = (t / CB) % N;
+  const int slot = t / (CB * N);
+  const int64_t cell = (int64_t)group * CPB + slot;
+  const bool cell_ok = cell < P.n_cell;
+  const int colg = chunk * CB + col;
+  const bool act = cell_ok && colg < P.cols;
+
+  int cx = 0, cy = 0, cz = 0;
+  if (cell_ok) {
+    cx = (int)(cell % P.ncx);
+    cy = (int)((cell / P.ncx) % P.ncy);
+    cz = (int)(cell / ((int64_t)P.ncx * P.ncy));
+  }
+  const T* __restrict__ X = (const T*)P.x;
+  T* __restrict__ Y = (T*)P.y;
+  T cs = (T)1;
+  if (P.colscale && act) cs = (T)P.colscale[colg >> 1];
+
+  // block staging: weighted potential and the metric of the block's cells
+  {
+    const int64_t c0 = (int64_t)group * CPB;
+    // (zeros without a potential, so that phase B needs no branch on it)
+    for (int q = t; q < CPB * VOL; q += THREADS) {
+      const int64_t ce = c0 + q / VOL;
+      sV[q] = (P.vw && ce < P.n_cell) ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
+    }
+    for (int it = t; it < CPB * VOL; it += THREADS) {
+      const int sl = it / VOL, q = it % VOL;
+      const int64_t ce = c0 + sl;
+      T* g = sG + it * 6;
+      if (ce >= P.n_cell) {
+        for (int u = 0; u < 6; ++u) g[u] = (T)0;
+        continue;
+      }
+      const int a = q % N, b = (q / N) % N, c = q / (N * N);
+      const double xa = P.eta[a], xb = P.eta[b], xc = P.eta[c];
+      const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
+                              {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
+      const double* C = P.corners + ce * 24;
+      double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+      for (int vz = 0; vz < 2; ++vz)
+        for (int vy = 0; vy < 2; ++vy)
+          for (int vx = 0; vx < 2; ++vx) {
+            const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
+            const double d0 = (vx ? 0.5 : -0.5) * f[vy][1] * f[vz][2];
+            const double d1 = f[vx][0] * (vy ? 0.5 : -0.5) * f[vz][2];
+            const double d2 = f[vx][0] * f[vy][1] * (vz ? 0.5 : -0.5);
+            for (int d = 0; d < 3; ++d) {
+              J[d][0] += X3[d] * d0;
+              J[d][1] += X3[d] * d1;
+              J[d][2] += X3[d] * d2;
+            }
+          }
+      double A[3][3];  // adjugate rows: J^-1 = A / det
+      A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+      A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+      A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+      A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+      A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+      A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+      A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+      A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+      A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+      const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+      const double s = P.kin * P.wq[a] * P.wq[b] * P.wq[c] / det;
+      g[0] = (T)(s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]));
+      g[1] = (T)(s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]));
+      g[2] = (T)(s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]));
+      g[3] = (T)(s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]));
+      g[4] = (T)(s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]));
+      g[5] = (T)(s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]));
+    }
+  }
+  auto sidx = [&](int y, int x, int z) { return (((slot * N + y) * N + x) * N + z) * CB + col; };
+  const int NxI = P.Nx - 2, NyI = P.Ny - 2;
+
+  // node (i, j, k) of this cell -> element offset and inside flag
+  const int J = cy * P.p + pl;
+  const bool jok = P.fullgrid ? true : (J > 0 && J < P.Ny - 1);
+  unsigned imask = 0, kmask = 0;
+#pragma unroll
+  for (int q = 0; q < N; ++q) {
+    const int I = cx * P.p + q, K = cz * P.p + q;
+    if (P.fullgrid || (I > 0 && I < P.Nx - 1)) imask |= 1u << q;
+    if (P.fullgrid || (K > 0 && K < P.Nz - 1)) kmask |= 1u << q;
+  }
+  if (!act || !jok) imask = 0;
+  int64_t n0, nk;  // node index of (0, j, 0) and the node stride along z
+  if (P.fullgrid) {
+    n0 = (int64_t)cx * P.p + (int64_t)P.Nx * ((int64_t)J + (int64_t)P.Ny * cz * P.p);
+    nk = (int64_t)P.Nx * P.Ny;
+  } else {
+    n0 = (int64_t)(cx * P.p - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (cz * P.p - 1));
+    nk = (int64_t)NxI * NyI;
+  }
+
+  // ---------------- A: plane j = pl -------------------------------------------------------------
+  T tu[N][N], tx[N][N];  // [x][z]
+  {
+    T u[N][N];  // [i][k]
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        // every load is issued from a valid address (masked entries read
+        // element 0 and are zeroed), so the gather has no branches
+        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
+        const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
+        const T val = X[nd * P.ld + colg * (ok ? 1 : 0)];
+        const T mv = (T)P.minv[P.lowdin ? nd : 0];
+        u[i][k] = ok ? val * (P.lowdin ? mv * cs : cs) : (T)0;
+      }
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      T line[N], o1[N], o2[N];
+#pragma unroll
+      for (int i = 0; i < N; ++i) line[i] = u[i][k];
+      eo2<T, N, 1, -1>(P.fB, P.fD, line, o1, o2);
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        tu[a][k] = o1[a];
+        tx[a][k] = o2[a];
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < N; ++a) {
+      T o1[N], o2[N];
+      eo<T, N, 1>(P.fB, tu[a], o1);
+      eo<T, N, 1>(P.fB, tx[a], o2);
+#pragma unroll
+      for (int c = 0; c < N; ++c) {
+        tu[a][c] = o1[c];
+        tx[a][c] = o2[c];
+      }
+    }
+  }
+  // ---------------- transpose: (j; a, c) -> (a; j, c) --------------------------------------------
+  T v[N][N], w[N][N];  // [y node][z point] at x point a = pl
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tu[a][c];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int c = 0; c < N; ++c) v[j][c] = sX[sidx(j, pl, c)];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sX[sidx(pl, a, c)] = tx[a][c];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int c = 0; c < N; ++c) w[j][c] = sX[sidx(j, pl, c)];
+  __syncthreads();
+
+  // ---------------- B: plane a = pl, Gauss points (b, c) ------------------------------------------
+  double energy = 0.0;
+  T dx[N][N], uq[N][N], dy[N][N];  // [b][c]; reused in place for the fluxes
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    T l1[N], l2[N], o1[N], o2[N];
+#pragma unroll
+    for (int j = 0; j < N; ++j) {
+      l1[j] = v[j][c];
+      l2[j] = w[j][c];
+    }
+    eo<T, N, 1>(P.fB, l1, o1);
+    eo<T, N, 1>(P.fB, l2, o2);
+#pragma unroll
+    for (int b = 0; b < N; ++b) {
+      uq[b][c] = o1[b];
+      dx[b][c] = o2[b];
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    T l[N], d[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) l[b] = uq[b][c];
+    eo<T, N, -1>(P.fG, l, d);
+#pragma unroll
+    for (int b = 0; b < N; ++b) dy[b][c] = d[b];
+  }
+  // per y line: z derivative, the three fluxes, the potential term and the
+  // transposed z derivative; dx <- f_x, dy <- f_y, uq <- V u + Dg_z^T f_z
+#pragma unroll
+  for (int b = 0; b < N; ++b) {
+    T dz[N], fz[N], r[N];
+    eo<T, N, -1>(P.fG, uq[b], dz);
+    T le = 0;
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      const int q = pl + N * (b + N * c);
+      const T* g = sG + (slot * VOL + q) * 6;
+      const T ux = dx[b][c], uy = dy[b][c], uz = dz[c];
+      const T fx = g[0] * ux + g[1] * uy + g[2] * uz;
+      const T fy = g[1] * ux + g[3] * uy + g[4] * uz;
+      const T f3 = g[2] * ux + g[4] * uy + g[5] * uz;
+      const T pot = sV[slot * VOL + q] * uq[b][c];
+      acc_energy<T>(energy, le, fx * ux + fy * uy + f3 * uz + pot * uq[b][c]);
+      dx[b][c] = fx;
+      dy[b][c] = fy;
+      fz[c] = f3;
+      uq[b][c] = pot;
+    }
+    flush_energy<T>(energy, le);
+    eo<T, N, -1>(P.fGt, fz, r);
+#pragma unroll
+    for (int c = 0; c < N; ++c) uq[b][c] += r[c];
+    __builtin_amdgcn_sched_barrier(0);
+  }
+  // per z line: transposed y derivative of f_y, then transposed y interpolation
+  // of both arrays: s_x = B_y^T f_x goes straight into the transpose buffer
+  // (every thread has finished reading w), s = B_y^T (uq + Dg_y^T f_y) stays
+  T s[N][N];  // [j][c]
+#pragma unroll
+  for (int c = 0; c < N; ++c) {
+    T l[N], r[N], o[N];
+#pragma unroll
+    for (int b = 0; b < N; ++b) l[b] = dx[b][c];
+    eo<T, N, 1>(P.fBt, l, o);
+#pragma unroll
+    for (int j = 0; j < N; ++j) sX[sidx(j, pl, c)] = o[j];
+#pragma unroll
+    for (int b = 0; b < N; ++b) l[b] = dy[b][c];
+    eo<T, N, -1>(P.fGt, l, r);
+#pragma unroll
+    for (int b = 0; b < N; ++b) l[b] = uq[b][c] + r[b];
+    eo<T, N, 1>(P.fBt, l, o);
+#pragma unroll
+    for (int j = 0; j < N; ++j) s[j][c] = o[j];
+  }
+  // ---------------- transposes: (a; j, c) -> (j; a, c) -------------------------------------------
+  // the quadratic form is parked in LDS first (keeps its accumulation chain
+  // from being sunk into the final reduction)
+  sRed[t] = act ? energy : 0.0;
+  T s2[N][N], sx2[N][N];  // [x point a][z point c] at node plane j = pl
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sx2[a][c] = sX[sidx(pl, a, c)];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < N; ++j)
+#pragma unroll
+    for (int c = 0; c < N; ++c) sX[sidx(j, pl, c)] = s[j][c];
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < N; ++a)
+#pragma unroll
+    for (int c = 0; c < N; ++c) s2[a][c] = sX[sidx(pl, a, c)];
+
+  // ---------------- C: plane j = pl: x then z transposed, scatter ---------------------------------
+  {
+    T h[N][N];  // [i][c]
+#pragma unroll
+    for (int c = 0; c < N; ++c) {
+      T l1[N], l2[N], o1[N], o2[N];
+#pragma unroll
+      for (int a = 0; a < N; ++a) {
+        l1[a] = s2[a][c];
+        l2[a] = sx2[a][c];
+      }
+      eo<T, N, 1>(P.fBt, l1, o1);
+      eo<T, N, -1>(P.fDt, l2, o2);
+#pragma unroll
+      for (int i = 0; i < N; ++i) h[i][c] = o1[i] + o2[i];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+      T o[N];
+      eo<T, N, 1>(P.fBt, h[i], o);
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
+        const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
+        const T mv = (T)P.minv[P.lowdin ? nd : 0];
+        const T val = P.lowdin ? o[k] * mv : o[k];
+        if (ok) unsafeAtomicAdd(Y + (nd * P.ld + colg), val);
+      }
+    }
+  }
+  // ---------------- per-column quadratic form ------------------------------------------------------
+  if (P.energy) {
+    __syncthreads();
+    if (t < CB) {
+      double acc = 0.0;
+      for (int u = t; u < THREADS; u += CB) acc += sRed[u];
+      if (chunk * CB + t < P.cols) P.energy[(int64_t)group * P.cols + chunk * CB + t] = acc;
+    }
+  }
+}
+
+// LDS bytes of one block of cpb cells (transpose buffer, potential, 6 metric
+// entries per Gauss point, quadratic-form partials)
+template <typename T, int N, int CB>
+constexpr int cplane_lds(int cpb) {
+  constexpr int VOL = N * N * N;
+  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) * 7 + cpb * N * CB * 8;
+}
+
+// cells per block: at most 512 threads; the metric makes a cell's LDS about
+// 1.4x that of a box cell, so the budgets are larger than the box kernel's
+// (an FP64 block still runs alone on its CU at one wave per SIMD)
+template <typename T, int N, int CB>
+constexpr int cplane_cpb() {
+  constexpr int budget = sizeof(T) == 8 ? 96 * 1024 : 48 * 1024;
+  int cpb = 1;
+  while (cpb * 2 * N * CB <= 512 && cplane_lds<T, N, CB>(cpb * 2) <= budget) cpb *= 2;
+  return cpb;
+}
+
+template <typename T, int N, int CB>
+tdfe_status launch_cplane(tdfe_ctx* c, CurvedParams<T>& P, int64_t* groups_out) {
+  constexpr int CPB = cplane_cpb<T, N, CB>();
+  static_assert(cplane_lds<T, N, CB>(CPB) <= 160 * 1024, "LDS");
+  const int64_t groups = (c->n_cell + CPB - 1) / CPB;
+  P.nchunks = (P.cols + CB - 1) / CB;
+  if (groups_out) *groups_out = groups;
+  hipLaunchKernelGGL((cplane_kernel<T, N, CB, CPB>), dim3((unsigned)(groups * P.nchunks)), dim3(CPB * N * CB), 0,
+                     c->stream, P);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+template <typename T, int N>
+tdfe_status launch_cplane_n(tdfe_ctx* c, CurvedParams<T>& P, int64_t* g) {
+  if (P.cols <= 1) return launch_cplane<T, N, 1>(c, P, g);
+  if (P.cols <= 2) return launch_cplane<T, N, 2>(c, P, g);
+  if (P.cols <= 4) return launch_cplane<T, N, 4>(c, P, g);
+  if (P.cols <= 8) return launch_cplane<T, N, 8>(c, P, g);
+  return launch_cplane<T, N, 16>(c, P, g);
+}
+
+template <typename T>
+tdfe_status launch_curved(tdfe_ctx* c, const ApplyArgs& a) {
+  static_assert(sizeof(CurvedParams<T>) <= 4096, "kernel arguments exceed 4 KB");
+  CurvedParams<T> P{};
+  P.x = a.x;
+  P.y = a.y;
+  P.ld = a.ld;
+  P.cols = a.cols;
+  P.colscale = a.colscale;
+  P.kin = a.kin;
+  P.vw = a.fp32 ? (const void*)a.vw32 : (const void*)a.vw;
+  P.minv = c->minv;
+  P.corners = c->corners;
+  P.energy = a.energy;
+  P.done = a.done_flag;
+  P.ncx = c->ncx;
+  P.ncy = c->ncy;
+  P.ncz = c->ncz;
+  P.p = c->p;
+  P.Nx = c->Nx;
+  P.Ny = c->Ny;
+  P.Nz = c->Nz;
+  P.n_cell = c->n_cell;
+  P.lowdin = a.lowdin;
+  P.fullgrid = a.fullgrid;
+  const int N = c->n;
+  for (int i = 0; i < N; ++i) {
+    P.eta[i] = c->eta[i];
+    P.wq[i] = c->wq[i];
+  }
+  fold(c->B, N, 1, false, P.fB);
+  fold(c->B, N, 1, true, P.fBt);
+  fold(c->D, N, -1, false, P.fD);
+  fold(c->D, N, -1, true, P.fDt);
+  fold(c->Dg, N, -1, false, P.fG);
+  fold(c->Dg, N, -1, true, P.fGt);
+  switch (N) {
+    case 2: return launch_cplane_n<T, 2>(c, P, a.n_blocks_out);
+    case 3: return launch_cplane_n<T, 3>(c, P, a.n_blocks_out);
+    case 4: return launch_cplane_n<T, 4>(c, P, a.n_blocks_out);
+    case 5: return launch_cplane_n<T, 5>(c, P, a.n_blocks_out);
+    case 6: return launch_cplane_n<T, 6>(c, P, a.n_blocks_out);
+    case 7: return launch_cplane_n<T, 7>(c, P, a.n_blocks_out);
+    case 8:
+      if constexpr (sizeof(T) == 4) return launch_cplane_n<T, 8>(c, P, a.n_blocks_out);
+      break;
+  }
+  return tdfe_fail(c, TDFE_EINVAL, "curved operator: unsupported order p=%d", c->p);
+}
+
+}  // namespace
+
+// true if the curved plane kernel handles this launch: trilinear cells, p <= 6,
+// and p = 7 in FP32 (an FP64 plane of 8 x 8 spills to scratch and runs slower
+// than the line-ownership kernel)
+bool tdfe_curved_kernel_ok(const tdfe_ctx* c, bool fp32) { return !c->box && (c->n <= 7 || (fp32 && c->n == 8)); }
+
+tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a) {
+  if (a.cols < 1) return tdfe_fail(c, TDFE_EINVAL, "apply: cols < 1");
+  if (!tdfe_curved_kernel_ok(c, a.fp32)) return tdfe_fail(c, TDFE_EINVAL, "curved operator: unsupported mesh or order");
+  // M^-1/2 exists on the interior DoFs only
+  if (a.lowdin && a.fullgrid) return tdfe_fail(c, TDFE_EINVAL, "apply: Loewdin scaling on the full node grid");
+  return a.fp32 ? launch_curved<float>(c, a) : launch_curved<double>(c, a);
+}

@@ -22,7 +22,7 @@ struct tdfe_ctx {
   int Nx = 0, Ny = 0, Nz = 0;
   int n_orb_max = 0, k_max = 0, precision = TDFE_FP64;
   bool box = false;  // rectilinear grid: axis-aligned cells
-  bool force_line_kernel = false;  // use the line-ownership operator kernel on box meshes too
+  bool force_line_kernel = false;  // use the line-ownership operator kernel on every mesh
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -142,6 +142,9 @@ tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
 // rectilinear-cell variant (tdfe_apply_box.hip), used by tdfe_launch_apply
 bool tdfe_box_kernel_ok(const tdfe_ctx* c);
 tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a);
+// trilinear-cell variant in the same layout (tdfe_apply_curved.hip)
+bool tdfe_curved_kernel_ok(const tdfe_ctx* c, bool fp32);
+tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a);
 
 // mixed precision: floor of the Lanczos stop tolerance relative to ||psibar||
 // (16 units of FP32 roundoff)

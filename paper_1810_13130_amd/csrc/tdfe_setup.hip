@@ -393,10 +393,10 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
     c->force_line_kernel = v && std::strcmp(v, "line") == 0;
   }
 
-  // Krylov chunk: as many orbitals as fit in 48 GB of basis storage
+  // Krylov chunk: as many orbitals as fit in 128 GB of basis storage (of 288 GB HBM)
   const size_t eb = c->precision == TDFE_FP64 ? 8 : 4;
   const double per_orb = (double)(c->k_max + 2) * (double)c->n_dof * 2.0 * (double)eb;
-  int chunk = (int)std::min<double>(c->n_orb_max, std::floor(48e9 / per_orb));
+  int chunk = (int)std::min<double>(c->n_orb_max, std::floor(128e9 / per_orb));
   if (chunk < 1) chunk = 1;
   if (chunk > TDFE_MAX_COLS / 2) chunk = TDFE_MAX_COLS / 2;
   c->chunk_orb = chunk;
