@@ -73,7 +73,10 @@ typedef struct {
 /* fe_mesh_setup: reference element (GLL nodes/weights, Gauss rule, 1D
  * interpolation/derivative tables) and mesh bookkeeping (Sec. "Higher-order
  * spectral finite-elements"; Eq. PsiExpansion for the Dirichlet DoFs).
- * Host-only: no device memory is touched until tdfe_bind_workspace.
+ * No device memory is touched until tdfe_bind_workspace; the free memory of
+ * the current device is queried once to size the Krylov basis: orbitals are
+ * processed in chunks whose basis ((k_max + 2) vectors per orbital) fits in
+ * 60% of it (128 GB if the query fails).
  * hip_stream: hipStream_t (may be 0).  *out receives a new context. */
 tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_ctx** out);
 
@@ -203,7 +206,8 @@ tdfe_status tdfe_gradient_query(tdfe_ctx* ctx, int n_orb, int n_steps, int check
  *    external one again on return.
  *  - dev_work: >= tdfe_gradient_query bytes, 256-byte aligned, caller-owned.
  *  - n_orb must fit one Lanczos chunk (every n_orb <= n_orb_max does unless
- *    the mesh exceeds ~128 GB of Krylov storage); Hartree needs a box mesh;
+ *    the Krylov basis of n_orb_max orbitals exceeds the chunk limit stated
+ *    at tdfe_fe_mesh_setup); Hartree needs a box mesh;
  *    XC must be none or LDA exchange.
  *  - TDFE_EINVAL if a Lanczos run needs more than k_store vectors,
  *    TDFE_ENOCONV if one does not converge within k_max.

@@ -562,8 +562,11 @@ int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
 }
 
 tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
+  // the FP32 copy of the potential exists in mixed contexts only
+  if (a.fp32 && c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply: FP32 launch in an FP64 context");
+  if (c->box_variant == 1 && tdfe_pair_kernel_ok(c) && !c->force_line_kernel) return tdfe_launch_apply_pair(c, a);
   if (tdfe_box_kernel_ok(c) && !c->force_line_kernel) return tdfe_launch_apply_box(c, a);
-  if (tdfe_curved_kernel_ok(c, a.fp32) && !c->force_line_kernel) return tdfe_launch_apply_curved(c, a);
+  if (tdfe_curved_kernel_ok(c, a.cols, a.fp32) && !c->force_line_kernel) return tdfe_launch_apply_curved(c, a);
   KParams P{};
   P.x = a.x;
   P.y = a.y;

@@ -450,14 +450,19 @@ tdfe_status launch_curved(tdfe_ctx* c, const ApplyArgs& a) {
 
 }  // namespace
 
-// true if the curved plane kernel handles this launch: trilinear cells, p <= 6,
-// and p = 7 in FP32 (an FP64 plane of 8 x 8 spills to scratch and runs slower
-// than the line-ownership kernel)
-bool tdfe_curved_kernel_ok(const tdfe_ctx* c, bool fp32) { return !c->box && (c->n <= 7 || (fp32 && c->n == 8)); }
+// true if the curved plane kernel handles this launch: trilinear cells, two or
+// more real columns (a single column leaves the metric staged in LDS for
+// only n threads per cell: a block of cells then has a few dozen threads, and
+// the line-ownership kernel measured 3.4x faster on the one-column stiffness
+// products of the Hartree solve), p <= 6, and p = 7 in FP32 (an FP64 plane of
+// 8 x 8 spills to scratch and runs slower than the line-ownership kernel)
+bool tdfe_curved_kernel_ok(const tdfe_ctx* c, int cols, bool fp32) {
+  return !c->box && cols >= 2 && (c->n <= 7 || (fp32 && c->n == 8));
+}
 
 tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a) {
   if (a.cols < 1) return tdfe_fail(c, TDFE_EINVAL, "apply: cols < 1");
-  if (!tdfe_curved_kernel_ok(c, a.fp32)) return tdfe_fail(c, TDFE_EINVAL, "curved operator: unsupported mesh or order");
+  if (!tdfe_curved_kernel_ok(c, a.cols, a.fp32)) return tdfe_fail(c, TDFE_EINVAL, "curved operator: unsupported mesh or order");
   // M^-1/2 exists on the interior DoFs only
   if (a.lowdin && a.fullgrid) return tdfe_fail(c, TDFE_EINVAL, "apply: Loewdin scaling on the full node grid");
   return a.fp32 ? launch_curved<float>(c, a) : launch_curved<double>(c, a);

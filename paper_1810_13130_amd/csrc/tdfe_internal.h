@@ -23,6 +23,7 @@ struct tdfe_ctx {
   int n_orb_max = 0, k_max = 0, precision = TDFE_FP64;
   bool box = false;  // rectilinear grid: axis-aligned cells
   bool force_line_kernel = false;  // use the line-ownership operator kernel on every mesh
+  int box_variant = 0;             // box meshes: 0 = plane kernel, 1 = lane-pair kernel (even n)
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -142,8 +143,11 @@ tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
 // rectilinear-cell variant (tdfe_apply_box.hip), used by tdfe_launch_apply
 bool tdfe_box_kernel_ok(const tdfe_ctx* c);
 tdfe_status tdfe_launch_apply_box(tdfe_ctx* c, const ApplyArgs& a);
+// lane-pair variant for box cells of even n (tdfe_apply_pair.hip)
+bool tdfe_pair_kernel_ok(const tdfe_ctx* c);
+tdfe_status tdfe_launch_apply_pair(tdfe_ctx* c, const ApplyArgs& a);
 // trilinear-cell variant in the same layout (tdfe_apply_curved.hip)
-bool tdfe_curved_kernel_ok(const tdfe_ctx* c, bool fp32);
+bool tdfe_curved_kernel_ok(const tdfe_ctx* c, int cols, bool fp32);
 tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a);
 
 // mixed precision: floor of the Lanczos stop tolerance relative to ||psibar||

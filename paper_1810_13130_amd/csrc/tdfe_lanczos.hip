@@ -505,6 +505,34 @@ tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes) {
   return TDFE_OK;
 }
 
+// Orbitals per Krylov chunk for a call on n_orb orbitals: at most the
+// workspace's chunk_orb, chosen to minimise the operator's padded column work
+// (a launch on `cols` real columns costs about the next power of two up to 16,
+// then whole blocks of 16), with a small charge per chunk so that ties go to
+// fewer chunks.  32 orbitals with room for 9 run as 4 x 8, not 9 + 9 + 9 + 5.
+static int chunk_size(const tdfe_ctx* c, int n_orb) {
+  const int cap = c->chunk_orb;
+  if (n_orb <= cap) return n_orb;
+  auto padded = [](int cols) {
+    if (cols > 16) return (cols + 15) / 16 * 16;
+    int q = 1;
+    while (q < cols) q <<= 1;
+    return q;
+  };
+  int best = cap;
+  double best_cost = 1e300;
+  for (int sz = cap; sz >= 1; --sz) {
+    const int n = (n_orb + sz - 1) / sz;
+    const int last = n_orb - (n - 1) * sz;
+    const double cost = (double)(n - 1) * padded(2 * sz) + padded(2 * last) + 4.0 * n;
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = sz;
+    }
+  }
+  return best;
+}
+
 tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb, double tau,
                              double tol, int* k_out, double* err_out, int* kmax_out, int* ksum_out,
                              double* errmax_out, LanczosHook* hook) {
@@ -515,8 +543,9 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
   // when the input is also the output, every chunk must read the input before
   // any chunk writes: the combination of a chunk only writes that chunk's
   // columns, and copy_in of a chunk only reads them, so chunk order is safe.
-  for (int o0 = 0; o0 < n_orb; o0 += c->chunk_orb) {
-    const int Nc = std::min(c->chunk_orb, n_orb - o0);
+  const int csz = chunk_size(c, n_orb);
+  for (int o0 = 0; o0 < n_orb; o0 += csz) {
+    const int Nc = std::min(csz, n_orb - o0);
     tdfe_status s;
     if (c->precision == TDFE_FP64)
       s = run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,

@@ -391,12 +391,20 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
   {
     const char* v = std::getenv("TDFE_APPLY_VARIANT");
     c->force_line_kernel = v && std::strcmp(v, "line") == 0;
+    c->box_variant = (v && std::strcmp(v, "pair") == 0) ? 1 : 0;
   }
 
-  // Krylov chunk: as many orbitals as fit in 128 GB of basis storage (of 288 GB HBM)
+  // Krylov chunk: as many orbitals as fit in 60% of the device memory free at
+  // creation (about 170 GB on an idle 288 GB device; 128 GB if it cannot be queried)
   const size_t eb = c->precision == TDFE_FP64 ? 8 : 4;
   const double per_orb = (double)(c->k_max + 2) * (double)c->n_dof * 2.0 * (double)eb;
-  int chunk = (int)std::min<double>(c->n_orb_max, std::floor(128e9 / per_orb));
+  double basis_bytes = 128e9;
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) basis_bytes = 0.6 * (double)free_b;
+    else (void)hipGetLastError();
+  }
+  int chunk = (int)std::min<double>(c->n_orb_max, std::floor(basis_bytes / per_orb));
   if (chunk < 1) chunk = 1;
   if (chunk > TDFE_MAX_COLS / 2) chunk = TDFE_MAX_COLS / 2;
   c->chunk_orb = chunk;

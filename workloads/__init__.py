@@ -49,7 +49,7 @@ CONFIGS = {
               atoms=dict(seed=2, count=4, box=4.0, min_dist=2.0, Z=(1, 4)),
               orbitals=dict(seed=1000, sigma=2.5)),
     3: Config("graded-16atoms-p6-31^3-32orb", -16.0, 16.0, (31, 31, 31), 6, 7, 32, 0.05, 500, 1e-10,
-              hartree=True, xc="xc", kick=1e-3, graded=True,
+              k_max=192, hartree=True, xc="xc", kick=1e-3, graded=True,
               atoms=dict(seed=3, count=16, box=5.0, min_dist=1.8, Z=(1, 4, 6)),
               orbitals=dict(seed=2000, sigma=3.5), vmap=dict(s=1.5, h_min=0.25)),
     4: Config("ae-like-6atoms-p7-39^3-24orb", -16.0, 16.0, (39, 39, 39), 7, 8, 24, 0.005, 1000, 1e-10,
