@@ -18,8 +18,10 @@
 // round trips (two arrays each way) instead of fifteen.  Every 1D contraction
 // uses the reflection symmetry of the GLL nodes and Gauss points
 // (B[n-1-a][n-1-i] = B[a][i], D and Dg antisymmetric): even/odd folding halves
-// the multiply-adds.  The folded tables are kernel arguments, so they are
-// uniform (scalar registers / scalar cache) and take no vector registers.
+// the multiply-adds.  The folded tables are evaluated at compile time for the
+// kernel's order (make_foldset), so each coefficient is an instruction
+// constant: no table loads, and no scalar-memory waits that would also wait
+// for the LDS transposes.
 #include "tdfe_fold.h"
 
 namespace {
@@ -42,19 +44,8 @@ struct PlaneParams {
   int ncx, ncy, ncz, p, Nx, Ny, Nz;
   int64_t n_cell;
   int lowdin, fullgrid;
-  double wq[TDFE_MAXN];
-  T w2[sizeof(T) == 4 ? TDFE_MAXN * TDFE_MAXN : 1];  // wq[b] wq[c] (FP32 kernels)
-  Folded<T> fB, fBt, fD, fDt, fG, fGt;               // B, B^T, D, D^T, Dg, Dg^T
+  double wq[TDFE_MAXN];  // Gauss weights (indexed by the thread's plane)
 };
-
-// product of two 1D Gauss weights in the kernel's precision
-template <typename T>
-__device__ __forceinline__ T wprod(const PlaneParams<T>& P, int b, int c) {
-  if constexpr (sizeof(T) == 4)
-    return P.w2[b * TDFE_MAXN + c];
-  else
-    return P.wq[b] * P.wq[c];
-}
 
 // occupancy target: FP64 planes of n >= 6 need more than 256 registers per
 // lane, so they run one wave per SIMD and use the accumulation registers
@@ -77,6 +68,9 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   constexpr int VOL = N * N * N;
   constexpr int THREADS = CPB * N * CB;
   constexpr bool TWO = plane_two_buffers<T, N>();
+  // 1D tables of order N, folded, as compile-time constants
+  constexpr FoldSet<N> FS = make_foldset<N>();
+  auto wprod = [&](int b, int c) { return (T)(FS.wq[b] * FS.wq[c]); };
   __shared__ T sX[CPB * VOL * CB];
   __shared__ T sY[TWO ? CPB * VOL * CB : 1];
   __shared__ T sV[CPB * VOL];  // weighted potential of the block's cells
@@ -106,14 +100,42 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   T cs = (T)1;
   if (P.colscale && act) cs = (T)P.colscale[colg >> 1];
 
-  // weighted potential of the block's cells -> LDS (read per line in phase B)
-  if (P.vw) {
-    const int64_t c0 = (int64_t)group * CPB;
-    for (int q = t; q < CPB * VOL; q += THREADS) {
-      const int64_t ce = c0 + q / VOL;
-      sV[q] = ce < P.n_cell ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
-    }
+  // block staging: the weighted potential of the block's cells, their M^-1/2
+  // factors along x, y and z and their metric go to LDS.  The loads are issued
+  // here, the phase A gather right after them, and the LDS stores follow both,
+  // so that a wave waits for memory once rather than once per array.
+  constexpr int NFC = 3 * N + 3;  // per cell: m_x[N], m_y[N], m_z[N], metric[3]
+  constexpr int NV = (CPB * VOL + THREADS - 1) / THREADS;
+  constexpr int NF = (CPB * NFC + THREADS - 1) / THREADS;
+  __shared__ double sF[CPB * NFC];
+  const int64_t c0 = (int64_t)group * CPB;
+  T vr[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int q = t + k * THREADS;
+    const int64_t ce = c0 + q / VOL;
+    const bool ok = P.vw && q < CPB * VOL && ce < P.n_cell;
+    vr[k] = ok ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
   }
+  double fr[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int f = t + k * THREADS;
+    const int r = f % NFC;
+    const int64_t ce = c0 + f / NFC;
+    const bool ok = f < CPB * NFC && ce < P.n_cell;
+    const int64_t cv = ok ? ce : 0;
+    const int ex = (int)(cv % P.ncx), ey = (int)((cv / P.ncx) % P.ncy);
+    const int ez = (int)(cv / ((int64_t)P.ncx * P.ncy));
+    // one load from a selected (always valid) address: no branches
+    const double* src = r < N ? P.m1x + (ex * P.p + r)
+                        : r < 2 * N ? P.m1y + (ey * P.p + r - N)
+                        : r < 3 * N ? P.m1z + (ez * P.p + r - 2 * N)
+                                    : P.cellgeo + (cv * 4 + r - 3 * N);
+    const double val = *src;
+    fr[k] = ok ? val : 0.0;
+  }
+  const double* sFc = sF + slot * NFC;  // this thread's cell
   // LDS index: slot, y index, x index, z index, column
   auto sidx = [&](int y, int x, int z) { return (((slot * N + y) * N + x) * N + z) * CB + col; };
   const int NxI = P.Nx - 2, NyI = P.Ny - 2;
@@ -144,9 +166,6 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       e0 = ((int64_t)(cx * P.p - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (cz * P.p - 1))) * P.ld + colg;
       kstride = (int64_t)NxI * NyI * P.ld;
     }
-    T my = (T)1;
-    if (P.lowdin && imask) my = (T)P.m1y[J] * cs;
-    else my = cs;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
 #pragma unroll
@@ -157,12 +176,26 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
         u[i][k] = ok ? val : (T)0;
       }
     }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int q = t + k * THREADS;
+      if (q < CPB * VOL) sV[q] = vr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int f = t + k * THREADS;
+      if (f < CPB * NFC) sF[f] = fr[k];
+    }
+    __syncthreads();
+    T my = (T)1;
+    if (P.lowdin && imask) my = (T)sFc[N + j] * cs;
+    else my = cs;
     if (P.lowdin) {
       T fx[N], fz[N];
 #pragma unroll
       for (int q = 0; q < N; ++q) {
-        fx[q] = ((imask >> q) & 1u) ? (T)P.m1x[cx * P.p + q] : (T)0;
-        fz[q] = ((kmask >> q) & 1u) ? (T)P.m1z[cz * P.p + q] : (T)0;
+        fx[q] = ((imask >> q) & 1u) ? (T)sFc[q] : (T)0;
+        fz[q] = ((kmask >> q) & 1u) ? (T)sFc[2 * N + q] : (T)0;
       }
 #pragma unroll
       for (int k = 0; k < N; ++k)
@@ -180,7 +213,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       T line[N], o1[N], o2[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) line[i] = u[i][k];
-      eo2<T, N, 1, -1>(P.fB, P.fD, line, o1, o2);
+      eo2<T, N, 1, -1>(FS.B, FS.D, line, o1, o2);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         tu[a][k] = o1[a];
@@ -191,8 +224,8 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       T o1[N], o2[N];
-      eo<T, N, 1>(P.fB, tu[a], o1);
-      eo<T, N, 1>(P.fB, tx[a], o2);
+      eo<T, N, 1>(FS.B, tu[a], o1);
+      eo<T, N, 1>(FS.B, tx[a], o2);
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         tu[a][c] = o1[c];
@@ -247,10 +280,14 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   T gx = 0, gy = 0, gz = 0;
   const bool havev = P.vw != nullptr;
   if (cell_ok) {
-    const T wa = (T)P.wq[pl];
-    gx = (T)(P.kin * P.cellgeo[cell * 4 + 0]) * wa;
-    gy = (T)(P.kin * P.cellgeo[cell * 4 + 1]) * wa;
-    gz = (T)(P.kin * P.cellgeo[cell * 4 + 2]) * wa;
+    // Gauss weight of this thread's x point, selected from the constants (an
+    // array indexed per lane would be a memory load and a wait)
+    T wa = (T)FS.wq[0];
+#pragma unroll
+    for (int q = 1; q < N; ++q) wa = pl == q ? (T)FS.wq[q] : wa;
+    gx = (T)(P.kin * sFc[3 * N + 0]) * wa;
+    gy = (T)(P.kin * sFc[3 * N + 1]) * wa;
+    gz = (T)(P.kin * sFc[3 * N + 2]) * wa;
   }
   // B1: x flux from w, transposed y interpolation, straight into the transpose
   // buffer (free: every thread has finished reading w)
@@ -259,16 +296,16 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     T l[N], o[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) l[j] = w[j][c];
-    eo<T, N, 1>(P.fB, l, o);  // u_x at (pl, b, c)
+    eo<T, N, 1>(FS.B, l, o);  // u_x at (pl, b, c)
     T le = 0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      const T f = gx * wprod(P, b, c) * o[b];
+      const T f = gx * wprod(b, c) * o[b];
       acc_energy<T>(energy, le, f * o[b]);
       o[b] = f;
     }
     flush_energy<T>(energy, le);
-    eo<T, N, 1>(P.fBt, o, l);
+    eo<T, N, 1>(FS.Bt, o, l);
 #pragma unroll
     for (int j = 0; j < N; ++j) sX[sidx(j, pl, c)] = l[j];
     __builtin_amdgcn_sched_barrier(0);
@@ -282,7 +319,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       T l[N], o[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) l[j] = v[j][c];
-      eo<T, N, 1>(P.fB, l, o);
+      eo<T, N, 1>(FS.B, l, o);
       T le = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
@@ -299,16 +336,16 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       T d[N], r[N];
-      eo<T, N, -1>(P.fG, uq[b], d);
+      eo<T, N, -1>(FS.G, uq[b], d);
       T le = 0;
 #pragma unroll
       for (int c = 0; c < N; ++c) {
-        const T f = gz * wprod(P, b, c) * d[c];
+        const T f = gz * wprod(b, c) * d[c];
         acc_energy<T>(energy, le, f * d[c]);
         d[c] = f;
       }
       flush_energy<T>(energy, le);
-      eo<T, N, -1>(P.fGt, d, r);
+      eo<T, N, -1>(FS.Gt, d, r);
 #pragma unroll
       for (int c = 0; c < N; ++c) acc[b][c] += r[c];
     }
@@ -318,19 +355,19 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       T l[N], d[N], r[N];
 #pragma unroll
       for (int b = 0; b < N; ++b) l[b] = uq[b][c];
-      eo<T, N, -1>(P.fG, l, d);
+      eo<T, N, -1>(FS.G, l, d);
       T le = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        const T f = gy * wprod(P, b, c) * d[b];
+        const T f = gy * wprod(b, c) * d[b];
         acc_energy<T>(energy, le, f * d[b]);
         d[b] = f;
       }
       flush_energy<T>(energy, le);
-      eo<T, N, -1>(P.fGt, d, r);
+      eo<T, N, -1>(FS.Gt, d, r);
 #pragma unroll
       for (int b = 0; b < N; ++b) r[b] += acc[b][c];
-      eo<T, N, 1>(P.fBt, r, l);
+      eo<T, N, 1>(FS.Bt, r, l);
       if constexpr (TWO) {
 #pragma unroll
         for (int j = 0; j < N; ++j) sY[sidx(j, pl, c)] = l[j];
@@ -381,8 +418,8 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
           l2[a] = sx2[a][c];
         }
       }
-      eo<T, N, 1>(P.fBt, l1, o1);
-      eo<T, N, -1>(P.fDt, l2, o2);
+      eo<T, N, 1>(FS.Bt, l1, o1);
+      eo<T, N, -1>(FS.Dt, l2, o2);
 #pragma unroll
       for (int i = 0; i < N; ++i) h[i][c] = o1[i] + o2[i];
     }
@@ -412,17 +449,17 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       fz[q] = (T)1;
     }
     if (P.lowdin && imask) {
-      my = (T)P.m1y[J];
+      my = (T)sFc[N + j];
 #pragma unroll
       for (int q = 0; q < N; ++q) {
-        if ((imask >> q) & 1u) fx[q] = (T)P.m1x[cx * P.p + q];
-        if ((kmask >> q) & 1u) fz[q] = (T)P.m1z[cz * P.p + q];
+        if ((imask >> q) & 1u) fx[q] = (T)sFc[q];
+        if ((kmask >> q) & 1u) fz[q] = (T)sFc[2 * N + q];
       }
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       T o[N];
-      eo<T, N, 1>(P.fBt, h[i], o);
+      eo<T, N, 1>(FS.Bt, h[i], o);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         if (((imask >> i) & (kmask >> k) & 1u) != 0)
@@ -450,7 +487,7 @@ template <typename T, int N, int CB>
 constexpr int plane_lds(int cpb) {
   constexpr int VOL = N * N * N;
   return cpb * VOL * CB * (int)sizeof(T) * (plane_two_buffers<T, N>() ? 2 : 1) + cpb * VOL * (int)sizeof(T) +
-         cpb * N * CB * 8;
+         cpb * N * CB * 8 + cpb * (3 * N + 3) * 8;
 }
 
 // cells per block: at most 512 threads, and LDS small enough for the
@@ -530,15 +567,6 @@ tdfe_status launch_box(tdfe_ctx* c, const ApplyArgs& a) {
   P.fullgrid = a.fullgrid;
   const int N = c->n;
   for (int i = 0; i < N; ++i) P.wq[i] = c->wq[i];
-  if constexpr (sizeof(T) == 4)
-    for (int b = 0; b < N; ++b)
-      for (int q = 0; q < N; ++q) P.w2[b * TDFE_MAXN + q] = (T)(c->wq[b] * c->wq[q]);
-  fold(c->B, N, 1, false, P.fB);
-  fold(c->B, N, 1, true, P.fBt);
-  fold(c->D, N, -1, false, P.fD);
-  fold(c->D, N, -1, true, P.fDt);
-  fold(c->Dg, N, -1, false, P.fG);
-  fold(c->Dg, N, -1, true, P.fGt);
   return launch_plane_p<T>(c, P, a.n_blocks_out);
 }
 

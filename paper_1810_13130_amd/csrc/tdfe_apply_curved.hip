@@ -35,7 +35,6 @@ struct CurvedParams {
   int lowdin, fullgrid;
   double eta[TDFE_MAXN];  // Gauss points on [-1, 1]
   double wq[TDFE_MAXN];   // Gauss weights
-  Folded<T> fB, fBt, fD, fDt, fG, fGt;
 };
 
 template <typename T, int N>
@@ -48,6 +47,8 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     cplane_kernel(CurvedParams<T> P) {
   constexpr int VOL = N * N * N;
   constexpr int THREADS = CPB * N * CB;
+  // 1D tables of order N, folded, as compile-time constants
+  constexpr FoldSet<N> FS = make_foldset<N>();
   __shared__ T sX[CPB * VOL * CB];
   __shared__ T sV[CPB * VOL];
   __shared__ T sG[CPB * VOL * 6];
@@ -176,7 +177,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       T line[N], o1[N], o2[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) line[i] = u[i][k];
-      eo2<T, N, 1, -1>(P.fB, P.fD, line, o1, o2);
+      eo2<T, N, 1, -1>(FS.B, FS.D, line, o1, o2);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         tu[a][k] = o1[a];
@@ -186,8 +187,8 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       T o1[N], o2[N];
-      eo<T, N, 1>(P.fB, tu[a], o1);
-      eo<T, N, 1>(P.fB, tx[a], o2);
+      eo<T, N, 1>(FS.B, tu[a], o1);
+      eo<T, N, 1>(FS.B, tx[a], o2);
 #pragma unroll
       for (int c = 0; c < N; ++c) {
         tu[a][c] = o1[c];
@@ -229,8 +230,8 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       l1[j] = v[j][c];
       l2[j] = w[j][c];
     }
-    eo<T, N, 1>(P.fB, l1, o1);
-    eo<T, N, 1>(P.fB, l2, o2);
+    eo<T, N, 1>(FS.B, l1, o1);
+    eo<T, N, 1>(FS.B, l2, o2);
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       uq[b][c] = o1[b];
@@ -242,7 +243,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     T l[N], d[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) l[b] = uq[b][c];
-    eo<T, N, -1>(P.fG, l, d);
+    eo<T, N, -1>(FS.G, l, d);
 #pragma unroll
     for (int b = 0; b < N; ++b) dy[b][c] = d[b];
   }
@@ -251,7 +252,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
   for (int b = 0; b < N; ++b) {
     T dz[N], fz[N], r[N];
-    eo<T, N, -1>(P.fG, uq[b], dz);
+    eo<T, N, -1>(FS.G, uq[b], dz);
     T le = 0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
@@ -269,7 +270,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       uq[b][c] = pot;
     }
     flush_energy<T>(energy, le);
-    eo<T, N, -1>(P.fGt, fz, r);
+    eo<T, N, -1>(FS.Gt, fz, r);
 #pragma unroll
     for (int c = 0; c < N; ++c) uq[b][c] += r[c];
     __builtin_amdgcn_sched_barrier(0);
@@ -283,15 +284,15 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     T l[N], r[N], o[N];
 #pragma unroll
     for (int b = 0; b < N; ++b) l[b] = dx[b][c];
-    eo<T, N, 1>(P.fBt, l, o);
+    eo<T, N, 1>(FS.Bt, l, o);
 #pragma unroll
     for (int j = 0; j < N; ++j) sX[sidx(j, pl, c)] = o[j];
 #pragma unroll
     for (int b = 0; b < N; ++b) l[b] = dy[b][c];
-    eo<T, N, -1>(P.fGt, l, r);
+    eo<T, N, -1>(FS.Gt, l, r);
 #pragma unroll
     for (int b = 0; b < N; ++b) l[b] = uq[b][c] + r[b];
-    eo<T, N, 1>(P.fBt, l, o);
+    eo<T, N, 1>(FS.Bt, l, o);
 #pragma unroll
     for (int j = 0; j < N; ++j) s[j][c] = o[j];
   }
@@ -327,15 +328,15 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
         l1[a] = s2[a][c];
         l2[a] = sx2[a][c];
       }
-      eo<T, N, 1>(P.fBt, l1, o1);
-      eo<T, N, -1>(P.fDt, l2, o2);
+      eo<T, N, 1>(FS.Bt, l1, o1);
+      eo<T, N, -1>(FS.Dt, l2, o2);
 #pragma unroll
       for (int i = 0; i < N; ++i) h[i][c] = o1[i] + o2[i];
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       T o[N];
-      eo<T, N, 1>(P.fBt, h[i], o);
+      eo<T, N, 1>(FS.Bt, h[i], o);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
@@ -428,12 +429,6 @@ tdfe_status launch_curved(tdfe_ctx* c, const ApplyArgs& a) {
     P.eta[i] = c->eta[i];
     P.wq[i] = c->wq[i];
   }
-  fold(c->B, N, 1, false, P.fB);
-  fold(c->B, N, 1, true, P.fBt);
-  fold(c->D, N, -1, false, P.fD);
-  fold(c->D, N, -1, true, P.fDt);
-  fold(c->Dg, N, -1, false, P.fG);
-  fold(c->Dg, N, -1, true, P.fGt);
   switch (N) {
     case 2: return launch_cplane_n<T, 2>(c, P, a.n_blocks_out);
     case 3: return launch_cplane_n<T, 3>(c, P, a.n_blocks_out);

@@ -11,7 +11,7 @@
 // quad permutation.  The mirror symmetry of the 1D tables
 // (A[n-1-c][n-1-k] = S A[c][k], S = +1 for B, -1 for D and Dg) makes the two
 // lanes run identical code with identical coefficients: lane 1 only multiplies
-// its inputs by S.  A lane then keeps half the registers of a plane-owning
+// its inputs by S.  All tables are compile-time constants (make_pairset).  A lane then keeps half the registers of a plane-owning
 // thread, which lets FP64 run more than one wave per SIMD.
 #include "tdfe_fold.h"
 
@@ -52,13 +52,56 @@ struct PairParams {
   int64_t n_cell;
   int lowdin, fullgrid;
   double wq[TDFE_MAXN];
-  FoldE<T> fB, fBt, fD, fDt, fG, fGt;  // B, B^T, D, D^T, Dg, Dg^T (x and y directions)
-  SplitT<T> zB, zBt, zG, zGt;          // B, B^T, Dg, Dg^T along z
 };
+
+// the kernel's tables for order N, evaluated at compile time
+struct PairSet {
+  FoldE<double> fB, fBt, fD, fDt, fG, fGt;  // B, B^T, D, D^T, Dg, Dg^T (x and y directions)
+  SplitT<double> zB, zBt, zG, zGt;          // B, B^T, Dg, Dg^T along z
+  double wq[TDFE_MAXN];
+};
+
+constexpr void fold_even(const double* A, int N, bool transpose, FoldE<double>& F) {
+  const int H = N / 2;
+  for (int a = 0; a < H; ++a)
+    for (int i = 0; i < H; ++i) {
+      const double ai = transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i];
+      const double aj = transpose ? A[(N - 1 - i) * TDFE_MAXN + a] : A[a * TDFE_MAXN + N - 1 - i];
+      F.E[a * PH + i] = 0.5 * (ai + aj);
+      F.O[a * PH + i] = 0.5 * (ai - aj);
+    }
+}
+
+constexpr void split_tab(const double* A, int N, bool transpose, SplitT<double>& F) {
+  const int H = N / 2;
+  for (int c = 0; c < H; ++c)
+    for (int k = 0; k < H; ++k) {
+      F.own[c * PH + k] = transpose ? A[k * TDFE_MAXN + c] : A[c * TDFE_MAXN + k];
+      F.oth[c * PH + k] = transpose ? A[k * TDFE_MAXN + N - 1 - c] : A[(N - 1 - c) * TDFE_MAXN + k];
+    }
+}
+
+template <int N>
+constexpr PairSet make_pairset() {
+  const tdfe1d::Rule R = tdfe1d::make_rule(N - 1);
+  PairSet F{};
+  fold_even(R.B, N, false, F.fB);
+  fold_even(R.B, N, true, F.fBt);
+  fold_even(R.D, N, false, F.fD);
+  fold_even(R.D, N, true, F.fDt);
+  fold_even(R.Dg, N, false, F.fG);
+  fold_even(R.Dg, N, true, F.fGt);
+  split_tab(R.B, N, false, F.zB);
+  split_tab(R.B, N, true, F.zBt);
+  split_tab(R.Dg, N, false, F.zG);
+  split_tab(R.Dg, N, true, F.zGt);
+  for (int i = 0; i < TDFE_MAXN; ++i) F.wq[i] = R.wq[i];
+  return F;
+}
 
 // out[a] = sum_i A[a][i] in[i], A folded with symmetry S (even N)
 template <typename T, int N, int S>
-__device__ __forceinline__ void eoe(const FoldE<T>& F, const T* in, T* out) {
+__device__ __forceinline__ void eoe(const FoldE<double>& F, const T* in, T* out) {
   constexpr int H = N / 2;
   T e[H], o[H];
 #pragma unroll
@@ -71,8 +114,8 @@ __device__ __forceinline__ void eoe(const FoldE<T>& F, const T* in, T* out) {
     T Pv = 0, Qv = 0;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      Pv += F.E[a * PH + i] * e[i];
-      Qv += F.O[a * PH + i] * o[i];
+      Pv += (T)F.E[a * PH + i] * e[i];
+      Qv += (T)F.O[a * PH + i] * o[i];
     }
     out[a] = Pv + Qv;
     out[N - 1 - a] = S > 0 ? Pv - Qv : Qv - Pv;
@@ -94,7 +137,7 @@ __device__ __forceinline__ T pair_swap(T v) {
 // contraction along the paired direction: in/out hold this lane's H local
 // entries; sg = S on lane 1, 1 on lane 0
 template <typename T, int N>
-__device__ __forceinline__ void zsplit(const SplitT<T>& F, const T* in, T* out, T sg) {
+__device__ __forceinline__ void zsplit(const SplitT<double>& F, const T* in, T* out, T sg) {
   constexpr int H = N / 2;
   T x[H], own[H], oth[H];
 #pragma unroll
@@ -104,8 +147,8 @@ __device__ __forceinline__ void zsplit(const SplitT<T>& F, const T* in, T* out, 
     T a = 0, b = 0;
 #pragma unroll
     for (int k = 0; k < H; ++k) {
-      a += F.own[c * PH + k] * x[k];
-      b += F.oth[c * PH + k] * x[k];
+      a += (T)F.own[c * PH + k] * x[k];
+      b += (T)F.oth[c * PH + k] * x[k];
     }
     own[c] = a;
     oth[c] = b;
@@ -126,6 +169,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
   constexpr int H = N / 2;
   constexpr int VOL = N * N * N;
   constexpr int THREADS = 2 * CPB * N * CB;
+  constexpr PairSet FS = make_pairset<N>();
   __shared__ T sX[CPB * VOL * CB];
   __shared__ T sV[CPB * VOL];
   __shared__ double sRed[THREADS];
@@ -237,8 +281,8 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
       T line[N], o1[N], o2[N];
 #pragma unroll
       for (int i = 0; i < N; ++i) line[i] = u[i][k];
-      eoe<T, N, 1>(P.fB, line, o1);
-      eoe<T, N, -1>(P.fD, line, o2);
+      eoe<T, N, 1>(FS.fB, line, o1);
+      eoe<T, N, -1>(FS.fD, line, o2);
 #pragma unroll
       for (int a = 0; a < N; ++a) {
         tu[a][k] = o1[a];
@@ -248,8 +292,8 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
 #pragma unroll
     for (int a = 0; a < N; ++a) {
       T o1[H], o2[H];
-      zsplit<T, N>(P.zB, tu[a], o1, (T)1);
-      zsplit<T, N>(P.zB, tx[a], o2, (T)1);
+      zsplit<T, N>(FS.zB, tu[a], o1, (T)1);
+      zsplit<T, N>(FS.zB, tx[a], o2, (T)1);
 #pragma unroll
       for (int c = 0; c < H; ++c) {
         tu[a][c] = o1[c];
@@ -298,16 +342,16 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
     T l[N], o[N];
 #pragma unroll
     for (int j = 0; j < N; ++j) l[j] = w[j][c];
-    eoe<T, N, 1>(P.fB, l, o);
+    eoe<T, N, 1>(FS.fB, l, o);
     T le = 0;
 #pragma unroll
     for (int b = 0; b < N; ++b) {
-      const T f = gx * ((T)P.wq[b] * wc[c]) * o[b];
+      const T f = gx * ((T)FS.wq[b] * wc[c]) * o[b];
       acc_energy<T>(energy, le, f * o[b]);
       o[b] = f;
     }
     flush_energy<T>(energy, le);
-    eoe<T, N, 1>(P.fBt, o, l);
+    eoe<T, N, 1>(FS.fBt, o, l);
 #pragma unroll
     for (int j = 0; j < N; ++j) sX[sidx(j, pl, zg(c))] = l[j];
     __builtin_amdgcn_sched_barrier(0);
@@ -321,7 +365,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
       T l[N], o[N];
 #pragma unroll
       for (int j = 0; j < N; ++j) l[j] = v[j][c];
-      eoe<T, N, 1>(P.fB, l, o);
+      eoe<T, N, 1>(FS.fB, l, o);
       T le = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
@@ -337,16 +381,16 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
 #pragma unroll
     for (int b = 0; b < N; ++b) {
       T d[H], rr[H];
-      zsplit<T, N>(P.zG, uq[b], d, sgn);
+      zsplit<T, N>(FS.zG, uq[b], d, sgn);
       T le = 0;
 #pragma unroll
       for (int c = 0; c < H; ++c) {
-        const T f = gz * ((T)P.wq[b] * wc[c]) * d[c];
+        const T f = gz * ((T)FS.wq[b] * wc[c]) * d[c];
         acc_energy<T>(energy, le, f * d[c]);
         d[c] = f;
       }
       flush_energy<T>(energy, le);
-      zsplit<T, N>(P.zGt, d, rr, sgn);
+      zsplit<T, N>(FS.zGt, d, rr, sgn);
 #pragma unroll
       for (int c = 0; c < H; ++c) acc[b][c] += rr[c];
     }
@@ -356,19 +400,19 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
       T l[N], d[N], rr[N];
 #pragma unroll
       for (int b = 0; b < N; ++b) l[b] = uq[b][c];
-      eoe<T, N, -1>(P.fG, l, d);
+      eoe<T, N, -1>(FS.fG, l, d);
       T le = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) {
-        const T f = gy * ((T)P.wq[b] * wc[c]) * d[b];
+        const T f = gy * ((T)FS.wq[b] * wc[c]) * d[b];
         acc_energy<T>(energy, le, f * d[b]);
         d[b] = f;
       }
       flush_energy<T>(energy, le);
-      eoe<T, N, -1>(P.fGt, d, rr);
+      eoe<T, N, -1>(FS.fGt, d, rr);
 #pragma unroll
       for (int b = 0; b < N; ++b) rr[b] += acc[b][c];
-      eoe<T, N, 1>(P.fBt, rr, l);
+      eoe<T, N, 1>(FS.fBt, rr, l);
 #pragma unroll
       for (int j = 0; j < N; ++j) s[j][c] = l[j];
     }
@@ -403,8 +447,8 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
         l1[a] = s2[a][c];
         l2[a] = sx2[a][c];
       }
-      eoe<T, N, 1>(P.fBt, l1, o1);
-      eoe<T, N, -1>(P.fDt, l2, o2);
+      eoe<T, N, 1>(FS.fBt, l1, o1);
+      eoe<T, N, -1>(FS.fDt, l2, o2);
 #pragma unroll
       for (int i = 0; i < N; ++i) hh[i][c] = o1[i] + o2[i];
     }
@@ -413,7 +457,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       T o[H];
-      zsplit<T, N>(P.zBt, hh[i], o, (T)1);
+      zsplit<T, N>(FS.zBt, hh[i], o, (T)1);
 #pragma unroll
       for (int k = 0; k < H; ++k) {
         if (((Q.imask >> i) & (Q.kmask >> k) & 1u) != 0)
@@ -475,28 +519,6 @@ tdfe_status launch_pair_n(tdfe_ctx* c, PairParams<T>& P, int64_t* g) {
 }
 
 template <typename T>
-void fold_even(const double* A, int N, bool transpose, FoldE<T>& F) {
-  auto at = [&](int a, int i) { return transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i]; };
-  const int H = N / 2;
-  for (int a = 0; a < H; ++a)
-    for (int i = 0; i < H; ++i) {
-      F.E[a * PH + i] = (T)(0.5 * (at(a, i) + at(a, N - 1 - i)));
-      F.O[a * PH + i] = (T)(0.5 * (at(a, i) - at(a, N - 1 - i)));
-    }
-}
-
-template <typename T>
-void split_tab(const double* A, int N, bool transpose, SplitT<T>& F) {
-  auto at = [&](int a, int i) { return transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i]; };
-  const int H = N / 2;
-  for (int c = 0; c < H; ++c)
-    for (int k = 0; k < H; ++k) {
-      F.own[c * PH + k] = (T)at(c, k);
-      F.oth[c * PH + k] = (T)at(N - 1 - c, k);
-    }
-}
-
-template <typename T>
 tdfe_status launch_pair_box(tdfe_ctx* c, const ApplyArgs& a) {
   static_assert(sizeof(PairParams<T>) <= 4096, "kernel arguments exceed 4 KB");
   PairParams<T> P{};
@@ -525,16 +547,6 @@ tdfe_status launch_pair_box(tdfe_ctx* c, const ApplyArgs& a) {
   P.fullgrid = a.fullgrid;
   const int N = c->n;
   for (int i = 0; i < N; ++i) P.wq[i] = c->wq[i];
-  fold_even(c->B, N, false, P.fB);
-  fold_even(c->B, N, true, P.fBt);
-  fold_even(c->D, N, false, P.fD);
-  fold_even(c->D, N, true, P.fDt);
-  fold_even(c->Dg, N, false, P.fG);
-  fold_even(c->Dg, N, true, P.fGt);
-  split_tab(c->B, N, false, P.zB);
-  split_tab(c->B, N, true, P.zBt);
-  split_tab(c->Dg, N, false, P.zG);
-  split_tab(c->Dg, N, true, P.zGt);
   switch (N) {
     case 2: return launch_pair_n<T, 2>(c, P, a.n_blocks_out);
     case 4: return launch_pair_n<T, 4>(c, P, a.n_blocks_out);

@@ -5,6 +5,7 @@
 // of size n/2 each.
 #pragma once
 #include "tdfe_internal.h"
+#include "tdfe_rule1d.h"
 
 namespace {
 
@@ -19,6 +20,46 @@ struct Folded {
   T mc[EO_MAX_H];            // A[a][H] (odd N)
   T mr[EO_MAX_H + 1];        // A[H][i], i <= H (odd N)
 };
+
+// the six folded tables of order N (B, B^T, D, D^T, Dg, Dg^T) and the Gauss
+// weights, evaluated at compile time: a kernel declares
+//   constexpr FoldSet<N> FS = make_foldset<N>();
+// and every coefficient becomes a constant of the instruction stream
+template <int N>
+struct FoldSet {
+  Folded<double> B, Bt, D, Dt, G, Gt;
+  double wq[TDFE_MAXN];
+};
+
+constexpr void fold_c(const double* A, int N, int S, bool transpose, Folded<double>& F) {
+  const int H = N / 2;
+  for (int a = 0; a < H; ++a)
+    for (int i = 0; i < H; ++i) {
+      const double ai = transpose ? A[i * TDFE_MAXN + a] : A[a * TDFE_MAXN + i];
+      const double aj = transpose ? A[(N - 1 - i) * TDFE_MAXN + a] : A[a * TDFE_MAXN + N - 1 - i];
+      F.E[a * EO_MAX_H + i] = 0.5 * (ai + aj);
+      F.O[a * EO_MAX_H + i] = 0.5 * (ai - aj);
+    }
+  if (N & 1) {
+    for (int a = 0; a < H; ++a) F.mc[a] = transpose ? A[H * TDFE_MAXN + a] : A[a * TDFE_MAXN + H];
+    for (int i = 0; i <= H; ++i) F.mr[i] = transpose ? A[i * TDFE_MAXN + H] : A[H * TDFE_MAXN + i];
+    if (S < 0) F.mr[H] = 0.0;
+  }
+}
+
+template <int N>
+constexpr FoldSet<N> make_foldset() {
+  const tdfe1d::Rule R = tdfe1d::make_rule(N - 1);
+  FoldSet<N> F{};
+  fold_c(R.B, N, 1, false, F.B);
+  fold_c(R.B, N, 1, true, F.Bt);
+  fold_c(R.D, N, -1, false, F.D);
+  fold_c(R.D, N, -1, true, F.Dt);
+  fold_c(R.Dg, N, -1, false, F.G);
+  fold_c(R.Dg, N, -1, true, F.Gt);
+  for (int i = 0; i < TDFE_MAXN; ++i) F.wq[i] = R.wq[i];
+  return F;
+}
 
 // quadratic form: FP32 kernels sum each line in FP32 and promote the line
 // sums; FP64 kernels accumulate directly
@@ -39,9 +80,10 @@ __device__ __forceinline__ int remap_block(int p, int G) {
   return p;
 }
 
-// out[a] = sum_i A[a][i] in[i] by even/odd folding; A given folded, symmetry S
-template <typename T, int N, int S>
-__device__ __forceinline__ void eo(const Folded<T>& F, const T* in, T* out) {
+// out[a] = sum_i A[a][i] in[i] by even/odd folding; A given folded (in any
+// precision, converted to T), symmetry S
+template <typename T, int N, int S, typename FT>
+__device__ __forceinline__ void eo(const Folded<FT>& F, const T* in, T* out) {
   constexpr int H = N / 2;
   T e[H > 0 ? H : 1], o[H > 0 ? H : 1];
 #pragma unroll
@@ -54,10 +96,10 @@ __device__ __forceinline__ void eo(const Folded<T>& F, const T* in, T* out) {
     T Pv = 0, Qv = 0;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      Pv += F.E[a * EO_MAX_H + i] * e[i];
-      Qv += F.O[a * EO_MAX_H + i] * o[i];
+      Pv += (T)F.E[a * EO_MAX_H + i] * e[i];
+      Qv += (T)F.O[a * EO_MAX_H + i] * o[i];
     }
-    if constexpr (N & 1) Pv += F.mc[a] * in[H];
+    if constexpr (N & 1) Pv += (T)F.mc[a] * in[H];
     out[a] = Pv + Qv;
     out[N - 1 - a] = S > 0 ? Pv - Qv : Qv - Pv;
   }
@@ -65,19 +107,19 @@ __device__ __forceinline__ void eo(const Folded<T>& F, const T* in, T* out) {
     T m = 0;
     if constexpr (S > 0) {
 #pragma unroll
-      for (int i = 0; i < H; ++i) m += F.mr[i] * e[i];
-      m += F.mr[H] * in[H];
+      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * e[i];
+      m += (T)F.mr[H] * in[H];
     } else {
 #pragma unroll
-      for (int i = 0; i < H; ++i) m += F.mr[i] * o[i];
+      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * o[i];
     }
     out[H] = m;
   }
 }
 
 // two matrices on the same input line share the fold
-template <typename T, int N, int S1, int S2>
-__device__ __forceinline__ void eo2(const Folded<T>& F1, const Folded<T>& F2, const T* in, T* out1, T* out2) {
+template <typename T, int N, int S1, int S2, typename FT>
+__device__ __forceinline__ void eo2(const Folded<FT>& F1, const Folded<FT>& F2, const T* in, T* out1, T* out2) {
   eo<T, N, S1>(F1, in, out1);
   eo<T, N, S2>(F2, in, out2);
 }

@@ -4,15 +4,16 @@
 // nodes of an order-p element are the GLL points (end points and roots of
 // P_p'), the overlap M uses the GLL rule (hence diagonal) and every other
 // integral the Gauss-Legendre rule with nq = p + 1 points.  The 1D tables
-// are computed here on the host by Newton iteration on the Legendre
-// three-term recurrence and barycentric Lagrange formulas; the per-point
-// geometry and M are computed on the device.
+// come from the constexpr rule of tdfe_rule1d.h (Newton iteration on the
+// Legendre three-term recurrence, barycentric Lagrange formulas), evaluated
+// here at run time; the per-point geometry and M are computed on the device.
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
 #include <cstring>
 
 #include "tdfe_internal.h"
+#include "tdfe_rule1d.h"
 
 tdfe_status tdfe_fail(tdfe_ctx* c, tdfe_status s, const char* fmt, ...) {
   if (c) {
@@ -27,99 +28,6 @@ tdfe_status tdfe_fail(tdfe_ctx* c, tdfe_status s, const char* fmt, ...) {
 }
 
 namespace {
-
-// P_m(x) and P_m'(x) by the three-term recurrence
-void legendre(int m, double x, double& P, double& dP) {
-  double p0 = 1.0, p1 = x;
-  if (m == 0) {
-    P = 1.0;
-    dP = 0.0;
-    return;
-  }
-  for (int k = 2; k <= m; ++k) {
-    const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
-    p0 = p1;
-    p1 = p2;
-  }
-  P = p1;
-  dP = (std::fabs(x) < 1.0) ? m * (x * p1 - p0) / (x * x - 1.0) : 0.5 * m * (m + 1) * std::pow(x, m + 1);
-}
-
-void gll_nodes(int p, double* x, double* w) {
-  x[0] = -1.0;
-  x[p] = 1.0;
-  for (int i = 1; i < p; ++i) {
-    double r = -std::cos(M_PI * i / p);
-    for (int it = 0; it < 100; ++it) {
-      // Newton on P_p' with P_p'' from Legendre's equation
-      double P, dP;
-      legendre(p, r, P, dP);
-      const double d2P = (2.0 * r * dP - p * (p + 1.0) * P) / (1.0 - r * r);
-      const double dr = dP / d2P;
-      r -= dr;
-      if (std::fabs(dr) < 1e-16) break;
-    }
-    x[i] = r;
-  }
-  for (int i = 0; i <= p; ++i) {
-    double P, dP;
-    legendre(p, x[i], P, dP);
-    w[i] = 2.0 / (p * (p + 1.0) * P * P);
-  }
-}
-
-void gauss_rule(int nq, double* x, double* w) {
-  for (int i = 0; i < nq; ++i) {
-    double r = -std::cos(M_PI * (i + 0.75) / (nq + 0.5));
-    for (int it = 0; it < 100; ++it) {
-      double P, dP;
-      legendre(nq, r, P, dP);
-      const double dr = P / dP;
-      r -= dr;
-      if (std::fabs(dr) < 1e-16) break;
-    }
-    double P, dP;
-    legendre(nq, r, P, dP);
-    x[i] = r;
-    w[i] = 2.0 / ((1.0 - r * r) * dP * dP);
-  }
-}
-
-// barycentric Lagrange basis on nodes[0..n) evaluated (value, derivative) at x
-void lagrange_eval(int n, const double* nodes, double x, double* val, double* der) {
-  double lam[TDFE_MAXN];
-  for (int i = 0; i < n; ++i) {
-    lam[i] = 1.0;
-    for (int m = 0; m < n; ++m)
-      if (m != i) lam[i] /= (nodes[i] - nodes[m]);
-  }
-  int hit = -1;
-  for (int i = 0; i < n; ++i)
-    if (std::fabs(x - nodes[i]) < 1e-14) hit = i;
-  if (hit >= 0) {
-    for (int i = 0; i < n; ++i) {
-      val[i] = (i == hit) ? 1.0 : 0.0;
-      if (i != hit) {
-        der[i] = (lam[i] / lam[hit]) / (nodes[hit] - nodes[i]);
-      } else {
-        double s = 0.0;
-        for (int m = 0; m < n; ++m)
-          if (m != hit) s += 1.0 / (nodes[hit] - nodes[m]);
-        der[i] = s;
-      }
-    }
-    return;
-  }
-  double den = 0.0;
-  for (int i = 0; i < n; ++i) den += lam[i] / (x - nodes[i]);
-  for (int i = 0; i < n; ++i) {
-    val[i] = (lam[i] / (x - nodes[i])) / den;
-    double s = 0.0;
-    for (int m = 0; m < n; ++m)
-      if (m != i) s += 1.0 / (x - nodes[m]);
-    der[i] = val[i] * s;
-  }
-}
 
 // ----------------------------------------------------------------------------------------------
 // device geometry kernels
@@ -348,21 +256,18 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
   const size_t nv = (size_t)(c->ncx + 1) * (c->ncy + 1) * (c->ncz + 1) * 3;
   c->vertices.assign(d->vertices, d->vertices + nv);
 
-  // reference element tables
-  gll_nodes(c->p, c->xi, c->w);
-  gauss_rule(c->nq, c->eta, c->wq);
-  std::memset(c->B, 0, sizeof c->B);
-  std::memset(c->D, 0, sizeof c->D);
-  std::memset(c->Dg, 0, sizeof c->Dg);
-  for (int a = 0; a < c->nq; ++a) {
-    double v[TDFE_MAXN], dv[TDFE_MAXN];
-    lagrange_eval(c->n, c->xi, c->eta[a], v, dv);
-    for (int i = 0; i < c->n; ++i) {
-      c->B[a * TDFE_MAXN + i] = v[i];
-      c->D[a * TDFE_MAXN + i] = dv[i];
-    }
-    lagrange_eval(c->nq, c->eta, c->eta[a], v, dv);
-    for (int b = 0; b < c->nq; ++b) c->Dg[a * TDFE_MAXN + b] = dv[b];
+  // reference element tables (the same constexpr rule the operator kernels
+  // evaluate at compile time)
+  {
+    const tdfe1d::Rule R = tdfe1d::make_rule(c->p);
+    static_assert(tdfe1d::MAXN == TDFE_MAXN, "table stride");
+    std::memcpy(c->xi, R.xi, sizeof c->xi);
+    std::memcpy(c->w, R.w, sizeof c->w);
+    std::memcpy(c->eta, R.eta, sizeof c->eta);
+    std::memcpy(c->wq, R.wq, sizeof c->wq);
+    std::memcpy(c->B, R.B, sizeof c->B);
+    std::memcpy(c->D, R.D, sizeof c->D);
+    std::memcpy(c->Dg, R.Dg, sizeof c->Dg);
   }
 
   // rectilinear (box) detection: x depends only on the x index, etc.
