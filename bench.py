@@ -42,12 +42,24 @@ def apply_work(n, nq, n_cell, n_dof, n_orb, elem_bytes=8):
     return bytes_, flops
 
 
+# sources of the box-cell operator kernels (the lane-pair FP64 kernel and the
+# plane FP32 kernel) whose counters profiles/ holds
+OPERATOR_SOURCES = ("tdfe_apply_box.hip", "tdfe_apply_pair.hip", "tdfe_fold.h", "tdfe_rule1d.h")
+
+
+def operator_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for name in OPERATOR_SOURCES:
+        with open(os.path.join(ROOT, "paper_1810_13130_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
 def profiled_traffic(label):
     """HBM bytes per operator launch from the committed rocprofv3 counter summary,
-    or None when the operator source has changed since the counters were taken."""
-    import hashlib
-    prof = os.path.join(ROOT, "profiles", "plane_kernel_16x16x16_p5_8orb_hbm_bytes.md")
-    src = os.path.join(ROOT, "paper_1810_13130_amd", "csrc", "tdfe_apply_box.hip")
+    or None when the operator sources have changed since the counters were taken."""
+    prof = os.path.join(ROOT, "profiles", "operator_16x16x16_p5_8orb_hbm_bytes.md")
     try:
         text = open(prof).read()
     except OSError:
@@ -57,7 +69,7 @@ def profiled_traffic(label):
         if "=" in line and not line.startswith("|"):
             k, v = (x.strip() for x in line.split("=", 1))
             vals[k] = v
-    if vals.get("source_sha256_prefix") != hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]:
+    if vals.get("source_sha256_prefix") != operator_source_hash():
         return None
     v = vals.get(f"traffic_bytes_per_launch.{label}")
     return float(v) if v is not None else None
@@ -266,7 +278,7 @@ def main():
     ctx, dt_wall, ks_total, mu64 = run(tdfe.FP64)
     steps_per_s = args.steps / dt_wall
     t_apply = time_apply(ctx, False)
-    roof = roofline(ctx, t_apply, 8, FP64_VECTOR_PEAK_TFLOPS, "plane_kernel<double,6,16,2> (Hbar, 16^3 p=5, 8 orbitals)")
+    roof = roofline(ctx, t_apply, 8, FP64_VECTOR_PEAK_TFLOPS, "pair_kernel<double,6,16,1> (Hbar, 16^3 p=5, 8 orbitals)")
     gdof = ctx.n_dof * n_orb / t_apply / 1e9
     n_dof, n_cell = ctx.n_dof, ctx.n_cell
     ctx.close()

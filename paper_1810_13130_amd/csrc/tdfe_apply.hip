@@ -564,9 +564,21 @@ int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
 tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
   // the FP32 copy of the potential exists in mixed contexts only
   if (a.fp32 && c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply: FP32 launch in an FP64 context");
-  if (c->box_variant == 1 && tdfe_pair_kernel_ok(c) && !c->force_line_kernel) return tdfe_launch_apply_pair(c, a);
-  if (tdfe_box_kernel_ok(c) && !c->force_line_kernel) return tdfe_launch_apply_box(c, a);
-  if (tdfe_curved_kernel_ok(c, a.cols, a.fp32) && !c->force_line_kernel) return tdfe_launch_apply_curved(c, a);
+  // default policy, from measurements on the benchmark and graded workloads:
+  // box cells: the lane-pair kernel for FP64 at even n (two waves per SIMD;
+  // 130 us against 170 us for the plane kernel at 16^3 cells, p = 5, 8
+  // orbitals), the plane kernel otherwise; trilinear cells: the plane kernel
+  // for two or more columns at p <= 7, the line kernel for one column and at
+  // p = 8
+  if (c->variant != TDFE_VARIANT_LINE) {
+    if (c->box) {
+      const bool pair = c->variant == TDFE_VARIANT_PAIR || (c->variant == 0 && !a.fp32);
+      if (pair && tdfe_pair_kernel_ok(c)) return tdfe_launch_apply_pair(c, a);
+      if (tdfe_box_kernel_ok(c)) return tdfe_launch_apply_box(c, a);
+    } else if (tdfe_curved_kernel_ok(c, a.cols, a.fp32)) {
+      return tdfe_launch_apply_curved(c, a);
+    }
+  }
   KParams P{};
   P.x = a.x;
   P.y = a.y;

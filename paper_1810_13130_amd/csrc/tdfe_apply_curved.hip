@@ -27,6 +27,7 @@ struct CurvedParams {
   double kin;
   const void* vw;
   const double* minv;
+  const float* minv32;  // FP32 copy (FP32 kernels)
   const double* corners;  // [n_cell][2][2][2][3]
   double* energy;
   const int* done;
@@ -75,63 +76,56 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   }
   const T* __restrict__ X = (const T*)P.x;
   T* __restrict__ Y = (T*)P.y;
+  // M^-1/2 in the kernel's precision (a conversion right after each load
+  // would make the gather wait for every value)
+  using MT = T;
+  const MT* __restrict__ MV;
+  if constexpr (sizeof(T) == 8)
+    MV = (const MT*)P.minv;
+  else
+    MV = (const MT*)P.minv32;
   T cs = (T)1;
   if (P.colscale && act) cs = (T)P.colscale[colg >> 1];
 
-  // block staging: weighted potential and the metric of the block's cells
+  // block staging in three steps, so that a wave waits for memory once and
+  // computes while its gather is in flight: (1) the block's potential and cell
+  // corners are loaded into registers and the phase A gather (values and
+  // M^-1/2 per node) is issued; (2) potential and corners go to LDS; (3) the
+  // metric of every Gauss point of the block is computed from the LDS corners;
+  // only then are the gathered values used.
+  constexpr int NV = (CPB * VOL + THREADS - 1) / THREADS;
+  constexpr int NCR = (CPB * 24 + THREADS - 1) / THREADS;
+  __shared__ double sC[CPB * 24];
+  __shared__ double sEW[2 * N];  // Gauss points, then weights
   {
-    const int64_t c0 = (int64_t)group * CPB;
-    // (zeros without a potential, so that phase B needs no branch on it)
-    for (int q = t; q < CPB * VOL; q += THREADS) {
-      const int64_t ce = c0 + q / VOL;
-      sV[q] = (P.vw && ce < P.n_cell) ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
-    }
-    for (int it = t; it < CPB * VOL; it += THREADS) {
-      const int sl = it / VOL, q = it % VOL;
-      const int64_t ce = c0 + sl;
-      T* g = sG + it * 6;
-      if (ce >= P.n_cell) {
-        for (int u = 0; u < 6; ++u) g[u] = (T)0;
-        continue;
+    constexpr tdfe1d::Rule R = tdfe1d::make_rule(N - 1);
+    if (t < 2 * N) {
+      double v = R.eta[0];
+#pragma unroll
+      for (int q = 0; q < N; ++q) {
+        v = t == q ? R.eta[q] : v;
+        v = t == N + q ? R.wq[q] : v;
       }
-      const int a = q % N, b = (q / N) % N, c = q / (N * N);
-      const double xa = P.eta[a], xb = P.eta[b], xc = P.eta[c];
-      const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
-                              {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
-      const double* C = P.corners + ce * 24;
-      double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      for (int vz = 0; vz < 2; ++vz)
-        for (int vy = 0; vy < 2; ++vy)
-          for (int vx = 0; vx < 2; ++vx) {
-            const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
-            const double d0 = (vx ? 0.5 : -0.5) * f[vy][1] * f[vz][2];
-            const double d1 = f[vx][0] * (vy ? 0.5 : -0.5) * f[vz][2];
-            const double d2 = f[vx][0] * f[vy][1] * (vz ? 0.5 : -0.5);
-            for (int d = 0; d < 3; ++d) {
-              J[d][0] += X3[d] * d0;
-              J[d][1] += X3[d] * d1;
-              J[d][2] += X3[d] * d2;
-            }
-          }
-      double A[3][3];  // adjugate rows: J^-1 = A / det
-      A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-      A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-      A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-      A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-      A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-      A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-      A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-      A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-      A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-      const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
-      const double s = P.kin * P.wq[a] * P.wq[b] * P.wq[c] / det;
-      g[0] = (T)(s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]));
-      g[1] = (T)(s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]));
-      g[2] = (T)(s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]));
-      g[3] = (T)(s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]));
-      g[4] = (T)(s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]));
-      g[5] = (T)(s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]));
+      sEW[t] = v;
     }
+  }
+  const int64_t c0 = (int64_t)group * CPB;
+  T vr[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int q = t + k * THREADS;
+    const int64_t ce = c0 + q / VOL;
+    // zeros without a potential, so that phase B needs no branch on it
+    const bool ok = P.vw && q < CPB * VOL && ce < P.n_cell;
+    vr[k] = ok ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
+  }
+  double cr[NCR];
+#pragma unroll
+  for (int k = 0; k < NCR; ++k) {
+    const int f = t + k * THREADS;
+    const bool ok = f < CPB * 24 && c0 + f / 24 < P.n_cell;
+    const double val = P.corners[ok ? c0 * 24 + f : 0];
+    cr[k] = ok ? val : 0.0;
   }
   auto sidx = [&](int y, int x, int z) { return (((slot * N + y) * N + x) * N + z) * CB + col; };
   const int NxI = P.Nx - 2, NyI = P.Ny - 2;
@@ -156,10 +150,78 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     nk = (int64_t)NxI * NyI;
   }
 
+  // metric of the block's Gauss points from the LDS corners (read in phase B,
+  // after the transposes' barriers); Gauss points and weights from LDS
+  auto compute_metric = [&]() {
+      for (int it = t; it < CPB * VOL; it += THREADS) {
+        const int sl = it / VOL, q = it % VOL;
+        const int64_t ce = c0 + sl;
+        T* g = sG + it * 6;
+        if (ce >= P.n_cell) {
+          for (int w6 = 0; w6 < 6; ++w6) g[w6] = (T)0;
+          continue;
+        }
+        const int a = q % N, b = (q / N) % N, c = q / (N * N);
+        const double xa = sEW[a], xb = sEW[b], xc = sEW[c];
+        const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
+                                {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
+        const double* C = sC + sl * 24;
+        double Jm[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+        for (int vz = 0; vz < 2; ++vz)
+          for (int vy = 0; vy < 2; ++vy)
+            for (int vx = 0; vx < 2; ++vx) {
+              const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
+              const double d0 = (vx ? 0.5 : -0.5) * f[vy][1] * f[vz][2];
+              const double d1 = f[vx][0] * (vy ? 0.5 : -0.5) * f[vz][2];
+              const double d2 = f[vx][0] * f[vy][1] * (vz ? 0.5 : -0.5);
+              for (int d = 0; d < 3; ++d) {
+                Jm[d][0] += X3[d] * d0;
+                Jm[d][1] += X3[d] * d1;
+                Jm[d][2] += X3[d] * d2;
+              }
+            }
+        double A[3][3];  // adjugate rows: J^-1 = A / det
+        A[0][0] = Jm[1][1] * Jm[2][2] - Jm[1][2] * Jm[2][1];
+        A[0][1] = Jm[0][2] * Jm[2][1] - Jm[0][1] * Jm[2][2];
+        A[0][2] = Jm[0][1] * Jm[1][2] - Jm[0][2] * Jm[1][1];
+        A[1][0] = Jm[1][2] * Jm[2][0] - Jm[1][0] * Jm[2][2];
+        A[1][1] = Jm[0][0] * Jm[2][2] - Jm[0][2] * Jm[2][0];
+        A[1][2] = Jm[0][2] * Jm[1][0] - Jm[0][0] * Jm[1][2];
+        A[2][0] = Jm[1][0] * Jm[2][1] - Jm[1][1] * Jm[2][0];
+        A[2][1] = Jm[0][1] * Jm[2][0] - Jm[0][0] * Jm[2][1];
+        A[2][2] = Jm[0][0] * Jm[1][1] - Jm[0][1] * Jm[1][0];
+        const double det = Jm[0][0] * A[0][0] + Jm[0][1] * A[1][0] + Jm[0][2] * A[2][0];
+        const double s = P.kin * sEW[N + a] * sEW[N + b] * sEW[N + c] / det;
+        g[0] = (T)(s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]));
+        g[1] = (T)(s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]));
+        g[2] = (T)(s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]));
+        g[3] = (T)(s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]));
+        g[4] = (T)(s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]));
+        g[5] = (T)(s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]));
+      }
+  };
+
   // ---------------- A: plane j = pl -------------------------------------------------------------
   T tu[N][N], tx[N][N];  // [x][z]
   {
-    T u[N][N];  // [i][k]
+    // FP64 (one wave per SIMD): the gather is issued first and the metric is
+    // computed while it is in flight.  FP32 (fewer registers to spare): metric
+    // first, then the gather.
+    if constexpr (sizeof(T) == 4) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int q = t + k * THREADS;
+        if (q < CPB * VOL) sV[q] = vr[k];
+      }
+#pragma unroll
+      for (int k = 0; k < NCR; ++k) {
+        const int f = t + k * THREADS;
+        if (f < CPB * 24) sC[f] = cr[k];
+      }
+      __syncthreads();
+      compute_metric();
+    }
+    T u[N][N], mv[N][N];  // [i][k]: gathered values and M^-1/2, all loads in flight together
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
@@ -168,9 +230,32 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
         // element 0 and are zeroed), so the gather has no branches
         const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
         const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
-        const T val = X[nd * P.ld + colg * (ok ? 1 : 0)];
-        const T mv = (T)P.minv[P.lowdin ? nd : 0];
-        u[i][k] = ok ? val * (P.lowdin ? mv * cs : cs) : (T)0;
+        u[i][k] = X[nd * P.ld + colg * (ok ? 1 : 0)];
+        mv[i][k] = MV[P.lowdin ? nd : 0];
+      }
+    // keep the scaling below from being interleaved with the loads (which
+    // would make each load wait for its own value)
+    __builtin_amdgcn_sched_barrier(0);
+    if constexpr (sizeof(T) == 8) {
+#pragma unroll
+      for (int k = 0; k < NV; ++k) {
+        const int q = t + k * THREADS;
+        if (q < CPB * VOL) sV[q] = vr[k];
+      }
+#pragma unroll
+      for (int k = 0; k < NCR; ++k) {
+        const int f = t + k * THREADS;
+        if (f < CPB * 24) sC[f] = cr[k];
+      }
+      __syncthreads();
+      compute_metric();
+    }
+#pragma unroll
+    for (int k = 0; k < N; ++k)
+#pragma unroll
+      for (int i = 0; i < N; ++i) {
+        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
+        u[i][k] = ok ? u[i][k] * (P.lowdin ? mv[i][k] * cs : cs) : (T)0;
       }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
@@ -335,14 +420,22 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) {
+      // the line's M^-1/2 values are loaded before its contraction, so that
+      // one wait per line covers them
+      T ml[N];
+#pragma unroll
+      for (int k = 0; k < N; ++k) {
+        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
+        const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
+        ml[k] = MV[P.lowdin ? nd : 0];
+      }
       T o[N];
       eo<T, N, 1>(FS.Bt, h[i], o);
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
         const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
-        const T mv = (T)P.minv[P.lowdin ? nd : 0];
-        const T val = P.lowdin ? o[k] * mv : o[k];
+        const T val = P.lowdin ? o[k] * ml[k] : o[k];
         if (ok) unsafeAtomicAdd(Y + (nd * P.ld + colg), val);
       }
     }
@@ -363,7 +456,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 template <typename T, int N, int CB>
 constexpr int cplane_lds(int cpb) {
   constexpr int VOL = N * N * N;
-  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) * 7 + cpb * N * CB * 8;
+  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) * 7 + cpb * N * CB * 8 + cpb * 24 * 8;
 }
 
 // cells per block: at most 512 threads; the metric makes a cell's LDS about
@@ -411,6 +504,7 @@ tdfe_status launch_curved(tdfe_ctx* c, const ApplyArgs& a) {
   P.kin = a.kin;
   P.vw = a.fp32 ? (const void*)a.vw32 : (const void*)a.vw;
   P.minv = c->minv;
+  P.minv32 = c->minv32;
   P.corners = c->corners;
   P.energy = a.energy;
   P.done = a.done_flag;
@@ -436,23 +530,21 @@ tdfe_status launch_curved(tdfe_ctx* c, const ApplyArgs& a) {
     case 5: return launch_cplane_n<T, 5>(c, P, a.n_blocks_out);
     case 6: return launch_cplane_n<T, 6>(c, P, a.n_blocks_out);
     case 7: return launch_cplane_n<T, 7>(c, P, a.n_blocks_out);
-    case 8:
-      if constexpr (sizeof(T) == 4) return launch_cplane_n<T, 8>(c, P, a.n_blocks_out);
-      break;
+    case 8: return launch_cplane_n<T, 8>(c, P, a.n_blocks_out);
   }
   return tdfe_fail(c, TDFE_EINVAL, "curved operator: unsupported order p=%d", c->p);
 }
 
 }  // namespace
 
-// true if the curved plane kernel handles this launch: trilinear cells, two or
-// more real columns (a single column leaves the metric staged in LDS for
-// only n threads per cell: a block of cells then has a few dozen threads, and
-// the line-ownership kernel measured 3.4x faster on the one-column stiffness
-// products of the Hartree solve), p <= 6, and p = 7 in FP32 (an FP64 plane of
-// 8 x 8 spills to scratch and runs slower than the line-ownership kernel)
+// true if the curved plane kernel handles this launch: trilinear cells, p <= 7,
+// two or more real columns (one column leaves n threads per cell with the
+// metric staged for the whole cell: the line kernel is faster there, 0.64 ms
+// against 2.2 ms for the one-column stiffness products of the Hartree solve on
+// the graded mesh)
 bool tdfe_curved_kernel_ok(const tdfe_ctx* c, int cols, bool fp32) {
-  return !c->box && cols >= 2 && (c->n <= 7 || (fp32 && c->n == 8));
+  (void)fp32;
+  return !c->box && cols >= 2 && c->n <= 8;
 }
 
 tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a) {

@@ -11,8 +11,9 @@
 // quad permutation.  The mirror symmetry of the 1D tables
 // (A[n-1-c][n-1-k] = S A[c][k], S = +1 for B, -1 for D and Dg) makes the two
 // lanes run identical code with identical coefficients: lane 1 only multiplies
-// its inputs by S.  All tables are compile-time constants (make_pairset).  A lane then keeps half the registers of a plane-owning
-// thread, which lets FP64 run more than one wave per SIMD.
+// its inputs by S.  All tables are compile-time constants (make_pairset).  A
+// lane then keeps half the registers of a plane-owning thread, which lets FP64
+// run two waves per SIMD.
 #include "tdfe_fold.h"
 
 namespace {
@@ -203,13 +204,40 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
   T cs = (T)1;
   if (P.colscale && act) cs = (T)P.colscale[colg >> 1];
 
-  if (P.vw) {
-    const int64_t c0 = (int64_t)group * CPB;
-    for (int q = t; q < CPB * VOL; q += THREADS) {
-      const int64_t ce = c0 + q / VOL;
-      sV[q] = ce < P.n_cell ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
-    }
+  // block staging (as in the plane kernel): potential, M^-1/2 factors along
+  // x, y, z and the metric of the block's cells; loads issued before the
+  // phase A gather, LDS stores after it, one wait for memory per wave
+  constexpr int NFC = 3 * N + 3;
+  constexpr int NV = (CPB * VOL + THREADS - 1) / THREADS;
+  constexpr int NF = (CPB * NFC + THREADS - 1) / THREADS;
+  __shared__ double sF[CPB * NFC];
+  const int64_t c0 = (int64_t)group * CPB;
+  T vr[NV];
+#pragma unroll
+  for (int k = 0; k < NV; ++k) {
+    const int q = t + k * THREADS;
+    const int64_t ce = c0 + q / VOL;
+    const bool ok = P.vw && q < CPB * VOL && ce < P.n_cell;
+    vr[k] = ok ? ((const T*)P.vw)[ce * VOL + q % VOL] : (T)0;
   }
+  double fr[NF];
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    const int f = t + k * THREADS;
+    const int r = f % NFC;
+    const int64_t ce = c0 + f / NFC;
+    const bool ok = f < CPB * NFC && ce < P.n_cell;
+    const int64_t cv = ok ? ce : 0;
+    const int ex = (int)(cv % P.ncx), ey = (int)((cv / P.ncx) % P.ncy);
+    const int ez = (int)(cv / ((int64_t)P.ncx * P.ncy));
+    const double* src = r < N ? P.m1x + (ex * P.p + r)
+                        : r < 2 * N ? P.m1y + (ey * P.p + r - N)
+                        : r < 3 * N ? P.m1z + (ez * P.p + r - 2 * N)
+                                    : P.cellgeo + (cv * 4 + r - 3 * N);
+    const double val = *src;
+    fr[k] = ok ? val : 0.0;
+  }
+  const double* sFc = sF + slot * NFC;
   auto sidx = [&](int y, int x, int z) { return (((slot * N + y) * N + x) * N + z) * CB + col; };
   const int NxI = P.Nx - 2, NyI = P.Ny - 2;
 
@@ -221,7 +249,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
     int64_t e0, kstride;
     T fx[N], fz[H], my;
   };
-  auto plane_nodes = [&](PlaneNodes& Q) {
+  auto plane_nodes = [&](PlaneNodes& Q, bool factors) {
     const int J = cy * P.p + pl;
     const bool jok = P.fullgrid ? true : (J > 0 && J < P.Ny - 1);
     Q.imask = 0;
@@ -250,14 +278,14 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
     for (int q = 0; q < N; ++q) Q.fx[q] = (T)1;
 #pragma unroll
     for (int q = 0; q < H; ++q) Q.fz[q] = (T)1;
-    if (P.lowdin && Q.imask) {
-      Q.my = (T)P.m1y[J];
+    if (factors && P.lowdin && Q.imask) {
+      Q.my = (T)sFc[N + pl];
 #pragma unroll
       for (int q = 0; q < N; ++q)
-        if ((Q.imask >> q) & 1u) Q.fx[q] = (T)P.m1x[cx * P.p + q];
+        if ((Q.imask >> q) & 1u) Q.fx[q] = (T)sFc[q];
 #pragma unroll
       for (int q = 0; q < H; ++q)
-        if ((Q.kmask >> q) & 1u) Q.fz[q] = (T)P.m1z[cz * P.p + zg(q)];
+        if ((Q.kmask >> q) & 1u) Q.fz[q] = (T)sFc[2 * N + zg(q)];
     }
   };
 
@@ -265,7 +293,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
   T tu[N][H], tx[N][H];  // [x point][local z]
   {
     PlaneNodes Q;
-    plane_nodes(Q);
+    plane_nodes(Q, false);
     T u[N][H];
 #pragma unroll
     for (int k = 0; k < H; ++k)
@@ -274,8 +302,24 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
         const bool ok = ((Q.imask >> i) & (Q.kmask >> k) & 1u) != 0;
         const int64_t e = ok ? Q.e0 + (int64_t)i * P.ld + (int64_t)zg(k) * Q.kstride : 0;
         const T val = X[e];
-        u[i][k] = ok ? val * (Q.fx[i] * Q.fz[k] * (Q.my * cs)) : (T)0;
+        u[i][k] = ok ? val : (T)0;
       }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int q = t + k * THREADS;
+      if (q < CPB * VOL) sV[q] = vr[k];
+    }
+#pragma unroll
+    for (int k = 0; k < NF; ++k) {
+      const int f = t + k * THREADS;
+      if (f < CPB * NFC) sF[f] = fr[k];
+    }
+    __syncthreads();
+    plane_nodes(Q, true);
+#pragma unroll
+    for (int k = 0; k < H; ++k)
+#pragma unroll
+      for (int i = 0; i < N; ++i) u[i][k] *= Q.fx[i] * Q.fz[k] * (Q.my * cs);
 #pragma unroll
     for (int k = 0; k < H; ++k) {
       T line[N], o1[N], o2[N];
@@ -328,14 +372,18 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
   double energy = 0.0;
   T gx = 0, gy = 0, gz = 0;
   if (cell_ok) {
-    const T wa = (T)P.wq[pl];
-    gx = (T)(P.kin * P.cellgeo[cell * 4 + 0]) * wa;
-    gy = (T)(P.kin * P.cellgeo[cell * 4 + 1]) * wa;
-    gz = (T)(P.kin * P.cellgeo[cell * 4 + 2]) * wa;
-  }
-  T wc[H];  // z Gauss weights of this lane's points
+    T wa = (T)FS.wq[0];  // selected from the constants: no per-lane memory load
 #pragma unroll
-  for (int c = 0; c < H; ++c) wc[c] = (T)(h ? P.wq[N - 1 - c] : P.wq[c]);
+    for (int q = 1; q < N; ++q) wa = pl == q ? (T)FS.wq[q] : wa;
+    gx = (T)(P.kin * sFc[3 * N + 0]) * wa;
+    gy = (T)(P.kin * sFc[3 * N + 1]) * wa;
+    gz = (T)(P.kin * sFc[3 * N + 2]) * wa;
+  }
+  // z Gauss weights of this lane's points: the rule's weights are symmetric
+  // (bitwise, for every order), so the mirror point's weight is wq[c] itself
+  T wc[H];
+#pragma unroll
+  for (int c = 0; c < H; ++c) wc[c] = (T)FS.wq[c];
   // B1: x flux from w, transposed y interpolation, into the transpose buffer
 #pragma unroll
   for (int c = 0; c < H; ++c) {
@@ -453,7 +501,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
       for (int i = 0; i < N; ++i) hh[i][c] = o1[i] + o2[i];
     }
     PlaneNodes Q;
-    plane_nodes(Q);
+    plane_nodes(Q, true);
 #pragma unroll
     for (int i = 0; i < N; ++i) {
       T o[H];
@@ -483,7 +531,7 @@ __global__ void __launch_bounds__(2 * CPB * N * CB) __attribute__((amdgpu_waves_
 template <typename T, int N, int CB>
 constexpr int pair_lds(int cpb) {
   constexpr int VOL = N * N * N;
-  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) + 2 * cpb * N * CB * 8;
+  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) + 2 * cpb * N * CB * 8 + cpb * (3 * N + 3) * 8;
 }
 
 // cells per block: at most 256 threads (blocks of a few waves pack the CUs
@@ -558,7 +606,7 @@ tdfe_status launch_pair_box(tdfe_ctx* c, const ApplyArgs& a) {
 
 }  // namespace
 
-// true if the paired box kernel can handle this context (rectilinear mesh, odd p <= 7)
+// true if the lane-pair box kernel can handle this context (rectilinear mesh, odd p <= 7)
 bool tdfe_pair_kernel_ok(const tdfe_ctx* c) { return c->box && c->n % 2 == 0 && c->n <= 8; }
 
 tdfe_status tdfe_launch_apply_pair(tdfe_ctx* c, const ApplyArgs& a) {

@@ -22,8 +22,10 @@ struct tdfe_ctx {
   int Nx = 0, Ny = 0, Nz = 0;
   int n_orb_max = 0, k_max = 0, precision = TDFE_FP64;
   bool box = false;  // rectilinear grid: axis-aligned cells
-  bool force_line_kernel = false;  // use the line-ownership operator kernel on every mesh
-  int box_variant = 0;             // box meshes: 0 = plane kernel, 1 = lane-pair kernel (even n)
+  // operator kernel choice (TDFE_APPLY_VARIANT at creation): 0 default policy
+  // (see tdfe_launch_apply), 1 "line" everywhere, 2 "pair" for box cells of
+  // even n in both precisions, 3 "plane" kernels wherever they exist
+  int variant = 0;
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -44,6 +46,7 @@ struct tdfe_ctx {
   // device pointers into the workspace
   double* tab = nullptr;      // device copy of the 1D tables (see tab_* offsets)
   double* minv = nullptr;     // [n_dof] M^-1/2
+  float* minv32 = nullptr;    // [n_dof] FP32 copy (mixed contexts)
   double* mdiag = nullptr;    // [n_dof] M
   double* dofxyz = nullptr;   // [n_dof][3]
   double* nodexyz_ptr = nullptr;  // [n_nodes][3]
@@ -148,6 +151,9 @@ bool tdfe_pair_kernel_ok(const tdfe_ctx* c);
 tdfe_status tdfe_launch_apply_pair(tdfe_ctx* c, const ApplyArgs& a);
 // trilinear-cell variant in the same layout (tdfe_apply_curved.hip)
 bool tdfe_curved_kernel_ok(const tdfe_ctx* c, int cols, bool fp32);
+#define TDFE_VARIANT_LINE 1
+#define TDFE_VARIANT_PAIR 2
+#define TDFE_VARIANT_PLANE 3
 tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a);
 
 // mixed precision: floor of the Lanczos stop tolerance relative to ||psibar||

@@ -90,8 +90,8 @@ __global__ void quad_geometry_kernel(GeoParams P, double* xq, double* wdet, int*
 
 // per global node: position, GLL-lumped overlap summed over the cells that
 // contain it (fixed order), and the DoF outputs for interior nodes
-__global__ void node_kernel(GeoParams P, double* nodexyz, double* mdiag, double* minv, double* dofxyz,
-                            int* bad) {
+__global__ void node_kernel(GeoParams P, double* nodexyz, double* mdiag, double* minv, float* minv32,
+                            double* dofxyz, int* bad) {
   const int64_t nn = (int64_t)P.Nx * P.Ny * P.Nz;
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= nn) return;
@@ -133,6 +133,7 @@ __global__ void node_kernel(GeoParams P, double* nodexyz, double* mdiag, double*
     const int64_t dof = (I - 1) + (int64_t)(P.Nx - 2) * ((J - 1) + (int64_t)(P.Ny - 2) * (K - 1));
     mdiag[dof] = m;
     minv[dof] = 1.0 / sqrt(m);
+    if (minv32) minv32[dof] = (float)(1.0 / sqrt(m));
     dofxyz[dof * 3 + 0] = x[0];
     dofxyz[dof * 3 + 1] = x[1];
     dofxyz[dof * 3 + 2] = x[2];
@@ -210,6 +211,8 @@ void carve(tdfe_ctx* c, char* base) {
   c->partial = k.take<double>(c->n_partial);
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
   c->counters = k.take<unsigned>(256);
+  // FP32 copy of M^-1/2 for the mixed path's operator (placed last)
+  c->minv32 = c->precision == TDFE_FP64 ? k.take<float>(1) : k.take<float>(nd);
   c->ws_need = k.off + 256;
   // node coordinates live right after dofxyz; keep the pointer in the ctx via fb's neighbour
   c->nodexyz_ptr = nodexyz;
@@ -295,8 +298,10 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
   c->box = box;
   {
     const char* v = std::getenv("TDFE_APPLY_VARIANT");
-    c->force_line_kernel = v && std::strcmp(v, "line") == 0;
-    c->box_variant = (v && std::strcmp(v, "pair") == 0) ? 1 : 0;
+    c->variant = 0;
+    if (v && std::strcmp(v, "line") == 0) c->variant = TDFE_VARIANT_LINE;
+    if (v && std::strcmp(v, "pair") == 0) c->variant = TDFE_VARIANT_PAIR;
+    if (v && std::strcmp(v, "plane") == 0) c->variant = TDFE_VARIANT_PLANE;
   }
 
   // Krylov chunk: as many orbitals as fit in 60% of the device memory free at
@@ -428,7 +433,8 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
   {
     const int64_t n = c->n_nodes;
     hipLaunchKernelGGL(node_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, G,
-                       c->nodexyz_ptr, c->mdiag, c->minv, c->dofxyz, bad);
+                       c->nodexyz_ptr, c->mdiag, c->minv, c->precision == TDFE_FP64 ? nullptr : c->minv32,
+                       c->dofxyz, bad);
     TDFE_HIP(c, hipGetLastError());
   }
   int hbad = 0;

@@ -1,12 +1,15 @@
-"""GPU parity of the lane-pair operator kernel on box cells (even n = p + 1).
+"""GPU parity of the two box-cell operator kernels at even n = p + 1.
 
-The kernel is selected with TDFE_APPLY_VARIANT=pair at context creation.  Each
-odd order p = 1, 3, 5, 7 is checked against the FP64 oracle on a small box mesh
+The lane-pair kernel (two lanes per plane) is the FP64 default at even n; the
+plane kernel is the FP32 default and serves every odd n.  TDFE_APPLY_VARIANT
+(read at context creation) selects either one for both precisions.  Each odd
+order p = 1, 3, 5, 7 is checked against the FP64 oracle on a small box mesh
 with an uneven cell count per axis and an orbital count that selects a
 different column-block width (ragged chunks included), in FP64 (1e-12) and in
-FP32 storage (2e-6); the Lanczos exponential exercises the kernel's per-column
-quadratic form (the Lanczos alpha), and the benchmark workload's full-size
-operator is compared with the oracle and with the plane kernel.
+FP32 storage (2e-6), for both kernels; the Lanczos exponential exercises the
+kernels' per-column quadratic form (the Lanczos alpha); and the benchmark
+workload's full-size operator is compared across the kernels and with the
+oracle.
 """
 import numpy as np
 import pytest
@@ -22,17 +25,14 @@ MIXED = 1
 ORBS = {1: 1, 3: 5, 5: 9, 7: 2}
 
 
-@pytest.fixture
-def pair(monkeypatch):
-    monkeypatch.setenv("TDFE_APPLY_VARIANT", "pair")
-
-
 def _box(p, n_orb, ncell=(3, 2, 2)):
     return W.scaled(W.CONFIGS[2], ncell=ncell, p=p, n_orb=n_orb)
 
 
+@pytest.mark.parametrize("variant", ["pair", "plane"])
 @pytest.mark.parametrize("p", sorted(ORBS))
-def test_pair_operator_fp64(p, pair):
+def test_box_operator_fp64(p, variant, monkeypatch):
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", variant)
     n_orb = ORBS[p]
     cfg = _box(p, n_orb)
     ctx = gpu_context(cfg, n_orb=n_orb, k_max=4)
@@ -42,8 +42,10 @@ def test_pair_operator_fp64(p, pair):
     assert rel(y, op.apply_Hbar(m, vq, x)) < 1e-12
 
 
+@pytest.mark.parametrize("variant", ["pair", "plane"])
 @pytest.mark.parametrize("p", sorted(ORBS))
-def test_pair_operator_fp32(p, pair):
+def test_box_operator_fp32(p, variant, monkeypatch):
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", variant)
     n_orb = ORBS[p]
     cfg = _box(p, n_orb)
     ctx = gpu_context(cfg, n_orb=n_orb, k_max=4, precision=MIXED)
@@ -55,7 +57,9 @@ def test_pair_operator_fp32(p, pair):
     assert rel(y.cpu().numpy(), op.apply_Hbar(m, vq, x)) < 2e-6
 
 
-def test_pair_lanczos_matches_oracle(pair):
+@pytest.mark.parametrize("variant", ["pair", "plane"])
+def test_box_lanczos_matches_oracle(variant, monkeypatch):
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", variant)
     cfg = W.scaled(W.CONFIGS[2], ncell=(4, 4, 4), p=5, n_orb=3)
     ctx = gpu_context(cfg, n_orb=3)
     m, vq = oracle_mesh(cfg)
@@ -68,12 +72,12 @@ def test_pair_lanczos_matches_oracle(pair):
     assert all(abs(a - b) <= 1 for a, b in zip(ks, kref))
 
 
-def test_pair_full_size_benchmark_operator(monkeypatch):
+def test_box_kernels_agree_on_full_size_benchmark_operator(monkeypatch):
     cfg = W.CONFIGS[2]
     m, vq = oracle_mesh(cfg)
     x = torch.from_numpy(W.random_block(m.n_dof, cfg.n_orb, 7)).cuda()
+    y_default = gpu_context(cfg, k_max=4).apply_H(x).cpu().numpy()
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", "plane")
     y_plane = gpu_context(cfg, k_max=4).apply_H(x).cpu().numpy()
-    monkeypatch.setenv("TDFE_APPLY_VARIANT", "pair")
-    y_pair = gpu_context(cfg, k_max=4).apply_H(x).cpu().numpy()
-    assert rel(y_pair, y_plane) < 1e-13
-    assert rel(y_pair, op.apply_Hbar(m, vq, x.cpu().numpy())) < 1e-12
+    assert rel(y_default, y_plane) < 1e-13
+    assert rel(y_default, op.apply_Hbar(m, vq, x.cpu().numpy())) < 1e-12

@@ -1,8 +1,8 @@
 """GPU parity of the operator on trilinear (curved) cells, every supported order.
 
 The curved-cell operator has two kernels: the plane-ownership kernel (two or
-more real columns at orders p <= 6, and p = 7 in FP32) and the line-ownership
-kernel (one column, FP64 at p = 7 and p = 8, or on request).  Each order is
+more real columns at orders p <= 7) and the line-ownership kernel (one
+column, p = 8, or on request).  Each order is
 checked against the FP64 oracle on a small graded mesh with an uneven cell
 count per axis and an orbital count that selects a different column-block
 width (ragged column chunks included), in FP64 (1e-12) and in FP32 storage
