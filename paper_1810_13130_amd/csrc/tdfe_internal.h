@@ -92,6 +92,7 @@ struct tdfe_ctx {
   bool bound = false, have_potential = false, have_scf = false, scf_init = false;
   int hartree = 0, xc = 0;
   std::vector<double> nucZ, nucR, occ, occ_host;
+  int occ_ver = 0, occ_dev_ver = -1, occ_dev_n = -1;  // device copy of the occupations is current when equal
   double pcg_tol = 1e-13;
   int pcg_maxit = 5000;
   int last_poisson_iters = 0;
@@ -165,7 +166,14 @@ tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a);
 tdfe_status tdfe_poll_events(tdfe_ctx* c);
 
 // vector kernels (tdfe_lanczos.hip)
+// zero fill of a word-aligned device range (a kernel, not hipMemsetAsync)
 tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes);
+// pinned readback area: ints [TDFE_READBACK_OFFSET_INTS, 4096) of c->poll
+#define TDFE_READBACK_OFFSET_INTS 1024
+#define TDFE_READBACK_BYTES (3072 * 4)
+// enqueue a copy of `bytes` device bytes to readback offset `off`; *host is
+// valid after the stream has been synchronised
+tdfe_status tdfe_readback(tdfe_ctx* c, const void* dev_src, size_t bytes, size_t off, const void** host);
 // called once per orbital chunk after the adaptive loop (before the combination):
 // W = basis storage (k_max+1 vectors of vstride elements, float if fp32),
 // scale[j*Nc+o] = 1/beta_{j}, kconv/alpha/beta/nrm as in the Lanczos scalar block

@@ -393,8 +393,8 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   const double tol_rel = sizeof(T) == 4 ? TDFE_MIXED_TOL_FLOOR : 0.0;
 
   hipLaunchKernelGGL(init_scal_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc);
-  TDFE_HIP(c, hipMemsetAsync(Hq, 0, (size_t)vstride * sizeof(T), c->stream));
-  TDFE_HIP(c, hipMemsetAsync(err_flag, 0, sizeof(int), c->stream));
+  TDFE_TRY(tdfe_zero(c, Hq, (size_t)vstride * sizeof(T)));
+  TDFE_TRY(tdfe_zero(c, err_flag, sizeof(int)));
   hipLaunchKernelGGL((copy_in_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, in, ld, 2 * o0, W, C, nd,
                      c->partial);
   hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
@@ -468,19 +468,19 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                        vstride, C, nd, S, Nc, K, out, ld, 2 * o0);
     TDFE_HIP(c, hipGetLastError());
   }
-  std::vector<int> kc(Nc), st(Nc);
-  std::vector<double> er(Nc);
-  int ef = 0;
-  TDFE_HIP(c, hipMemcpyAsync(kc.data(), S.kconv, Nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  TDFE_HIP(c, hipMemcpyAsync(st.data(), S.status, Nc * sizeof(int), hipMemcpyDeviceToHost, c->stream));
-  TDFE_HIP(c, hipMemcpyAsync(er.data(), S.err, Nc * sizeof(double), hipMemcpyDeviceToHost, c->stream));
-  TDFE_HIP(c, hipMemcpyAsync(&ef, err_flag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  // results through the pinned readback area (Nc <= 32: 128 + 128 + 256 + 4 bytes)
+  const void *hk = nullptr, *hs = nullptr, *he = nullptr, *hf = nullptr;
+  TDFE_TRY(tdfe_readback(c, S.kconv, Nc * sizeof(int), 0, &hk));
+  TDFE_TRY(tdfe_readback(c, S.status, Nc * sizeof(int), 256, &hs));
+  TDFE_TRY(tdfe_readback(c, S.err, Nc * sizeof(double), 512, &he));
+  TDFE_TRY(tdfe_readback(c, err_flag, sizeof(int), 1024, &hf));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
   for (int o = 0; o < Nc; ++o) {
-    k_out[o] = kc[o];
-    err_out[o] = er[o];
-    status_out[o] = st[o];
+    k_out[o] = ((const volatile int*)hk)[o];
+    err_out[o] = ((const volatile double*)he)[o];
+    status_out[o] = ((const volatile int*)hs)[o];
   }
+  const int ef = *(const volatile int*)hf;
   if (ef) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
   return TDFE_OK;
 }
@@ -500,8 +500,44 @@ tdfe_status tdfe_poll_events(tdfe_ctx* c) {
   return TDFE_OK;
 }
 
+// zero fill by a kernel: hipMemsetAsync costs tens of microseconds of stream
+// idle time around its own fill launch, more than the fill itself here
+__global__ void zero_kernel(unsigned* p, int64_t nwords) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t n4 = ((uintptr_t)p % 16 == 0) ? nwords / 4 : 0;
+  uint4* q = (uint4*)p;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += stride) q[i] = make_uint4(0, 0, 0, 0);
+  for (int64_t i = 4 * n4 + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nwords; i += stride) p[i] = 0u;
+}
+
 tdfe_status tdfe_zero(tdfe_ctx* c, void* p, size_t bytes) {
-  TDFE_HIP(c, hipMemsetAsync(p, 0, bytes, c->stream));
+  if (bytes == 0) return TDFE_OK;
+  if (bytes % 4 != 0 || (uintptr_t)p % 4 != 0) return tdfe_fail(c, TDFE_EINVAL, "zero fill: size or address not word aligned");
+  const int64_t nw = (int64_t)(bytes / 4);
+  const int64_t blocks = std::min<int64_t>((nw / 4 + 255) / 256 + 1, 4096);
+  hipLaunchKernelGGL(zero_kernel, dim3((unsigned)blocks), dim3(256), 0, c->stream, (unsigned*)p, nw);
+  TDFE_HIP(c, hipGetLastError());
+  return TDFE_OK;
+}
+
+// copy of a few device words into the pinned readback area; the kernel's
+// stores reach host memory before the stream completes, so one stream
+// synchronisation makes all readbacks of a call visible
+__global__ void readback_kernel(const unsigned* src, unsigned* dst, int nwords) {
+  for (int i = threadIdx.x; i < nwords; i += blockDim.x) dst[i] = src[i];
+  __threadfence_system();
+}
+
+tdfe_status tdfe_readback(tdfe_ctx* c, const void* dev_src, size_t bytes, size_t off, const void** host) {
+  if (bytes % 4 != 0 || off % 8 != 0 || off + bytes > TDFE_READBACK_BYTES)
+    return tdfe_fail(c, TDFE_EINVAL, "readback: %zu bytes at offset %zu", bytes, off);
+  char* h = (char*)(c->poll + TDFE_READBACK_OFFSET_INTS) + off;
+  void* d = nullptr;
+  TDFE_HIP(c, hipHostGetDevicePointer(&d, (void*)h, 0));
+  hipLaunchKernelGGL(readback_kernel, dim3(1), dim3(256), 0, c->stream, (const unsigned*)dev_src, (unsigned*)d,
+                     (int)(bytes / 4));
+  TDFE_HIP(c, hipGetLastError());
+  *host = h;
   return TDFE_OK;
 }
 
@@ -581,7 +617,7 @@ static tdfe_status apply_checked(tdfe_ctx* c, const void* dev_psibar, void* dev_
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "apply_H before bind_workspace");
   if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "apply_H before set_potential");
   const int cols = 2 * n_orb;
-  if (zero) TDFE_HIP(c, hipMemsetAsync(dev_out, 0, (size_t)c->n_dof * cols * sizeof(double), c->stream));
+  if (zero) TDFE_TRY(tdfe_zero(c, dev_out, (size_t)c->n_dof * cols * sizeof(double)));
   ApplyArgs a{};
   a.x = dev_psibar;
   a.y = dev_out;

@@ -19,6 +19,7 @@
 #include <cmath>
 
 #include "tdfe_internal.h"
+#include "tdfe_fold.h"
 
 namespace {
 
@@ -57,18 +58,17 @@ template <int N, int CB>
 __global__ void __launch_bounds__(N* N* CB) density_kernel(DensParams P) {
   constexpr int VOL = N * N * N;
   constexpr int T = N * N * CB;
+  // folded interpolation table B as compile-time constants
+  constexpr FoldSet<N> FS = make_foldset<N>();
   __shared__ double sU[VOL * CB];
-  __shared__ double sB[N * N];
   __shared__ double sred[T];
   const int t = threadIdx.x;
   const int col = t % CB, line = t / CB;
   const int64_t cell = blockIdx.x;
-  for (int i = t; i < N * N; i += T) sB[i] = P.tab[TAB_B + (i / N) * TDFE_MAXN + (i % N)];
   const int cx = (int)(cell % P.ncx), cy = (int)((cell / P.ncx) % P.ncy), cz = (int)(cell / ((int64_t)P.ncx * P.ncy));
   double racc[N];
 #pragma unroll
   for (int a = 0; a < N; ++a) racc[a] = 0.0;
-  __syncthreads();
   auto L = [&](int z, int y, int x) { return ((z * N + y) * N + x) * CB + col; };
   for (int c0 = 0; c0 < P.cols; c0 += CB) {
     const int cg = c0 + col;
@@ -77,36 +77,35 @@ __global__ void __launch_bounds__(N* N* CB) density_kernel(DensParams P) {
     {
       const int i = line % N, j = line / N;
       const int I = cx * P.p + i, J = cy * P.p + j;
+      // branch-free gather: all loads of the z-line (values and M^-1/2) are
+      // issued from valid addresses before any is used
+      double v[N], m[N];
+      unsigned inm = 0;  // interior nodes of the line
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         const int K = cz * P.p + k;
-        double v = 0.0;
-        if (ok && I > 0 && I < P.Nx - 1 && J > 0 && J < P.Ny - 1 && K > 0 && K < P.Nz - 1) {
-          const int64_t d = dof_of(I, J, K, P.Nx, P.Ny);
-          v = P.psi[d * P.cols + cg] * P.minv[d];
-        }
-        r1[k] = v;
+        const bool in = ok && I > 0 && I < P.Nx - 1 && J > 0 && J < P.Ny - 1 && K > 0 && K < P.Nz - 1;
+        if (in) inm |= 1u << k;
+        const int64_t d = in ? dof_of(I, J, K, P.Nx, P.Ny) : 0;
+        v[k] = P.psi[d * P.cols + (in ? cg : 0)];
+        m[k] = P.minv[d];
       }
 #pragma unroll
-      for (int c = 0; c < N; ++c) {
-        double s = 0;
+      for (int k = 0; k < N; ++k) r1[k] = ((inm >> k) & 1u) ? v[k] * m[k] : 0.0;
+      double o[N];
+      eo<double, N, 1>(FS.B, r1, o);
 #pragma unroll
-        for (int k = 0; k < N; ++k) s += sB[c * N + k] * r1[k];
-        sU[L(c, j, i)] = s;
-      }
+      for (int c = 0; c < N; ++c) sU[L(c, j, i)] = o[c];
     }
     __syncthreads();
     {
       const int i = line % N, c = line / N;
 #pragma unroll
       for (int j = 0; j < N; ++j) r1[j] = sU[L(c, j, i)];
+      double o[N];
+      eo<double, N, 1>(FS.B, r1, o);
 #pragma unroll
-      for (int b = 0; b < N; ++b) {
-        double s = 0;
-#pragma unroll
-        for (int j = 0; j < N; ++j) s += sB[b * N + j] * r1[j];
-        sU[L(c, b, i)] = s;
-      }
+      for (int b = 0; b < N; ++b) sU[L(c, b, i)] = o[b];
     }
     __syncthreads();
     {
@@ -114,13 +113,10 @@ __global__ void __launch_bounds__(N* N* CB) density_kernel(DensParams P) {
 #pragma unroll
       for (int i = 0; i < N; ++i) r1[i] = sU[L(c, b, i)];
       const double f = ok ? P.occ[cg >> 1] : 0.0;
+      double o[N];
+      eo<double, N, 1>(FS.B, r1, o);
 #pragma unroll
-      for (int a = 0; a < N; ++a) {
-        double s = 0;
-#pragma unroll
-        for (int i = 0; i < N; ++i) s += sB[a * N + i] * r1[i];
-        racc[a] += f * s * s;
-      }
+      for (int a = 0; a < N; ++a) racc[a] += f * o[a] * o[a];
     }
     __syncthreads();
   }
@@ -824,6 +820,12 @@ tdfe_status interp_launch_f(tdfe_ctx* c, const double* phi, const double* rho, i
 tdfe_status upload_occ(tdfe_ctx* c, int n_orb, double** dev) {
   // occupations live in the scalar block's tail
   double* occ = c->scal + (size_t)(8 * c->k_max + 32) * c->n_orb_max - c->n_orb_max;
+  *dev = occ;
+  // uploaded once per set of occupations and orbital count (an upload per
+  // density evaluation would stall the stream for a host staging copy)
+  if (c->occ_dev_ver == c->occ_ver && c->occ_dev_n == n_orb) return TDFE_OK;
+  c->occ_dev_ver = c->occ_ver;
+  c->occ_dev_n = n_orb;
   // persistent host copy: the asynchronous upload may still read it after return
   c->occ_host.assign(c->n_orb_max, 1.0);
   for (int o = 0; o < n_orb && o < (int)c->occ.size(); ++o) c->occ_host[o] = c->occ[o];
@@ -1135,7 +1137,7 @@ tdfe_status pcg_solve(tdfe_ctx* c) {
   };
   hipLaunchKernelGGL(pcg_rhs_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, c->cload, (const double*)c->lift,
                      (const double*)c->phi, x, c->Nx, c->Ny, c->Nz);
-  TDFE_HIP(c, hipMemsetAsync(Ap, 0, nn * sizeof(double), c->stream));
+  TDFE_TRY(tdfe_zero(c, Ap, nn * sizeof(double)));
   TDFE_TRY(apply_K(x, false, nullptr));
   hipLaunchKernelGGL(pcg_start_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, (const double*)c->cload, r, z, pv, Ap,
                      (const double*)c->dinvK, nn, part);
@@ -1172,9 +1174,11 @@ tdfe_status pcg_solve(tdfe_ctx* c) {
   hipLaunchKernelGGL(pcg_store_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, (const double*)x, c->phi, c->Nx, c->Ny,
                      c->Nz);
   TDFE_HIP(c, hipGetLastError());
-  int fl[3];
-  TDFE_HIP(c, hipMemcpyAsync(fl, flags, 3 * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  const void* hfl = nullptr;
+  TDFE_TRY(tdfe_readback(c, flags, 3 * sizeof(int), 2048, &hfl));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  int fl[3];
+  for (int i = 0; i < 3; ++i) fl[i] = ((const volatile int*)hfl)[i];
   c->last_poisson_iters = fl[1];
   if (fl[2] == 2) return tdfe_fail(c, TDFE_ENONFINITE, "Hartree CG: p^T K p <= 0");
   if (fl[2] == 1 || !fl[0])
@@ -1215,7 +1219,7 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
   hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
   TDFE_HIP(c, hipGetLastError());
   if (c->hartree) {
-    TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
+    TDFE_TRY(tdfe_zero(c, c->cload, c->n_nodes * sizeof(double)));
     TDFE_TRY(load_launch(c));
     if (c->box) {
       TDFE_TRY(fdm_solve(c, true, c->phi));
@@ -1225,9 +1229,11 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
   }
   TDFE_TRY(interp_launch(c, W));
   if (mu || charge) {
-    double h[4];
-    TDFE_HIP(c, hipMemcpyAsync(h, red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    const void* hr = nullptr;
+    TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hr));
     TDFE_HIP(c, hipStreamSynchronize(c->stream));
+    double h[4];
+    for (int i = 0; i < 4; ++i) h[i] = ((const volatile double*)hr)[i];
     if (charge) *charge = h[0];
     if (mu) {
       mu[0] = h[1];
@@ -1262,7 +1268,7 @@ tdfe_status tdfe_fdm_setup(tdfe_ctx* c) {
 
 // lift = (K f)_interior with f the boundary data (interior zero)
 tdfe_status tdfe_compute_lift(tdfe_ctx* c) {
-  TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
+  TDFE_TRY(tdfe_zero(c, c->cload, c->n_nodes * sizeof(double)));
   ApplyArgs a{};
   a.x = c->fb;
   a.y = c->cload;
@@ -1279,7 +1285,7 @@ tdfe_status tdfe_compute_lift(tdfe_ctx* c) {
 }
 
 tdfe_status tdfe_load_vector(tdfe_ctx* c, const double* f, bool weighted) {
-  TDFE_HIP(c, hipMemsetAsync(c->cload, 0, c->n_nodes * sizeof(double), c->stream));
+  TDFE_TRY(tdfe_zero(c, c->cload, c->n_nodes * sizeof(double)));
   return load_launch_f(c, f, weighted ? 1 : 0);
 }
 
@@ -1326,6 +1332,7 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   c->nucZ.assign(s->Z, s->Z + s->n_nuclei);
   c->nucR.assign(s->R, s->R + 3 * s->n_nuclei);
   c->occ.assign(s->n_orb, 1.0);
+  ++c->occ_ver;
   if (s->occupation)
     for (int o = 0; o < s->n_orb; ++o) c->occ[o] = s->occupation[o];
   c->pcg_tol = s->pcg_tol;
@@ -1370,9 +1377,11 @@ tdfe_status tdfe_dipole(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* 
   double* red = c->partial + c->n_cell * 4;
   hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
   TDFE_HIP(c, hipGetLastError());
-  double h[4];
-  TDFE_HIP(c, hipMemcpyAsync(h, red, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  const void* hr = nullptr;
+  TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hr));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  double h[4];
+  for (int i = 0; i < 4; ++i) h[i] = ((const volatile double*)hr)[i];
   host_mu[0] = h[1];
   host_mu[1] = h[2];
   host_mu[2] = h[3];

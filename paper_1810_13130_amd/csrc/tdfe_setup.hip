@@ -341,6 +341,7 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
   c->ws = (char*)dev;
   c->ws_bytes = bytes;
   carve(c, c->ws);
+  c->occ_dev_ver = -1;  // device-side copies in the old workspace are gone
 
   // 1D tables
   std::vector<double> tab(TAB_SIZE, 0.0);
