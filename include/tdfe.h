@@ -178,7 +178,10 @@ typedef struct {
  * with W = V_H + V_xc and V_field = -field_E z (Eq. VField), held over the
  * step.  Without SCF terms the step is one exp(-i dt Hbar) psibar.  The first
  * call after set_scf computes W_0 from psibar (and W_{-1} := W_0).
- * psibar is updated in place; rep may be NULL (no synchronisation then). */
+ * psibar is updated in place; rep may be NULL.  The call synchronises its
+ * stream once, at the end, to collect the Lanczos convergence status (and the
+ * report); a device-side failure found there (TDFE_EINVAL for a Chebyshev
+ * table overflow) is returned after psibar has been written. */
 tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double dt, double field_E,
                              double tol, tdfe_step_report* rep);
 

@@ -183,15 +183,27 @@ struct LanczosHook {
                                  int k_enqueued, bool fp32) = 0;
   virtual ~LanczosHook() {}
 };
+// defer = 0 or 1: leave the per-orbital results (k, status, error estimate)
+// in device result slot `defer` and return without synchronising; the caller
+// enqueues tdfe_lanczos_enqueue_results, synchronises the stream once and
+// calls tdfe_lanczos_results (host outputs and hook must then be null)
 tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb,
                              double tau, double tol, int* k_out, double* err_out, int* kmax_out,
-                             int* ksum_out, double* errmax_out, LanczosHook* hook = nullptr);
+                             int* ksum_out, double* errmax_out, LanczosHook* hook = nullptr, int defer = -1);
+bool tdfe_lanczos_can_defer(const tdfe_ctx* c);
+tdfe_status tdfe_lanczos_enqueue_results(tdfe_ctx* c, int slot, const void** host);
+tdfe_status tdfe_lanczos_results(tdfe_ctx* c, const void* host, int n_orb, double tol, int* kmax_out,
+                                 int* ksum_out, double* errmax_out);
 
 // scf kernels (tdfe_scf.hip)
 tdfe_status tdfe_density_dev(tdfe_ctx* c, const void* psibar, int n_orb, double* rho, double* partial3);
 tdfe_status tdfe_dipole_dev(tdfe_ctx* c, const double* rho, double mu[3], double* charge);
 tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, double* w_out,
                                double* mu, double* charge);
+// the same, without synchronising: *host_red (if not null) receives the
+// readback address of {charge, mu_x, mu_y, mu_z}, valid after a stream sync
+tdfe_status tdfe_scf_potential_async(tdfe_ctx* c, const void* psibar, int n_orb, double* w_out,
+                                     const void** host_red);
 tdfe_status tdfe_fdm_setup(tdfe_ctx* c);
 tdfe_status tdfe_compute_lift(tdfe_ctx* c);
 // c->cload = sum_e I^T (w f), w = varpi detJ if weighted else 1 (full grid, zeroed first)

@@ -377,9 +377,22 @@ int pad_cols(int C) {
   return p;
 }
 
+// per-orbital results of one chunk into a deferred-result slot:
+// [n_max] k, [n_max] status, [n_max] error estimate, [1] Chebyshev-table flag
+__global__ void stash_results_kernel(const int* kconv, const int* status, const double* err, const int* err_flag,
+                                     int Nc, int o0, int n_max, double* slot) {
+  for (int o = threadIdx.x; o < Nc; o += blockDim.x) {
+    slot[o0 + o] = (double)kconv[o];
+    slot[n_max + o0 + o] = (double)status[o];
+    slot[2 * n_max + o0 + o] = err[o];
+  }
+  if (threadIdx.x == 0 && *err_flag) slot[3 * n_max] = 1.0;
+}
+
 template <typename T>
 tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out, int ld, int o0, int Nc,
-                      double tau, double tol, int* k_out, double* err_out, int* status_out, LanczosHook* hook) {
+                      double tau, double tol, int* k_out, double* err_out, int* status_out, LanczosHook* hook,
+                      double* defer_slot) {
   const int C = 2 * Nc;
   const int64_t nd = c->n_dof;
   const int64_t vstride = nd * C;
@@ -467,6 +480,14 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     hipLaunchKernelGGL((combine_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)W,
                        vstride, C, nd, S, Nc, K, out, ld, 2 * o0);
     TDFE_HIP(c, hipGetLastError());
+  }
+  if (defer_slot) {
+    // results stay on the device until the caller's single readback
+    hipLaunchKernelGGL(stash_results_kernel, dim3(1), dim3(64), 0, c->stream, (const int*)S.kconv,
+                       (const int*)S.status, (const double*)S.err, (const int*)err_flag, Nc, o0, c->n_orb_max,
+                       defer_slot);
+    TDFE_HIP(c, hipGetLastError());
+    return TDFE_OK;
   }
   // results through the pinned readback area (Nc <= 32: 128 + 128 + 256 + 4 bytes)
   const void *hk = nullptr, *hs = nullptr, *he = nullptr, *hf = nullptr;
@@ -569,10 +590,52 @@ static int chunk_size(const tdfe_ctx* c, int n_orb) {
   return best;
 }
 
+// deferred-result slot `slot` (0 or 1) in the scalar block, past the Lanczos
+// scalars of a full chunk and before the occupations
+static double* result_slot(tdfe_ctx* c, int slot) {
+  const size_t base = (size_t)(6 * c->k_max + 6) * c->n_orb_max;
+  return c->scal + base + (size_t)slot * (3 * c->n_orb_max + 1);
+}
+
+bool tdfe_lanczos_can_defer(const tdfe_ctx* c) { return (size_t)(3 * c->n_orb_max + 1) * 8 <= 4096; }
+
+tdfe_status tdfe_lanczos_enqueue_results(tdfe_ctx* c, int slot, const void** host) {
+  return tdfe_readback(c, result_slot(c, slot), (size_t)(3 * c->n_orb_max + 1) * 8, 4096 + (size_t)slot * 4096,
+                       host);
+}
+
+tdfe_status tdfe_lanczos_results(tdfe_ctx* c, const void* host, int n_orb, double tol, int* kmax_out,
+                                 int* ksum_out, double* errmax_out) {
+  const volatile double* h = (const volatile double*)host;
+  const int nm = c->n_orb_max;
+  int kmax = 0, ksum = 0, bad = 0;
+  double emax = 0.0;
+  for (int o = 0; o < n_orb; ++o) {
+    const int k = (int)h[o];
+    kmax = std::max(kmax, k);
+    ksum += k;
+    emax = std::max(emax, (double)h[2 * nm + o]);
+    if ((int)h[nm + o] == 2) bad = 1;
+  }
+  if (kmax_out) *kmax_out = kmax;
+  if (ksum_out) *ksum_out = ksum;
+  if (errmax_out) *errmax_out = emax;
+  if (h[3 * nm] != 0.0) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
+  if (bad) return tdfe_fail(c, TDFE_ENOCONV, "Lanczos reached k_max=%d without eps <= %g", c->k_max, tol);
+  return TDFE_OK;
+}
+
 tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void* out, int n_orb, double tau,
                              double tol, int* k_out, double* err_out, int* kmax_out, int* ksum_out,
-                             double* errmax_out, LanczosHook* hook) {
+                             double* errmax_out, LanczosHook* hook, int defer) {
   const int ld = 2 * n_orb;
+  double* slot = nullptr;
+  if (defer >= 0) {
+    if (defer > 1 || hook || k_out || err_out || kmax_out || ksum_out || errmax_out || !tdfe_lanczos_can_defer(c))
+      return tdfe_fail(c, TDFE_EINVAL, "lanczos: deferred results need slot 0/1 and no host outputs");
+    slot = result_slot(c, defer);
+    TDFE_TRY(tdfe_zero(c, slot + 3 * c->n_orb_max, sizeof(double)));
+  }
   std::vector<int> ks(n_orb), st(n_orb);
   std::vector<double> es(n_orb);
   const void* v = c->precision == TDFE_FP64 ? (const void*)vw : (const void*)c->vw32;
@@ -585,12 +648,13 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
     tdfe_status s;
     if (c->precision == TDFE_FP64)
       s = run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
-                            es.data() + o0, st.data() + o0, hook);
+                            es.data() + o0, st.data() + o0, hook, slot);
     else
       s = run_chunk<float>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
-                           es.data() + o0, st.data() + o0, hook);
+                           es.data() + o0, st.data() + o0, hook, slot);
     if (s != TDFE_OK) return s;
   }
+  if (slot) return TDFE_OK;
   int kmax = 0, ksum = 0, bad = 0;
   double emax = 0.0;
   for (int o = 0; o < n_orb; ++o) {

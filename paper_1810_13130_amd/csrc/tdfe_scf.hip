@@ -1214,6 +1214,22 @@ tdfe_status tdfe_density_dev(tdfe_ctx* c, const void* psibar, int n_orb, double*
 // W = V_H[rho] + V_xc[rho] at the Gauss points for the orbitals psibar;
 // mu/charge (host, may be null) receive the dipole and charge of rho
 tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, double* W, double* mu, double* charge) {
+  const void* hr = nullptr;
+  TDFE_TRY(tdfe_scf_potential_async(c, psibar, n_orb, W, (mu || charge) ? &hr : nullptr));
+  if (hr) {
+    TDFE_HIP(c, hipStreamSynchronize(c->stream));
+    const volatile double* h = (const volatile double*)hr;
+    if (charge) *charge = h[0];
+    if (mu) {
+      mu[0] = h[1];
+      mu[1] = h[2];
+      mu[2] = h[3];
+    }
+  }
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_scf_potential_async(tdfe_ctx* c, const void* psibar, int n_orb, double* W, const void** host_red) {
   TDFE_TRY(tdfe_density_dev(c, psibar, n_orb, c->rho, c->partial));
   double* red = c->partial + c->n_cell * 4;
   hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
@@ -1228,18 +1244,8 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
     }
   }
   TDFE_TRY(interp_launch(c, W));
-  if (mu || charge) {
-    const void* hr = nullptr;
-    TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hr));
-    TDFE_HIP(c, hipStreamSynchronize(c->stream));
-    double h[4];
-    for (int i = 0; i < 4; ++i) h[i] = ((const volatile double*)hr)[i];
-    if (charge) *charge = h[0];
-    if (mu) {
-      mu[0] = h[1];
-      mu[1] = h[2];
-      mu[2] = h[3];
-    }
+  if (host_red) {
+    TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, host_red));
   }
   return TDFE_OK;
 }
@@ -1401,17 +1407,30 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
   const int64_t nqd = c->n_quad;
   float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
   tdfe_step_report r{};
-  tdfe_status st = TDFE_OK, s2;
+  // the Lanczos results of the step (Krylov dimensions, error estimates,
+  // convergence) and the dipole stay on the device until one readback and one
+  // stream synchronisation at the end of the step
+  const bool defer = tdfe_lanczos_can_defer(c);
+  const void *hpred = nullptr, *hcorr = nullptr, *hred = nullptr;
+  tdfe_status st = TDFE_OK, s2 = TDFE_OK;
+  double eh = 0.0;
+  auto lanczos = [&](const void* in, void* out, double tau, int slot, int* kmax, int* ksum, double* emax) {
+    if (defer) return tdfe_lanczos_run(c, c->vw, in, out, n_orb, tau, tol, nullptr, nullptr, nullptr, nullptr,
+                                       nullptr, nullptr, slot);
+    return tdfe_lanczos_run(c, c->vw, in, out, n_orb, tau, tol, nullptr, nullptr, kmax, ksum, emax);
+  };
   if (!c->have_scf) {
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
                        (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, field_E, c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
-    st = tdfe_lanczos_run(c, c->vw, dev_psibar, dev_psibar, n_orb, dt, tol, nullptr, nullptr, &r.k_corr_max,
-                          &r.k_corr_sum, &r.err_max);
-    if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
+    s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
+    if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
     if (rep) {
-      s2 = tdfe_dipole(c, dev_psibar, n_orb, r.mu, &r.charge);
-      if (s2 != TDFE_OK) return s2;
+      TDFE_TRY(tdfe_density_dev(c, dev_psibar, n_orb, c->rho, c->partial));
+      double* red = c->partial + c->n_cell * 4;
+      hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
+      TDFE_HIP(c, hipGetLastError());
+      TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hred));
     }
   } else {
     if (!c->scf_init) {
@@ -1423,23 +1442,40 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
                        (const double*)c->w1, 1.25, (const double*)c->w2, -0.25, field_E, c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
-    double eh = 0.0;
-    st = tdfe_lanczos_run(c, c->vw, dev_psibar, c->half, n_orb, 0.5 * dt, tol, nullptr, nullptr, &r.k_pred_max,
-                          &r.k_pred_sum, &eh);
+    st = lanczos(dev_psibar, c->half, 0.5 * dt, 0, &r.k_pred_max, &r.k_pred_sum, &eh);
     if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
-    TDFE_TRY(tdfe_scf_potential(c, c->half, n_orb, c->wh, nullptr, nullptr));
+    TDFE_TRY(tdfe_scf_potential_async(c, c->half, n_orb, c->wh, nullptr));
     // corrector with the midpoint potential
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
                        (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, field_E, c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
-    s2 = tdfe_lanczos_run(c, c->vw, dev_psibar, dev_psibar, n_orb, dt, tol, nullptr, nullptr, &r.k_corr_max,
-                          &r.k_corr_sum, &r.err_max);
+    s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
     if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
-    if (s2 == TDFE_ENOCONV) st = s2;
-    r.err_max = std::max(r.err_max, eh);
     // history: W_{n-2} <- W_{n-1}, W_{n-1} <- W[rho(psibar^n)]
     std::swap(c->w1, c->w2);
-    TDFE_TRY(tdfe_scf_potential(c, dev_psibar, n_orb, c->w1, rep ? r.mu : nullptr, rep ? &r.charge : nullptr));
+    TDFE_TRY(tdfe_scf_potential_async(c, dev_psibar, n_orb, c->w1, rep ? &hred : nullptr));
+  }
+  if (defer) {
+    if (c->have_scf) TDFE_TRY(tdfe_lanczos_enqueue_results(c, 0, &hpred));
+    TDFE_TRY(tdfe_lanczos_enqueue_results(c, 1, &hcorr));
+  }
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  if (defer) {
+    if (hpred) {
+      st = tdfe_lanczos_results(c, hpred, n_orb, tol, &r.k_pred_max, &r.k_pred_sum, &eh);
+      if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
+    }
+    s2 = tdfe_lanczos_results(c, hcorr, n_orb, tol, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
+    if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
+  }
+  if (s2 == TDFE_ENOCONV) st = s2;
+  r.err_max = std::max(r.err_max, eh);
+  if (hred) {
+    const volatile double* h = (const volatile double*)hred;
+    r.charge = h[0];
+    r.mu[0] = h[1];
+    r.mu[1] = h[2];
+    r.mu[2] = h[3];
   }
   r.poisson_iters = c->last_poisson_iters;
   if (rep) {

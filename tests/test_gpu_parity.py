@@ -151,6 +151,25 @@ def test_lanczos_not_converged_reports_enoconv():
     assert e.value.status == tdfe.ENOCONV
 
 
+@pytest.mark.parametrize("scf", [False, True])
+def test_magnus_step_reports_enoconv(scf):
+    """The step collects the Lanczos status at its end (one synchronisation):
+    a Krylov cap too small for the tolerance is reported as ENOCONV, with and
+    without the predictor-corrector SCF path, and a capped step leaves a
+    finite state that the next normal step can continue from."""
+    from paper_1810_13130_amd import tdfe
+    cfg = _cfg2_small(n_orb=2)
+    ctx = gpu_context(cfg, n_orb=2, k_max=3)
+    if scf:
+        Z, R = W.atoms(cfg)
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=2)
+    g = gpu_initial_state(ctx, cfg)
+    with pytest.raises(tdfe.TdfeError) as e:
+        ctx.magnus_step(g, cfg.dt, 0.0, 1e-14)
+    assert e.value.status == tdfe.ENOCONV
+    assert torch.isfinite(torch.view_as_real(g)).all()
+
+
 def test_magnus_harmonic_trap_20_steps():
     cfg = W.CONFIGS[1]
     ctx = gpu_context(cfg, n_orb=1)
