@@ -85,6 +85,7 @@ struct tdfe_ctx {
 
   // host pinned poll buffer
   int* poll = nullptr;
+  int flag_gen = 0;  // generation number of the Lanczos convergence flag (poll[32])
   hipEvent_t* evs = nullptr;  // [TDFE_N_EVENTS] look-ahead polling points
   int n_evs = 0;
 

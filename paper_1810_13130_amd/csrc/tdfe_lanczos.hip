@@ -194,7 +194,7 @@ __global__ void __launch_bounds__(RED_THREADS)
 __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int M,
                           double amax,
                           double bk, double ylr, double yli, double yr, double yi, const double* Lyr,
-                          const double* Lyi, int nthreads, int* err_flag, int* host_flag) {
+                          const double* Lyi, int nthreads, int* err_flag, int* host_flag, int gen) {
   const int t = threadIdx.x;
   int fin = 0;
   if (M < 0) {
@@ -240,17 +240,19 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
     }
   }
   // the orbital that completes the set raises the host-visible flag (pinned
-  // memory, cleared by the host before the run); the host reads it once an
-  // iteration's event has completed
+  // memory) to this run's generation number: a write left over from an
+  // earlier run cannot be mistaken for this one, so the host needs no
+  // synchronisation between runs; the host reads it once an iteration's
+  // event has completed
   if (fin && host_flag) {
-    *host_flag = 1;
+    *host_flag = gen;
     __threadfence_system();
   }
 }
 
 __global__ void __launch_bounds__(CHK_THREADS)
     check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int* err_flag,
-                 int* host_flag) {
+                 int* host_flag, int gen) {
   __shared__ ChebLds L;
   __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
   const int o = blockIdx.x;
@@ -267,11 +269,11 @@ __global__ void __launch_bounds__(CHK_THREADS)
     const int M = cheb_expm_e1_wave(k, sa, sb, tau, L.J, &L.M, &L.inv, yr, yi, &amax);
     const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
     stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], ylr, yli, yr, yi, nullptr, nullptr,
-              CHK_THREADS, err_flag, host_flag);
+              CHK_THREADS, err_flag, host_flag, gen);
   } else {
     const int M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
     stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], L.yr[k - 1], L.yi[k - 1], 0.0, 0.0, L.yr,
-              L.yi, CHK_THREADS, err_flag, host_flag);
+              L.yi, CHK_THREADS, err_flag, host_flag, gen);
   }
 }
 
@@ -281,7 +283,7 @@ __global__ void __launch_bounds__(CHK_THREADS)
 // reduction)
 __global__ void __launch_bounds__(RED_THREADS)
     beta_check_kernel(const double* __restrict__ partial, int64_t nblocks, int C, Scal S, int Nc, int k, int k_max,
-                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag) {
+                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen) {
   __shared__ double sred[RED_THREADS];
   __shared__ double J[TDFE_MAX_BESSEL + 2];
   __shared__ double sa[CHK_THREADS], sb[CHK_THREADS];
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(RED_THREADS)
   const int M = cheb_expm_e1_wave<true>(k, sa, sb, tau, J, &Ms, &invs, yr, yi, &amax);
   const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
   stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, bk, ylr, yli, yr, yi, nullptr, nullptr, CHK_THREADS,
-            err_flag, host_flag);
+            err_flag, host_flag, gen);
 }
 
 // z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk
@@ -358,14 +360,14 @@ __global__ void init_scal_kernel(Scal S, int Nc) {
 }
 
 // orbitals with zero norm are finished before the first iteration
-__global__ void zero_norm_kernel(Scal S, int Nc, int* host_flag) {
+__global__ void zero_norm_kernel(Scal S, int Nc, int* host_flag, int gen) {
   const int o = threadIdx.x;
   if (o < Nc && !(S.nrm[o] > 0.0)) {
     S.status[o] = 1;
     S.kconv[o] = 0;
     if (atomicAdd(S.nconv, 1) + 1 == Nc) {
       *S.done = 1;
-      *host_flag = 1;
+      *host_flag = gen;
       __threadfence_system();
     }
   }
@@ -412,13 +414,13 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                      c->partial);
   hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
                      (int64_t)RED_BLOCKS, C, S.nrm, 2, S.scale, S.cs, (const double*)nullptr, (const int*)nullptr);
-  // host-visible copy of the done flag (pinned memory; all earlier work on the
-  // stream has completed, so nothing else writes it now)
+  // host-visible copy of the done flag (pinned memory), tagged with this
+  // run's generation number
   volatile int* hflag = c->poll + 32;
-  *hflag = 0;
+  const int gen = ++c->flag_gen;
   int* dflag = nullptr;
   TDFE_HIP(c, hipHostGetDevicePointer((void**)&dflag, (void*)(c->poll + 32), 0));
-  hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc, dflag);
+  hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc, dflag, gen);
   TDFE_HIP(c, hipGetLastError());
 
   const int LOOK = 2;
@@ -456,20 +458,20 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     // beta_k, the scale 1/beta_k of the next basis vector and the stop test
     if (k <= CHK_THREADS) {
       hipLaunchKernelGGL(beta_check_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial,
-                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag);
+                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag, gen);
     } else {
       hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
                          (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 3, S.scale + (size_t)k * Nc,
                          S.cs + (size_t)k * Nc, (const double*)nullptr, (const int*)S.done);
       hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
-                         err_flag, dflag);
+                         err_flag, dflag, gen);
     }
     TDFE_HIP(c, hipGetLastError());
     TDFE_HIP(c, hipEventRecord(c->evs[k % RING], c->stream));
     if (k > LOOK) {
       const int kk = k - LOOK;
       TDFE_HIP(c, hipEventSynchronize(c->evs[kk % RING]));
-      if (*hflag) break;
+      if (*hflag == gen) break;
     }
   }
   if (hook)

@@ -315,8 +315,13 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
     else (void)hipGetLastError();
   }
   int chunk = (int)std::min<double>(c->n_orb_max, std::floor(basis_bytes / per_orb));
-  if (chunk < 1) chunk = 1;
   if (chunk > TDFE_MAX_COLS / 2) chunk = TDFE_MAX_COLS / 2;
+  {
+    // optional cap (tests use it to run several chunks on small meshes)
+    const char* v = std::getenv("TDFE_MAX_CHUNK_ORB");
+    if (v && std::atoi(v) > 0) chunk = std::min(chunk, std::atoi(v));
+  }
+  if (chunk < 1) chunk = 1;
   c->chunk_orb = chunk;
   carve(c, nullptr);
   *out = c;
@@ -443,7 +448,10 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
   if (hbad) return tdfe_fail(c, TDFE_EINVAL, "mesh has a non-positive Jacobian");
   // pinned poll buffer for the Lanczos convergence flags
-  if (!c->poll) TDFE_HIP(c, hipHostMalloc((void**)&c->poll, 4096 * sizeof(int), hipHostMallocDefault));
+  if (!c->poll) {
+    TDFE_HIP(c, hipHostMalloc((void**)&c->poll, 4096 * sizeof(int), hipHostMallocDefault));
+    std::memset(c->poll, 0, 4096 * sizeof(int));  // flags compare against generation numbers >= 1
+  }
   c->bound = true;
   c->have_potential = false;
   c->have_scf = false;

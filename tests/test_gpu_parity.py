@@ -170,6 +170,28 @@ def test_magnus_step_reports_enoconv(scf):
     assert torch.isfinite(torch.view_as_real(g)).all()
 
 
+def test_magnus_step_capped_runs_match_across_chunkings(monkeypatch):
+    """Krylov runs that end at k_max leave their convergence flag write for
+    the next run to ignore: three one-orbital chunks per run (each stopping
+    at k_max) must give exactly the state of one three-orbital chunk."""
+    from paper_1810_13130_amd import tdfe
+    cfg = _cfg2_small(n_orb=3)
+    out = []
+    for cap in (None, "1"):
+        if cap:
+            monkeypatch.setenv("TDFE_MAX_CHUNK_ORB", cap)
+        ctx = gpu_context(cfg, n_orb=3, k_max=4)
+        Z, R = W.atoms(cfg)
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=3)
+        g = gpu_initial_state(ctx, cfg)
+        for _ in range(2):
+            with pytest.raises(tdfe.TdfeError) as e:
+                ctx.magnus_step(g, cfg.dt, 0.0, 1e-14)
+            assert e.value.status == tdfe.ENOCONV
+        out.append(g.cpu().numpy())
+    assert np.abs(out[0] - out[1]).max() <= 1e-12 * np.abs(out[0]).max()
+
+
 def test_magnus_harmonic_trap_20_steps():
     cfg = W.CONFIGS[1]
     ctx = gpu_context(cfg, n_orb=1)
