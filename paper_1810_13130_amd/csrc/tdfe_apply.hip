@@ -17,6 +17,7 @@
 // column is accumulated from the quadrature-point fluxes and reduced per
 // workgroup; it equals Re<x, Hbar x> and feeds the Lanczos alpha.
 #include "tdfe_internal.h"
+#include "tdfe_rule1d.h"
 
 namespace {
 
@@ -73,7 +74,12 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   __shared__ T sGY[GEOM ? CPB * VOL * CB : 1];
   __shared__ T sGZ[GEOM ? CPB * VOL * CB : 1];
   __shared__ T sGeo[GEOM ? CPB * VOL * 6 : 1];
-  __shared__ T sB[N * N], sDg[N * N], sW3[VOL];
+  __shared__ T sW3[VOL];
+  __shared__ double sEta[N];
+  __shared__ double sCor[GEOM ? CPB * 24 : 1];
+  // 1D tables as compile-time constants (the weights and Gauss points, read
+  // with per-thread indices, stay in LDS)
+  constexpr tdfe1d::Rule R = tdfe1d::make_rule(N - 1);
   __shared__ double sRed[S::THREADS];
 
   if (P.done && *P.done) return;
@@ -91,11 +97,8 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   const bool col_ok = colg < P.cols;
   const bool act = cell_ok && col_ok;
 
-  for (int i = t; i < N * N; i += S::THREADS) {
-    sB[i] = (T)P.tab[TAB_B + (i / N) * TDFE_MAXN + (i % N)];
-    sDg[i] = (T)P.tab[TAB_DG + (i / N) * TDFE_MAXN + (i % N)];
-  }
   for (int i = t; i < VOL; i += S::THREADS) sW3[i] = (T)P.tab[TAB_W3Q + i];
+  if (t < N) sEta[t] = P.tab[TAB_ETA + t];
 
   int cx = 0, cy = 0, cz = 0;
   if (cell_ok) {
@@ -109,17 +112,68 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   T cs = (T)1;
   if (P.colscale && col_ok) cs = (T)P.colscale[colg >> 1];
 
+  const int NxI = P.Nx - 2, NyI = P.Ny - 2;
+  auto node_index = [&](int i, int j, int k, bool& inside) -> int64_t {
+    const int I = cx * P.p + i, J = cy * P.p + j, K = cz * P.p + k;
+    if (P.fullgrid) {
+      inside = true;
+      return (int64_t)I + (int64_t)P.Nx * ((int64_t)J + (int64_t)P.Ny * K);
+    }
+    inside = I > 0 && I < P.Nx - 1 && J > 0 && J < P.Ny - 1 && K > 0 && K < P.Nz - 1;
+    return (int64_t)(I - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (K - 1));
+  };
+
+
+  // prologue: the block's cell corners and this thread's z-line gather (values
+  // and M^-1/2, from valid addresses, masked later) are issued together; the
+  // metric is computed from LDS while the gather is in flight
+  constexpr int NCR = GEOM ? (CPB * 24 + S::THREADS - 1) / S::THREADS : 1;
+  double cr[NCR];
+  if constexpr (GEOM) {
+#pragma unroll
+    for (int k = 0; k < NCR; ++k) {
+      const int f = t + k * S::THREADS;
+      const int64_t c0 = (int64_t)group * CPB;
+      const bool ok = f < CPB * 24 && c0 + f / 24 < P.n_cell;
+      const double val = P.corners[ok ? c0 * 24 + f : 0];
+      cr[k] = ok ? val : 0.0;
+    }
+  }
+  T gx1[N], gm1[N];
+  unsigned gmask = 0;
+  {
+    const int i = line % N, j = line / N;
+#pragma unroll
+    for (int k = 0; k < N; ++k) {
+      bool inside;
+      const int64_t id = node_index(i, j, k, inside);
+      const bool ok = act && inside;
+      if (ok) gmask |= 1u << k;
+      const int64_t id0 = ok ? id : 0;
+      gx1[k] = X[id0 * P.ld + (ok ? colg : 0)];
+      gm1[k] = (T)P.minv[P.lowdin ? id0 : 0];
+    }
+  }
+  if constexpr (GEOM) {
+#pragma unroll
+    for (int k = 0; k < NCR; ++k) {
+      const int f = t + k * S::THREADS;
+      if (f < CPB * 24) sCor[f] = cr[k];
+    }
+  }
+  __syncthreads();
   // geometry of curved cells: 6 entries of detJ w J^-1 J^-T at every Gauss point
   if constexpr (GEOM) {
+    const T* sW3q = sW3;
     for (int it = t; it < CPB * VOL; it += S::THREADS) {
       const int sl = it / VOL, q = it % VOL;
       const int64_t ce = (int64_t)group * CPB + sl;
       if (ce >= P.n_cell) continue;
       const int a = q % N, b = (q / N) % N, c = q / (N * N);
-      const double xa = P.tab[TAB_ETA + a], xb = P.tab[TAB_ETA + b], xc = P.tab[TAB_ETA + c];
+      const double xa = sEta[a], xb = sEta[b], xc = sEta[c];
       const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
                               {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
-      const double* C = P.corners + ce * 24;
+      const double* C = sCor + sl * 24;
       double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
       for (int vz = 0; vz < 2; ++vz)
         for (int vy = 0; vy < 2; ++vy)
@@ -147,7 +201,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
       A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
       const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
-      const double s = P.tab[TAB_W3Q + q] / det;
+      const double s = (double)sW3q[q] / det;
       T* g = sGeo + (sl * VOL + q) * 6;
       g[0] = (T)(s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]));
       g[1] = (T)(s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]));
@@ -159,17 +213,6 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   }
   __syncthreads();
 
-  const int NxI = P.Nx - 2, NyI = P.Ny - 2;
-  auto node_index = [&](int i, int j, int k, bool& inside) -> int64_t {
-    const int I = cx * P.p + i, J = cy * P.p + j, K = cz * P.p + k;
-    if (P.fullgrid) {
-      inside = true;
-      return (int64_t)I + (int64_t)P.Nx * ((int64_t)J + (int64_t)P.Ny * K);
-    }
-    inside = I > 0 && I < P.Nx - 1 && J > 0 && J < P.Ny - 1 && K > 0 && K < P.Nz - 1;
-    return (int64_t)(I - 1) + (int64_t)NxI * ((int64_t)(J - 1) + (int64_t)NyI * (K - 1));
-  };
-
   double energy = 0.0;
   T r1[N], r2[N];
 
@@ -177,23 +220,13 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   {
     const int i = line % N, j = line / N;
 #pragma unroll
-    for (int k = 0; k < N; ++k) {
-      T v = (T)0;
-      if (act) {
-        bool inside;
-        const int64_t id = node_index(i, j, k, inside);
-        if (inside) {
-          v = X[id * P.ld + colg] * cs;
-          if (P.lowdin) v *= (T)P.minv[id];
-        }
-      }
-      r1[k] = v;
-    }
+    for (int k = 0; k < N; ++k)
+      r1[k] = ((gmask >> k) & 1u) ? gx1[k] * (P.lowdin ? gm1[k] * cs : cs) : (T)0;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
       T s = 0;
 #pragma unroll
-      for (int k = 0; k < N; ++k) s += sB[c * N + k] * r1[k];
+      for (int k = 0; k < N; ++k) s += (T)R.B[c * tdfe1d::MAXN + k] * r1[k];
       sU[lidx<N, CB>(slot, c, j, i, col)] = s;
     }
   }
@@ -207,7 +240,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
     for (int b = 0; b < N; ++b) {
       T s = 0;
 #pragma unroll
-      for (int j = 0; j < N; ++j) s += sB[b * N + j] * r1[j];
+      for (int j = 0; j < N; ++j) s += (T)R.B[b * tdfe1d::MAXN + j] * r1[j];
       sU[lidx<N, CB>(slot, c, b, i, col)] = s;
     }
   }
@@ -231,7 +264,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
     for (int a = 0; a < N; ++a) {
       T s = 0;
 #pragma unroll
-      for (int i = 0; i < N; ++i) s += sB[a * N + i] * r1[i];
+      for (int i = 0; i < N; ++i) s += (T)R.B[a * tdfe1d::MAXN + i] * r1[i];
       uq[a] = s;
     }
     T du[N];
@@ -239,7 +272,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
     for (int a = 0; a < N; ++a) {
       T s = 0;
 #pragma unroll
-      for (int q = 0; q < N; ++q) s += sDg[a * N + q] * uq[q];
+      for (int q = 0; q < N; ++q) s += (T)R.Dg[a * tdfe1d::MAXN + q] * uq[q];
       du[a] = s;
     }
     if constexpr (!GEOM) {
@@ -255,7 +288,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int a = 0; a < N; ++a) {
         T s = pot[a];
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[q * N + a] * f[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[q * tdfe1d::MAXN + a] * f[q];
         sU[lidx<N, CB>(slot, c, b, a, col)] = uq[a];
         sR[lidx<N, CB>(slot, c, b, a, col)] = s;
       }
@@ -283,7 +316,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int b = 0; b < N; ++b) {
         T s = 0;
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[b * N + q] * r1[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[b * tdfe1d::MAXN + q] * r1[q];
         f[b] = (T)gy * sW3[a + N * (b + N * c)] * s;
         energy += (double)f[b] * (double)s;
       }
@@ -291,7 +324,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int b = 0; b < N; ++b) {
         T s = r2[b];
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[q * N + b] * f[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[q * tdfe1d::MAXN + b] * f[q];
         sR[lidx<N, CB>(slot, c, b, a, col)] = s;
       }
     }
@@ -309,7 +342,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int c = 0; c < N; ++c) {
         T s = 0;
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[c * N + q] * r1[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[c * tdfe1d::MAXN + q] * r1[q];
         f[c] = (T)gz * sW3[a + N * (b + N * c)] * s;
         energy += (double)f[c] * (double)s;
       }
@@ -317,14 +350,14 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int c = 0; c < N; ++c) {
         T s = r2[c];
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[q * N + c] * f[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[q * tdfe1d::MAXN + c] * f[q];
         r1[c] = s;
       }
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         T s = 0;
 #pragma unroll
-        for (int c = 0; c < N; ++c) s += sB[c * N + k] * r1[c];
+        for (int c = 0; c < N; ++c) s += (T)R.B[c * tdfe1d::MAXN + k] * r1[c];
         sR[lidx<N, CB>(slot, k, b, a, col)] = s;
       }
     }
@@ -339,7 +372,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int b = 0; b < N; ++b) {
         T s = 0;
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[b * N + q] * r1[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[b * tdfe1d::MAXN + q] * r1[q];
         sGY[lidx<N, CB>(slot, c, b, a, col)] = s;
       }
     }
@@ -351,7 +384,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int c = 0; c < N; ++c) {
         T s = 0;
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[c * N + q] * r1[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[c * tdfe1d::MAXN + q] * r1[q];
         sGZ[lidx<N, CB>(slot, c, b, a, col)] = s;
       }
     }
@@ -380,7 +413,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int a = 0; a < N; ++a) {
         T s = pot[a];
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[q * N + a] * fx[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[q * tdfe1d::MAXN + a] * fx[q];
         sU[lidx<N, CB>(slot, c, b, a, col)] = s;
       }
     }
@@ -397,7 +430,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int b = 0; b < N; ++b) {
         T s = r1[b];
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[q * N + b] * r2[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[q * tdfe1d::MAXN + b] * r2[q];
         sU[lidx<N, CB>(slot, c, b, a, col)] = s;
       }
     }
@@ -414,14 +447,14 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
       for (int c = 0; c < N; ++c) {
         T s = r1[c];
 #pragma unroll
-        for (int q = 0; q < N; ++q) s += sDg[q * N + c] * r2[q];
+        for (int q = 0; q < N; ++q) s += (T)R.Dg[q * tdfe1d::MAXN + c] * r2[q];
         r1[c] = s;  // reads only r1[c] itself and r2
       }
 #pragma unroll
       for (int k = 0; k < N; ++k) {
         T s = 0;
 #pragma unroll
-        for (int c = 0; c < N; ++c) s += sB[c * N + k] * r1[c];
+        for (int c = 0; c < N; ++c) s += (T)R.B[c * tdfe1d::MAXN + k] * r1[c];
         sR[lidx<N, CB>(slot, k, b, a, col)] = s;
       }
     }
@@ -436,7 +469,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
     for (int j = 0; j < N; ++j) {
       T s = 0;
 #pragma unroll
-      for (int b = 0; b < N; ++b) s += sB[b * N + j] * r1[b];
+      for (int b = 0; b < N; ++b) s += (T)R.B[b * tdfe1d::MAXN + j] * r1[b];
       sR[lidx<N, CB>(slot, k, j, a, col)] = s;
     }
   }
@@ -450,7 +483,7 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
     for (int i = 0; i < N; ++i) {
       T s = 0;
 #pragma unroll
-      for (int a = 0; a < N; ++a) s += sB[a * N + i] * r1[a];
+      for (int a = 0; a < N; ++a) s += (T)R.B[a * tdfe1d::MAXN + i] * r1[a];
       if (act) {
         bool inside;
         const int64_t id = node_index(i, j, k, inside);
