@@ -14,11 +14,14 @@ Readings (the paper defers the details to another reference):
 * the external and field potentials are evaluated exactly; a field of
   amplitude E_n along z is V_field = -E_n z (Eq. VField) held over step n;
 * the corrector restarts from psibar^{n-1} with the full dt;
-* a density-independent H takes one exp(-i dt Hbar) per step.
+* a density-independent H takes one exp(-i dt Hbar) per step;
+* a nonlocal Kleinman-Bylander term (Eq. VPSP), when given, is part of Hbar
+  in both exponentials.
 """
 import numpy as np
 
 from .lanczos import lanczos_expm
+from .nonlocal_kb import apply_nonlocal_bar
 from .operators import apply_Hbar
 from . import scf
 
@@ -32,8 +35,10 @@ class System:
     """
 
     def __init__(self, mesh, vext, hartree=False, xc="none", Z=(), R=(), occ=None,
-                 tol=1e-10, k_max=128, pcg_tol=1e-13, pcg_maxit=5000):
+                 tol=1e-10, k_max=128, pcg_tol=1e-13, pcg_maxit=5000, nonlocal_kb=None):
         self.mesh = mesh
+        # (C, E) of the Kleinman-Bylander term (oracle.nonlocal_kb.kb_matrix) or None
+        self.nonlocal_kb = nonlocal_kb
         self.vext = np.asarray(vext, dtype=np.float64)
         self.hartree = scf.Hartree(mesh, Z, R, pcg_tol, pcg_maxit) if hartree else None
         self.xc = xc
@@ -52,8 +57,14 @@ class System:
             w = w + scf.xc_potential(rho, self.xc)
         return w, rho
 
+    def apply(self, v, x):
+        y = apply_Hbar(self.mesh, v, x)
+        if self.nonlocal_kb is not None:
+            y = y + apply_nonlocal_bar(self.mesh, self.nonlocal_kb[0], self.nonlocal_kb[1], x)
+        return y
+
     def expm(self, v, psibar, tau):
-        return lanczos_expm(lambda x: apply_Hbar(self.mesh, v, x), psibar, tau, self.tol, self.k_max)
+        return lanczos_expm(lambda x: self.apply(v, x), psibar, tau, self.tol, self.k_max)
 
 
 class State:

@@ -235,6 +235,33 @@ def fd_indices(n=200, count=10, seed=55):
     return np.random.default_rng(seed).choice(n, count, replace=False)
 
 
+# Kleinman-Bylander projector recipe (nonlocal pseudopotential term, Eq.
+# VPSP): per atom an s and three p channels, u_lm = Y_lm-like polynomial times
+# a Gaussian, dV_l a short-range Gaussian well of the channel's strength.  The
+# values stand in for pseudo-atomic tables that are not available here.
+KB_DEFAULT = dict(sigma_u=0.9, rc=0.75, A=(-1.5, 0.8))
+
+
+def kb_projector_values(cfg, xyz, kb=None):
+    """(u, dV) at the points xyz (..., 3): arrays (n_proj, ...) with n_proj =
+    4 per atom, ordered atom-major, channels s, p_x, p_y, p_z."""
+    kb = dict(KB_DEFAULT, **(kb or {}))
+    _, R = atoms(cfg)
+    xyz = np.asarray(xyz)
+    us, dvs = [], []
+    for Ra in R:
+        d = xyz - Ra
+        r2 = np.sum(d * d, axis=-1)
+        env = np.exp(-r2 / (2.0 * kb["sigma_u"] ** 2))
+        well = np.exp(-r2 / (2.0 * kb["rc"] ** 2))
+        us.append(env)
+        dvs.append(kb["A"][0] * well)
+        for ax in range(3):
+            us.append(d[..., ax] * env)
+            dvs.append(kb["A"][1] * well)
+    return np.array(us), np.array(dvs)
+
+
 def random_block(n_dof, n_orb, seed):
     """A seeded random complex block (n_dof, n_orb) for operator tests."""
     rng = np.random.default_rng(seed)
