@@ -120,6 +120,33 @@ typedef struct {
 /* set_scf: density-dependent part of V_KS.  Resets the extrapolation history. */
 tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);
 
+/* Nonlocal pseudopotential term in the Kleinman-Bylander form (Eq. VPSP):
+ * V_NL phi = sum_p (int u_p dV_p phi / D_p) u_p dV_p with D_p = int u_p dV_p u_p.
+ * Its Galerkin matrix C^T diag(1/D) C, c_pj = int u_p dV_p N_j, is added (in
+ * Loewdin form, M^-1/2 C^T diag(1/D) C M^-1/2) to every later application of
+ * Hbar: apply_H*, lanczos_expm, magnus_step and the adjoint, in both
+ * precisions (the mixed path keeps an FP32 copy of C M^-1/2 and accumulates
+ * the projections in FP64).  All integrals use the Gauss rule of the mesh.
+ *
+ * projector_query: *bytes = device store needed for n_proj projectors
+ * (0 <= n_proj <= TDFE_MAX_PROJ); about n_proj n_dof 8 bytes (12 in mixed
+ * contexts) plus small scratch.
+ *
+ * set_projectors: dev_u, dev_dv are [n_proj][n_cell][nq^3] FP64 device
+ * arrays of u_p and dV_p at the Gauss points; dev_store is a caller-owned
+ * device buffer of >= the queried size (256-byte aligned) that the library
+ * uses until the next set_projectors call or the context's destruction (the
+ * caller keeps it alive and does not touch it).  n_proj = 0 removes the term
+ * (pointers may then be NULL).  The inputs are read during the call only.
+ * Synchronises the stream.  Errors: TDFE_ESTATE before bind_workspace,
+ * TDFE_ENOMEM if store_bytes is too small, TDFE_EINVAL for null pointers,
+ * misalignment, n_proj out of range or a D_p that is zero or not finite (the
+ * term is then off). */
+#define TDFE_MAX_PROJ 1024
+tdfe_status tdfe_projector_query(const tdfe_ctx* ctx, int n_proj, size_t* bytes);
+tdfe_status tdfe_set_projectors(tdfe_ctx* ctx, int n_proj, const double* dev_u, const double* dev_dv,
+                                void* dev_store, size_t store_bytes);
+
 /* apply_H: dev_out = Hbar dev_psibar for n_orb orbitals (both [n_dof][n_orb]
  * complex128), Hbar = M^-1/2 (1/2 K + V-mass) M^-1/2 with the current total
  * potential (Eqs. DiscreteHamiltonian, TDKSMatVecStandard).  Gauss quadrature
@@ -127,8 +154,9 @@ tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);
 tdfe_status tdfe_apply_H(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, int n_orb);
 
 /* apply_H_add: dev_out += Hbar dev_psibar (same operator as apply_H, no
- * zeroing of dev_out): exactly one launch of the operator kernel, for
- * composite operators and for timing that kernel alone. */
+ * zeroing of dev_out): exactly one launch of the operator kernel (followed by
+ * the nonlocal kernels when projectors are set), for composite operators and
+ * for timing that kernel alone. */
 tdfe_status tdfe_apply_H_add(tdfe_ctx* ctx, const void* dev_psibar, void* dev_out, int n_orb);
 
 /* apply_H_add_f32: dev_out += Hbar dev_psibar in FP32 (the mixed-precision

@@ -594,7 +594,7 @@ int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
   return c->n_cell;
 }
 
-tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
+static tdfe_status launch_local(tdfe_ctx* c, const ApplyArgs& a) {
   // the FP32 copy of the potential exists in mixed contexts only
   if (a.fp32 && c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply: FP32 launch in an FP64 context");
   // default policy, from measurements on the benchmark and graded workloads:
@@ -641,4 +641,10 @@ tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
   const bool geom = !c->box;
   if (a.fp32) return launch_p<float>(c, P, geom);
   return launch_p<double>(c, P, geom);
+}
+
+tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a) {
+  TDFE_TRY(launch_local(c, a));
+  if (a.nonlocal) TDFE_TRY(tdfe_launch_nonlocal(c, a));
+  return TDFE_OK;
 }

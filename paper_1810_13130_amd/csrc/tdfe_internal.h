@@ -97,6 +97,9 @@ struct tdfe_ctx {
   double pcg_tol = 1e-13;
   int pcg_maxit = 5000;
   int last_poisson_iters = 0;
+  // Kleinman-Bylander term: caller-owned store of the projector tables, off when n_proj == 0
+  int n_proj = 0;
+  void* nl_store = nullptr;
 };
 
 // error helpers ----------------------------------------------------------------
@@ -143,6 +146,7 @@ struct ApplyArgs {
   int64_t* n_blocks_out;
   const int* done_flag; // early-exit flag (device) or NULL
   bool fp32;            // x, y stored as float
+  bool nonlocal;        // Hbar launches: add the Kleinman-Bylander term when projectors are set
 };
 tdfe_status tdfe_launch_apply(tdfe_ctx* c, const ApplyArgs& a);
 // rectilinear-cell variant (tdfe_apply_box.hip), used by tdfe_launch_apply
@@ -157,6 +161,9 @@ bool tdfe_curved_kernel_ok(const tdfe_ctx* c, int cols, bool fp32);
 #define TDFE_VARIANT_PAIR 2
 #define TDFE_VARIANT_PLANE 3
 tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a);
+// nonlocal term after the local kernel (tdfe_nonlocal.hip): Loewdin launches
+// on the DoF numbering only; appends one row to the energy partials
+tdfe_status tdfe_launch_nonlocal(tdfe_ctx* c, const ApplyArgs& a);
 
 // mixed precision: floor of the Lanczos stop tolerance relative to ||psibar||
 // (16 units of FP32 roundoff)

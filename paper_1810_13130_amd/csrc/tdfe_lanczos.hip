@@ -441,6 +441,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     a.vw32 = (const float*)vw;
     a.lowdin = true;
     a.fullgrid = false;
+    a.nonlocal = true;
     a.energy = c->partial;
     int64_t groups = 0;
     a.n_blocks_out = &groups;
@@ -692,6 +693,7 @@ static tdfe_status apply_checked(tdfe_ctx* c, const void* dev_psibar, void* dev_
   a.kin = 0.5;
   a.vw = c->vw;
   a.lowdin = true;
+  a.nonlocal = true;
   a.fp32 = false;
   return tdfe_launch_apply(c, a);
 }
@@ -719,6 +721,7 @@ tdfe_status tdfe_apply_H_add_f32(tdfe_ctx* c, const void* dev_psibar, void* dev_
   a.kin = 0.5;
   a.vw32 = c->vw32;
   a.lowdin = true;
+  a.nonlocal = true;
   a.fp32 = true;
   return tdfe_launch_apply(c, a);
 }

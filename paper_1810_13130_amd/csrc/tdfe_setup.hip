@@ -207,7 +207,8 @@ void carve(tdfe_ctx* c, char* base) {
   c->krylov = k.take<char>((size_t)(c->k_max + 1) * nd * cols * elem_bytes(c));
   c->hq = k.take<char>((size_t)nd * cols * elem_bytes(c));
   c->half = k.take<double>((size_t)nd * 2 * c->n_orb_max);
-  c->n_partial = std::max<int64_t>(ne, 4096) * std::max(cols, 8);
+  // block partials of the operator kernels, plus rows appended after them (the nonlocal term's)
+  c->n_partial = (std::max<int64_t>(ne, 4096) + 8) * std::max(cols, 8);
   c->partial = k.take<double>(c->n_partial);
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
   c->counters = k.take<unsigned>(256);

@@ -64,6 +64,8 @@ SIGNATURES = {
     "tdfe_mass_diag": [_P, _P],
     "tdfe_set_potential": [_P, _P],
     "tdfe_set_scf": [_P, ctypes.POINTER(ScfDesc)],
+    "tdfe_projector_query": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "tdfe_set_projectors": [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t],
     "tdfe_apply_H": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add_f32": [_P, _P, _P, ctypes.c_int],
@@ -208,6 +210,32 @@ class Context:
         s.pcg_tol = pcg_tol
         s.pcg_maxit = pcg_maxit
         self._check(self.lib.tdfe_set_scf(self.h, ctypes.byref(s)))
+
+    def projector_query(self, n_proj):
+        b = ctypes.c_size_t()
+        self._check(self.lib.tdfe_projector_query(self.h, n_proj, ctypes.byref(b)))
+        return b.value
+
+    def set_projectors(self, u, dv):
+        """Kleinman-Bylander term from u_p and dV_p at the Gauss points
+        ([n_proj][n_cell][nq^3] FP64 device tensors); u = None removes it.
+        The device store is a torch tensor held by this object."""
+        import torch
+        if u is None:
+            self._check(self.lib.tdfe_set_projectors(self.h, 0, None, None, None, 0))
+            self._nl_store = None
+            return
+        assert u.dtype == torch.float64 and dv.dtype == torch.float64 and u.is_cuda and dv.is_cuda
+        assert u.is_contiguous() and dv.is_contiguous() and u.shape == dv.shape
+        n_proj = u.shape[0]
+        assert u.numel() == n_proj * self.n_quad
+        nbytes = self.projector_query(n_proj)
+        store = torch.empty(nbytes + 256, dtype=torch.uint8, device="cuda")
+        base = store.data_ptr()
+        off = (-base) % 256
+        self._check(self.lib.tdfe_set_projectors(self.h, n_proj, _ptr(u), _ptr(dv),
+                                                 ctypes.c_void_p(base + off), nbytes))
+        self._nl_store = store
 
     @staticmethod
     def _orb(psi):

@@ -98,6 +98,15 @@ def test_query_sizes_and_call_order(lib):
     L, g = ctypes.c_double(), (ctypes.c_double * 4)()
     assert lib.tdfe_dipole_gradient(h, None, 1, 4, E, 0.1, 1e-8, 2, 8, buf, 1 << 20, ctypes.byref(L), g) == tdfe.EINVAL
     assert lib.tdfe_dipole_gradient(h, buf, 1, 4, E, 0.1, 1e-8, 2, 8, buf, 1 << 20, ctypes.byref(L), g) == tdfe.ESTATE
+    # Kleinman-Bylander store: Cbar (n_proj x n_dof FP64) plus scratch; set only after bind
+    pb = ctypes.c_size_t()
+    assert lib.tdfe_projector_query(h, 4, ctypes.byref(pb)) == 0
+    assert pb.value >= 4 * nd.value * 8 + nq.value * 8
+    assert lib.tdfe_projector_query(h, 0, ctypes.byref(pb)) == 0 and pb.value == 0
+    assert lib.tdfe_projector_query(h, -1, ctypes.byref(pb)) == tdfe.EINVAL
+    assert lib.tdfe_projector_query(h, 1025, ctypes.byref(pb)) == tdfe.EINVAL
+    assert lib.tdfe_projector_query(h, 4, None) == tdfe.EINVAL
+    assert lib.tdfe_set_projectors(h, 4, buf, buf, buf, 1 << 30) == tdfe.ESTATE
     assert lib.tdfe_bind_workspace(h, None, 0) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, ctypes.c_void_p(4096 + 8), ws.value) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, ctypes.c_void_p(4096), ws.value - 1) == tdfe.ENOMEM

@@ -1,0 +1,184 @@
+"""GPU parity of the Kleinman-Bylander nonlocal term (Eq. VPSP) against the
+CPU FP64 oracle (oracle.nonlocal_kb, pinned by test_oracle_nonlocal).
+
+The projector values u_p, dV_p come from the workload recipe, evaluated by
+each side at its own Gauss points.  FP64 results: 1e-12 relative for one
+operator application (fixed FP64 sums), 1e-10 for Krylov and Magnus
+results; the mixed path is held to the FP32 operator bar (2e-6) and the
+dipole bar (1e-5).  Every case also checks that the term changes the result
+far above the tolerance, so that a silently dropped term fails.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import gpu_context, gpu_initial_state, oracle_mesh, rel
+from oracle import lanczos, nonlocal_kb as nl, operators as op
+from oracle.magnus import State, System, magnus_step
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _cfg2(n_orb=3, nc=4, p=4):
+    return W.scaled(W.CONFIGS[2], ncell=(nc, nc, nc), p=p, n_orb=n_orb)
+
+
+def _cfg3(n_orb=3, nc=3, p=3):
+    return W.scaled(W.CONFIGS[3], ncell=(nc, nc, nc), p=p, n_orb=n_orb)
+
+
+def _gpu_projectors(ctx, cfg):
+    xq = ctx.quad_coords().cpu().numpy()
+    u, dv = W.kb_projector_values(cfg, xq)
+    ctx.set_projectors(torch.from_numpy(np.ascontiguousarray(u.reshape(u.shape[0], -1))).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(dv.reshape(dv.shape[0], -1))).cuda())
+    return u.shape[0]
+
+
+def _oracle_projectors(m, cfg):
+    u, dv = W.kb_projector_values(cfg, m.quad_xyz.reshape(m.n_cell, -1, 3))
+    return nl.kb_matrix(m, u, dv)
+
+
+def _ref_apply(m, vq, CE, x):
+    return op.apply_Hbar(m, vq, x) + nl.apply_nonlocal_bar(m, CE[0], CE[1], x)
+
+
+CASES = {
+    "box_plane": lambda n: _cfg2(n, p=4),       # odd n: plane kernel
+    "box_pair": lambda n: _cfg2(n, nc=3, p=5),  # even n: lane-pair kernel
+    "graded": lambda n: _cfg3(n),               # trilinear cells
+}
+
+
+@pytest.mark.parametrize("which,n_orb", [("box_plane", 3), ("box_pair", 1), ("box_pair", 4), ("graded", 3),
+                                         ("graded", 1), ("box_plane", 40)])
+def test_apply_H_with_projectors_matches_oracle(which, n_orb):
+    """40 orbitals = 80 real columns: two column chunks of the projection."""
+    cfg = CASES[which](n_orb)
+    ctx = gpu_context(cfg, n_orb=n_orb, k_max=8)
+    n_proj = _gpu_projectors(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    CE = _oracle_projectors(m, cfg)
+    assert n_proj == CE[0].shape[0] > 0
+    x = W.random_block(m.n_dof, n_orb, 21)
+    y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+    ref = _ref_apply(m, vq, CE, x)
+    assert rel(y, ref) < 1e-12
+    assert rel(ref, op.apply_Hbar(m, vq, x)) > 1e-6
+
+
+def test_apply_H_with_projectors_full_size_benchmark_workload():
+    """16^3 cells, p = 5, 8 orbitals, 16 projectors (4 atoms x s, p)."""
+    cfg = W.CONFIGS[2]
+    ctx = gpu_context(cfg, k_max=8)
+    _gpu_projectors(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    CE = _oracle_projectors(m, cfg)
+    x = W.random_block(m.n_dof, cfg.n_orb, 7)
+    y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(y, _ref_apply(m, vq, CE, x)) < 1e-12
+
+
+def test_removing_projectors_restores_local_operator():
+    cfg = _cfg2(2)
+    ctx = gpu_context(cfg, n_orb=2, k_max=8)
+    m, vq = oracle_mesh(cfg)
+    x = torch.from_numpy(W.random_block(m.n_dof, 2, 3)).cuda()
+    y0 = ctx.apply_H(x).cpu().numpy()
+    _gpu_projectors(ctx, cfg)
+    y1 = ctx.apply_H(x).cpu().numpy()
+    ctx.set_projectors(None, None)
+    y2 = ctx.apply_H(x).cpu().numpy()
+    assert rel(y1, y0) > 1e-6
+    assert rel(y2, y0) < 1e-14  # the local kernel's scatter order may vary between launches
+
+
+def test_zero_projector_norm_is_rejected():
+    from paper_1810_13130_amd import tdfe
+    cfg = _cfg2(1, nc=3, p=3)
+    ctx = gpu_context(cfg, n_orb=1, k_max=8)
+    u = torch.zeros((2, ctx.n_quad), dtype=torch.float64, device="cuda")
+    u[0] = 1.0
+    dv = torch.ones_like(u)
+    with pytest.raises(tdfe.TdfeError) as e:
+        ctx.set_projectors(u, dv)
+    assert e.value.status == tdfe.EINVAL
+    m, vq = oracle_mesh(cfg)
+    x = W.random_block(m.n_dof, 1, 4)
+    # the term stays off after a rejected set
+    y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+    assert rel(y, op.apply_Hbar(m, vq, x)) < 1e-12
+
+
+@pytest.mark.parametrize("which,n_orb,tau", [("box_plane", 3, 0.05), ("box_pair", 2, -0.03), ("graded", 2, 0.05)])
+def test_lanczos_expm_with_projectors_matches_oracle(which, n_orb, tau):
+    """The Krylov recurrence takes alpha from the operator's energy partials,
+    to which the nonlocal term appends its own row."""
+    cfg = CASES[which](n_orb)
+    ctx = gpu_context(cfg, n_orb=n_orb)
+    _gpu_projectors(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    CE = _oracle_projectors(m, cfg)
+    x = W.random_block(m.n_dof, n_orb, 9)
+    x /= np.linalg.norm(x, axis=0)
+    g = torch.from_numpy(x).cuda()
+    ks, errs = ctx.lanczos_expm(g, tau, 1e-12)
+    z, kref, _ = lanczos.lanczos_expm(lambda v: _ref_apply(m, vq, CE, v), x, tau, 1e-12)
+    assert rel(g.cpu().numpy(), z) < 1e-10
+    assert all(abs(a - b) <= 1 for a, b in zip(ks, kref))
+    z0, _, _ = lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), x, tau, 1e-12)
+    assert rel(z, z0) > 1e-6
+
+
+@pytest.mark.parametrize("which", ["box_plane", "graded"])
+def test_magnus_scf_with_projectors_matches_oracle(which):
+    cfg = CASES[which](3)
+    ctx = gpu_context(cfg, n_orb=3)
+    Z, R = W.atoms(cfg)
+    ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=3, pcg_tol=1e-14)
+    _gpu_projectors(ctx, cfg)
+    g = gpu_initial_state(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    sysm = System(m, vq, hartree=True, xc="x", Z=Z, R=R, tol=1e-12, pcg_tol=1e-14,
+                  nonlocal_kb=_oracle_projectors(m, cfg))
+    st = State(sysm, W.initial_psibar(cfg, m.dof_xyz, m.M))
+    for n in range(3):
+        rep = ctx.magnus_step(g, cfg.dt, 0.0, 1e-12)
+        ref = magnus_step(sysm, st, cfg.dt)
+        assert np.abs(rep["mu"] - ref["dipole"]).max() < 1e-10 * np.abs(ref["dipole"]).max()
+        assert abs(rep["charge"] - ref["charge"]) < 1e-10 * abs(ref["charge"])
+    assert rel(g.cpu().numpy(), st.psibar) < 1e-10
+
+
+def test_fp32_operator_with_projectors_matches_oracle():
+    cfg = CASES["graded"](3)
+    ctx = gpu_context(cfg, n_orb=3, k_max=8, precision=1)
+    _gpu_projectors(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    CE = _oracle_projectors(m, cfg)
+    x = W.random_block(m.n_dof, 3, 42)
+    xg = torch.from_numpy(x).to(torch.complex64).cuda()
+    y = torch.zeros_like(xg)
+    ctx.apply_H_add_f32(xg, y)
+    assert rel(y.cpu().numpy(), _ref_apply(m, vq, CE, x)) < 2e-6
+
+
+def test_mixed_magnus_with_projectors_dipole_within_1e5():
+    cfg = _cfg2(3)
+    ctx = gpu_context(cfg, n_orb=3, precision=1)
+    Z, R = W.atoms(cfg)
+    ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=3)
+    _gpu_projectors(ctx, cfg)
+    g = gpu_initial_state(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    sysm = System(m, vq, hartree=True, xc="x", Z=Z, R=R, tol=1e-10, pcg_tol=1e-14,
+                  nonlocal_kb=_oracle_projectors(m, cfg))
+    st = State(sysm, W.initial_psibar(cfg, m.dof_xyz, m.M))
+    mu_g, mu_r = [], []
+    for n in range(6):
+        mu_g.append(ctx.magnus_step(g, cfg.dt, 0.0, 1e-10)["mu"])
+        mu_r.append(magnus_step(sysm, st, cfg.dt)["dipole"])
+    mu_g, mu_r = np.array(mu_g), np.array(mu_r)
+    assert np.abs(mu_g - mu_r).max() <= 1e-5 * np.abs(mu_r).max()
