@@ -135,6 +135,70 @@ def graded_apply(reps=3):
     return out
 
 
+def nonlocal_term(n_steps=30, reps=50):
+    """Kleinman-Bylander term (Eq. VPSP) on the benchmark workload: 4 atoms x
+    (s, p_x, p_y, p_z) Gaussian projectors from the workload recipe.  Magnus
+    steps/s with the term, the operator launch with and without it, and the
+    streaming bytes of its passes (Cbar read by both passes, x over the boxes,
+    the output read and written over the crossed lines) against HBM."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[2]
+    out = {"workload": cfg.name + " + Kleinman-Bylander projectors (4 atoms x s, p)"}
+    for prec, name, eb in ((tdfe.FP64, "f64", 8), (tdfe.MIXED_FP32, "mixed", 4)):
+        ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=cfg.n_orb, k_max=cfg.k_max, precision=prec)
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
+        Z, R = W.atoms(cfg)
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=cfg.n_orb)
+        dt_ = torch.complex128 if prec == tdfe.FP64 else torch.complex64
+        f = ctx.apply_H_add if prec == tdfe.FP64 else ctx.apply_H_add_f32
+        x = torch.randn(ctx.n_dof, cfg.n_orb, dtype=dt_, device="cuda")
+        y = torch.zeros_like(x)
+
+        def launch_us():
+            for _ in range(3):
+                f(x, y)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for _ in range(reps):
+                f(x, y)
+            e1.record()
+            torch.cuda.synchronize()
+            return e0.elapsed_time(e1) * 1e3 / reps
+
+        t_local = launch_us()
+        u, dv = W.kb_projector_values(cfg, xq)
+        ctx.set_projectors(torch.from_numpy(np.ascontiguousarray(u.reshape(u.shape[0], -1))).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(dv.reshape(dv.shape[0], -1))).cuda())
+        groups, stored, box_dofs, line_dofs = ctx.projector_info()
+        t_nl = launch_us()
+        cols = 2 * cfg.n_orb
+        nl_bytes = 2 * stored * eb + box_dofs * cols * eb + 2 * line_dofs * cols * eb
+        psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
+                                                ctx.mass_diag().cpu().numpy())).cuda()
+        for _ in range(3):
+            ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n_steps):
+            ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        extra = t_nl - t_local
+        out.update({"n_proj": int(u.shape[0]), "groups": groups, "stored_entries": stored, "box_dofs": box_dofs,
+                    "line_dofs": line_dofs})
+        out[name] = {"steps_per_s": n_steps / wall, "launch_us_local": t_local, "launch_us_with_term": t_nl,
+                     "term_us": extra, "term_bytes": nl_bytes,
+                     "term_hbm_frac": nl_bytes / (extra * 1e-6) / (HBM_PEAK_GBS * 1e9) if extra > 0 else None}
+        del x, y, psi
+        ctx.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def cpu_oracle_baseline(cfg, ks_total):
     """Bounded sample of the CPU oracle on this host, scaled to steps/s."""
     import threadpoolctl
@@ -189,6 +253,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
     ap.add_argument("--no-graded", action="store_true")
+    ap.add_argument("--no-nonlocal", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -319,6 +384,8 @@ def main():
         out["adjoint"] = adjoint_rate()
     if not args.no_graded:
         out["graded_apply"] = graded_apply()
+    if not args.no_nonlocal:
+        out["nonlocal"] = nonlocal_term()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_baseline(cfg, int(round(ks_total / args.steps)))
     print(json.dumps(out), flush=True)

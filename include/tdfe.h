@@ -128,9 +128,15 @@ tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);
  * precisions (the mixed path keeps an FP32 copy of C M^-1/2 and accumulates
  * the projections in FP64).  All integrals use the Gauss rule of the mesh.
  *
+ * Projectors are compact around their atoms: C M^-1/2 is stored on the
+ * smallest box of the DoF grid that holds every entry above 2^-60 of the
+ * projector's largest one (consecutive projectors with nearly the same box
+ * share it), and the hot passes touch those boxes only.
+ *
  * projector_query: *bytes = device store needed for n_proj projectors
- * (0 <= n_proj <= TDFE_MAX_PROJ); about n_proj n_dof 8 bytes (12 in mixed
- * contexts) plus small scratch.
+ * (0 <= n_proj <= TDFE_MAX_PROJ): the bound n_proj n_dof 8 bytes (12 in
+ * mixed contexts) for the boxes, plus scratch of about 8 (n_quad + n_dof)
+ * bytes and 2 MB per 256 blocks of partial sums.
  *
  * set_projectors: dev_u, dev_dv are [n_proj][n_cell][nq^3] FP64 device
  * arrays of u_p and dV_p at the Gauss points; dev_store is a caller-owned
@@ -146,6 +152,13 @@ tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);
 tdfe_status tdfe_projector_query(const tdfe_ctx* ctx, int n_proj, size_t* bytes);
 tdfe_status tdfe_set_projectors(tdfe_ctx* ctx, int n_proj, const double* dev_u, const double* dev_dv,
                                 void* dev_store, size_t store_bytes);
+/* projector_info: the compact layout chosen by the last set_projectors
+ * (zeros when the term is off): number of groups sharing a box, stored
+ * entries of C M^-1/2, DoFs in the boxes summed over groups (rows of x the
+ * projection streams), and DoFs on the grid lines crossed by boxes (rows of
+ * the output the add pass reads and writes, each once). */
+tdfe_status tdfe_projector_info(const tdfe_ctx* ctx, int* n_groups, int64_t* stored, int64_t* box_dofs,
+                                int64_t* line_dofs);
 
 /* apply_H: dev_out = Hbar dev_psibar for n_orb orbitals (both [n_dof][n_orb]
  * complex128), Hbar = M^-1/2 (1/2 K + V-mass) M^-1/2 with the current total

@@ -100,6 +100,12 @@ struct tdfe_ctx {
   // Kleinman-Bylander term: caller-owned store of the projector tables, off when n_proj == 0
   int n_proj = 0;
   void* nl_store = nullptr;
+  int nl_groups = 0, nl_blocks = 0;  // projector groups (shared boxes) and blocks of the hot passes
+  int nl_np_max = 0;                 // most projectors in one group
+  int nl_lines = 0, nl_add_lpb = 0, nl_add_blocks = 0;  // line partition of the add pass
+  int64_t nl_line_dofs = 0;                             // DoFs on those lines (x ranges)
+  int64_t nl_packed = 0;             // stored entries of Cbar
+  int64_t nl_box_dofs = 0;           // DoFs in the groups' boxes (summed over groups)
 };
 
 // error helpers ----------------------------------------------------------------

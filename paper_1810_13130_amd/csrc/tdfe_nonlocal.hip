@@ -3,34 +3,74 @@
 // The term acts on phi as sum_p (int chi_p phi / D_p) chi_p with chi_p =
 // u_p dV_p and D_p = int u_p dV_p u_p.  On the FE basis its Galerkin matrix is
 // C^T diag(E) C with c_pj = int chi_p N_j (Gauss rule) and E_p = 1 / D_p; in
-// the Loewdin form (Eq. TDKSMatVecStandard) the library stores
-// Cbar = C M^-1/2 ([n_proj][n_dof], projector-major) and adds
+// the Loewdin form (Eq. TDKSMatVecStandard) the library keeps
+// Cbar = C M^-1/2 and adds
 //   Hbar x += Cbar^T diag(E) Cbar x
-// after the local operator kernel of every Hamiltonian launch:
-//   project   per-block partials of t = Cbar (cs x)     (cs: the launch's column scale)
-//   finalize  t (fixed-order sum), E t, and the term's share of the quadratic form
-//   add       y += Cbar^T (E t)
-// These are tall-skinny contractions over the DoFs: one streaming pass over
-// Cbar and x each, HBM-bound.
+// after the local operator kernel of every Hamiltonian launch.
+//
+// Projectors are compact around their atoms, so Cbar is stored per group of
+// projectors (consecutive projectors whose supports nearly coincide, e.g. the
+// s and p channels of one atom) on a box of the structured DoF grid: the
+// smallest box holding every entry of magnitude above 2^-60 of the
+// projector's largest entry.  The dropped entries change a projection by at
+// most 2^-60 sqrt(n_dof) of |Cbar_p| |x| (below 1e-14 at 10^7 DoFs).
+// Hot passes, both over the boxes only (one launch each for all groups):
+//   project   per-block partials of t = Cbar (cs x)   (cs: the launch's column scale)
+//   finalize  t (fixed-order sum over the group's blocks), E t, E t^2
+//   add       y += Cbar^T (E t) line by line over the DoF lines crossed by
+//             boxes; each (DoF, column) has one owner, which adds its groups in order
+// Both are HBM-bound streaming passes (Cbar over the boxes; x over the boxes,
+// y over the lines).
+#include <algorithm>
+#include <climits>
+
 #include "tdfe_internal.h"
 
 namespace {
 
-constexpr int NL_BLOCKS = 256;    // blocks of the projection pass
 constexpr int NL_THREADS = 256;
-constexpr int NL_PCH = 16;        // projectors per register chunk
+constexpr int NL_PCH = 16;           // projectors per group (register accumulators)
+constexpr int NL_TARGET_BLOCKS = 4096;
+constexpr int NL_SETUP_BLOCKS = 256;
+constexpr double NL_DROP = 8.673617379884035e-19;  // 2^-60
+
+struct NlGroup {
+  int I0, J0, K0;   // first DoF of the box (0-based interior DoF coordinates)
+  int nx, ny, nz;   // box extent
+  int p0, np;       // projectors p0 .. p0 + np - 1
+  int b0, nb;       // blocks b0 .. b0 + nb - 1 of the hot passes
+  int lpb;          // box lines (x rows) per block
+  int pad;
+  int64_t off;      // element offset of the group's Cbar: [np][nz][ny][nx]
+};
+
+// a line of the DoF grid (fixed J, K) crossed by at least one group box:
+// x range [I_lo, I_hi] spans the boxes of groups gids[gs .. gs + gn)
+struct NlLine {
+  int J, K, I_lo, I_hi, gs, gn;
+};
 
 struct NlLayout {
-  double* cbar;     // [n_proj][n_dof]
-  float* cbar32;    // [n_proj][n_dof] (mixed contexts)
+  double* cbar;     // packed groups (at most n_proj x n_dof)
+  float* cbar32;    // the same in FP32 (mixed contexts)
   double* E;        // [n_proj]
-  double* part;     // [NL_BLOCKS][n_proj][TDFE_MAX_COLS]
+  double* part;     // [max blocks][NL_PCH][TDFE_MAX_COLS]
   double* tE;       // [n_proj][TDFE_MAX_COLS]
   double* eP;       // [n_proj][TDFE_MAX_COLS]
-  double* scratch;  // [n_quad] (set-up)
-  double* red;      // [NL_BLOCKS + 8] (set-up)
+  NlGroup* groups;  // [n_proj]
+  int* pgrp;        // [n_proj] group of each projector
+  int* blk2grp;     // [max blocks]
+  int* box;         // [n_proj][6] set-up: I0, J0, K0, I1, J1, K1
+  double* amax;     // [n_proj] set-up: largest |Cbar_p|
+  double* chi;      // [n_quad] set-up
+  double* dense;    // [n_dof] set-up: Cbar_p on every DoF
+  double* red;      // [NL_SETUP_BLOCKS] set-up
+  NlLine* lines;    // [at most nyi nzi] lines of the add pass
+  int* gids;        // [at most nyi nzi n_proj] groups of each line
   size_t bytes;
 };
+
+int nl_max_blocks(int n_proj) { return NL_TARGET_BLOCKS + n_proj; }
 
 NlLayout nl_layout(const tdfe_ctx* c, int n_proj, char* base) {
   NlLayout L{};
@@ -41,21 +81,30 @@ NlLayout nl_layout(const tdfe_ctx* c, int n_proj, char* base) {
     off += bytes;
     return p;
   };
-  const size_t np = (size_t)n_proj;
+  const size_t np = (size_t)n_proj, mb = (size_t)nl_max_blocks(n_proj);
   L.cbar = (double*)take(np * c->n_dof * sizeof(double));
   L.cbar32 = (float*)take(c->precision == TDFE_FP64 ? sizeof(float) : np * c->n_dof * sizeof(float));
   L.E = (double*)take(np * sizeof(double));
-  L.part = (double*)take((size_t)NL_BLOCKS * np * TDFE_MAX_COLS * sizeof(double));
+  L.part = (double*)take(mb * NL_PCH * TDFE_MAX_COLS * sizeof(double));
   L.tE = (double*)take(np * TDFE_MAX_COLS * sizeof(double));
   L.eP = (double*)take(np * TDFE_MAX_COLS * sizeof(double));
-  L.scratch = (double*)take((size_t)c->n_quad * sizeof(double));
-  L.red = (double*)take((NL_BLOCKS + 8) * sizeof(double));
+  L.groups = (NlGroup*)take(np * sizeof(NlGroup));
+  L.pgrp = (int*)take(np * sizeof(int));
+  L.blk2grp = (int*)take(mb * sizeof(int));
+  L.box = (int*)take(np * 6 * sizeof(int));
+  L.amax = (double*)take(np * sizeof(double));
+  L.chi = (double*)take((size_t)c->n_quad * sizeof(double));
+  L.dense = (double*)take((size_t)c->n_dof * sizeof(double));
+  L.red = (double*)take(NL_SETUP_BLOCKS * sizeof(double));
+  const size_t nlines = (size_t)(c->Ny - 2) * (c->Nz - 2);
+  L.lines = (NlLine*)take(nlines * sizeof(NlLine));
+  L.gids = (int*)take(nlines * np * sizeof(int));
   L.bytes = off + 256;
   return L;
 }
 
 // ---------------------------------------------------------------------------------------------
-// set-up
+// set-up kernels
 // ---------------------------------------------------------------------------------------------
 __global__ void nl_chi_kernel(const double* u, const double* dv, double* chi, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -78,7 +127,7 @@ __global__ void nl_norm_partial_kernel(const double* wdet, const double* chi, co
   if (threadIdx.x == 0) part[blockIdx.x] = s[0];
 }
 
-// E_p = 1 / D_p from the block partials; a zero D_p is reported through *bad
+// E_p = 1 / D_p from the block partials; a zero or non-finite D_p sets *bad
 __global__ void nl_norm_final_kernel(const double* part, int nb, double* E, int* bad) {
   if (threadIdx.x != 0) return;
   double D = 0.0;
@@ -91,77 +140,217 @@ __global__ void nl_norm_final_kernel(const double* part, int nb, double* E, int*
   }
 }
 
-// Cbar_p(dof) = c_p(node(dof)) M^-1/2(dof), with an FP32 copy when requested
-__global__ void nl_extract_kernel(const double* cload, const double* minv, double* cbar, float* cbar32, int Nx,
-                                  int Ny, int64_t n_dof) {
+// dense[d] = c_p(node(d)) M^-1/2(d)
+__global__ void nl_extract_kernel(const double* cload, const double* minv, double* dense, int Nx, int Ny,
+                                  int64_t n_dof) {
   const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (d >= n_dof) return;
   const int64_t nxi = Nx - 2, nyi = Ny - 2;
   const int64_t I = d % nxi + 1, J = (d / nxi) % nyi + 1, K = d / (nxi * nyi) + 1;
-  const double v = cload[I + (int64_t)Nx * (J + (int64_t)Ny * K)] * minv[d];
-  cbar[d] = v;
-  if (cbar32) cbar32[d] = (float)v;
+  dense[d] = cload[I + (int64_t)Nx * (J + (int64_t)Ny * K)] * minv[d];
+}
+
+// per-block max |v| (exact, order independent)
+__global__ void nl_absmax_partial_kernel(const double* v, int64_t n, double* part) {
+  __shared__ double s[NL_THREADS];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * NL_THREADS + threadIdx.x; i < n; i += (int64_t)gridDim.x * NL_THREADS)
+    m = fmax(m, fabs(v[i]));
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = NL_THREADS / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) s[threadIdx.x] = fmax(s[threadIdx.x], s[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+// amax = max of the partials; the box starts empty (I0 > I1)
+__global__ void nl_absmax_final_kernel(const double* part, int nb, double* amax, int* box, int nxi, int nyi,
+                                       int nzi) {
+  if (threadIdx.x != 0) return;
+  double m = 0.0;
+  for (int b = 0; b < nb; ++b) m = fmax(m, part[b]);
+  *amax = m;
+  box[0] = nxi;
+  box[1] = nyi;
+  box[2] = nzi;
+  box[3] = -1;
+  box[4] = -1;
+  box[5] = -1;
+}
+
+// smallest DoF box holding every |v| > NL_DROP amax (integer min / max atomics)
+__global__ void nl_box_kernel(const double* v, int64_t n_dof, int nxi, int nyi, const double* amax, int* box) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= n_dof) return;
+  if (!(fabs(v[d]) > NL_DROP * *amax)) return;
+  const int I = (int)(d % nxi), J = (int)((d / nxi) % nyi), K = (int)(d / ((int64_t)nxi * nyi));
+  atomicMin(box + 0, I);
+  atomicMin(box + 1, J);
+  atomicMin(box + 2, K);
+  atomicMax(box + 3, I);
+  atomicMax(box + 4, J);
+  atomicMax(box + 5, K);
+}
+
+// dst[(k ny + j) nx + i] = dense[box DoF (i, j, k)] (FP32 copy alongside when requested)
+__global__ void nl_pack_kernel(const double* dense, NlGroup G, int nxi, int nyi, double* dst, float* dst32) {
+  const int64_t vol = (int64_t)G.nx * G.ny * G.nz;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= vol) return;
+  const int i = (int)(e % G.nx), j = (int)((e / G.nx) % G.ny), k = (int)(e / ((int64_t)G.nx * G.ny));
+  const double v = dense[(G.I0 + i) + (int64_t)nxi * ((G.J0 + j) + (int64_t)nyi * (G.K0 + k))];
+  dst[e] = v;
+  if (dst32) dst32[e] = (float)v;
 }
 
 // ---------------------------------------------------------------------------------------------
-// apply
+// hot kernels
 // ---------------------------------------------------------------------------------------------
-// per-block partials of t[p][col] = sum_r Cbar[p][r] cs[col] x[r][col] for a
-// chunk of NL_PCH projectors; thread t serves column t % CP of rows
-// t / CP, t / CP + NL_THREADS / CP, ... of the block's row range
-template <typename T, typename CT, int CP>
+// Walk over the slots of a block: slot s covers x positions rg + RG sl of box
+// line l0 + s / nslot (sl = s % nslot).  The walk is the same for every lane
+// of the block, so its state lives in scalar registers.
+struct SlotWalk {
+  int sl, j, k;
+  int64_t dline, eline;  // DoF of the line's first box entry; element offset of the line
+  __device__ void start(const NlGroup& G, int l0, int nxi, int nyi) {
+    sl = 0;
+    j = l0 % G.ny;
+    k = l0 / G.ny;
+    dline = G.I0 + (int64_t)nxi * ((G.J0 + j) + (int64_t)nyi * (G.K0 + k));
+    eline = (int64_t)l0 * G.nx;
+  }
+  __device__ void next(const NlGroup& G, int nslot, int nxi, int nyi) {
+    if (++sl == nslot) {
+      sl = 0;
+      eline += G.nx;
+      if (++j == G.ny) {
+        j = 0;
+        ++k;
+        dline += (int64_t)nxi * (nyi - G.ny + 1);
+      } else {
+        dline += nxi;
+      }
+    }
+  }
+};
+
+// block b serves box lines [l0, l1) of its group; thread t takes column t % CP
+// and the x positions t / CP + RG sl of each line.  U slots are loaded before
+// any is used (invalid slots read a valid address and contribute zero);
+// projector indices past the group's np read the group's last projector and
+// are discarded.
+template <typename T, typename CT, int CP, int NP, int U>
 __global__ void __launch_bounds__(NL_THREADS)
     nl_project_kernel(const T* __restrict__ x, int ld, int cols, const double* __restrict__ colscale,
-                      const CT* __restrict__ cbar, int64_t n_dof, int p0, int np, double* __restrict__ part,
-                      int n_proj, const int* done) {
-  constexpr int RG = NL_THREADS / CP;  // row groups per block
-  __shared__ double s[NL_PCH][NL_THREADS];
+                      const CT* __restrict__ cbar, const NlGroup* __restrict__ groups,
+                      const int* __restrict__ blk2grp, int nxi, int nyi, double* __restrict__ part, const int* done) {
+  constexpr int RG = NL_THREADS / CP;
+  __shared__ double s[NP][NL_THREADS];
   if (done && *done) return;
-  const int t = threadIdx.x;
-  const int col = t % CP, rg = t / CP;
+  const int b = blockIdx.x;
+  const NlGroup G = groups[blk2grp[b]];
+  const int t = threadIdx.x, col = t % CP, rg = t / CP;
   const bool cok = col < cols;
-  const int64_t rows_per_block = (n_dof + gridDim.x - 1) / gridDim.x;
-  const int64_t r0 = (int64_t)blockIdx.x * rows_per_block;
-  const int64_t r1 = r0 + rows_per_block < n_dof ? r0 + rows_per_block : n_dof;
-  double acc[NL_PCH];
+  const int colc = cok ? col : 0;
+  const int l0 = (b - G.b0) * G.lpb;
+  const int l1 = min(l0 + G.lpb, G.ny * G.nz);
+  const int nslot = (G.nx + RG - 1) / RG;
+  const int S = (l1 - l0) * nslot;
+  const int64_t vol = (int64_t)G.nx * G.ny * G.nz;
+  const CT* cg = cbar + G.off;
+  int64_t qoff[NP];
 #pragma unroll
-  for (int q = 0; q < NL_PCH; ++q) acc[q] = 0.0;
-  for (int64_t r = r0 + rg; r < r1; r += RG) {
-    const double xv = cok ? (double)x[r * ld + col] : 0.0;
+  for (int q = 0; q < NP; ++q) qoff[q] = (int64_t)min(q, G.np - 1) * vol;
+  SlotWalk w;
+  w.start(G, l0, nxi, nyi);
+  const int64_t d0 = w.dline, e0 = w.eline;
+  double acc[NP];
 #pragma unroll
-    for (int q = 0; q < NL_PCH; ++q)
-      if (q < np) acc[q] += (double)cbar[(int64_t)(p0 + q) * n_dof + r] * xv;
+  for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+  for (int s0 = 0; s0 < S; s0 += U) {
+    T xr[U];
+    CT cr[U][NP];
+    bool ok[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int i = rg + RG * w.sl;
+      const bool v = s0 + u < S && i < G.nx;
+      ok[u] = v && cok;
+      const int64_t d = v ? w.dline + i : d0;
+      const int64_t e = v ? w.eline + i : e0;
+      xr[u] = x[d * ld + colc];
+#pragma unroll
+      for (int q = 0; q < NP; ++q) cr[u][q] = cg[qoff[q] + e];
+      w.next(G, nslot, nxi, nyi);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const double xv = ok[u] ? (double)xr[u] : 0.0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) acc[q] += (double)cr[u][q] * xv;
+    }
   }
 #pragma unroll
-  for (int q = 0; q < NL_PCH; ++q) s[q][t] = acc[q];
+  for (int q = 0; q < NP; ++q) s[q][t] = acc[q];
   __syncthreads();
-  // sum over the row groups (fixed order), one column per thread
-  if (t < CP && cok) {
-    const double cs = colscale ? colscale[t >> 1] : 1.0;
-    for (int q = 0; q < np; ++q) {
+  // sum over the RG lanes of each (projector, column), fixed order
+  for (int pr = t; pr < NP * CP; pr += NL_THREADS) {
+    const int q = pr / CP, cc = pr % CP;
+    if (q < G.np && cc < cols) {
       double v = 0.0;
-      for (int g = 0; g < RG; ++g) v += s[q][g * CP + t];
-      part[((int64_t)blockIdx.x * n_proj + p0 + q) * TDFE_MAX_COLS + t] = v * cs;
+      for (int g = 0; g < RG; ++g) v += s[q][g * CP + cc];
+      const double cs = colscale ? colscale[cc >> 1] : 1.0;
+      part[((int64_t)b * NL_PCH + q) * TDFE_MAX_COLS + cc] = v * cs;
     }
   }
 }
 
-// t[p][col] = sum_b part[b][p][col]; tE = E t; eP = E t^2 (one block per projector)
-__global__ void nl_finalize_kernel(const double* part, int nb, int n_proj, int cols, const double* E, double* tE,
-                                   double* eP, const int* done) {
+// t[p][col] = sum over the group's blocks (slices of blocks per lane group,
+// then the slices in order); tE = E t; eP = E t^2.  One block per projector.
+__global__ void __launch_bounds__(NL_THREADS)
+    nl_finalize_kernel(const double* __restrict__ part, const NlGroup* __restrict__ groups,
+                       const int* __restrict__ pgrp, int cols, const double* __restrict__ E, double* tE, double* eP,
+                       const int* done) {
+  __shared__ double s[NL_THREADS];
   if (done && *done) return;
-  const int p = blockIdx.x, col = threadIdx.x;
-  if (col >= cols) return;
-  double t = 0.0;
-  for (int b = 0; b < nb; ++b) t += part[((int64_t)b * n_proj + p) * TDFE_MAX_COLS + col];
-  tE[p * TDFE_MAX_COLS + col] = E[p] * t;
-  eP[p * TDFE_MAX_COLS + col] = E[p] * t * t;
+  const int p = blockIdx.x, t = threadIdx.x;
+  const int cw = cols <= 16 ? 16 : cols <= 32 ? 32 : 64;
+  const int nsl = NL_THREADS / cw;
+  const int col = t % cw, sl = t / cw;
+  const NlGroup G = groups[pgrp[p]];
+  const int q = p - G.p0;
+  double acc = 0.0;
+  if (col < cols) {
+    const double* pp = part + (int64_t)q * TDFE_MAX_COLS + col;
+    int b = G.b0 + sl;
+    const int b1 = G.b0 + G.nb;
+    for (; b + 3 * nsl < b1; b += 4 * nsl) {
+      const double v0 = pp[(int64_t)b * NL_PCH * TDFE_MAX_COLS];
+      const double v1 = pp[(int64_t)(b + nsl) * NL_PCH * TDFE_MAX_COLS];
+      const double v2 = pp[(int64_t)(b + 2 * nsl) * NL_PCH * TDFE_MAX_COLS];
+      const double v3 = pp[(int64_t)(b + 3 * nsl) * NL_PCH * TDFE_MAX_COLS];
+      acc += v0;
+      acc += v1;
+      acc += v2;
+      acc += v3;
+    }
+    for (; b < b1; b += nsl) acc += pp[(int64_t)b * NL_PCH * TDFE_MAX_COLS];
+  }
+  s[t] = acc;
+  __syncthreads();
+  if (t < cols) {
+    double v = 0.0;
+    for (int k = 0; k < nsl; ++k) v += s[k * cw + t];
+    tE[p * TDFE_MAX_COLS + t] = E[p] * v;
+    eP[p * TDFE_MAX_COLS + t] = E[p] * v * v;
+  }
 }
 
 // the term's share of the per-column quadratic form, as one more row of the
 // operator kernel's block partials
-__global__ void nl_energy_kernel(const double* eP, int n_proj, int cols, double* energy_row, const int* done) {
-  if (done && *done) return;
+__device__ __forceinline__ void nl_energy_row(const double* eP, int n_proj, int cols, double* energy_row) {
   const int col = threadIdx.x;
   if (col >= cols) return;
   double e = 0.0;
@@ -169,31 +358,115 @@ __global__ void nl_energy_kernel(const double* eP, int n_proj, int cols, double*
   energy_row[col] = e;
 }
 
-// y[r][col] += sum_p Cbar[p][r] tE[p][col]
-template <typename T, typename CT>
-__global__ void __launch_bounds__(NL_THREADS)
-    nl_add_kernel(T* __restrict__ y, int ld, int cols, const CT* __restrict__ cbar, int64_t n_dof,
-                  const double* __restrict__ tE, int n_proj, const int* done) {
+__global__ void nl_energy_kernel(const double* eP, int n_proj, int cols, double* energy_row, const int* done) {
   if (done && *done) return;
-  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t r = idx / cols;
-  const int col = (int)(idx % cols);
-  if (r >= n_dof) return;
-  double acc = 0.0;
-  for (int p = 0; p < n_proj; ++p) acc += (double)cbar[(int64_t)p * n_dof + r] * tE[p * TDFE_MAX_COLS + col];
-  y[r * ld + col] += (T)acc;
+  nl_energy_row(eP, n_proj, cols, energy_row);
 }
 
-template <typename T, typename CT, int CP>
-tdfe_status nl_project_launch(tdfe_ctx* c, const T* x, int ld, int cols, const double* colscale, const int* done,
-                              const CT* cbar, const NlLayout& L) {
-  for (int p0 = 0; p0 < c->n_proj; p0 += NL_PCH) {
-    const int np = std::min(NL_PCH, c->n_proj - p0);
-    hipLaunchKernelGGL((nl_project_kernel<T, CT, CP>), dim3(NL_BLOCKS), dim3(NL_THREADS), 0, c->stream, x, ld, cols,
-                       colscale, cbar, c->n_dof, p0, np, L.part, c->n_proj, done);
+// y[d][col] += sum over the groups g whose box holds d of
+// sum_q Cbar_g[q][d] tE[p0_g + q][col].  Block b serves lines
+// [b lpb, (b + 1) lpb); every (d, col) of a line's range belongs to one
+// thread, which adds the groups in their stored order: no atomics, and the
+// result does not depend on scheduling.  Block 0 also writes the energy row
+// (all projections are final by now).
+template <typename T, typename CT, int CP, int NP, int U>
+__global__ void __launch_bounds__(NL_THREADS)
+    nl_add_kernel(T* __restrict__ y, int ld, int cols, const CT* __restrict__ cbar,
+                  const NlGroup* __restrict__ groups, const NlLine* __restrict__ lines, const int* __restrict__ gids,
+                  int n_lines, int lpb, int nxi, int nyi, const double* __restrict__ tE, const double* __restrict__ eP,
+                  int n_proj, double* energy_row, const int* done) {
+  constexpr int RG = NL_THREADS / CP;
+  if (done && *done) return;
+  const int b = blockIdx.x;
+  if (b == 0 && energy_row) nl_energy_row(eP, n_proj, cols, energy_row);
+  const int t = threadIdx.x, col = t % CP, rg = t / CP;
+  if (col >= cols) return;
+  const int L0 = b * lpb, L1 = min(L0 + lpb, n_lines);
+  for (int li = L0; li < L1; ++li) {
+    const NlLine ln = lines[li];
+    const int64_t dline = (int64_t)nxi * (ln.J + (int64_t)nyi * ln.K);
+    for (int I0 = ln.I_lo + rg; I0 <= ln.I_hi; I0 += RG * U) {
+      T yv[U];
+      double acc[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int I = min(I0 + RG * u, ln.I_hi);
+        yv[u] = y[(dline + I) * ld + col];
+        acc[u] = 0.0;
+      }
+      for (int gi = ln.gs; gi < ln.gs + ln.gn; ++gi) {
+        const NlGroup G = groups[gids[gi]];
+        const int64_t vol = (int64_t)G.nx * G.ny * G.nz;
+        const int64_t eline = ((int64_t)(ln.K - G.K0) * G.ny + (ln.J - G.J0)) * G.nx - G.I0;
+        const CT* cg = cbar + G.off;
+        double te[NP];
+        int64_t qoff[NP];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) {
+          const int qc = min(q, G.np - 1);
+          qoff[q] = (int64_t)qc * vol;
+          te[q] = q < G.np ? tE[(G.p0 + qc) * TDFE_MAX_COLS + col] : 0.0;
+        }
+        CT cr[U][NP];
+        bool in[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const int I = I0 + RG * u;
+          in[u] = I >= G.I0 && I < G.I0 + G.nx && I <= ln.I_hi;
+          const int64_t e = eline + (in[u] ? I : G.I0);
+#pragma unroll
+          for (int q = 0; q < NP; ++q) cr[u][q] = cg[qoff[q] + e];
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          double v = 0.0;
+#pragma unroll
+          for (int q = 0; q < NP; ++q) v += (double)cr[u][q] * te[q];
+          if (in[u]) acc[u] += v;
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int I = I0 + RG * u;
+        if (I <= ln.I_hi) y[(dline + I) * ld + col] = yv[u] + (T)acc[u];
+      }
+    }
+  }
+}
+
+template <typename T, typename CT, int CP, int NP>
+tdfe_status nl_passes(tdfe_ctx* c, const T* x, T* y, int ld, int cols, const double* cs, const int* done,
+                      double* energy_row, const CT* cbar, const NlLayout& L) {
+  constexpr int U = NP >= 16 ? 2 : 32 / NP;
+  const int nxi = c->Nx - 2, nyi = c->Ny - 2;
+  if (c->nl_blocks > 0) {
+    hipLaunchKernelGGL((nl_project_kernel<T, CT, CP, NP, U>), dim3(c->nl_blocks), dim3(NL_THREADS), 0, c->stream, x,
+                       ld, cols, cs, cbar, (const NlGroup*)L.groups, (const int*)L.blk2grp, nxi, nyi, L.part, done);
+    TDFE_HIP(c, hipGetLastError());
+  }
+  hipLaunchKernelGGL(nl_finalize_kernel, dim3(c->n_proj), dim3(NL_THREADS), 0, c->stream, (const double*)L.part,
+                     (const NlGroup*)L.groups, (const int*)L.pgrp, cols, (const double*)L.E, L.tE, L.eP, done);
+  TDFE_HIP(c, hipGetLastError());
+  if (c->nl_add_blocks > 0) {
+    hipLaunchKernelGGL((nl_add_kernel<T, CT, CP, NP, U>), dim3(c->nl_add_blocks), dim3(NL_THREADS), 0, c->stream,
+                       y, ld, cols, cbar, (const NlGroup*)L.groups, (const NlLine*)L.lines, (const int*)L.gids,
+                       c->nl_lines, c->nl_add_lpb, nxi, nyi, (const double*)L.tE, (const double*)L.eP, c->n_proj,
+                       energy_row, done);
+    TDFE_HIP(c, hipGetLastError());
+  } else if (energy_row) {
+    hipLaunchKernelGGL(nl_energy_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)L.eP, c->n_proj, cols,
+                       energy_row, done);
     TDFE_HIP(c, hipGetLastError());
   }
   return TDFE_OK;
+}
+
+template <typename T, typename CT, int CP>
+tdfe_status nl_passes_np(tdfe_ctx* c, const T* x, T* y, int ld, int cols, const double* cs, const int* done,
+                         double* energy_row, const CT* cbar, const NlLayout& L) {
+  if (c->nl_np_max <= 4) return nl_passes<T, CT, CP, 4>(c, x, y, ld, cols, cs, done, energy_row, cbar, L);
+  if (c->nl_np_max <= 8) return nl_passes<T, CT, CP, 8>(c, x, y, ld, cols, cs, done, energy_row, cbar, L);
+  return nl_passes<T, CT, CP, 16>(c, x, y, ld, cols, cs, done, energy_row, cbar, L);
 }
 
 // columns [col0, col0 + cols) of the launch (cols <= TDFE_MAX_COLS, col0 even)
@@ -203,25 +476,26 @@ tdfe_status nl_apply_t(tdfe_ctx* c, const ApplyArgs& a, int col0, int cols, doub
   const T* x = (const T*)a.x + col0;
   T* y = (T*)a.y + col0;
   const double* cs = a.colscale ? a.colscale + col0 / 2 : nullptr;
-  if (cols <= 16)
-    TDFE_TRY((nl_project_launch<T, CT, 16>(c, x, a.ld, cols, cs, a.done_flag, cbar, L)));
-  else if (cols <= 32)
-    TDFE_TRY((nl_project_launch<T, CT, 32>(c, x, a.ld, cols, cs, a.done_flag, cbar, L)));
-  else
-    TDFE_TRY((nl_project_launch<T, CT, 64>(c, x, a.ld, cols, cs, a.done_flag, cbar, L)));
-  hipLaunchKernelGGL(nl_finalize_kernel, dim3(c->n_proj), dim3(64), 0, c->stream, (const double*)L.part, NL_BLOCKS,
-                     c->n_proj, cols, (const double*)L.E, L.tE, L.eP, a.done_flag);
+  if (cols <= 16) return nl_passes_np<T, CT, 16>(c, x, y, a.ld, cols, cs, a.done_flag, energy_row, cbar, L);
+  if (cols <= 32) return nl_passes_np<T, CT, 32>(c, x, y, a.ld, cols, cs, a.done_flag, energy_row, cbar, L);
+  return nl_passes_np<T, CT, 64>(c, x, y, a.ld, cols, cs, a.done_flag, energy_row, cbar, L);
+}
+
+// chi = u dV, the load vector c_p on every node, Cbar_p on every DoF (dense)
+tdfe_status nl_dense_column(tdfe_ctx* c, const double* u, const double* dv, const NlLayout& L) {
+  const int64_t nq = c->n_quad;
+  hipLaunchKernelGGL(nl_chi_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, c->stream, u, dv, L.chi, nq);
   TDFE_HIP(c, hipGetLastError());
-  if (energy_row) {
-    hipLaunchKernelGGL(nl_energy_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)L.eP, c->n_proj, cols,
-                       energy_row, a.done_flag);
-    TDFE_HIP(c, hipGetLastError());
-  }
-  const int64_t n = c->n_dof * cols;
-  hipLaunchKernelGGL((nl_add_kernel<T, CT>), dim3((unsigned)((n + NL_THREADS - 1) / NL_THREADS)), dim3(NL_THREADS),
-                     0, c->stream, y, a.ld, cols, cbar, c->n_dof, (const double*)L.tE, c->n_proj, a.done_flag);
+  TDFE_TRY(tdfe_load_vector(c, L.chi, true));
+  hipLaunchKernelGGL(nl_extract_kernel, dim3((unsigned)((c->n_dof + 255) / 256)), dim3(256), 0, c->stream,
+                     (const double*)c->cload, (const double*)c->minv, L.dense, c->Nx, c->Ny, c->n_dof);
   TDFE_HIP(c, hipGetLastError());
   return TDFE_OK;
+}
+
+int64_t box_vol(const int* b) {
+  if (b[3] < b[0]) return 0;
+  return (int64_t)(b[3] - b[0] + 1) * (b[4] - b[1] + 1) * (b[5] - b[2] + 1);
 }
 
 }  // namespace
@@ -262,46 +536,203 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "set_projectors before bind_workspace");
   if (n_proj < 0 || n_proj > TDFE_MAX_PROJ)
     return tdfe_fail(c, TDFE_EINVAL, "set_projectors: n_proj outside [0, %d]", TDFE_MAX_PROJ);
-  if (n_proj == 0) {
-    c->n_proj = 0;
-    c->nl_store = nullptr;
-    return TDFE_OK;
-  }
-  if (!dev_u || !dev_dv || !dev_store) return tdfe_fail(c, TDFE_EINVAL, "set_projectors: null pointer");
-  if ((uintptr_t)dev_store % 256 != 0) return tdfe_fail(c, TDFE_EINVAL, "set_projectors: store not 256-byte aligned");
+  if (n_proj > 0 && (!dev_u || !dev_dv || !dev_store)) return tdfe_fail(c, TDFE_EINVAL, "set_projectors: null pointer");
+  if (n_proj > 0 && (uintptr_t)dev_store % 256 != 0)
+    return tdfe_fail(c, TDFE_EINVAL, "set_projectors: store not 256-byte aligned");
   const NlLayout L = nl_layout(c, n_proj, (char*)dev_store);
-  if (store_bytes < L.bytes) return tdfe_fail(c, TDFE_ENOMEM, "set_projectors: store of %zu bytes, %zu needed",
-                                              store_bytes, L.bytes);
-  c->n_proj = 0;  // the term is off until its tables are complete
-  const int64_t nq = c->n_quad;
+  if (n_proj > 0 && store_bytes < L.bytes)
+    return tdfe_fail(c, TDFE_ENOMEM, "set_projectors: store of %zu bytes, %zu needed", store_bytes, L.bytes);
+  // the term is off until its tables are complete
+  c->n_proj = 0;
+  c->nl_store = nullptr;
+  c->nl_blocks = 0;
+  c->nl_groups = 0;
+  c->nl_packed = 0;
+  c->nl_box_dofs = 0;
+  c->nl_lines = c->nl_add_lpb = c->nl_add_blocks = 0;
+  c->nl_line_dofs = 0;
+  if (n_proj == 0) return TDFE_OK;
+  const int64_t nq = c->n_quad, nd = c->n_dof;
+  const int nxi = c->Nx - 2, nyi = c->Ny - 2, nzi = c->Nz - 2;
+  const unsigned gd = (unsigned)((nd + 255) / 256);
   int* bad = (int*)c->counters + 210;
   TDFE_TRY(tdfe_zero(c, bad, sizeof(int)));
+
+  // pass 1: D_p, the largest entry and the box of each projector
   for (int p = 0; p < n_proj; ++p) {
     const double* u = dev_u + (size_t)p * nq;
-    const double* dv = dev_dv + (size_t)p * nq;
-    hipLaunchKernelGGL(nl_chi_kernel, dim3((unsigned)((nq + 255) / 256)), dim3(256), 0, c->stream, u, dv, L.scratch,
-                       nq);
-    TDFE_HIP(c, hipGetLastError());
-    // c_p on every node (Gauss rule, weights varpi detJ), then Cbar on the DoFs
-    TDFE_TRY(tdfe_load_vector(c, L.scratch, true));
-    hipLaunchKernelGGL(nl_extract_kernel, dim3((unsigned)((c->n_dof + 255) / 256)), dim3(256), 0, c->stream,
-                       (const double*)c->cload, (const double*)c->minv, L.cbar + (size_t)p * c->n_dof,
-                       c->precision == TDFE_FP64 ? nullptr : L.cbar32 + (size_t)p * c->n_dof, c->Nx, c->Ny,
-                       c->n_dof);
-    TDFE_HIP(c, hipGetLastError());
-    hipLaunchKernelGGL(nl_norm_partial_kernel, dim3(NL_BLOCKS), dim3(NL_THREADS), 0, c->stream,
-                       (const double*)c->wdet, (const double*)L.scratch, u, nq, L.red);
-    hipLaunchKernelGGL(nl_norm_final_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)L.red, NL_BLOCKS,
-                       L.E + p, bad);
+    TDFE_TRY(nl_dense_column(c, u, dev_dv + (size_t)p * nq, L));
+    hipLaunchKernelGGL(nl_norm_partial_kernel, dim3(NL_SETUP_BLOCKS), dim3(NL_THREADS), 0, c->stream,
+                       (const double*)c->wdet, (const double*)L.chi, u, nq, L.red);
+    hipLaunchKernelGGL(nl_norm_final_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)L.red,
+                       NL_SETUP_BLOCKS, L.E + p, bad);
+    hipLaunchKernelGGL(nl_absmax_partial_kernel, dim3(NL_SETUP_BLOCKS), dim3(NL_THREADS), 0, c->stream,
+                       (const double*)L.dense, nd, L.red);
+    hipLaunchKernelGGL(nl_absmax_final_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)L.red,
+                       NL_SETUP_BLOCKS, L.amax + p, L.box + 6 * p, nxi, nyi, nzi);
+    hipLaunchKernelGGL(nl_box_kernel, dim3(gd), dim3(256), 0, c->stream, (const double*)L.dense, nd, nxi, nyi,
+                       (const double*)(L.amax + p), L.box + 6 * p);
     TDFE_HIP(c, hipGetLastError());
   }
-  const void* hb = nullptr;
-  TDFE_TRY(tdfe_readback(c, bad, sizeof(int), 3072, &hb));
+  std::vector<int> box((size_t)6 * n_proj);
+  int hbad = 0;
+  TDFE_HIP(c, hipMemcpyAsync(box.data(), L.box, box.size() * sizeof(int), hipMemcpyDeviceToHost, c->stream));
+  TDFE_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
-  if (*(const volatile int*)hb)
-    return tdfe_fail(c, TDFE_EINVAL, "set_projectors: int u dV u is zero or not finite for a projector");
+  if (hbad) return tdfe_fail(c, TDFE_EINVAL, "set_projectors: int u dV u is zero or not finite for a projector");
+
+  // groups: consecutive projectors whose union box is at most 25% larger than the larger of the two
+  std::vector<NlGroup> groups;
+  std::vector<int> pgrp(n_proj);
+  int gb[6] = {0, 0, 0, -1, -1, -1};
+  for (int p = 0; p < n_proj; ++p) {
+    const int* b = &box[(size_t)6 * p];
+    bool join = false;
+    int ub[6];
+    if (!groups.empty() && groups.back().np < NL_PCH) {
+      const int64_t vg = box_vol(gb), vb = box_vol(b);
+      if (vb == 0) {
+        join = true;
+        std::copy(gb, gb + 6, ub);
+      } else if (vg > 0) {
+        for (int a = 0; a < 3; ++a) {
+          ub[a] = std::min(gb[a], b[a]);
+          ub[a + 3] = std::max(gb[a + 3], b[a + 3]);
+        }
+        join = 4 * box_vol(ub) <= 5 * std::max(vg, vb);
+      }
+    }
+    if (join) {
+      std::copy(ub, ub + 6, gb);
+      groups.back().np += 1;
+    } else {
+      NlGroup g{};
+      g.p0 = p;
+      g.np = 1;
+      groups.push_back(g);
+      std::copy(b, b + 6, gb);
+    }
+    NlGroup& g = groups.back();
+    if (box_vol(gb) > 0) {
+      g.I0 = gb[0];
+      g.J0 = gb[1];
+      g.K0 = gb[2];
+      g.nx = gb[3] - gb[0] + 1;
+      g.ny = gb[4] - gb[1] + 1;
+      g.nz = gb[5] - gb[2] + 1;
+    } else {
+      g.I0 = g.J0 = g.K0 = 0;
+      g.nx = g.ny = g.nz = 0;
+    }
+    pgrp[p] = (int)groups.size() - 1;
+  }
+  // packed offsets and the block partition of the hot passes
+  int64_t total = 0, off = 0;
+  for (const NlGroup& g : groups) total += (int64_t)g.nx * g.ny * g.nz;
+  const int64_t epb = std::max<int64_t>(256, (total + NL_TARGET_BLOCKS - 1) / NL_TARGET_BLOCKS);
+  std::vector<int> blk2grp;
+  for (size_t gi = 0; gi < groups.size(); ++gi) {
+    NlGroup& g = groups[gi];
+    g.off = off;
+    off += (int64_t)g.np * g.nx * g.ny * g.nz;
+    g.b0 = (int)blk2grp.size();
+    if (g.nx > 0) {
+      g.lpb = (int)std::max<int64_t>(1, (epb + g.nx - 1) / g.nx);
+      g.nb = (g.ny * g.nz + g.lpb - 1) / g.lpb;
+    } else {
+      g.lpb = 1;
+      g.nb = 0;
+    }
+    blk2grp.insert(blk2grp.end(), (size_t)g.nb, (int)gi);
+  }
+  if ((int64_t)blk2grp.size() > nl_max_blocks(n_proj) || off > (int64_t)n_proj * nd)
+    return tdfe_fail(c, TDFE_EINVAL, "set_projectors: internal partition error");
+
+  // pass 2: pack each projector's Cbar into its group box
+  for (const NlGroup& g : groups) {
+    const int64_t vol = (int64_t)g.nx * g.ny * g.nz;
+    if (vol == 0) continue;
+    for (int q = 0; q < g.np; ++q) {
+      const int p = g.p0 + q;
+      TDFE_TRY(nl_dense_column(c, dev_u + (size_t)p * nq, dev_dv + (size_t)p * nq, L));
+      const int64_t o = g.off + q * vol;
+      hipLaunchKernelGGL(nl_pack_kernel, dim3((unsigned)((vol + 255) / 256)), dim3(256), 0, c->stream,
+                         (const double*)L.dense, g, nxi, nyi, L.cbar + o,
+                         c->precision == TDFE_FP64 ? (float*)nullptr : L.cbar32 + o);
+      TDFE_HIP(c, hipGetLastError());
+    }
+  }
+  // lines of the add pass: every (J, K) crossed by a group box, with its groups in order
+  std::vector<NlLine> lines;
+  std::vector<int> gids;
+  int64_t line_elems = 0;
+  {
+    int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
+    for (const NlGroup& g : groups) {
+      if (g.nx == 0) continue;
+      lo[1] = std::min(lo[1], g.J0);
+      lo[2] = std::min(lo[2], g.K0);
+      hi[1] = std::max(hi[1], g.J0 + g.ny - 1);
+      hi[2] = std::max(hi[2], g.K0 + g.nz - 1);
+    }
+    for (int K = lo[2]; K <= hi[2]; ++K)
+      for (int J = lo[1]; J <= hi[1]; ++J) {
+        NlLine ln{J, K, INT_MAX, -1, (int)gids.size(), 0};
+        for (size_t gi = 0; gi < groups.size(); ++gi) {
+          const NlGroup& g = groups[gi];
+          if (g.nx == 0 || J < g.J0 || J >= g.J0 + g.ny || K < g.K0 || K >= g.K0 + g.nz) continue;
+          gids.push_back((int)gi);
+          ln.gn += 1;
+          ln.I_lo = std::min(ln.I_lo, g.I0);
+          ln.I_hi = std::max(ln.I_hi, g.I0 + g.nx - 1);
+        }
+        if (ln.gn > 0) {
+          lines.push_back(ln);
+          line_elems += ln.I_hi - ln.I_lo + 1;
+        }
+      }
+  }
+  if ((int64_t)lines.size() > (int64_t)nyi * nzi || (int64_t)gids.size() > (int64_t)nyi * nzi * n_proj)
+    return tdfe_fail(c, TDFE_EINVAL, "set_projectors: internal line table error");
+  int add_lpb = 1, add_blocks = 0;
+  if (!lines.empty()) {
+    const int64_t epb = std::max<int64_t>(128, (line_elems + 4 * NL_TARGET_BLOCKS - 1) / (4 * NL_TARGET_BLOCKS));
+    const int64_t avg = std::max<int64_t>(1, line_elems / (int64_t)lines.size());
+    add_lpb = (int)std::max<int64_t>(1, epb / avg);
+    add_blocks = (int)((lines.size() + add_lpb - 1) / add_lpb);
+    TDFE_HIP(c, hipMemcpyAsync(L.lines, lines.data(), lines.size() * sizeof(NlLine), hipMemcpyHostToDevice,
+                               c->stream));
+    TDFE_HIP(c, hipMemcpyAsync(L.gids, gids.data(), gids.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  }
+  TDFE_HIP(c, hipMemcpyAsync(L.groups, groups.data(), groups.size() * sizeof(NlGroup), hipMemcpyHostToDevice,
+                             c->stream));
+  TDFE_HIP(c, hipMemcpyAsync(L.pgrp, pgrp.data(), pgrp.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
+  if (!blk2grp.empty())
+    TDFE_HIP(c, hipMemcpyAsync(L.blk2grp, blk2grp.data(), blk2grp.size() * sizeof(int), hipMemcpyHostToDevice,
+                               c->stream));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
   c->nl_store = dev_store;
+  c->nl_blocks = (int)blk2grp.size();
+  c->nl_groups = (int)groups.size();
+  c->nl_packed = off;
+  c->nl_box_dofs = total;
+  c->nl_lines = (int)lines.size();
+  c->nl_line_dofs = line_elems;
+  c->nl_add_lpb = add_lpb;
+  c->nl_add_blocks = add_blocks;
+  c->nl_np_max = 1;
+  for (const NlGroup& g : groups) c->nl_np_max = std::max(c->nl_np_max, g.np);
   c->n_proj = n_proj;
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_projector_info(const tdfe_ctx* c, int* n_groups, int64_t* stored, int64_t* box_dofs,
+                                int64_t* line_dofs) {
+  if (!c || !n_groups || !stored || !box_dofs || !line_dofs) return TDFE_EINVAL;
+  *n_groups = c->nl_groups;
+  *stored = c->nl_packed;
+  *box_dofs = c->nl_box_dofs;
+  *line_dofs = c->nl_line_dofs;
   return TDFE_OK;
 }
 

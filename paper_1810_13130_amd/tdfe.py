@@ -66,6 +66,7 @@ SIGNATURES = {
     "tdfe_set_scf": [_P, ctypes.POINTER(ScfDesc)],
     "tdfe_projector_query": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_set_projectors": [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t],
+    "tdfe_projector_info": [_P, _IP, _I64P, _I64P, _I64P],
     "tdfe_apply_H": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add_f32": [_P, _P, _P, ctypes.c_int],
@@ -236,6 +237,13 @@ class Context:
         self._check(self.lib.tdfe_set_projectors(self.h, n_proj, _ptr(u), _ptr(dv),
                                                  ctypes.c_void_p(base + off), nbytes))
         self._nl_store = store
+
+    def projector_info(self):
+        """(groups, stored entries of Cbar, DoFs in the boxes, DoFs on the crossed lines)."""
+        g, st, bd, ld = ctypes.c_int(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tdfe_projector_info(self.h, ctypes.byref(g), ctypes.byref(st), ctypes.byref(bd),
+                                                 ctypes.byref(ld)))
+        return g.value, st.value, bd.value, ld.value
 
     @staticmethod
     def _orb(psi):

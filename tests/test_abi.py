@@ -107,6 +107,10 @@ def test_query_sizes_and_call_order(lib):
     assert lib.tdfe_projector_query(h, 1025, ctypes.byref(pb)) == tdfe.EINVAL
     assert lib.tdfe_projector_query(h, 4, None) == tdfe.EINVAL
     assert lib.tdfe_set_projectors(h, 4, buf, buf, buf, 1 << 30) == tdfe.ESTATE
+    ng, st, bd, ld = ctypes.c_int(7), ctypes.c_int64(7), ctypes.c_int64(7), ctypes.c_int64(7)
+    assert lib.tdfe_projector_info(h, ctypes.byref(ng), ctypes.byref(st), ctypes.byref(bd), ctypes.byref(ld)) == 0
+    assert (ng.value, st.value, bd.value, ld.value) == (0, 0, 0, 0)
+    assert lib.tdfe_projector_info(h, ctypes.byref(ng), ctypes.byref(st), ctypes.byref(bd), None) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, None, 0) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, ctypes.c_void_p(4096 + 8), ws.value) == tdfe.EINVAL
     assert lib.tdfe_bind_workspace(h, ctypes.c_void_p(4096), ws.value - 1) == tdfe.ENOMEM

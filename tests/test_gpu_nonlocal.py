@@ -79,6 +79,10 @@ def test_apply_H_with_projectors_full_size_benchmark_workload():
     x = W.random_block(m.n_dof, cfg.n_orb, 7)
     y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
     assert rel(y, _ref_apply(m, vq, CE, x)) < 1e-12
+    # compact layout: the s and p channels of each atom share one box
+    groups, stored, box_dofs, line_dofs = ctx.projector_info()
+    assert groups == len(W.atoms(cfg)[0])
+    assert 0 < stored <= CE[0].shape[0] * m.n_dof and 0 < line_dofs <= m.n_dof and box_dofs > 0
 
 
 def test_removing_projectors_restores_local_operator():
