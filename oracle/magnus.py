@@ -12,7 +12,8 @@ Readings (the paper defers the details to another reference):
   from the integer instants: W(t_{n-1} + dt/4) ~ 1.25 W_{n-1} - 0.25 W_{n-2};
   the first step uses W_{-1} := W_0;
 * the external and field potentials are evaluated exactly; a field of
-  amplitude E_n along z is V_field = -E_n z (Eq. VField) held over step n;
+  amplitude E_n along z is V_field = -E_n z (Eq. VField) held over step n
+  (along a direction d: -E_n (d . r));
 * the corrector restarts from psibar^{n-1} with the full dt;
 * a density-independent H takes one exp(-i dt Hbar) per step;
 * a nonlocal Kleinman-Bylander term (Eq. VPSP), when given, is part of Hbar
@@ -81,9 +82,13 @@ class State:
         self.ks = []
 
 
-def magnus_step(system, state, dt, E=0.0):
-    """Advance ``state`` by one step; returns a report dict."""
-    vfield = -E * system.zq
+def magnus_step(system, state, dt, E=0.0, direction=None):
+    """Advance ``state`` by one step; returns a report dict.  The field
+    potential is -E z, or -E (d . r) for a field direction d."""
+    if direction is None:
+        vfield = -E * system.zq
+    else:
+        vfield = -E * (system.mesh.quad_xyz @ np.asarray(direction, dtype=np.float64))
     psi0 = state.psibar
     rep = {}
     if system.scf:
