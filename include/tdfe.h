@@ -216,8 +216,9 @@ typedef struct {
  *   psibar^{n-1/2} = exp(-i dt/2 Hbar(V_P)) psibar^{n-1}
  *   V_C = V_ext + V_field + W[rho(psibar^{n-1/2})]
  *   psibar^n = exp(-i dt Hbar(V_C)) psibar^{n-1},   W_n = W[rho(psibar^n)]
- * with W = V_H + V_xc and V_field = -field_E z (Eq. VField), held over the
- * step.  Without SCF terms the step is one exp(-i dt Hbar) psibar.  The first
+ * with W = V_H + V_xc and V_field = -field_E (d . r) (Eq. VField), held over
+ * the step; d is the field direction (tdfe_set_field_direction, z unless
+ * set).  Without SCF terms the step is one exp(-i dt Hbar) psibar.  The first
  * call after set_scf computes W_0 from psibar (and W_{-1} := W_0).
  * psibar is updated in place; rep may be NULL.  The call synchronises its
  * stream once, at the end, to collect the Lanczos convergence status (and the
@@ -225,6 +226,53 @@ typedef struct {
  * table overflow) is returned after psibar has been written. */
 tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double dt, double field_E,
                              double tol, tdfe_step_report* rep);
+
+/* Excitations and observables (Sec. on the numerical studies and its table
+ * of simulation parameters; Eq. VField).
+ *
+ * set_field_direction: d (HOST double[3], finite, not zero) of the field
+ * potential V_field = -E_n (d . r) used by later magnus_step and
+ * dipole_gradient calls and by tdfe_kick; used as given (a unit vector makes
+ * E_n the field strength).  Default (0, 0, 1).
+ *
+ * kick: psibar <- exp(-i kappa d . r) psibar at the DoF nodes for n_orb
+ * orbitals: the delta kick that excites a linear-response run.  It is the
+ * impulse of the field E(t) = -kappa delta(t) in V_field.
+ *
+ * field_samples (host only, no context): out[i] = E(t[i]) for
+ *   TDFE_FIELD_GAUSSIAN  params {kappa, t0, w}:  kappa exp(-(t - t0)^2 / w^2)
+ *   TDFE_FIELD_SIN2      params {kappa, omega, T}: kappa sin^2(pi t / T) sin(omega t)
+ *                        on [0, T], 0 outside.
+ * A Magnus step from t_{n-1} holds the field at the step's midpoint,
+ * E_n = E(t_{n-1} + dt / 2).  EINVAL for an unknown shape, non-finite
+ * parameters, w <= 0 or T <= 0.
+ *
+ * absorption_spectrum: S(w_k) = (2 w_k / 3 pi) sum_a Im[mu~_a(w_k) / E~_a(w_k)]
+ * for dev_omega[k], k < n_omega, written to dev_S[k].  dev_mu is [3][n_t]
+ * FP64 device: row a holds the a-component of the dipole, sampled at
+ * t_n = n dt (t_0 = 0 the excitation), of the run excited along axis a.
+ *   mu~_a(w) = sum_n c_n e^{i w t_n} e^{-alpha t_n^2} (mu_a(t_n) - mu_a(0)) dt,
+ *   E~_a(w)  = sum_n c_n e^{i w t_n} E_a(t_n) dt          (dev_field [3][n_t]),
+ *            = -kappa                                      (dev_field NULL: kick),
+ * c_n the trapezoid weights (1/2 at both ends).  alpha >= 0 is the Gaussian
+ * window.  Enqueued on hip_stream; no context; EINVAL for n_t < 2, dt <= 0,
+ * alpha < 0, a zero kick without field samples, null pointers.
+ *
+ * power_spectrum: P(w_k) = Im sum_{n=1}^{n_t-2} c_n e^{-i w_k t_n} mu''_n dt with
+ * mu''_n = (mu_{n+1} - 2 mu_n + mu_{n-1}) / dt^2 and trapezoid weights over
+ * n = 1 .. n_t - 2: the dipole power spectrum of a strong-field run from one
+ * dipole component sampled at t_n = n dt (dev_mu [n_t]).  EINVAL for
+ * n_t < 3, dt <= 0, null pointers. */
+#define TDFE_FIELD_GAUSSIAN 1
+#define TDFE_FIELD_SIN2 2
+tdfe_status tdfe_set_field_direction(tdfe_ctx* ctx, const double* dir);
+tdfe_status tdfe_kick(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double kappa);
+tdfe_status tdfe_field_samples(int shape, const double* params, int n, const double* t, double* out);
+tdfe_status tdfe_absorption_spectrum(const double* dev_mu, const double* dev_field, int n_t, double dt, double kappa,
+                                     double alpha, const double* dev_omega, int n_omega, double* dev_S,
+                                     void* hip_stream);
+tdfe_status tdfe_power_spectrum(const double* dev_mu, int n_t, double dt, const double* dev_omega, int n_omega,
+                                double* dev_P, void* hip_stream);
 
 /* gradient_query: device workspace bytes that tdfe_dipole_gradient needs for
  * n_orb orbitals, n_steps steps, a state checkpoint every checkpoint_every
@@ -236,8 +284,9 @@ tdfe_status tdfe_gradient_query(tdfe_ctx* ctx, int n_orb, int n_steps, int check
                                 size_t* bytes);
 
 /* dipole_gradient: L = mu_z(psibar^N) after n_steps magnus_step steps from
- * dev_psibar0 with the field amplitudes host_E[n_steps] (V_field = -E_n z on
- * step n, Eq. VField; Magnus step as in tdfe_magnus_step, Eqs. ApproxMagnus,
+ * dev_psibar0 with the field amplitudes host_E[n_steps] (V_field = -E_n (d . r)
+ * on step n with d the field direction, z unless set; Eq. VField; Magnus step
+ * as in tdfe_magnus_step, Eqs. ApproxMagnus,
  * PsiTimeDiscrete), and host_grad[n] = dL/dE_n of that discrete scheme
  * (reverse mode: exact adjoints of the density, Hartree, exchange and
  * extrapolation steps; the exponential's Frechet derivative is taken in the

@@ -2,7 +2,8 @@
 // amplitudes E_n of the predictor-corrector Magnus scheme (reverse mode).
 //
 // The forward map is the step of the Magnus ABI with V_field = -E_n z on
-// step n (Eq. VField), the second-order Magnus propagator (Eq. Magnus2) and
+// step n (Eq. VField; -E_n (d . r) for a field direction d other than z, and
+// then z below reads d . r), the second-order Magnus propagator (Eq. Magnus2) and
 // the predictor-corrector midpoint potential (Sec. on the midpoint
 // Hamiltonian):
 //   V_P = V_ext - E_n z + 1.25 W_n - 0.25 W_{n-1}       (W_{-1} := W_0)
@@ -229,13 +230,13 @@ __global__ void add_kernel(const double* a, const double* b, double* out, int64_
   out[i] = a[i] + b[i];
 }
 
-// partial[b] = sum over this block's grid-stride range of (v1 + v2) z
+// partial[b] = sum over this block's grid-stride range of (v1 + v2) (d . r), d the field direction
 __global__ void __launch_bounds__(EW) zdot_kernel(const double* v1, const double* v2, const double* xq, int64_t n,
-                                                  double* partial) {
+                                                  double dx, double dy, double dz, double* partial) {
   __shared__ double sred[EW];
   double acc = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < n; i += (int64_t)gridDim.x * EW)
-    acc += ((v1 ? v1[i] : 0.0) + (v2 ? v2[i] : 0.0)) * xq[i * 3 + 2];
+    acc += ((v1 ? v1[i] : 0.0) + (v2 ? v2[i] : 0.0)) * (dx * xq[i * 3] + dy * xq[i * 3 + 1] + dz * xq[i * 3 + 2]);
   sred[threadIdx.x] = acc;
   __syncthreads();
   for (int s = EW / 2; s > 0; s >>= 1) {
@@ -550,7 +551,8 @@ struct Grad {
 
   tdfe_status field_grad(int n, const double* v1, const double* v2) {
     double* part = (double*)(base + g.o_part);
-    hipLaunchKernelGGL(zdot_kernel, dim3(RED_BLOCKS), dim3(EW), 0, c->stream, v1, v2, c->xq, c->n_quad, part);
+    hipLaunchKernelGGL(zdot_kernel, dim3(RED_BLOCKS), dim3(EW), 0, c->stream, v1, v2, c->xq, c->n_quad,
+                       c->fdir[0], c->fdir[1], c->fdir[2], part);
     hipLaunchKernelGGL(neg_sum_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, RED_BLOCKS,
                        (double*)(base + g.o_de) + n);
     TDFE_HIP(c, hipGetLastError());

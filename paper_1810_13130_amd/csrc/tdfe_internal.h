@@ -97,6 +97,7 @@ struct tdfe_ctx {
   double pcg_tol = 1e-13;
   int pcg_maxit = 5000;
   int last_poisson_iters = 0;
+  double fdir[3] = {0.0, 0.0, 1.0};  // field direction d: V_field = -E_n (d . r)
   // Kleinman-Bylander term: caller-owned store of the projector tables, off when n_proj == 0
   int n_proj = 0;
   void* nl_store = nullptr;

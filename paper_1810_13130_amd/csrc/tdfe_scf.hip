@@ -329,11 +329,13 @@ __global__ void __launch_bounds__(N* N) interp_xc_kernel(const double* phi, cons
 }
 
 // vw = wdet * (vext - E z + ca * A + cb * B)   (A, B may be null)
+// (Ex, Ey, Ez) = E_n times the field direction: V_field = -E_n (d . r) (Eq. VField)
 __global__ void assemble_vw_kernel(const double* vext, const double* xq, const double* wdet, const double* A, double ca,
-                                   const double* Bv, double cb, double E, double* vw, float* vw32, int64_t n) {
+                                   const double* Bv, double cb, double Ex, double Ey, double Ez, double* vw,
+                                   float* vw32, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  double v = vext[i] - E * xq[i * 3 + 2];
+  double v = vext[i] - (Ex * xq[i * 3] + Ey * xq[i * 3 + 1] + Ez * xq[i * 3 + 2]);
   if (A) v += ca * A[i];
   if (Bv) v += cb * Bv[i];
   const double x = wdet[i] * v;
@@ -1312,7 +1314,7 @@ tdfe_status tdfe_assemble_vw(tdfe_ctx* c, const double* A, double ca, const doub
   const int64_t nqd = c->n_quad;
   float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
   hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet, A, ca, B, cb,
-                     E, c->vw, v32, nqd);
+                     E * c->fdir[0], E * c->fdir[1], E * c->fdir[2], c->vw, v32, nqd);
   TDFE_HIP(c, hipGetLastError());
   return TDFE_OK;
 }
@@ -1421,7 +1423,8 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
   };
   if (!c->have_scf) {
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, field_E, c->vw, v32, nqd);
+                       (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, field_E * c->fdir[0],
+                       field_E * c->fdir[1], field_E * c->fdir[2], c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
     s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
     if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
@@ -1440,14 +1443,16 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
     }
     // predictor: W(t + dt/4) ~ 1.25 W_{n-1} - 0.25 W_{n-2}
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
-                       (const double*)c->w1, 1.25, (const double*)c->w2, -0.25, field_E, c->vw, v32, nqd);
+                       (const double*)c->w1, 1.25, (const double*)c->w2, -0.25, field_E * c->fdir[0],
+                       field_E * c->fdir[1], field_E * c->fdir[2], c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
     st = lanczos(dev_psibar, c->half, 0.5 * dt, 0, &r.k_pred_max, &r.k_pred_sum, &eh);
     if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
     TDFE_TRY(tdfe_scf_potential_async(c, c->half, n_orb, c->wh, nullptr));
     // corrector with the midpoint potential
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
-                       (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, field_E, c->vw, v32, nqd);
+                       (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, field_E * c->fdir[0],
+                       field_E * c->fdir[1], field_E * c->fdir[2], c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
     s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
     if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;

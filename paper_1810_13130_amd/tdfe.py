@@ -67,6 +67,12 @@ SIGNATURES = {
     "tdfe_projector_query": [_P, ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_set_projectors": [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t],
     "tdfe_projector_info": [_P, _IP, _I64P, _I64P, _I64P],
+    "tdfe_set_field_direction": [_P, _DP],
+    "tdfe_kick": [_P, _P, ctypes.c_int, ctypes.c_double],
+    "tdfe_field_samples": [ctypes.c_int, _DP, ctypes.c_int, _DP, _DP],
+    "tdfe_absorption_spectrum": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
+                                 ctypes.c_int, _P, _P],
+    "tdfe_power_spectrum": [_P, ctypes.c_int, ctypes.c_double, _P, ctypes.c_int, _P, _P],
     "tdfe_apply_H": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add": [_P, _P, _P, ctypes.c_int],
     "tdfe_apply_H_add_f32": [_P, _P, _P, ctypes.c_int],
@@ -245,6 +251,14 @@ class Context:
                                                  ctypes.byref(ld)))
         return g.value, st.value, bd.value, ld.value
 
+    def set_field_direction(self, d):
+        dd = (ctypes.c_double * 3)(*[float(v) for v in d])
+        self._check(self.lib.tdfe_set_field_direction(self.h, dd))
+
+    def kick(self, psibar, kappa):
+        n_orb = self._orb(psibar)
+        self._check(self.lib.tdfe_kick(self.h, _ptr(psibar), n_orb, float(kappa)))
+
     @staticmethod
     def _orb(psi):
         import torch
@@ -359,3 +373,52 @@ def dipole_of_field(E, ctx, psibar0, dt, tol=1e-10, checkpoint_every=None, k_sto
     if _DIPOLE_FN is None:
         _DIPOLE_FN = _dipole_function()
     return _DIPOLE_FN.apply(E, ctx, psibar0, dt, tol, checkpoint_every, k_store)
+
+
+FIELD_GAUSSIAN = 1
+FIELD_SIN2 = 2
+
+
+def field_samples(shape, params, t):
+    """E(t) for TDFE_FIELD_GAUSSIAN {kappa, t0, w} or TDFE_FIELD_SIN2 {kappa, omega, T}."""
+    lib = load()
+    p = np.ascontiguousarray(np.asarray(params, dtype=np.float64))
+    tt = np.ascontiguousarray(np.asarray(t, dtype=np.float64).reshape(-1))
+    out = np.empty_like(tt)
+    s = lib.tdfe_field_samples(int(shape), p.ctypes.data_as(_DP), tt.size, tt.ctypes.data_as(_DP),
+                               out.ctypes.data_as(_DP))
+    if s != OK:
+        raise TdfeError(s, "field_samples: bad shape or parameters")
+    return out
+
+
+def absorption_spectrum(mu, dt, omega, alpha, kappa=None, field=None):
+    """S(w) on the device: mu [3][n_t] (row a: a-component of the run excited
+    along a), omega [n_w], field [3][n_t] or a kick strength kappa."""
+    import torch
+    lib = load()
+    assert mu.dtype == torch.float64 and mu.is_cuda and mu.is_contiguous() and mu.shape[0] == 3
+    assert omega.dtype == torch.float64 and omega.is_cuda and omega.is_contiguous()
+    if field is not None:
+        assert field.dtype == torch.float64 and field.is_cuda and field.is_contiguous() and field.shape == mu.shape
+    out = torch.empty_like(omega)
+    s = lib.tdfe_absorption_spectrum(_ptr(mu), _ptr(field) if field is not None else None, mu.shape[1], float(dt),
+                                     float(kappa) if kappa is not None else 0.0, float(alpha), _ptr(omega),
+                                     omega.numel(), _ptr(out), _stream_handle())
+    if s != OK:
+        raise TdfeError(s, "absorption_spectrum: bad arguments")
+    return out
+
+
+def power_spectrum(mu, dt, omega):
+    """P(w) on the device from one dipole component mu [n_t]."""
+    import torch
+    lib = load()
+    assert mu.dtype == torch.float64 and mu.is_cuda and mu.is_contiguous() and mu.dim() == 1
+    assert omega.dtype == torch.float64 and omega.is_cuda and omega.is_contiguous()
+    out = torch.empty_like(omega)
+    s = lib.tdfe_power_spectrum(_ptr(mu), mu.numel(), float(dt), _ptr(omega), omega.numel(), _ptr(out),
+                                _stream_handle())
+    if s != OK:
+        raise TdfeError(s, "power_spectrum: bad arguments")
+    return out

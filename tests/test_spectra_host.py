@@ -1,0 +1,77 @@
+"""Host logic of the excitation and spectrum entry points (no GPU needed):
+the field shapes against the oracle's, and argument checks that must fail
+before any device work."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from oracle import spectra as sp
+
+
+@pytest.fixture(scope="module")
+def tdfe():
+    from paper_1810_13130_amd import tdfe as T
+    if not os.path.exists(T.LIB_PATH):
+        pytest.skip("libtdfe.so not built")
+    T.load()
+    return T
+
+
+def test_field_shapes_match_oracle(tdfe):
+    t = np.linspace(-2.0, 1100.0, 20001)
+    g = tdfe.field_samples(tdfe.FIELD_GAUSSIAN, (2e-5, 3.0, 0.2), t)
+    assert np.abs(g - sp.field_gaussian(t, 2e-5, 3.0, 0.2)).max() <= 1e-15 * 2e-5
+    om = 0.03
+    T = 5 * 2 * np.pi / om
+    l = tdfe.field_samples(tdfe.FIELD_SIN2, (0.01, om, T), t)
+    assert np.abs(l - sp.field_sin2(t, 0.01, om, T)).max() <= 1e-15 * 0.01
+    assert l[t > T].tolist() == [0.0] * int(np.sum(t > T)) and l[t < 0].tolist() == [0.0] * int(np.sum(t < 0))
+
+
+def test_field_shape_errors(tdfe):
+    with pytest.raises(tdfe.TdfeError):
+        tdfe.field_samples(7, (1.0, 0.0, 1.0), [0.0])
+    with pytest.raises(tdfe.TdfeError):
+        tdfe.field_samples(tdfe.FIELD_GAUSSIAN, (1.0, 0.0, 0.0), [0.0])
+    with pytest.raises(tdfe.TdfeError):
+        tdfe.field_samples(tdfe.FIELD_SIN2, (1.0, np.nan, 1.0), [0.0])
+
+
+def test_spectrum_argument_checks(tdfe):
+    lib = tdfe.load()
+    p = ctypes.c_void_p(4096)  # never dereferenced: the calls must fail on the host
+    E = tdfe.EINVAL
+    assert lib.tdfe_absorption_spectrum(p, None, 1, 0.1, 1e-3, 0.0, p, 4, p, None) == E  # n_t < 2
+    assert lib.tdfe_absorption_spectrum(p, None, 10, 0.0, 1e-3, 0.0, p, 4, p, None) == E  # dt
+    assert lib.tdfe_absorption_spectrum(p, None, 10, 0.1, 1e-3, -1.0, p, 4, p, None) == E  # alpha
+    assert lib.tdfe_absorption_spectrum(p, None, 10, 0.1, 0.0, 0.0, p, 4, p, None) == E  # zero kick
+    assert lib.tdfe_absorption_spectrum(None, None, 10, 0.1, 1e-3, 0.0, p, 4, p, None) == E
+    assert lib.tdfe_absorption_spectrum(p, None, 10, 0.1, 1e-3, 0.0, p, 0, p, None) == tdfe.OK  # nothing to do
+    assert lib.tdfe_power_spectrum(p, 2, 0.1, p, 4, p, None) == E
+    assert lib.tdfe_power_spectrum(p, 10, -0.1, p, 4, p, None) == E
+    assert lib.tdfe_power_spectrum(p, 10, 0.1, None, 4, p, None) == E
+
+
+def test_field_direction_and_kick_checks(tdfe):
+    import workloads as W
+    lib = tdfe.load()
+    d = tdfe.MeshDesc()
+    d.p, d.nq = 2, 3
+    d.ncell[0], d.ncell[1], d.ncell[2] = 2, 2, 2
+    v = np.ascontiguousarray(W.box_vertices(-1.0, 1.0, (2, 2, 2)).reshape(-1))
+    d.vertices = v.ctypes.data_as(tdfe._DP)
+    d.n_orb_max, d.k_max, d.precision = 1, 8, 0
+    h = ctypes.c_void_p()
+    assert lib.tdfe_fe_mesh_setup(ctypes.byref(d), None, ctypes.byref(h)) == 0
+    zero = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    bad = (ctypes.c_double * 3)(1.0, float("inf"), 0.0)
+    ok = (ctypes.c_double * 3)(1.0, 0.0, 0.0)
+    assert lib.tdfe_set_field_direction(h, zero) == tdfe.EINVAL
+    assert lib.tdfe_set_field_direction(h, bad) == tdfe.EINVAL
+    assert lib.tdfe_set_field_direction(h, ok) == tdfe.OK
+    assert lib.tdfe_kick(h, ctypes.c_void_p(4096), 1, 1e-3) == tdfe.ESTATE
+    assert lib.tdfe_kick(h, ctypes.c_void_p(4096), 2, 1e-3) == tdfe.EINVAL
+    assert lib.tdfe_kick(h, ctypes.c_void_p(4096), 1, float("nan")) == tdfe.EINVAL
+    lib.tdfe_destroy(h)
