@@ -17,7 +17,18 @@ Readings (the paper defers the details to another reference):
 * the corrector restarts from psibar^{n-1} with the full dt;
 * a density-independent H takes one exp(-i dt Hbar) per step;
 * a nonlocal Kleinman-Bylander term (Eq. VPSP), when given, is part of Hbar
-  in both exponentials.
+  in both exponentials;
+* higher-order extrapolation (order 2) is the quadratic through the three
+  latest integer instants, W(t_{n-1} + s dt) ~ sum_k l_k(s) W_{n-1-k}; the
+  history before the first step repeats W_0.
+
+The fully self-consistent alternative (same section, steps i-iv) is
+``magnus_step_sc``: (i) extrapolate W to the midpoint t_{n-1} + dt/2 from
+earlier instants; (ii) propagate psibar^{n-1} over dt with it and evaluate
+W_n = W[rho(psibar^n)]; (iii) re-evaluate the midpoint W by interpolating
+between W_{n-1} and W_n, i.e. (W_{n-1} + W_n)/2; (iv) repeat (ii)-(iii) until
+the midpoint potential changes by at most ``sc_tol`` (largest change over the
+Gauss points, a reading: the paper leaves the convergence test open).
 """
 import numpy as np
 
@@ -79,31 +90,92 @@ class State:
             w0, _ = system.W(self.psibar)
             self.W1 = w0
             self.W2 = w0
+            self.W3 = w0
         self.ks = []
 
 
-def magnus_step(system, state, dt, E=0.0, direction=None):
-    """Advance ``state`` by one step; returns a report dict.  The field
-    potential is -E z, or -E (d . r) for a field direction d."""
+def extrapolation_weights(s, order):
+    """Lagrange weights l_k(s), k = 0..order, for the instants 0, -1, .., -order
+    (in steps from t_{n-1}) evaluated at s."""
+    nodes = [-float(k) for k in range(order + 1)]
+    w = []
+    for k, xk in enumerate(nodes):
+        lk = 1.0
+        for j, xj in enumerate(nodes):
+            if j != k:
+                lk *= (s - xj) / (xk - xj)
+        w.append(lk)
+    return w
+
+
+def _extrapolate(state, s, order):
+    hist = [state.W1, state.W2, state.W3]
+    return sum(wk * hk for wk, hk in zip(extrapolation_weights(s, order), hist))
+
+
+def _field(system, E, direction):
     if direction is None:
-        vfield = -E * system.zq
-    else:
-        vfield = -E * (system.mesh.quad_xyz @ np.asarray(direction, dtype=np.float64))
+        return -E * system.zq
+    return -E * (system.mesh.quad_xyz @ np.asarray(direction, dtype=np.float64))
+
+
+def magnus_step(system, state, dt, E=0.0, direction=None, order=1):
+    """Advance ``state`` by one step; returns a report dict.  The field
+    potential is -E z, or -E (d . r) for a field direction d; ``order`` is
+    the predictor's extrapolation order (1 linear, 2 quadratic)."""
+    vfield = _field(system, E, direction)
     psi0 = state.psibar
     rep = {}
     if system.scf:
-        vP = system.vext + vfield + 1.25 * state.W1 - 0.25 * state.W2
+        vP = system.vext + vfield + _extrapolate(state, 0.25, order)
         half, k1, e1 = system.expm(vP, psi0, 0.5 * dt)
         wh, _ = system.W(half)
         vC = system.vext + vfield + wh
         new, k2, e2 = system.expm(vC, psi0, dt)
         wn, rho = system.W(new)
-        state.W2, state.W1 = state.W1, wn
+        state.W3, state.W2, state.W1 = state.W2, state.W1, wn
         rep.update(k_pred=k1, k_corr=k2, err_pred=e1, err_corr=e2)
     else:
         new, k2, e2 = system.expm(system.vext + vfield, psi0, dt)
         rho = scf.density(system.mesh, new, system.occ)
         rep.update(k_corr=k2, err_corr=e2)
+    state.psibar = new
+    state.n += 1
+    state.t += dt
+    rep["dipole"] = scf.dipole(system.mesh, rho)
+    rep["charge"] = scf.charge(system.mesh, rho)
+    return rep
+
+
+def magnus_step_sc(system, state, dt, E=0.0, direction=None, order=1, sc_tol=1e-10, max_iter=50):
+    """Fully self-consistent midpoint step (steps i-iv above).  The report
+    adds the iteration count and the last change of the midpoint potential;
+    ``converged`` is False when max_iter iterations did not reach sc_tol (the
+    last iterate is kept)."""
+    vfield = _field(system, E, direction)
+    psi0 = state.psibar
+    rep = {"k_corr": [], "err_corr": []}
+    if not system.scf:
+        new, k, e = system.expm(system.vext + vfield, psi0, dt)
+        rho = scf.density(system.mesh, new, system.occ)
+        rep.update(k_corr=[k], err_corr=[e], sc_iters=1, sc_change=0.0, converged=True)
+    else:
+        wmid = _extrapolate(state, 0.5, order)                    # (i)
+        it, change, converged = 0, np.inf, False
+        while it < max_iter:
+            new, k, e = system.expm(system.vext + vfield + wmid, psi0, dt)   # (ii)
+            wn, rho = system.W(new)
+            it += 1
+            rep["k_corr"].append(k)
+            rep["err_corr"].append(e)
+            wmid_next = 0.5 * (state.W1 + wn)                     # (iii)
+            change = float(np.max(np.abs(wmid_next - wmid)))
+            wmid = wmid_next
+            if change <= sc_tol:                                  # (iv)
+                converged = True
+                break
+        state.W3, state.W2, state.W1 = state.W2, state.W1, wn
+        rep.update(sc_iters=it, sc_change=change, converged=converged)
     state.psibar = new
     state.n += 1
     state.t += dt
