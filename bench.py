@@ -252,6 +252,48 @@ def field_and_spectra(n_steps=30, n_t=20000, n_omega=2000):
             "power_sample_freq_per_s": n_t * n_omega / (t_pow * 1e-3)}
 
 
+def midpoint_modes(n_steps=20):
+    """The midpoint Hamiltonian options on the benchmark workload (FP64):
+    predictor-corrector with linear and quadratic predictors and the fully
+    self-consistent iteration (sc_tol 1e-10 Hartree), from the same state;
+    steps/s, propagations per step and the dipole gap to the self-consistent
+    trajectory."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[2]
+    out = {"workload": cfg.name, "steps": n_steps}
+    mus = {}
+    for name, mode, order in (("pc_linear", tdfe.MIDPOINT_PC, 1), ("pc_quadratic", tdfe.MIDPOINT_PC, 2),
+                              ("self_consistent", tdfe.MIDPOINT_SC, 1)):
+        ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=cfg.n_orb, k_max=cfg.k_max)
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
+        Z, R = W.atoms(cfg)
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=cfg.n_orb)
+        ctx.set_midpoint(mode, order=order, sc_tol=1e-10, sc_maxit=50)
+        psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
+                                                ctx.mass_diag().cpu().numpy())).cuda()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        mu, its = [], 0
+        for _ in range(n_steps):
+            rep = ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+            mu.append(rep["mu"])
+            its += rep["sc_iters"] if mode == tdfe.MIDPOINT_SC else 2
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t
+        mus[name] = np.array(mu)
+        out[name] = {"steps_per_s": n_steps / wall, "propagations_per_step": its / n_steps}
+        ctx.close()
+        torch.cuda.empty_cache()
+    ref = mus["self_consistent"]
+    dmu = np.abs(ref - ref[0]).max()
+    for name in ("pc_linear", "pc_quadratic"):
+        out[name]["dipole_gap_to_sc_rel_induced"] = float(np.abs(mus[name] - ref).max() / max(dmu, 1e-300))
+    return out
+
+
 def cpu_oracle_baseline(cfg, ks_total):
     """Bounded sample of the CPU oracle on this host, scaled to steps/s."""
     import threadpoolctl
@@ -308,6 +350,7 @@ def main():
     ap.add_argument("--no-graded", action="store_true")
     ap.add_argument("--no-nonlocal", action="store_true")
     ap.add_argument("--no-spectra", action="store_true")
+    ap.add_argument("--no-midpoint", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -442,6 +485,8 @@ def main():
         out["nonlocal"] = nonlocal_term()
     if not args.no_spectra:
         out["field_and_spectra"] = field_and_spectra()
+    if not args.no_midpoint:
+        out["midpoint"] = midpoint_modes()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_baseline(cfg, int(round(ks_total / args.steps)))
     print(json.dumps(out), flush=True)

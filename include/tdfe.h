@@ -207,11 +207,40 @@ typedef struct {
   int poisson_iters;          /* 0 for the exact box solver */
   double mu[3];               /* dipole of psibar^n */
   double charge;              /* charge of psibar^n */
+  int sc_iters;               /* self-consistent midpoint: propagations over dt (0 in the predictor-corrector mode) */
+  double sc_change;           /* self-consistent midpoint: last max change of the midpoint W */
 } tdfe_step_report;
+
+/* set_midpoint: how magnus_step evaluates Hbar at the step's midpoint (Sec.
+ * "Approximating the second-order Magnus operator").
+ *   TDFE_MIDPOINT_PC (default): the predictor-corrector below, its predictor
+ *     W(t_{n-1} + dt/4) extrapolated from the order + 1 latest instants;
+ *   TDFE_MIDPOINT_SC: the fully self-consistent iteration (steps i-iv):
+ *     (i) W_mid = W(t_{n-1} + dt/2) extrapolated likewise; (ii) psibar^n =
+ *     exp(-i dt Hbar(V_ext + V_field + W_mid)) psibar^{n-1}, W_n =
+ *     W[rho(psibar^n)]; (iii) W_mid <- (W_{n-1} + W_n)/2; (iv) repeat (ii)-(iii)
+ *     until max over the Gauss points of the change of W_mid <= sc_tol
+ *     (Hartree), at most sc_maxit propagations; TDFE_ENOCONV beyond, with
+ *     the last iterate written and kept as W_n.  One host synchronisation
+ *     per iteration.
+ * order: 1 (linear: weights 1.25, -0.25 at dt/4; 1.5, -0.5 at dt/2) or 2
+ * (quadratic through W_{n-1}, W_{n-2}, W_{n-3}); the history before the
+ * first step repeats W_0.  Applies to later magnus_step calls; the field
+ * gradient supports the default only (TDFE_EINVAL otherwise). */
+#define TDFE_MIDPOINT_PC 0
+#define TDFE_MIDPOINT_SC 1
+typedef struct {
+  int mode;      /* TDFE_MIDPOINT_PC or TDFE_MIDPOINT_SC */
+  int order;     /* extrapolation order, 1 or 2 */
+  double sc_tol; /* SC: > 0 */
+  int sc_maxit;  /* SC: >= 1 */
+} tdfe_midpoint_desc;
+tdfe_status tdfe_set_midpoint(tdfe_ctx* ctx, const tdfe_midpoint_desc* m);
 
 /* magnus_step: one second-order Magnus step with the predictor-corrector
  * midpoint Hamiltonian (Eqs. ApproxMagnus, PsiTimeDiscrete; Sec.
- * "Approximating the second-order Magnus operator"):
+ * "Approximating the second-order Magnus operator"; the self-consistent
+ * alternative and the quadratic predictor are chosen by tdfe_set_midpoint):
  *   V_P = V_ext + V_field + 1.25 W_{n-1} - 0.25 W_{n-2}
  *   psibar^{n-1/2} = exp(-i dt/2 Hbar(V_P)) psibar^{n-1}
  *   V_C = V_ext + V_field + W[rho(psibar^{n-1/2})]

@@ -701,6 +701,8 @@ tdfe_status tdfe_dipole_gradient(tdfe_ctx* c, const void* dev_psibar0, int n_orb
   if (c->xc == TDFE_XC_XC)
     return tdfe_fail(c, TDFE_EINVAL, "gradient: the exchange-correlation kernel is available for LDA exchange only");
   if (c->hartree && !c->box) return tdfe_fail(c, TDFE_EINVAL, "gradient: Hartree needs a box mesh");
+  if (c->mid_mode != TDFE_MIDPOINT_PC || c->mid_order != 1)
+    return tdfe_fail(c, TDFE_EINVAL, "gradient: the predictor-corrector midpoint with linear extrapolation only");
   Grad G;
   G.c = c;
   G.g = layout(c, n_orb, n_steps, checkpoint_every, k_store);

@@ -62,6 +62,9 @@ struct tdfe_ctx {
   float* vw32 = nullptr;      // FP32 copy for the mixed path
   double* w1 = nullptr;       // W_{n-1}  (unweighted, [n_cell][nq^3])
   double* w2 = nullptr;       // W_{n-2}
+  double* w3 = nullptr;       // W_{n-3}
+  double* wn = nullptr;       // self-consistent midpoint: W_n of the current iterate
+  double* scbuf = nullptr;    // [512] self-consistent midpoint: block maxima of the change
   double* wh = nullptr;       // W_{n-1/2}
   double* rho = nullptr;      // [n_cell][nq^3]
   double* phi = nullptr;      // [n_nodes] Hartree potential, boundary values included
@@ -98,6 +101,9 @@ struct tdfe_ctx {
   int pcg_maxit = 5000;
   int last_poisson_iters = 0;
   double fdir[3] = {0.0, 0.0, 1.0};  // field direction d: V_field = -E_n (d . r)
+  int mid_mode = TDFE_MIDPOINT_PC, mid_order = 1;  // midpoint Hamiltonian of the Magnus step
+  double sc_tol = 1e-10;
+  int sc_maxit = 50;
   // Kleinman-Bylander term: caller-owned store of the projector tables, off when n_proj == 0
   int n_proj = 0;
   void* nl_store = nullptr;

@@ -331,16 +331,71 @@ __global__ void __launch_bounds__(N* N) interp_xc_kernel(const double* phi, cons
 // vw = wdet * (vext - E z + ca * A + cb * B)   (A, B may be null)
 // (Ex, Ey, Ez) = E_n times the field direction: V_field = -E_n (d . r) (Eq. VField)
 __global__ void assemble_vw_kernel(const double* vext, const double* xq, const double* wdet, const double* A, double ca,
-                                   const double* Bv, double cb, double Ex, double Ey, double Ez, double* vw,
-                                   float* vw32, int64_t n) {
+                                   const double* Bv, double cb, const double* Cv, double cc, double Ex, double Ey,
+                                   double Ez, double* vw, float* vw32, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   double v = vext[i] - (Ex * xq[i * 3] + Ey * xq[i * 3 + 1] + Ez * xq[i * 3 + 2]);
   if (A) v += ca * A[i];
   if (Bv) v += cb * Bv[i];
+  if (Cv) v += cc * Cv[i];
   const double x = wdet[i] * v;
   vw[i] = x;
   if (vw32) vw32[i] = (float)x;
+}
+
+// out = ca A + cb B (+ cc C)
+__global__ void combine3_kernel(const double* A, double ca, const double* B, double cb, const double* C, double cc,
+                                double* out, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  double v = ca * A[i] + cb * B[i];
+  if (C) v += cc * C[i];
+  out[i] = v;
+}
+
+// self-consistent midpoint: wmid <- (w1 + wn)/2; part[block] = largest |change|
+// (a NaN anywhere propagates to the result)
+constexpr int SC_BLOCKS = 256;
+__global__ void __launch_bounds__(EW) midpoint_update_kernel(const double* w1, const double* wn, double* wmid, int64_t n,
+                                                            double* part) {
+  __shared__ double s[EW];
+  double m = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < n; i += (int64_t)gridDim.x * EW) {
+    const double v = 0.5 * (w1[i] + wn[i]);
+    const double d = fabs(v - wmid[i]);
+    wmid[i] = v;
+    if (!(d <= m)) m = d;
+  }
+  s[threadIdx.x] = m;
+  __syncthreads();
+  for (int w = EW / 2; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w && !(s[threadIdx.x + w] <= s[threadIdx.x])) s[threadIdx.x] = s[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = s[0];
+}
+
+__global__ void max_final_kernel(const double* part, int nb, double* out) {
+  if (threadIdx.x != 0) return;
+  double m = 0.0;
+  for (int b = 0; b < nb; ++b)
+    if (!(part[b] <= m)) m = part[b];
+  *out = m;
+}
+
+// Lagrange weights of the instants t_{n-1}, t_{n-2}, t_{n-3} (abscissae 0, -1,
+// -2 in steps) at abscissa s; order 1 uses the first two
+void extrapolation_weights(double s, int order, double l[3]) {
+  if (order <= 1) {
+    l[0] = 1.0 + s;
+    l[1] = -s;
+    l[2] = 0.0;
+    return;
+  }
+  l[0] = (s + 1.0) * (s + 2.0) / 2.0;
+  l[1] = -s * (s + 2.0);
+  l[2] = s * (s + 1.0) / 2.0;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1314,7 +1369,7 @@ tdfe_status tdfe_assemble_vw(tdfe_ctx* c, const double* A, double ca, const doub
   const int64_t nqd = c->n_quad;
   float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
   hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet, A, ca, B, cb,
-                     E * c->fdir[0], E * c->fdir[1], E * c->fdir[2], c->vw, v32, nqd);
+                     (const double*)nullptr, 0.0, E * c->fdir[0], E * c->fdir[1], E * c->fdir[2], c->vw, v32, nqd);
   TDFE_HIP(c, hipGetLastError());
   return TDFE_OK;
 }
@@ -1327,6 +1382,22 @@ tdfe_status tdfe_occ_dev(tdfe_ctx* c, int n_orb, const double** dev) {
 }
 
 extern "C" {
+
+tdfe_status tdfe_set_midpoint(tdfe_ctx* c, const tdfe_midpoint_desc* m) {
+  if (!c || !m) return TDFE_EINVAL;
+  if (m->mode != TDFE_MIDPOINT_PC && m->mode != TDFE_MIDPOINT_SC)
+    return tdfe_fail(c, TDFE_EINVAL, "set_midpoint: unknown mode");
+  if (m->order != 1 && m->order != 2) return tdfe_fail(c, TDFE_EINVAL, "set_midpoint: order must be 1 or 2");
+  if (m->mode == TDFE_MIDPOINT_SC && (!(m->sc_tol > 0.0) || !std::isfinite(m->sc_tol) || m->sc_maxit < 1))
+    return tdfe_fail(c, TDFE_EINVAL, "set_midpoint: sc_tol > 0 and sc_maxit >= 1 required");
+  c->mid_mode = m->mode;
+  c->mid_order = m->order;
+  if (m->mode == TDFE_MIDPOINT_SC) {
+    c->sc_tol = m->sc_tol;
+    c->sc_maxit = m->sc_maxit;
+  }
+  return TDFE_OK;
+}
 
 tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   if (!c || !s) return TDFE_EINVAL;
@@ -1423,7 +1494,8 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
   };
   if (!c->have_scf) {
     hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
-                       (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, field_E * c->fdir[0],
+                       (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0,
+                       field_E * c->fdir[0],
                        field_E * c->fdir[1], field_E * c->fdir[2], c->vw, v32, nqd);
     TDFE_HIP(c, hipGetLastError());
     s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
@@ -1439,33 +1511,98 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
     if (!c->scf_init) {
       TDFE_TRY(tdfe_scf_potential(c, dev_psibar, n_orb, c->w1, nullptr, nullptr));
       TDFE_HIP(c, hipMemcpyAsync(c->w2, c->w1, nqd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+      TDFE_HIP(c, hipMemcpyAsync(c->w3, c->w1, nqd * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
       c->scf_init = true;
     }
-    // predictor: W(t + dt/4) ~ 1.25 W_{n-1} - 0.25 W_{n-2}
-    hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
-                       (const double*)c->w1, 1.25, (const double*)c->w2, -0.25, field_E * c->fdir[0],
-                       field_E * c->fdir[1], field_E * c->fdir[2], c->vw, v32, nqd);
-    TDFE_HIP(c, hipGetLastError());
-    st = lanczos(dev_psibar, c->half, 0.5 * dt, 0, &r.k_pred_max, &r.k_pred_sum, &eh);
-    if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
-    TDFE_TRY(tdfe_scf_potential_async(c, c->half, n_orb, c->wh, nullptr));
-    // corrector with the midpoint potential
-    hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
-                       (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, field_E * c->fdir[0],
-                       field_E * c->fdir[1], field_E * c->fdir[2], c->vw, v32, nqd);
-    TDFE_HIP(c, hipGetLastError());
-    s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
-    if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
-    // history: W_{n-2} <- W_{n-1}, W_{n-1} <- W[rho(psibar^n)]
-    std::swap(c->w1, c->w2);
-    TDFE_TRY(tdfe_scf_potential_async(c, dev_psibar, n_orb, c->w1, rep ? &hred : nullptr));
+    const double Ex = field_E * c->fdir[0], Ey = field_E * c->fdir[1], Ez = field_E * c->fdir[2];
+    double l[3];
+    extrapolation_weights(c->mid_mode == TDFE_MIDPOINT_SC ? 0.5 : 0.25, c->mid_order, l);
+    const double* w3 = c->mid_order >= 2 ? c->w3 : nullptr;
+    if (c->mid_mode == TDFE_MIDPOINT_PC) {
+      // predictor: W(t + dt/4) extrapolated from W_{n-1}, W_{n-2} (, W_{n-3})
+      hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
+                         (const double*)c->w1, l[0], (const double*)c->w2, l[1], w3, l[2], Ex, Ey, Ez, c->vw, v32,
+                         nqd);
+      TDFE_HIP(c, hipGetLastError());
+      st = lanczos(dev_psibar, c->half, 0.5 * dt, 0, &r.k_pred_max, &r.k_pred_sum, &eh);
+      if (st != TDFE_OK && st != TDFE_ENOCONV) return st;
+      TDFE_TRY(tdfe_scf_potential_async(c, c->half, n_orb, c->wh, nullptr));
+      // corrector with the midpoint potential
+      hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
+                         (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, Ex, Ey,
+                         Ez, c->vw, v32, nqd);
+      TDFE_HIP(c, hipGetLastError());
+      s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
+      if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
+      // history: W_{n-3} <- W_{n-2} <- W_{n-1} <- W[rho(psibar^n)]
+      double* t = c->w3;
+      c->w3 = c->w2;
+      c->w2 = c->w1;
+      c->w1 = t;
+      TDFE_TRY(tdfe_scf_potential_async(c, dev_psibar, n_orb, c->w1, rep ? &hred : nullptr));
+    } else {
+      // (i) W_mid extrapolated to t + dt/2; psibar^{n-1} kept in the half-step buffer
+      hipLaunchKernelGGL(combine3_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, (const double*)c->w1, l[0],
+                         (const double*)c->w2, l[1], w3, l[2], c->wh, nqd);
+      TDFE_HIP(c, hipGetLastError());
+      TDFE_HIP(c, hipMemcpyAsync(c->half, dev_psibar, (size_t)c->n_dof * n_orb * 2 * sizeof(double),
+                                 hipMemcpyDeviceToDevice, c->stream));
+      double change = 0.0;
+      int it = 0;
+      bool conv = false;
+      while (it < c->sc_maxit) {
+        // (ii) propagate psibar^{n-1} with W_mid, then W_n = W[rho(psibar^n)]
+        hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet,
+                           (const double*)c->wh, 1.0, (const double*)nullptr, 0.0, (const double*)nullptr, 0.0, Ex,
+                           Ey, Ez, c->vw, v32, nqd);
+        TDFE_HIP(c, hipGetLastError());
+        int km = 0, ks = 0;
+        double em = 0.0;
+        s2 = tdfe_lanczos_run(c, c->vw, c->half, dev_psibar, n_orb, dt, tol, nullptr, nullptr, &km, &ks, &em);
+        if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
+        if (s2 == TDFE_ENOCONV) st = s2;
+        r.k_corr_max = std::max(r.k_corr_max, km);
+        r.k_corr_sum += ks;
+        r.err_max = std::max(r.err_max, em);
+        TDFE_TRY(tdfe_scf_potential_async(c, dev_psibar, n_orb, c->wn, rep ? &hred : nullptr));
+        // (iii) W_mid <- (W_{n-1} + W_n)/2 and its largest change
+        hipLaunchKernelGGL(midpoint_update_kernel, dim3(SC_BLOCKS), dim3(EW), 0, c->stream, (const double*)c->w1,
+                           (const double*)c->wn, c->wh, nqd, c->scbuf);
+        hipLaunchKernelGGL(max_final_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)c->scbuf, SC_BLOCKS,
+                           c->scbuf + SC_BLOCKS);
+        TDFE_HIP(c, hipGetLastError());
+        const void* hc = nullptr;
+        TDFE_TRY(tdfe_readback(c, c->scbuf + SC_BLOCKS, sizeof(double), 3328, &hc));
+        TDFE_HIP(c, hipStreamSynchronize(c->stream));
+        change = *(const volatile double*)hc;
+        ++it;
+        // (iv) until the midpoint potential settles
+        if (change <= c->sc_tol) {
+          conv = true;
+          break;
+        }
+      }
+      double* t = c->w3;
+      c->w3 = c->w2;
+      c->w2 = c->w1;
+      c->w1 = c->wn;
+      c->wn = t;
+      r.sc_iters = it;
+      r.sc_change = change;
+      if (!conv && st == TDFE_OK) {
+        st = TDFE_ENOCONV;
+        tdfe_fail(c, TDFE_ENOCONV, "magnus_step: self-consistent midpoint not converged in %d iterations (change %g)",
+                  it, change);
+      }
+    }
   }
-  if (defer) {
+  const bool deferred = defer && !(c->have_scf && c->mid_mode == TDFE_MIDPOINT_SC);
+  if (deferred) {
     if (c->have_scf) TDFE_TRY(tdfe_lanczos_enqueue_results(c, 0, &hpred));
     TDFE_TRY(tdfe_lanczos_enqueue_results(c, 1, &hcorr));
   }
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
-  if (defer) {
+  if (deferred) {
     if (hpred) {
       st = tdfe_lanczos_results(c, hpred, n_orb, tol, &r.k_pred_max, &r.k_pred_sum, &eh);
       if (st != TDFE_OK && st != TDFE_ENOCONV) return st;

@@ -189,6 +189,9 @@ void carve(tdfe_ctx* c, char* base) {
   c->vw32 = k.take<float>(nqd);
   c->w1 = k.take<double>(nqd);
   c->w2 = k.take<double>(nqd);
+  c->w3 = k.take<double>(nqd);
+  c->wn = k.take<double>(nqd);
+  c->scbuf = k.take<double>(512);
   c->wh = k.take<double>(nqd);
   c->rho = k.take<double>(nqd);
   c->phi = k.take<double>(nn);

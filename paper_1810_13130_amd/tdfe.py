@@ -43,12 +43,23 @@ class ScfDesc(ctypes.Structure):
 class StepReport(ctypes.Structure):
     _fields_ = [("k_pred_max", ctypes.c_int), ("k_corr_max", ctypes.c_int), ("k_pred_sum", ctypes.c_int),
                 ("k_corr_sum", ctypes.c_int), ("err_max", ctypes.c_double), ("poisson_iters", ctypes.c_int),
-                ("mu", ctypes.c_double * 3), ("charge", ctypes.c_double)]
+                ("mu", ctypes.c_double * 3), ("charge", ctypes.c_double), ("sc_iters", ctypes.c_int),
+                ("sc_change", ctypes.c_double)]
 
     def as_dict(self):
         return {"k_pred_max": self.k_pred_max, "k_corr_max": self.k_corr_max, "k_pred_sum": self.k_pred_sum,
                 "k_corr_sum": self.k_corr_sum, "err_max": self.err_max, "poisson_iters": self.poisson_iters,
-                "mu": np.array(self.mu[:]), "charge": self.charge}
+                "mu": np.array(self.mu[:]), "charge": self.charge, "sc_iters": self.sc_iters,
+                "sc_change": self.sc_change}
+
+
+class MidpointDesc(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int), ("order", ctypes.c_int), ("sc_tol", ctypes.c_double),
+                ("sc_maxit", ctypes.c_int)]
+
+
+MIDPOINT_PC = 0
+MIDPOINT_SC = 1
 
 
 _P = ctypes.c_void_p
@@ -68,6 +79,7 @@ SIGNATURES = {
     "tdfe_set_projectors": [_P, ctypes.c_int, _P, _P, _P, ctypes.c_size_t],
     "tdfe_projector_info": [_P, _IP, _I64P, _I64P, _I64P],
     "tdfe_set_field_direction": [_P, _DP],
+    "tdfe_set_midpoint": [_P, ctypes.POINTER(MidpointDesc)],
     "tdfe_kick": [_P, _P, ctypes.c_int, ctypes.c_double],
     "tdfe_field_samples": [ctypes.c_int, _DP, ctypes.c_int, _DP, _DP],
     "tdfe_absorption_spectrum": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
@@ -250,6 +262,11 @@ class Context:
         self._check(self.lib.tdfe_projector_info(self.h, ctypes.byref(g), ctypes.byref(st), ctypes.byref(bd),
                                                  ctypes.byref(ld)))
         return g.value, st.value, bd.value, ld.value
+
+    def set_midpoint(self, mode=MIDPOINT_PC, order=1, sc_tol=1e-10, sc_maxit=50):
+        m = MidpointDesc()
+        m.mode, m.order, m.sc_tol, m.sc_maxit = mode, order, sc_tol, sc_maxit
+        self._check(self.lib.tdfe_set_midpoint(self.h, ctypes.byref(m)))
 
     def set_field_direction(self, d):
         dd = (ctypes.c_double * 3)(*[float(v) for v in d])

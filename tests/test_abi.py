@@ -107,6 +107,15 @@ def test_query_sizes_and_call_order(lib):
     assert lib.tdfe_projector_query(h, 1025, ctypes.byref(pb)) == tdfe.EINVAL
     assert lib.tdfe_projector_query(h, 4, None) == tdfe.EINVAL
     assert lib.tdfe_set_projectors(h, 4, buf, buf, buf, 1 << 30) == tdfe.ESTATE
+    md = tdfe.MidpointDesc()
+    for mode, order, tol_, it in ((5, 1, 1e-10, 10), (1, 3, 1e-10, 10), (1, 1, 0.0, 10), (1, 1, 1e-10, 0),
+                                  (1, 1, float("nan"), 10)):
+        md.mode, md.order, md.sc_tol, md.sc_maxit = mode, order, tol_, it
+        assert lib.tdfe_set_midpoint(h, ctypes.byref(md)) == tdfe.EINVAL
+    md.mode, md.order, md.sc_tol, md.sc_maxit = 1, 2, 1e-10, 10
+    assert lib.tdfe_set_midpoint(h, ctypes.byref(md)) == 0
+    md.mode, md.order = 0, 1
+    assert lib.tdfe_set_midpoint(h, ctypes.byref(md)) == 0
     ng, st, bd, ld = ctypes.c_int(7), ctypes.c_int64(7), ctypes.c_int64(7), ctypes.c_int64(7)
     assert lib.tdfe_projector_info(h, ctypes.byref(ng), ctypes.byref(st), ctypes.byref(bd), ctypes.byref(ld)) == 0
     assert (ng.value, st.value, bd.value, ld.value) == (0, 0, 0, 0)
