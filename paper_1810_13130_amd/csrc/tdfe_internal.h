@@ -109,7 +109,7 @@ struct tdfe_ctx {
   void* nl_store = nullptr;
   int nl_groups = 0, nl_blocks = 0;  // projector groups (shared boxes) and blocks of the hot passes
   int nl_np_max = 0;                 // most projectors in one group
-  int nl_lines = 0, nl_add_lpb = 0, nl_add_blocks = 0;  // line partition of the add pass
+  int nl_lines = 0, nl_add_blocks = 0;  // grid lines crossed by boxes; segments (blocks) of the add pass
   int64_t nl_line_dofs = 0;                             // DoFs on those lines (x ranges)
   int64_t nl_packed = 0;             // stored entries of Cbar
   int64_t nl_box_dofs = 0;           // DoFs in the groups' boxes (summed over groups)

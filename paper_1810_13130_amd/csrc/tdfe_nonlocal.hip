@@ -44,10 +44,18 @@ struct NlGroup {
   int64_t off;      // element offset of the group's Cbar: [np][nz][ny][nx]
 };
 
-// a line of the DoF grid (fixed J, K) crossed by at least one group box:
-// x range [I_lo, I_hi] spans the boxes of groups gids[gs .. gs + gn)
-struct NlLine {
-  int J, K, I_lo, I_hi, gs, gn;
+// the add pass: a segment of at most NL_SEG consecutive DoFs of a grid line
+// (fixed J, K) crossed by group boxes; its groups are the line's entries
+// lg[gs .. gs + gn)
+constexpr int NL_SEG = 32;
+struct NlSeg {
+  int J, K, I0, I1, gs, gn;
+};
+// a group crossing a line: Cbar of projector p0 + q at DoF I of the line is
+// cbar[cbase + q vol + I] for I0 <= I <= I1
+struct NlLineGroup {
+  int64_t cbase, vol;
+  int I0, I1, p0, np;
 };
 
 struct NlLayout {
@@ -65,8 +73,8 @@ struct NlLayout {
   double* chi;      // [n_quad] set-up
   double* dense;    // [n_dof] set-up: Cbar_p on every DoF
   double* red;      // [NL_SETUP_BLOCKS] set-up
-  NlLine* lines;    // [at most nyi nzi] lines of the add pass
-  int* gids;        // [at most nyi nzi n_proj] groups of each line
+  NlSeg* segs;      // [at most nyi nzi (nxi / NL_SEG + 1)] blocks of the add pass
+  NlLineGroup* lg;  // [at most nyi nzi n_proj] groups crossing each line
   size_t bytes;
 };
 
@@ -97,8 +105,8 @@ NlLayout nl_layout(const tdfe_ctx* c, int n_proj, char* base) {
   L.dense = (double*)take((size_t)c->n_dof * sizeof(double));
   L.red = (double*)take(NL_SETUP_BLOCKS * sizeof(double));
   const size_t nlines = (size_t)(c->Ny - 2) * (c->Nz - 2);
-  L.lines = (NlLine*)take(nlines * sizeof(NlLine));
-  L.gids = (int*)take(nlines * np * sizeof(int));
+  L.segs = (NlSeg*)take(nlines * ((size_t)(c->Nx - 2) / NL_SEG + 1) * sizeof(NlSeg));
+  L.lg = (NlLineGroup*)take(nlines * np * sizeof(NlLineGroup));
   L.bytes = off + 256;
   return L;
 }
@@ -236,24 +244,40 @@ struct SlotWalk {
   }
 };
 
-// block b serves box lines [l0, l1) of its group; thread t takes column t % CP
-// and the x positions t / CP + RG sl of each line.  U slots are loaded before
-// any is used (invalid slots read a valid address and contribute zero);
-// projector indices past the group's np read the group's last projector and
-// are discarded.
+template <typename T>
+struct Vec2;
+template <>
+struct Vec2<double> {
+  using type = double2;
+};
+template <>
+struct Vec2<float> {
+  using type = float2;
+};
+
+// block b serves box lines [l0, l1) of its group; thread t takes the column
+// pair t % CPP (two real columns, one vector load) and the x positions
+// t / CPP + RG sl of each line.  U slots are loaded before any is used
+// (invalid slots read a valid address and contribute zero); projector
+// indices past the group's np read the group's last projector and are
+// discarded.  Lanes of a wave that share a column pair are summed by a fixed
+// butterfly, then the four waves in order.
 template <typename T, typename CT, int CP, int NP, int U>
 __global__ void __launch_bounds__(NL_THREADS)
     nl_project_kernel(const T* __restrict__ x, int ld, int cols, const double* __restrict__ colscale,
                       const CT* __restrict__ cbar, const NlGroup* __restrict__ groups,
                       const int* __restrict__ blk2grp, int nxi, int nyi, double* __restrict__ part, const int* done) {
-  constexpr int RG = NL_THREADS / CP;
-  __shared__ double s[NP][NL_THREADS];
+  using T2 = typename Vec2<T>::type;
+  constexpr int CPP = CP / 2;
+  constexpr int RG = NL_THREADS / CPP;
+  constexpr int NW = NL_THREADS / 64;
+  __shared__ double s[NP][2][NW][CPP];
   if (done && *done) return;
   const int b = blockIdx.x;
   const NlGroup G = groups[blk2grp[b]];
-  const int t = threadIdx.x, col = t % CP, rg = t / CP;
-  const bool cok = col < cols;
-  const int colc = cok ? col : 0;
+  const int t = threadIdx.x, pr = t % CPP, rg = t / CPP;
+  const bool pok = 2 * pr < cols;
+  const int prc = pok ? pr : 0;
   const int l0 = (b - G.b0) * G.lpb;
   const int l1 = min(l0 + G.lpb, G.ny * G.nz);
   const int nslot = (G.nx + RG - 1) / RG;
@@ -266,41 +290,50 @@ __global__ void __launch_bounds__(NL_THREADS)
   SlotWalk w;
   w.start(G, l0, nxi, nyi);
   const int64_t d0 = w.dline, e0 = w.eline;
-  double acc[NP];
+  double acc[NP][2];
 #pragma unroll
-  for (int q = 0; q < NP; ++q) acc[q] = 0.0;
+  for (int q = 0; q < NP; ++q) acc[q][0] = acc[q][1] = 0.0;
   for (int s0 = 0; s0 < S; s0 += U) {
-    T xr[U];
+    T2 xr[U];
     CT cr[U][NP];
     bool ok[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {
       const int i = rg + RG * w.sl;
       const bool v = s0 + u < S && i < G.nx;
-      ok[u] = v && cok;
+      ok[u] = v && pok;
       const int64_t d = v ? w.dline + i : d0;
       const int64_t e = v ? w.eline + i : e0;
-      xr[u] = x[d * ld + colc];
+      xr[u] = *(const T2*)(x + d * ld + 2 * prc);
 #pragma unroll
       for (int q = 0; q < NP; ++q) cr[u][q] = cg[qoff[q] + e];
       w.next(G, nslot, nxi, nyi);
     }
 #pragma unroll
     for (int u = 0; u < U; ++u) {
-      const double xv = ok[u] ? (double)xr[u] : 0.0;
+      const double x0 = ok[u] ? (double)xr[u].x : 0.0, x1 = ok[u] ? (double)xr[u].y : 0.0;
 #pragma unroll
-      for (int q = 0; q < NP; ++q) acc[q] += (double)cr[u][q] * xv;
+      for (int q = 0; q < NP; ++q) {
+        acc[q][0] += (double)cr[u][q] * x0;
+        acc[q][1] += (double)cr[u][q] * x1;
+      }
     }
   }
+  const int lane = t & 63, wave = t >> 6;
 #pragma unroll
-  for (int q = 0; q < NP; ++q) s[q][t] = acc[q];
+  for (int q = 0; q < NP; ++q)
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      double v = acc[q][h];
+      for (int off = CPP; off < 64; off <<= 1) v += __shfl_xor(v, off, 64);
+      if (lane < CPP) s[q][h][wave][lane] = v;
+    }
   __syncthreads();
-  // sum over the RG lanes of each (projector, column), fixed order
-  for (int pr = t; pr < NP * CP; pr += NL_THREADS) {
-    const int q = pr / CP, cc = pr % CP;
+  for (int idx = t; idx < NP * CP; idx += NL_THREADS) {
+    const int q = idx / CP, cc = idx % CP;
     if (q < G.np && cc < cols) {
       double v = 0.0;
-      for (int g = 0; g < RG; ++g) v += s[q][g * CP + cc];
+      for (int k = 0; k < NW; ++k) v += s[q][cc & 1][k][cc >> 1];
       const double cs = colscale ? colscale[cc >> 1] : 1.0;
       part[((int64_t)b * NL_PCH + q) * TDFE_MAX_COLS + cc] = v * cs;
     }
@@ -364,72 +397,77 @@ __global__ void nl_energy_kernel(const double* eP, int n_proj, int cols, double*
 }
 
 // y[d][col] += sum over the groups g whose box holds d of
-// sum_q Cbar_g[q][d] tE[p0_g + q][col].  Block b serves lines
-// [b lpb, (b + 1) lpb); every (d, col) of a line's range belongs to one
-// thread, which adds the groups in their stored order: no atomics, and the
-// result does not depend on scheduling.  Block 0 also writes the energy row
-// (all projections are final by now).
-template <typename T, typename CT, int CP, int NP, int U>
+// sum_q Cbar_g[q][d] tE[p0_g + q][col].  Block b owns segment b; thread t
+// takes the column pair t % CPP (one vector load and store) of DoFs
+// t / CPP + RG u.  Each (DoF, column) belongs to one thread, which adds the
+// crossing groups in their stored order: no atomics, and the result does not
+// depend on scheduling.  Block 0 also writes the energy row (all projections
+// are final by now).
+template <typename T, typename CT, int CP, int NP>
 __global__ void __launch_bounds__(NL_THREADS)
-    nl_add_kernel(T* __restrict__ y, int ld, int cols, const CT* __restrict__ cbar,
-                  const NlGroup* __restrict__ groups, const NlLine* __restrict__ lines, const int* __restrict__ gids,
-                  int n_lines, int lpb, int nxi, int nyi, const double* __restrict__ tE, const double* __restrict__ eP,
-                  int n_proj, double* energy_row, const int* done) {
-  constexpr int RG = NL_THREADS / CP;
+    nl_add_kernel(T* __restrict__ y, int ld, int cols, const CT* __restrict__ cbar, const NlSeg* __restrict__ segs,
+                  const NlLineGroup* __restrict__ lgs, int nxi, int nyi, const double* __restrict__ tE,
+                  const double* __restrict__ eP, int n_proj, double* energy_row, const int* done) {
+  using T2 = typename Vec2<T>::type;
+  constexpr int CPP = CP / 2;
+  constexpr int RG = NL_THREADS / CPP;
+  constexpr int U = NL_SEG / RG;
+  static_assert(U >= 1 && U * RG == NL_SEG, "segment length must be a multiple of the DoF lanes");
   if (done && *done) return;
   const int b = blockIdx.x;
   if (b == 0 && energy_row) nl_energy_row(eP, n_proj, cols, energy_row);
-  const int t = threadIdx.x, col = t % CP, rg = t / CP;
-  if (col >= cols) return;
-  const int L0 = b * lpb, L1 = min(L0 + lpb, n_lines);
-  for (int li = L0; li < L1; ++li) {
-    const NlLine ln = lines[li];
-    const int64_t dline = (int64_t)nxi * (ln.J + (int64_t)nyi * ln.K);
-    for (int I0 = ln.I_lo + rg; I0 <= ln.I_hi; I0 += RG * U) {
-      T yv[U];
-      double acc[U];
+  const int t = threadIdx.x, pr = t % CPP, rg = t / CPP;
+  if (2 * pr >= cols) return;
+  const NlSeg sg = segs[b];
+  const int64_t dline = (int64_t)nxi * (sg.J + (int64_t)nyi * sg.K);
+  T2 yv[U];
+  double acc[U][2];
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int I = min(I0 + RG * u, ln.I_hi);
-        yv[u] = y[(dline + I) * ld + col];
-        acc[u] = 0.0;
+  for (int u = 0; u < U; ++u) {
+    const int I = min(sg.I0 + rg + RG * u, sg.I1);
+    yv[u] = *(const T2*)(y + (dline + I) * ld + 2 * pr);
+    acc[u][0] = acc[u][1] = 0.0;
+  }
+  for (int gi = sg.gs; gi < sg.gs + sg.gn; ++gi) {
+    const NlLineGroup g = lgs[gi];
+    double2 te[NP];
+    CT cr[U][NP];
+    bool in[U];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) {
+      const double2 v = *(const double2*)(tE + (g.p0 + min(q, g.np - 1)) * TDFE_MAX_COLS + 2 * pr);
+      te[q] = q < g.np ? v : make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const int I = sg.I0 + rg + RG * u;
+      in[u] = I <= sg.I1 && I >= g.I0 && I <= g.I1;
+      const int64_t e = g.cbase + (in[u] ? I : g.I0);
+#pragma unroll
+      for (int q = 0; q < NP; ++q) cr[u][q] = cbar[e + (int64_t)min(q, g.np - 1) * g.vol];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      double v0 = 0.0, v1 = 0.0;
+#pragma unroll
+      for (int q = 0; q < NP; ++q) {
+        v0 += (double)cr[u][q] * te[q].x;
+        v1 += (double)cr[u][q] * te[q].y;
       }
-      for (int gi = ln.gs; gi < ln.gs + ln.gn; ++gi) {
-        const NlGroup G = groups[gids[gi]];
-        const int64_t vol = (int64_t)G.nx * G.ny * G.nz;
-        const int64_t eline = ((int64_t)(ln.K - G.K0) * G.ny + (ln.J - G.J0)) * G.nx - G.I0;
-        const CT* cg = cbar + G.off;
-        double te[NP];
-        int64_t qoff[NP];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) {
-          const int qc = min(q, G.np - 1);
-          qoff[q] = (int64_t)qc * vol;
-          te[q] = q < G.np ? tE[(G.p0 + qc) * TDFE_MAX_COLS + col] : 0.0;
-        }
-        CT cr[U][NP];
-        bool in[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const int I = I0 + RG * u;
-          in[u] = I >= G.I0 && I < G.I0 + G.nx && I <= ln.I_hi;
-          const int64_t e = eline + (in[u] ? I : G.I0);
-#pragma unroll
-          for (int q = 0; q < NP; ++q) cr[u][q] = cg[qoff[q] + e];
-        }
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          double v = 0.0;
-#pragma unroll
-          for (int q = 0; q < NP; ++q) v += (double)cr[u][q] * te[q];
-          if (in[u]) acc[u] += v;
-        }
+      if (in[u]) {
+        acc[u][0] += v0;
+        acc[u][1] += v1;
       }
+    }
+  }
 #pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const int I = I0 + RG * u;
-        if (I <= ln.I_hi) y[(dline + I) * ld + col] = yv[u] + (T)acc[u];
-      }
+  for (int u = 0; u < U; ++u) {
+    const int I = sg.I0 + rg + RG * u;
+    if (I <= sg.I1) {
+      T2 o;
+      o.x = yv[u].x + (T)acc[u][0];
+      o.y = yv[u].y + (T)acc[u][1];
+      *(T2*)(y + (dline + I) * ld + 2 * pr) = o;
     }
   }
 }
@@ -437,7 +475,7 @@ __global__ void __launch_bounds__(NL_THREADS)
 template <typename T, typename CT, int CP, int NP>
 tdfe_status nl_passes(tdfe_ctx* c, const T* x, T* y, int ld, int cols, const double* cs, const int* done,
                       double* energy_row, const CT* cbar, const NlLayout& L) {
-  constexpr int U = NP >= 16 ? 2 : 32 / NP;
+  constexpr int U = NP >= 16 ? 1 : 16 / NP;
   const int nxi = c->Nx - 2, nyi = c->Ny - 2;
   if (c->nl_blocks > 0) {
     hipLaunchKernelGGL((nl_project_kernel<T, CT, CP, NP, U>), dim3(c->nl_blocks), dim3(NL_THREADS), 0, c->stream, x,
@@ -448,10 +486,9 @@ tdfe_status nl_passes(tdfe_ctx* c, const T* x, T* y, int ld, int cols, const dou
                      (const NlGroup*)L.groups, (const int*)L.pgrp, cols, (const double*)L.E, L.tE, L.eP, done);
   TDFE_HIP(c, hipGetLastError());
   if (c->nl_add_blocks > 0) {
-    hipLaunchKernelGGL((nl_add_kernel<T, CT, CP, NP, U>), dim3(c->nl_add_blocks), dim3(NL_THREADS), 0, c->stream,
-                       y, ld, cols, cbar, (const NlGroup*)L.groups, (const NlLine*)L.lines, (const int*)L.gids,
-                       c->nl_lines, c->nl_add_lpb, nxi, nyi, (const double*)L.tE, (const double*)L.eP, c->n_proj,
-                       energy_row, done);
+    hipLaunchKernelGGL((nl_add_kernel<T, CT, CP, NP>), dim3(c->nl_add_blocks), dim3(NL_THREADS), 0, c->stream, y,
+                       ld, cols, cbar, (const NlSeg*)L.segs, (const NlLineGroup*)L.lg, nxi, nyi, (const double*)L.tE,
+                       (const double*)L.eP, c->n_proj, energy_row, done);
     TDFE_HIP(c, hipGetLastError());
   } else if (energy_row) {
     hipLaunchKernelGGL(nl_energy_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)L.eP, c->n_proj, cols,
@@ -549,7 +586,7 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
   c->nl_groups = 0;
   c->nl_packed = 0;
   c->nl_box_dofs = 0;
-  c->nl_lines = c->nl_add_lpb = c->nl_add_blocks = 0;
+  c->nl_lines = c->nl_add_blocks = 0;
   c->nl_line_dofs = 0;
   if (n_proj == 0) return TDFE_OK;
   const int64_t nq = c->n_quad, nd = c->n_dof;
@@ -662,10 +699,12 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
       TDFE_HIP(c, hipGetLastError());
     }
   }
-  // lines of the add pass: every (J, K) crossed by a group box, with its groups in order
-  std::vector<NlLine> lines;
-  std::vector<int> gids;
+  // the add pass: every grid line (J, K) crossed by a group box, its groups in
+  // order, cut into segments of at most NL_SEG DoFs
+  std::vector<NlSeg> segs;
+  std::vector<NlLineGroup> lgs;
   int64_t line_elems = 0;
+  int n_lines = 0;
   {
     int lo[3] = {INT_MAX, INT_MAX, INT_MAX}, hi[3] = {-1, -1, -1};
     for (const NlGroup& g : groups) {
@@ -677,32 +716,34 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
     }
     for (int K = lo[2]; K <= hi[2]; ++K)
       for (int J = lo[1]; J <= hi[1]; ++J) {
-        NlLine ln{J, K, INT_MAX, -1, (int)gids.size(), 0};
-        for (size_t gi = 0; gi < groups.size(); ++gi) {
-          const NlGroup& g = groups[gi];
+        const int gs = (int)lgs.size();
+        int I_lo = INT_MAX, I_hi = -1;
+        for (const NlGroup& g : groups) {
           if (g.nx == 0 || J < g.J0 || J >= g.J0 + g.ny || K < g.K0 || K >= g.K0 + g.nz) continue;
-          gids.push_back((int)gi);
-          ln.gn += 1;
-          ln.I_lo = std::min(ln.I_lo, g.I0);
-          ln.I_hi = std::max(ln.I_hi, g.I0 + g.nx - 1);
+          NlLineGroup e{};
+          e.vol = (int64_t)g.nx * g.ny * g.nz;
+          e.cbase = g.off + ((int64_t)(K - g.K0) * g.ny + (J - g.J0)) * g.nx - g.I0;
+          e.I0 = g.I0;
+          e.I1 = g.I0 + g.nx - 1;
+          e.p0 = g.p0;
+          e.np = g.np;
+          lgs.push_back(e);
+          I_lo = std::min(I_lo, e.I0);
+          I_hi = std::max(I_hi, e.I1);
         }
-        if (ln.gn > 0) {
-          lines.push_back(ln);
-          line_elems += ln.I_hi - ln.I_lo + 1;
-        }
+        const int gn = (int)lgs.size() - gs;
+        if (gn == 0) continue;
+        ++n_lines;
+        line_elems += I_hi - I_lo + 1;
+        for (int I = I_lo; I <= I_hi; I += NL_SEG) segs.push_back(NlSeg{J, K, I, std::min(I + NL_SEG - 1, I_hi), gs, gn});
       }
   }
-  if ((int64_t)lines.size() > (int64_t)nyi * nzi || (int64_t)gids.size() > (int64_t)nyi * nzi * n_proj)
+  if ((int64_t)segs.size() > (int64_t)nyi * nzi * (nxi / NL_SEG + 1) || (int64_t)lgs.size() > (int64_t)nyi * nzi * n_proj)
     return tdfe_fail(c, TDFE_EINVAL, "set_projectors: internal line table error");
-  int add_lpb = 1, add_blocks = 0;
-  if (!lines.empty()) {
-    const int64_t epb = std::max<int64_t>(128, (line_elems + 4 * NL_TARGET_BLOCKS - 1) / (4 * NL_TARGET_BLOCKS));
-    const int64_t avg = std::max<int64_t>(1, line_elems / (int64_t)lines.size());
-    add_lpb = (int)std::max<int64_t>(1, epb / avg);
-    add_blocks = (int)((lines.size() + add_lpb - 1) / add_lpb);
-    TDFE_HIP(c, hipMemcpyAsync(L.lines, lines.data(), lines.size() * sizeof(NlLine), hipMemcpyHostToDevice,
+  if (!segs.empty()) {
+    TDFE_HIP(c, hipMemcpyAsync(L.segs, segs.data(), segs.size() * sizeof(NlSeg), hipMemcpyHostToDevice, c->stream));
+    TDFE_HIP(c, hipMemcpyAsync(L.lg, lgs.data(), lgs.size() * sizeof(NlLineGroup), hipMemcpyHostToDevice,
                                c->stream));
-    TDFE_HIP(c, hipMemcpyAsync(L.gids, gids.data(), gids.size() * sizeof(int), hipMemcpyHostToDevice, c->stream));
   }
   TDFE_HIP(c, hipMemcpyAsync(L.groups, groups.data(), groups.size() * sizeof(NlGroup), hipMemcpyHostToDevice,
                              c->stream));
@@ -716,10 +757,9 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
   c->nl_groups = (int)groups.size();
   c->nl_packed = off;
   c->nl_box_dofs = total;
-  c->nl_lines = (int)lines.size();
+  c->nl_lines = n_lines;
   c->nl_line_dofs = line_elems;
-  c->nl_add_lpb = add_lpb;
-  c->nl_add_blocks = add_blocks;
+  c->nl_add_blocks = (int)segs.size();
   c->nl_np_max = 1;
   for (const NlGroup& g : groups) c->nl_np_max = std::max(c->nl_np_max, g.np);
   c->n_proj = n_proj;
