@@ -294,6 +294,52 @@ def midpoint_modes(n_steps=20):
     return out
 
 
+def adaptive_mesh(n_elem=1728, n_steps=10):
+    """A priori graded mesh against a uniform one with the same element count:
+    the induced dipole of the benchmark workload's recipe (4 atoms, 8
+    orbitals, Hartree + exchange, kick, p = 5) over 10 steps, each against a
+    32^3-cell uniform reference."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    base = W.CONFIGS[2]
+    Z, R = W.atoms(base)
+
+    def run(verts, ncell):
+        ctx = tdfe.Context(base.p, ncell, verts, n_orb_max=base.n_orb, k_max=base.k_max)
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(base, xq).reshape(ctx.n_cell, -1)).cuda())
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=base.n_orb)
+        psi = torch.from_numpy(W.initial_psibar(base, ctx.dof_coords().cpu().numpy(),
+                                                ctx.mass_diag().cpu().numpy())).cuda()
+        mu = [ctx.dipole(psi)[0][2]]
+        for _ in range(n_steps):
+            mu.append(ctx.magnus_step(psi, base.dt, 0.0, base.tol)["mu"][2])
+        n_dof = ctx.n_dof
+        ctx.close()
+        torch.cuda.empty_cache()
+        mu = np.array(mu)
+        return mu - mu[0], n_dof
+
+    n1 = int(round(n_elem ** (1 / 3)))
+    uni = W.box_vertices(base.lo, base.hi, (n1, n1, n1))
+    axes, E = tdfe.adaptive_axes(base.p, base.lo, base.hi, R, Z, [1.0] * len(Z), [0.5] * len(Z), n_elem, samples=129)
+    ncell = tuple(len(a) - 1 for a in axes)
+    t = time.perf_counter()
+    ref, nd_ref = run(W.box_vertices(base.lo, base.hi, (32, 32, 32)), (32, 32, 32))
+    d_uni, nd_uni = run(uni, (n1, n1, n1))
+    d_ada, nd_ada = run(tdfe.rectilinear_vertices(*axes), ncell)
+    scale = np.abs(ref).max()
+    return {"workload": base.name + f" recipe, {n_steps} steps, p = {base.p}",
+            "reference": {"cells": [32, 32, 32], "n_dof": nd_ref},
+            "uniform": {"cells": [n1] * 3, "n_dof": nd_uni, "induced_dipole_rel_err": float(np.abs(d_uni - ref).max() / scale)},
+            "adaptive": {"cells": list(ncell), "n_dof": nd_ada, "E": E,
+                         "spacing_min_max": [float(min(np.diff(a).min() for a in axes)),
+                                             float(max(np.diff(a).max() for a in axes))],
+                         "induced_dipole_rel_err": float(np.abs(d_ada - ref).max() / scale)},
+            "wall_s": time.perf_counter() - t}
+
+
 def cpu_oracle_baseline(cfg, ks_total):
     """Bounded sample of the CPU oracle on this host, scaled to steps/s."""
     import threadpoolctl
@@ -351,6 +397,7 @@ def main():
     ap.add_argument("--no-nonlocal", action="store_true")
     ap.add_argument("--no-spectra", action="store_true")
     ap.add_argument("--no-midpoint", action="store_true")
+    ap.add_argument("--no-adaptive", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     args = ap.parse_args()
@@ -487,6 +534,8 @@ def main():
         out["field_and_spectra"] = field_and_spectra()
     if not args.no_midpoint:
         out["midpoint"] = midpoint_modes()
+    if not args.no_adaptive:
+        out["adaptive_mesh"] = adaptive_mesh()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_oracle_baseline(cfg, int(round(ks_total / args.steps)))
     print(json.dumps(out), flush=True)

@@ -303,6 +303,51 @@ tdfe_status tdfe_absorption_spectrum(const double* dev_mu, const double* dev_fie
 tdfe_status tdfe_power_spectrum(const double* dev_mu, int n_t, double dt, const double* dev_omega, int n_omega,
                                 double* dev_P, void* hip_stream);
 
+/* A priori mesh (Sec. "Efficient spatio-temporal discretization", Eqs.
+ * OptimalMeshMin, OptimalMeshSize): the element size h(r) = E g(r)^(-1/(p+3))
+ * that minimises the dipole-error bound at a fixed element count, with
+ *   g = sum over atoms of 2 Dbar^{p+1} phi + Dbar^{p+3} phi + Dbar^{p+1} V,
+ *   Dbar^k f = sum over multi-indices |l| = k of |D^l f|,
+ * phi = (pi s^2)^(-3/4) exp(-|r-R|^2/(2 s^2)) and V = -Z exp(-|r-R|^2/(2 a^2))
+ * standing in for the atom's ground-state orbital and potential, and E from
+ * int dr / h^3 = n_elem.  The mesh is rectilinear (no hanging nodes, so M
+ * stays diagonal and the box kernels and the exact Hartree solver apply):
+ * along each axis the spacing is the smallest h over the plane through the
+ * point, h_a(s) = E (max over the plane of g)^(-1/(p+3)), sampled on a
+ * uniform grid of samples^3 points of [lo, hi]^3; n_a = max(1, floor(c I_a
+ * + 1/2)) cells with I_a = int ds / h_a (trapezoid rule) and
+ * c^3 I_x I_y I_z = n_elem; the vertices equidistribute int ds / h_a
+ * (linear inversion between samples).  The sampling runs on the GPU (one
+ * thread per sample point; plane maxima and the count integral by fixed-order
+ * block reductions), the 1D steps on the host.
+ *
+ * adaptive_axes_query: *bytes = device scratch for the call (about
+ * 8 samples^3 bytes).
+ * adaptive_axes: host_axes is [3][max_cells + 1]: row a receives the
+ * n_a + 1 vertex coordinates of axis a (x, y, z), host_ncell[3] the counts,
+ * *host_E (may be NULL) the constant E.  dev_scratch: caller-owned, 256-byte
+ * aligned, >= the queried size.  Synchronises hip_stream.  EINVAL for a bad
+ * description (p outside 1..8, hi <= lo, no atoms or more than
+ * TDFE_MAX_ATOMS_MESH, non-positive widths, n_elem < 1, samples outside
+ * 3..1024); ENOMEM if the scratch is too small or an axis needs more than
+ * max_cells cells.  The vertices of fe_mesh_setup are then the tensor
+ * product of the three axes (x fastest). */
+#define TDFE_MAX_ATOMS_MESH 4096
+typedef struct {
+  int p;                /* element order the mesh is for */
+  double lo, hi;        /* domain [lo, hi]^3 */
+  int n_atoms;
+  const double* R;      /* HOST [n_atoms][3] positions */
+  const double* Z;      /* HOST [n_atoms] potential depths */
+  const double* s_orb;  /* HOST [n_atoms] orbital widths */
+  const double* a_pot;  /* HOST [n_atoms] potential widths */
+  double n_elem;        /* target number of elements */
+  int samples;          /* sample points per axis */
+} tdfe_adapt_desc;
+tdfe_status tdfe_adaptive_axes_query(const tdfe_adapt_desc* d, size_t* bytes);
+tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
+                               int max_cells, double* host_axes, int* host_ncell, double* host_E);
+
 /* gradient_query: device workspace bytes that tdfe_dipole_gradient needs for
  * n_orb orbitals, n_steps steps, a state checkpoint every checkpoint_every
  * steps and Krylov bases of up to k_store vectors (a multiple of 8, at most

@@ -53,6 +53,13 @@ class StepReport(ctypes.Structure):
                 "sc_change": self.sc_change}
 
 
+class AdaptDesc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("n_atoms", ctypes.c_int),
+                ("R", ctypes.POINTER(ctypes.c_double)), ("Z", ctypes.POINTER(ctypes.c_double)),
+                ("s_orb", ctypes.POINTER(ctypes.c_double)), ("a_pot", ctypes.POINTER(ctypes.c_double)),
+                ("n_elem", ctypes.c_double), ("samples", ctypes.c_int)]
+
+
 class MidpointDesc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("order", ctypes.c_int), ("sc_tol", ctypes.c_double),
                 ("sc_maxit", ctypes.c_int)]
@@ -80,6 +87,8 @@ SIGNATURES = {
     "tdfe_projector_info": [_P, _IP, _I64P, _I64P, _I64P],
     "tdfe_set_field_direction": [_P, _DP],
     "tdfe_set_midpoint": [_P, ctypes.POINTER(MidpointDesc)],
+    "tdfe_adaptive_axes_query": [ctypes.POINTER(AdaptDesc), ctypes.POINTER(ctypes.c_size_t)],
+    "tdfe_adaptive_axes": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_size_t, _P, ctypes.c_int, _DP, _IP, _DP],
     "tdfe_kick": [_P, _P, ctypes.c_int, ctypes.c_double],
     "tdfe_field_samples": [ctypes.c_int, _DP, ctypes.c_int, _DP, _DP],
     "tdfe_absorption_spectrum": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
@@ -439,3 +448,36 @@ def power_spectrum(mu, dt, omega):
     if s != OK:
         raise TdfeError(s, "power_spectrum: bad arguments")
     return out
+
+
+def adaptive_axes(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=4096):
+    """Vertex coordinates (x, y, z axes) of the graded rectilinear mesh whose
+    spacing follows the a priori element size h(r); returns (axes, E)."""
+    import torch
+    lib = load()
+    keep = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1)) for v in (R, Z, s_orb, a_pot)]
+    d = AdaptDesc()
+    d.p, d.lo, d.hi, d.n_atoms = p, lo, hi, len(keep[1])
+    d.R, d.Z, d.s_orb, d.a_pot = (k.ctypes.data_as(_DP) for k in keep)
+    d.n_elem, d.samples = float(n_elem), samples
+    nb = ctypes.c_size_t()
+    s = lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb))
+    if s != OK:
+        raise TdfeError(s, "adaptive_axes: bad description")
+    scratch = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    axes = np.zeros((3, max_cells + 1))
+    nc = (ctypes.c_int * 3)()
+    E = ctypes.c_double()
+    s = lib.tdfe_adaptive_axes(ctypes.byref(d), ctypes.c_void_p(base + off), nb.value, _stream_handle(), max_cells,
+                               axes.ctypes.data_as(_DP), nc, ctypes.byref(E))
+    if s != OK:
+        raise TdfeError(s, "adaptive_axes failed")
+    return [axes[a, :nc[a] + 1].copy() for a in range(3)], E.value
+
+
+def rectilinear_vertices(ax, ay, az):
+    """Vertex array [(nz+1)(ny+1)(nx+1)][3] (x fastest) of the tensor-product mesh."""
+    Z3, Y3, X3 = np.meshgrid(az, ay, ax, indexing="ij")
+    return np.stack([X3, Y3, Z3], axis=-1).reshape(-1, 3)

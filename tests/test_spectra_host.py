@@ -75,3 +75,21 @@ def test_field_direction_and_kick_checks(tdfe):
     assert lib.tdfe_kick(h, ctypes.c_void_p(4096), 2, 1e-3) == tdfe.EINVAL
     assert lib.tdfe_kick(h, ctypes.c_void_p(4096), 1, float("nan")) == tdfe.EINVAL
     lib.tdfe_destroy(h)
+
+
+def test_adaptive_axes_description_checks(tdfe):
+    lib = tdfe.load()
+    R = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    one = (ctypes.c_double * 1)(1.0)
+    d = tdfe.AdaptDesc()
+    d.p, d.lo, d.hi, d.n_atoms, d.R, d.Z, d.s_orb, d.a_pot, d.n_elem, d.samples = 4, -1.0, 1.0, 1, R, one, one, one, 100.0, 17
+    nb = ctypes.c_size_t()
+    assert lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb)) == 0 and nb.value >= 8 * 17 ** 3
+    for field, bad in (("p", 9), ("hi", -1.0), ("n_atoms", 0), ("n_elem", 0.5), ("samples", 2)):
+        old = getattr(d, field)
+        setattr(d, field, bad)
+        assert lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb)) == tdfe.EINVAL, field
+        setattr(d, field, old)
+    zero = (ctypes.c_double * 1)(0.0)
+    d.s_orb = zero
+    assert lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb)) == tdfe.EINVAL
