@@ -81,3 +81,38 @@ def test_box_kernels_agree_on_full_size_benchmark_operator(monkeypatch):
     y_plane = gpu_context(cfg, k_max=4).apply_H(x).cpu().numpy()
     assert rel(y_default, y_plane) < 1e-13
     assert rel(y_default, op.apply_Hbar(m, vq, x.cpu().numpy())) < 1e-12
+
+
+ODD_N_ORBS = {2: 3, 4: 2, 6: 1, 8: 1}
+
+
+@pytest.mark.parametrize("p", sorted(ODD_N_ORBS))
+def test_box_kernels_at_odd_n_on_non_uniform_axes(p):
+    """Rectilinear cells of unequal widths (the metric and the separable
+    M^-1/2 factors differ per cell and per node line) at every odd n = p + 1,
+    FP64 and FP32, against the oracle."""
+    from paper_1810_13130_amd import tdfe
+    n_orb = ODD_N_ORBS[p]
+    cfg = _box(p, n_orb)
+    axes = [cfg.lo + (cfg.hi - cfg.lo) * np.linspace(0.0, 1.0, n + 1) ** e for n, e in ((3, 1.3), (2, 0.8), (2, 1.0))]
+    axes[2] = np.array([cfg.lo, cfg.lo + 0.3 * (cfg.hi - cfg.lo), cfg.hi])
+    verts = tdfe.rectilinear_vertices(*axes)
+    ncell = (3, 2, 2)
+    from oracle.mesh import Mesh
+    m = Mesh(p, ncell, verts, p + 1)
+    vq = W.external_potential(cfg, m.quad_xyz)
+    x = W.random_block(m.n_dof, n_orb, 600 + p)
+    ref = op.apply_Hbar(m, vq, x)
+    for prec in (0, MIXED):
+        ctx = tdfe.Context(p, ncell, verts, n_orb_max=n_orb, k_max=4, precision=prec)
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
+        if prec == 0:
+            y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+            assert rel(y, ref) < 1e-12
+        else:
+            xg = torch.from_numpy(x).to(torch.complex64).cuda()
+            y = torch.zeros_like(xg)
+            ctx.apply_H_add_f32(xg, y)
+            assert rel(y.cpu().numpy(), ref) < 2e-6
+        ctx.close()
