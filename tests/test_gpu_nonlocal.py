@@ -221,3 +221,53 @@ def test_field_gradient_with_projectors_against_finite_differences():
         fd = (forward(ep) - forward(em)) / (2 * h)
         assert abs(fd - g[k]) <= 1e-5 * np.abs(g).max()
     ctx.close()
+
+
+def _many_projectors(xyz, centers, n_per_atom):
+    """n_per_atom projectors per centre: monomials of r - R up to degree 3
+    times a Gaussian, with a Gaussian well of either sign (grouped boxes of up
+    to 16 projectors)."""
+    mons = [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1), (2, 0, 0), (0, 2, 0), (0, 0, 2), (1, 1, 0), (1, 0, 1),
+            (0, 1, 1), (3, 0, 0), (0, 3, 0), (0, 0, 3), (1, 1, 1), (2, 1, 0), (0, 1, 2)]
+    us, dvs = [], []
+    for a, Rc in enumerate(centers):
+        d = xyz - np.asarray(Rc)
+        r2 = np.sum(d * d, axis=-1)
+        env = np.exp(-r2 / (2 * 0.8 ** 2))
+        well = np.exp(-r2 / (2 * 0.7 ** 2))
+        for m in mons[:n_per_atom]:
+            us.append(d[..., 0] ** m[0] * d[..., 1] ** m[1] * d[..., 2] ** m[2] * env)
+            dvs.append((-1.2 if sum(m) % 2 == 0 else 0.7) * well)
+    return np.array(us), np.array(dvs)
+
+
+@pytest.mark.parametrize("n_per_atom,n_orb", [(6, 3), (16, 2), (16, 17)])
+def test_large_projector_groups_match_oracle(n_per_atom, n_orb):
+    """Groups of up to 16 projectors sharing a box (the register-blocked
+    paths for 8 and 16 projectors per group), FP64 and FP32, up to 34 columns."""
+    from paper_1810_13130_amd import tdfe
+    cfg = W.scaled(W.CONFIGS[2], ncell=(4, 4, 4), p=4, n_orb=n_orb)
+    centers = [(-1.5, 0.5, 0.0), (2.0, -1.0, 1.0)]
+    m, vq = oracle_mesh(cfg)
+    u_o, dv_o = _many_projectors(m.quad_xyz.reshape(m.n_cell, -1, 3), centers, n_per_atom)
+    CE = nl.kb_matrix(m, u_o, dv_o)
+    x = W.random_block(m.n_dof, n_orb, 77)
+    ref = _ref_apply(m, vq, CE, x)
+    assert rel(ref, op.apply_Hbar(m, vq, x)) > 1e-6
+    for prec in (0, 1):
+        ctx = gpu_context(cfg, n_orb=n_orb, k_max=4, precision=prec)
+        xq = ctx.quad_coords().cpu().numpy()
+        u, dv = _many_projectors(xq, centers, n_per_atom)
+        ctx.set_projectors(torch.from_numpy(np.ascontiguousarray(u.reshape(u.shape[0], -1))).cuda(),
+                           torch.from_numpy(np.ascontiguousarray(dv.reshape(dv.shape[0], -1))).cuda())
+        groups, stored, box_dofs, line_dofs = ctx.projector_info()
+        assert groups < u.shape[0]
+        if prec == 0:
+            y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+            assert rel(y, ref) < 1e-12
+        else:
+            xg = torch.from_numpy(x).to(torch.complex64).cuda()
+            y = torch.zeros_like(xg)
+            ctx.apply_H_add_f32(xg, y)
+            assert rel(y.cpu().numpy(), ref) < 2e-6
+        ctx.close()
