@@ -376,6 +376,7 @@ def cpu_oracle_baseline(cfg, ks_total):
     threads = max([i.get("num_threads", 1) for i in info] + [1])
     return {
         "value": 1.0 / step, "unit": "Magnus steps/s", "cores": threads, "kind": "oracle",
+        "apply_H_gdof_orb_per_s": m.n_dof / t_it / 1e9,
         "sample": (f"oracle on this host: 1 Lanczos propagation of 1 orbital ({ks[0]} its, {t_it*1e3:.0f} ms/it), "
                    f"20 Hartree PCG its ({t_cg*1e3:.0f} ms/it), 1 density ({t_rho:.2f} s); step = "
                    f"{ks_total} Krylov its + 2x{pcg_its} PCG its + 2 densities = {step:.1f} s; "
