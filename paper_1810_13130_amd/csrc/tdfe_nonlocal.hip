@@ -399,10 +399,12 @@ __global__ void nl_energy_kernel(const double* eP, int n_proj, int cols, double*
 // y[d][col] += sum over the groups g whose box holds d of
 // sum_q Cbar_g[q][d] tE[p0_g + q][col].  Block b owns segment b; thread t
 // takes the column pair t % CPP (one vector load and store) of DoFs
-// t / CPP + RG u.  Each (DoF, column) belongs to one thread, which adds the
-// crossing groups in their stored order: no atomics, and the result does not
-// depend on scheduling.  Block 0 also writes the energy row (all projections
-// are final by now).
+// t / CPP + RG u.  The C values of the segment and the E t rows of up to
+// GS groups at a time are staged in LDS by the whole block (one global load
+// per value instead of one per column lane), then each (DoF, column) adds
+// the crossing groups in their stored order: no atomics, and the result does
+// not depend on scheduling.  Block 0 also writes the energy row (all
+// projections are final by now).
 template <typename T, typename CT, int CP, int NP>
 __global__ void __launch_bounds__(NL_THREADS)
     nl_add_kernel(T* __restrict__ y, int ld, int cols, const CT* __restrict__ cbar, const NlSeg* __restrict__ segs,
@@ -412,12 +414,15 @@ __global__ void __launch_bounds__(NL_THREADS)
   constexpr int CPP = CP / 2;
   constexpr int RG = NL_THREADS / CPP;
   constexpr int U = NL_SEG / RG;
+  constexpr int GS = 16 / NP > 0 ? 16 / NP : 1;  // groups staged at a time
   static_assert(U >= 1 && U * RG == NL_SEG, "segment length must be a multiple of the DoF lanes");
+  __shared__ double sC[GS][NP][NL_SEG];
+  __shared__ double sT[GS][NP][CP];
   if (done && *done) return;
   const int b = blockIdx.x;
   if (b == 0 && energy_row) nl_energy_row(eP, n_proj, cols, energy_row);
   const int t = threadIdx.x, pr = t % CPP, rg = t / CPP;
-  if (2 * pr >= cols) return;
+  const bool pok = 2 * pr < cols;
   const NlSeg sg = segs[b];
   const int64_t dline = (int64_t)nxi * (sg.J + (int64_t)nyi * sg.K);
   T2 yv[U];
@@ -425,41 +430,39 @@ __global__ void __launch_bounds__(NL_THREADS)
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int I = min(sg.I0 + rg + RG * u, sg.I1);
-    yv[u] = *(const T2*)(y + (dline + I) * ld + 2 * pr);
+    yv[u] = *(const T2*)(y + (dline + I) * ld + 2 * (pok ? pr : 0));
     acc[u][0] = acc[u][1] = 0.0;
   }
-  for (int gi = sg.gs; gi < sg.gs + sg.gn; ++gi) {
-    const NlLineGroup g = lgs[gi];
-    double2 te[NP];
-    CT cr[U][NP];
-    bool in[U];
-#pragma unroll
-    for (int q = 0; q < NP; ++q) {
-      const double2 v = *(const double2*)(tE + (g.p0 + min(q, g.np - 1)) * TDFE_MAX_COLS + 2 * pr);
-      te[q] = q < g.np ? v : make_double2(0.0, 0.0);
+  for (int g0 = sg.gs; g0 < sg.gs + sg.gn; g0 += GS) {
+    const int ng = min(GS, sg.gs + sg.gn - g0);
+    for (int idx = t; idx < ng * NP * NL_SEG; idx += NL_THREADS) {
+      const int gi = idx / (NP * NL_SEG), q = (idx / NL_SEG) % NP, i = idx % NL_SEG;
+      const NlLineGroup g = lgs[g0 + gi];
+      const int I = sg.I0 + i;
+      const bool in = q < g.np && I <= sg.I1 && I >= g.I0 && I <= g.I1;
+      sC[gi][q][i] = in ? (double)cbar[g.cbase + I + (int64_t)q * g.vol] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      const int I = sg.I0 + rg + RG * u;
-      in[u] = I <= sg.I1 && I >= g.I0 && I <= g.I1;
-      const int64_t e = g.cbase + (in[u] ? I : g.I0);
-#pragma unroll
-      for (int q = 0; q < NP; ++q) cr[u][q] = cbar[e + (int64_t)min(q, g.np - 1) * g.vol];
+    for (int idx = t; idx < ng * NP * CP; idx += NL_THREADS) {
+      const int gi = idx / (NP * CP), q = (idx / CP) % NP, c = idx % CP;
+      const NlLineGroup g = lgs[g0 + gi];
+      sT[gi][q][c] = (q < g.np && c < cols) ? tE[(g.p0 + q) * TDFE_MAX_COLS + c] : 0.0;
     }
-#pragma unroll
-    for (int u = 0; u < U; ++u) {
-      double v0 = 0.0, v1 = 0.0;
+    __syncthreads();
+    for (int gi = 0; gi < ng; ++gi) {
 #pragma unroll
       for (int q = 0; q < NP; ++q) {
-        v0 += (double)cr[u][q] * te[q].x;
-        v1 += (double)cr[u][q] * te[q].y;
-      }
-      if (in[u]) {
-        acc[u][0] += v0;
-        acc[u][1] += v1;
+        const double t0 = sT[gi][q][2 * pr], t1 = sT[gi][q][2 * pr + 1];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+          const double cv = sC[gi][q][rg + RG * u];
+          acc[u][0] += cv * t0;
+          acc[u][1] += cv * t1;
+        }
       }
     }
+    __syncthreads();
   }
+  if (!pok) return;
 #pragma unroll
   for (int u = 0; u < U; ++u) {
     const int I = sg.I0 + rg + RG * u;
