@@ -256,6 +256,22 @@ tdfe_status tdfe_set_midpoint(tdfe_ctx* ctx, const tdfe_midpoint_desc* m);
 tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double dt, double field_E,
                              double tol, tdfe_step_report* rep);
 
+/* propagate: n_steps magnus_step steps in one call, the field amplitude of
+ * step n being host_E[n] (NULL: no field).  In the predictor-corrector mode
+ * the steps are enqueued back to back with no synchronisation between them:
+ * each step's Krylov results are folded on the device and its {charge,
+ * mu_x, mu_y, mu_z} written to dev_mu + 4 n (dev_mu: [n_steps][4] FP64
+ * device, or NULL); one readback and one synchronisation at the end.  The
+ * self-consistent midpoint mode runs step by step.  rep (may be NULL)
+ * receives the totals: largest Krylov dimension and the sum over all
+ * propagations (in k_corr_max / k_corr_sum; per-step predictor and corrector
+ * are not separated in the batched mode), largest error estimate, and the
+ * last step's dipole and charge.  TDFE_ENOCONV if any Lanczos run reached
+ * k_max (all steps are still taken); other errors stop the run at the step
+ * that failed.  psibar is updated in place. */
+tdfe_status tdfe_propagate(tdfe_ctx* ctx, void* dev_psibar, int n_orb, int n_steps, double dt, const double* host_E,
+                           double tol, double* dev_mu, tdfe_step_report* rep);
+
 /* Excitations and observables (Sec. on the numerical studies and its table
  * of simulation parameters; Eq. VField).
  *

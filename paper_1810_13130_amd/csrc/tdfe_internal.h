@@ -212,6 +212,9 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
                              double tau, double tol, int* k_out, double* err_out, int* kmax_out,
                              int* ksum_out, double* errmax_out, LanczosHook* hook = nullptr, int defer = -1);
 bool tdfe_lanczos_can_defer(const tdfe_ctx* c);
+// device address of deferred result slot 0/1: k, status, error estimate per
+// orbital ([n_orb_max] each, as doubles) and the table-overflow flag
+double* tdfe_lanczos_result_slot(tdfe_ctx* c, int slot);
 tdfe_status tdfe_lanczos_enqueue_results(tdfe_ctx* c, int slot, const void** host);
 tdfe_status tdfe_lanczos_results(tdfe_ctx* c, const void* host, int n_orb, double tol, int* kmax_out,
                                  int* ksum_out, double* errmax_out);

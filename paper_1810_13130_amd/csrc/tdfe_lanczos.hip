@@ -600,6 +600,8 @@ static double* result_slot(tdfe_ctx* c, int slot) {
   return c->scal + base + (size_t)slot * (3 * c->n_orb_max + 1);
 }
 
+double* tdfe_lanczos_result_slot(tdfe_ctx* c, int slot) { return result_slot(c, slot); }
+
 bool tdfe_lanczos_can_defer(const tdfe_ctx* c) { return (size_t)(3 * c->n_orb_max + 1) * 8 <= 4096; }
 
 tdfe_status tdfe_lanczos_enqueue_results(tdfe_ctx* c, int slot, const void** host) {

@@ -344,6 +344,24 @@ __global__ void assemble_vw_kernel(const double* vext, const double* xq, const d
   if (vw32) vw32[i] = (float)x;
 }
 
+__global__ void copy4_kernel(const double* src, double* dst) {
+  if (threadIdx.x < 4) dst[threadIdx.x] = src[threadIdx.x];
+}
+
+// fold one Lanczos result slot (k, status, error per orbital; overflow flag)
+// into acc = {max k, sum k, max error, not-converged flag, overflow flag}
+__global__ void accum_results_kernel(const double* slot, int n_orb, int nm, double* acc) {
+  if (threadIdx.x != 0) return;
+  for (int o = 0; o < n_orb; ++o) {
+    const double k = slot[o];
+    acc[0] = fmax(acc[0], k);
+    acc[1] += k;
+    acc[2] = fmax(acc[2], slot[2 * nm + o]);
+    if (slot[nm + o] == 2.0) acc[3] = 1.0;
+  }
+  if (slot[3 * nm] != 0.0) acc[4] = 1.0;
+}
+
 // out = ca A + cb B (+ cc C)
 __global__ void combine3_kernel(const double* A, double ca, const double* B, double cb, const double* C, double cc,
                                 double* out, int64_t n) {
@@ -1469,8 +1487,16 @@ tdfe_status tdfe_dipole(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* 
   return TDFE_OK;
 }
 
-tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt, double field_E, double tol,
-                             tdfe_step_report* rep) {
+// batched steps (tdfe_propagate): the step ends without a synchronisation;
+// its Lanczos results are folded into acc on the device and its {charge,
+// mu} (when red_dst is set) copied to red_dst
+struct StepBatch {
+  double* acc;      // [8]: max k, sum k, max error estimate, not-converged flag, table-overflow flag
+  double* red_dst;  // [4] or null
+};
+
+static tdfe_status magnus_step_impl(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt, double field_E, double tol,
+                                    tdfe_step_report* rep, const StepBatch* batch) {
   if (!c || !dev_psibar) return TDFE_EINVAL;
   if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "magnus_step: n_orb out of range");
   if (!(dt > 0.0) || !std::isfinite(dt) || !(tol > 0.0) || !std::isfinite(field_E))
@@ -1500,12 +1526,16 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
     TDFE_HIP(c, hipGetLastError());
     s2 = lanczos(dev_psibar, dev_psibar, dt, 1, &r.k_corr_max, &r.k_corr_sum, &r.err_max);
     if (s2 != TDFE_OK && s2 != TDFE_ENOCONV) return s2;
-    if (rep) {
+    if (rep || (batch && batch->red_dst)) {
       TDFE_TRY(tdfe_density_dev(c, dev_psibar, n_orb, c->rho, c->partial));
       double* red = c->partial + c->n_cell * 4;
       hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
       TDFE_HIP(c, hipGetLastError());
-      TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hred));
+      if (batch && batch->red_dst) {
+        hipLaunchKernelGGL(copy4_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)red, batch->red_dst);
+        TDFE_HIP(c, hipGetLastError());
+      }
+      if (rep) TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hred));
     }
   } else {
     if (!c->scf_init) {
@@ -1540,6 +1570,11 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
       c->w2 = c->w1;
       c->w1 = t;
       TDFE_TRY(tdfe_scf_potential_async(c, dev_psibar, n_orb, c->w1, rep ? &hred : nullptr));
+      if (batch && batch->red_dst) {
+        hipLaunchKernelGGL(copy4_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)(c->partial + c->n_cell * 4),
+                           batch->red_dst);
+        TDFE_HIP(c, hipGetLastError());
+      }
     } else {
       // (i) W_mid extrapolated to t + dt/2; psibar^{n-1} kept in the half-step buffer
       hipLaunchKernelGGL(combine3_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, (const double*)c->w1, l[0],
@@ -1597,6 +1632,17 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
     }
   }
   const bool deferred = defer && !(c->have_scf && c->mid_mode == TDFE_MIDPOINT_SC);
+  if (batch) {
+    // tdfe_propagate batches only deferred predictor-corrector steps
+    if (!deferred) return tdfe_fail(c, TDFE_EINVAL, "magnus batch: step mode cannot defer its results");
+    if (c->have_scf)
+      hipLaunchKernelGGL(accum_results_kernel, dim3(1), dim3(64), 0, c->stream,
+                         (const double*)tdfe_lanczos_result_slot(c, 0), n_orb, c->n_orb_max, batch->acc);
+    hipLaunchKernelGGL(accum_results_kernel, dim3(1), dim3(64), 0, c->stream,
+                       (const double*)tdfe_lanczos_result_slot(c, 1), n_orb, c->n_orb_max, batch->acc);
+    TDFE_HIP(c, hipGetLastError());
+    return TDFE_OK;
+  }
   if (deferred) {
     if (c->have_scf) TDFE_TRY(tdfe_lanczos_enqueue_results(c, 0, &hpred));
     TDFE_TRY(tdfe_lanczos_enqueue_results(c, 1, &hcorr));
@@ -1625,6 +1671,79 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt
     if (!std::isfinite(r.charge)) return tdfe_fail(c, TDFE_ENONFINITE, "magnus_step: non-finite density");
   }
   return st;
+}
+
+tdfe_status tdfe_magnus_step(tdfe_ctx* c, void* dev_psibar, int n_orb, double dt, double field_E, double tol,
+                             tdfe_step_report* rep) {
+  return magnus_step_impl(c, dev_psibar, n_orb, dt, field_E, tol, rep, nullptr);
+}
+
+tdfe_status tdfe_propagate(tdfe_ctx* c, void* dev_psibar, int n_orb, int n_steps, double dt, const double* host_E,
+                           double tol, double* dev_mu, tdfe_step_report* rep) {
+  if (!c || !dev_psibar) return TDFE_EINVAL;
+  if (n_steps < 1) return tdfe_fail(c, TDFE_EINVAL, "propagate: n_steps < 1");
+  if (host_E)
+    for (int n = 0; n < n_steps; ++n)
+      if (!std::isfinite(host_E[n])) return tdfe_fail(c, TDFE_EINVAL, "propagate: non-finite field amplitude");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "propagate before bind_workspace");
+  const bool batched = tdfe_lanczos_can_defer(c) && !(c->have_scf && c->mid_mode == TDFE_MIDPOINT_SC);
+  if (!batched) {
+    // modes that synchronise inside a step: one step at a time, totals on the host
+    tdfe_step_report tot{}, r{};
+    tdfe_status worst = TDFE_OK;
+    for (int n = 0; n < n_steps; ++n) {
+      const tdfe_status s = magnus_step_impl(c, dev_psibar, n_orb, dt, host_E ? host_E[n] : 0.0, tol, &r, nullptr);
+      if (s != TDFE_OK && s != TDFE_ENOCONV) return s;
+      if (s == TDFE_ENOCONV) worst = s;
+      tot.k_pred_max = std::max(tot.k_pred_max, r.k_pred_max);
+      tot.k_corr_max = std::max(tot.k_corr_max, r.k_corr_max);
+      tot.k_pred_sum += r.k_pred_sum;
+      tot.k_corr_sum += r.k_corr_sum;
+      tot.err_max = std::max(tot.err_max, r.err_max);
+      tot.sc_iters += r.sc_iters;
+      tot.sc_change = std::max(tot.sc_change, r.sc_change);
+      if (dev_mu) {
+        const double v[4] = {r.charge, r.mu[0], r.mu[1], r.mu[2]};
+        TDFE_HIP(c, hipMemcpyAsync(dev_mu + 4 * (size_t)n, v, sizeof(v), hipMemcpyHostToDevice, c->stream));
+        TDFE_HIP(c, hipStreamSynchronize(c->stream));
+      }
+    }
+    tot.poisson_iters = r.poisson_iters;
+    tot.charge = r.charge;
+    for (int k = 0; k < 3; ++k) tot.mu[k] = r.mu[k];
+    if (rep) *rep = tot;
+    return worst;
+  }
+  double* acc = c->scbuf + 320;
+  TDFE_TRY(tdfe_zero(c, acc, 8 * sizeof(double)));
+  for (int n = 0; n < n_steps; ++n) {
+    StepBatch b{acc, dev_mu ? dev_mu + 4 * (size_t)n : (n == n_steps - 1 && rep ? acc + 8 : nullptr)};
+    TDFE_TRY(magnus_step_impl(c, dev_psibar, n_orb, dt, host_E ? host_E[n] : 0.0, tol, nullptr, &b));
+  }
+  const void *ha = nullptr, *hm = nullptr;
+  TDFE_TRY(tdfe_readback(c, acc, 8 * sizeof(double), 3584, &ha));
+  if (rep) TDFE_TRY(tdfe_readback(c, dev_mu ? dev_mu + 4 * (size_t)(n_steps - 1) : acc + 8, 4 * sizeof(double), 3712, &hm));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  const volatile double* a = (const volatile double*)ha;
+  if (rep) {
+    tdfe_step_report r{};
+    // the predictor and corrector runs are folded together
+    r.k_corr_max = (int)a[0];
+    r.k_corr_sum = (int)a[1];
+    r.err_max = a[2];
+    r.poisson_iters = c->last_poisson_iters;
+    const volatile double* m = (const volatile double*)hm;
+    r.charge = m[0];
+    r.mu[0] = m[1];
+    r.mu[1] = m[2];
+    r.mu[2] = m[3];
+    *rep = r;
+    if (!std::isfinite(r.charge)) return tdfe_fail(c, TDFE_ENONFINITE, "propagate: non-finite density");
+  }
+  if (a[4] != 0.0) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
+  if (a[3] != 0.0) return tdfe_fail(c, TDFE_ENOCONV, "propagate: a Lanczos run reached k_max=%d without eps <= %g",
+                                    c->k_max, tol);
+  return TDFE_OK;
 }
 
 }  // extern "C"

@@ -102,6 +102,8 @@ SIGNATURES = {
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
     "tdfe_magnus_step": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                          ctypes.POINTER(StepReport)],
+    "tdfe_propagate": [_P, _P, ctypes.c_int, ctypes.c_int, ctypes.c_double, _DP, ctypes.c_double, _P,
+                       ctypes.POINTER(StepReport)],
     "tdfe_gradient_query": [_P, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int,
                             ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_dipole_gradient": [_P, _P, ctypes.c_int, ctypes.c_int, _DP, ctypes.c_double, ctypes.c_double,
@@ -338,6 +340,22 @@ class Context:
         self._check(self.lib.tdfe_magnus_step(self.h, _ptr(psibar), n, dt, field_E, tol,
                                               ctypes.byref(rep) if report else None))
         return rep.as_dict() if report else None
+
+    def propagate(self, psibar, n_steps, dt, E=None, tol=1e-10, record=True):
+        """n_steps Magnus steps in one call; returns (records [n_steps][4] =
+        charge, mu_x, mu_y, mu_z per step as a device tensor or None, totals)."""
+        import torch
+        n = self._orb(psibar)
+        Eh = None
+        if E is not None:
+            Eh = np.ascontiguousarray(np.asarray(E, dtype=np.float64).reshape(-1))
+            assert Eh.size == n_steps
+        mu = torch.empty((n_steps, 4), dtype=torch.float64, device="cuda") if record else None
+        rep = StepReport()
+        self._check(self.lib.tdfe_propagate(self.h, _ptr(psibar), n, n_steps, dt,
+                                            Eh.ctypes.data_as(_DP) if Eh is not None else None, tol,
+                                            _ptr(mu) if mu is not None else None, ctypes.byref(rep)))
+        return mu, rep.as_dict()
 
     def gradient_query(self, n_orb, n_steps, checkpoint_every, k_store):
         b = ctypes.c_size_t()

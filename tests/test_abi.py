@@ -90,6 +90,10 @@ def test_query_sizes_and_call_order(lib):
     assert lib.tdfe_lanczos_expm(h, buf, 1, 0.1, 1e-8, None, None) == tdfe.ESTATE
     assert lib.tdfe_magnus_step(h, buf, 1, -0.1, 0.0, 1e-8, None) == tdfe.EINVAL
     assert lib.tdfe_magnus_step(h, buf, 1, 0.1, 0.0, 1e-8, None) == tdfe.ESTATE
+    assert lib.tdfe_propagate(h, buf, 1, 0, 0.1, None, 1e-8, None, None) == tdfe.EINVAL
+    bad_E = (ctypes.c_double * 2)(0.0, float("nan"))
+    assert lib.tdfe_propagate(h, buf, 1, 2, 0.1, bad_E, 1e-8, None, None) == tdfe.EINVAL
+    assert lib.tdfe_propagate(h, buf, 1, 2, 0.1, None, 1e-8, None, None) == tdfe.ESTATE
     assert b"before" in lib.tdfe_last_error(h)
     nb = ctypes.c_size_t()
     assert lib.tdfe_gradient_query(h, 1, 4, 2, 8, ctypes.byref(nb)) == tdfe.ESTATE
