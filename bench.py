@@ -350,10 +350,13 @@ def cpu_oracle_baseline(cfg, ks_total):
     m = Mesh(cfg.p, cfg.ncell, W.vertices(cfg), cfg.nq)
     vq = W.external_potential(cfg, m.quad_xyz)
     psi = W.initial_psibar(cfg, m.dof_xyz, m.M)
-    # (a) one Lanczos propagation of one orbital: cost per Krylov iteration
+    # (a) Lanczos propagations of two orbitals, one at a time: cost per Krylov iteration
     t = time.perf_counter()
-    _, ks, _ = lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), psi[:, :1], cfg.dt, cfg.tol)
-    t_it = (time.perf_counter() - t) / ks[0]
+    ks = []
+    for o in range(2):
+        _, k_o, _ = lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), psi[:, o:o + 1], cfg.dt, cfg.tol)
+        ks.append(k_o[0])
+    t_it = (time.perf_counter() - t) / sum(ks)
     # (b) 20 iterations of the oracle's Hartree PCG: cost per PCG iteration
     Z, R = W.atoms(cfg)
     h = scf.Hartree(m, Z, R, tol=1e-13, maxit=20)
@@ -377,7 +380,7 @@ def cpu_oracle_baseline(cfg, ks_total):
     return {
         "value": 1.0 / step, "unit": "Magnus steps/s", "cores": threads, "kind": "oracle",
         "apply_H_gdof_orb_per_s": m.n_dof / t_it / 1e9,
-        "sample": (f"oracle on this host: 1 Lanczos propagation of 1 orbital ({ks[0]} its, {t_it*1e3:.0f} ms/it), "
+        "sample": (f"oracle on this host: Lanczos propagations of 2 orbitals ({sum(ks)} its, {t_it*1e3:.0f} ms/it), "
                    f"20 Hartree PCG its ({t_cg*1e3:.0f} ms/it), 1 density ({t_rho:.2f} s); step = "
                    f"{ks_total} Krylov its + 2x{pcg_its} PCG its + 2 densities = {step:.1f} s; "
                    f"sample wall {time.perf_counter()-t0:.1f} s"),
@@ -501,6 +504,17 @@ def main():
     ctx, dt_wall, ks_total, mu64 = run(tdfe.FP64)
     steps_per_s = args.steps / dt_wall
     per_call = per_call_rate(ctx)
+    # the paper's production Krylov tolerance (1e-8) on the same workload, FP64
+    prod = None
+    if cfg.tol != 1e-8:
+        psi_p = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
+                                                  ctx.mass_diag().cpu().numpy())).cuda()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, tot_p = ctx.propagate(psi_p, args.steps, cfg.dt, None, 1e-8, record=False)
+        torch.cuda.synchronize()
+        prod = {"tol": 1e-8, "steps_per_s": args.steps / (time.perf_counter() - t0),
+                "krylov_its_per_step": tot_p["k_corr_sum"] / args.steps}
     t_apply = time_apply(ctx, False)
     roof = roofline(ctx, t_apply, 8, FP64_VECTOR_PEAK_TFLOPS, "pair_kernel<double,6,16,1> (Hbar, 16^3 p=5, 8 orbitals)")
     gdof = ctx.n_dof * n_orb / t_apply / 1e9
@@ -539,6 +553,7 @@ def main():
                    "hartree": "fast diagonalisation (exact)", "xc": cfg.xc},
         "apply_H_gdof_orb_per_s": gdof,
         "per_call_steps_per_s": per_call,
+        "production_tolerance": prod,
         "timed_region": "one tdfe_propagate call of the timed steps (per_call_steps_per_s: one magnus_step call per step)",
         "roofline": roof,
         "mixed": mixed,
