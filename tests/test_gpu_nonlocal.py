@@ -271,3 +271,20 @@ def test_large_projector_groups_match_oracle(n_per_atom, n_orb):
             ctx.apply_H_add_f32(xg, y)
             assert rel(y.cpu().numpy(), ref) < 2e-6
         ctx.close()
+
+
+def test_lanczos_with_projectors_in_one_orbital_chunks(monkeypatch):
+    """Krylov chunks of one orbital (two columns) each: the term's column
+    scale, leading dimension and energy row per chunk."""
+    monkeypatch.setenv("TDFE_MAX_CHUNK_ORB", "1")
+    cfg = CASES["box_plane"](3)
+    ctx = gpu_context(cfg, n_orb=3)
+    _gpu_projectors(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    CE = _oracle_projectors(m, cfg)
+    x = W.random_block(m.n_dof, 3, 19)
+    x /= np.linalg.norm(x, axis=0)
+    g = torch.from_numpy(x).cuda()
+    ctx.lanczos_expm(g, 0.04, 1e-12)
+    z, _, _ = lanczos.lanczos_expm(lambda v: _ref_apply(m, vq, CE, v), x, 0.04, 1e-12)
+    assert rel(g.cpu().numpy(), z) < 1e-10
