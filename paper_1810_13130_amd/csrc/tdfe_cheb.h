@@ -12,6 +12,9 @@
 #define TDFE_CHEB_THREADS 64
 #define TDFE_MAX_BESSEL 6144
 #define TDFE_KCAP 1024
+// per-wavefront Bessel table in global memory for cheb_expm_e1_wave_gtab:
+// the table plus two register chunks of padding for the look-ahead load
+#define TDFE_JTAB_STRIDE (TDFE_MAX_BESSEL + 2 + 2 * TDFE_CHEB_THREADS)
 
 struct ChebLds {
   double J[TDFE_MAX_BESSEL + 2];
@@ -76,10 +79,7 @@ __device__ __forceinline__ double lane_next(double v) {
 // wavefront: the Chebyshev vectors stay in registers and the tridiagonal
 // neighbours come from DPP lane shifts, so a term costs no LDS round trip.
 // Lane j returns row j of y in (yr, yi) (zero for j >= k).  J is an LDS
-// table of TDFE_MAX_BESSEL + 2 entries, Ms / invs LDS scalars.  WAVE_ONLY: the
-// calling wavefront is the only one left in its workgroup, so lane 0's table
-// is published with a wavefront-scope fence instead of a workgroup barrier.
-template <bool WAVE_ONLY = false>
+// table of TDFE_MAX_BESSEL + 2 entries, Ms / invs LDS scalars.
 __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* sb, double s, double* J, int* Ms,
                                         double* invs, double& yr, double& yi, double* amax) {
   const int t = threadIdx.x;
@@ -99,13 +99,7 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
   const double z = fabs(s) * rr;
   if (t == 0) *Ms = cheb_bessel(z, J, invs);
-  if constexpr (WAVE_ONLY) {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  } else {
-    __syncthreads();
-  }
+  __syncthreads();
   const int M = *Ms;
   const double jn = *invs;
   yr = 0.0;
@@ -128,6 +122,83 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
       vp = vc;
       vc = vn;
       const double cj = 2.0 * jn * J[mm];
+      const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
+      if (ph == 0) yr += cj * vn;
+      else if (ph == 1) yi -= sgn * cj * vn;
+      else if (ph == 2) yr -= cj * vn;
+      else yi += sgn * cj * vn;
+    }
+  }
+  const double pr = cos(s * cc), pim = -sin(s * cc);
+  const double a0 = yr, b0 = yi;
+  yr = a0 * pr - b0 * pim;
+  yi = a0 * pim + b0 * pr;
+  return M;
+}
+
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
+// The same series as cheb_expm_e1_wave, with the same arithmetic in the same
+// order, for a wavefront that has no LDS to spare (it runs inside a streaming
+// kernel): the Bessel values go to a global table Jg of TDFE_JTAB_STRIDE
+// doubles owned by the calling wavefront, every lane then holds 64
+// consecutive entries in one register (the next 64 loaded one chunk ahead),
+// and each term takes its coefficient by a lane read.  Called by one full
+// wavefront (lanes 0..63, all active, no other wavefront of the workgroup
+// involved).  a, bl, br: row t of T (diagonal, left and right off-diagonal;
+// zero for rows t >= k).  Returns M, or -1 if |s| r exceeds the table.
+__device__ inline int cheb_expm_e1_wave_gtab(int k, double a, double bl, double br, double s, double* Jg,
+                                             double& yr, double& yi, double* amax) {
+  const int t = threadIdx.x;
+  const bool row = t < k;
+  double lo = row ? a - fabs(bl) - fabs(br) : 1e300;
+  double hi = row ? a + fabs(bl) + fabs(br) : -1e300;
+  double am = row ? fabs(a) : 0.0;
+  for (int off = TDFE_CHEB_THREADS / 2; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    am = fmax(am, __shfl_xor(am, off));
+  }
+  *amax = am;
+  const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
+  const double z = fabs(s) * rr;
+  int m0 = 0;
+  double inv0 = 0.0;
+  if (t == 0) m0 = cheb_bessel(z, Jg, &inv0);
+  // lane 0's table stores complete and are visible to every lane's loads
+  __threadfence();
+  const int M = __builtin_amdgcn_readfirstlane(m0);
+  const double jn = lane_read(inv0, 0);
+  yr = 0.0;
+  yi = 0.0;
+  if (M < 0) return -1;
+  const double sgn = s >= 0.0 ? 1.0 : -1.0;
+  const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
+  const double ac = row ? a - cc : 0.0;
+  double jr = Jg[t];
+  double jnx = Jg[TDFE_CHEB_THREADS + t];
+  double vp = (t == 0) ? 1.0 : 0.0;
+  yr = jn * lane_read(jr, 0) * vp;
+  if (M >= 1) {
+    double left = lane_prev(vp), right = lane_next(vp);
+    double vc = (ac * vp + bl * left + br * right) * invr;
+    yi += -2.0 * sgn * jn * lane_read(jr, 1) * vc;
+    for (int mm = 2; mm <= M; ++mm) {
+      if ((mm & (TDFE_CHEB_THREADS - 1)) == 0) {
+        jr = jnx;
+        jnx = Jg[mm + TDFE_CHEB_THREADS + t];  // < TDFE_JTAB_STRIDE since mm <= M < TDFE_MAX_BESSEL
+      }
+      left = lane_prev(vc);
+      right = lane_next(vc);
+      const double w = ac * vc + bl * left + br * right;
+      const double vn = 2.0 * w * invr - vp;
+      vp = vc;
+      vc = vn;
+      const double cj = 2.0 * jn * lane_read(jr, mm & (TDFE_CHEB_THREADS - 1));
       const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
       if (ph == 0) yr += cj * vn;
       else if (ph == 1) yi -= sgn * cj * vn;

@@ -83,6 +83,7 @@ struct tdfe_ctx {
   void* half = nullptr;       // [n_dof][2 n_orb_max] predictor state (complex128)
   double* partial = nullptr;  // reduction partials
   double* scal = nullptr;     // per-orbital Lanczos scalars
+  double* jtab = nullptr;     // [chunk_orb][TDFE_JTAB_STRIDE] Bessel tables of the small exponential
   unsigned* counters = nullptr;
   int64_t n_partial = 0;
 

@@ -46,6 +46,7 @@ struct Scal {
   double* nrm;    // [Nc]
   double* err;    // [Nc]
   double* y;      // [Nc][k_max][2]
+  double* ext;    // [Nc][2] max |alpha_j| and the term count of the last small exponential
   int* kconv;     // [Nc]
   int* status;    // [Nc] 0 active, 1 converged, 2 not converged at k_max, 3 Chebyshev too long
   int* nconv;     // [1]
@@ -70,6 +71,8 @@ Scal carve_scal(tdfe_ctx* c, int Nc) {
   p += Nc;
   s.y = p;
   p += (size_t)2 * K * Nc;
+  s.ext = p;
+  p += (size_t)2 * Nc;
   int* ip = (int*)c->counters;
   s.kconv = ip;
   s.status = ip + 64;
@@ -116,6 +119,43 @@ __global__ void __launch_bounds__(RED_THREADS)
   if (threadIdx.x < C) partial[(int64_t)blockIdx.x * C + threadIdx.x] = sred[threadIdx.x];
 }
 
+// The small exponential of iteration k (k <= one wavefront) rides on the
+// update kernel of the same iteration: T_k needs alpha_1..alpha_k and
+// beta_1..beta_{k-1}, all known when the update starts, and only the stop
+// test waits for beta_k.  The first nblk blocks of the update grid each take
+// one active orbital: y = exp(-i tau T_k) e_1 into its result slot (kept
+// there when the orbital stops), and max |alpha| and the term count into ext.
+struct SmallExp {
+  Scal S;
+  int Nc;
+  int k;
+  int k_max;
+  int nblk;  // leading blocks that evaluate the small exponential (0: none)
+  double tau;
+  double* jtab;  // [Nc][TDFE_JTAB_STRIDE] Bessel tables
+};
+
+__device__ void small_exp_block(const SmallExp& e) {
+  const int o = blockIdx.x;
+  const int t = threadIdx.x;
+  if (t >= CHK_THREADS || e.S.status[o] != 0) return;
+  const int k = e.k, Nc = e.Nc;
+  const bool row = t < k;
+  const double a = row ? e.S.alpha[(size_t)t * Nc + o] : 0.0;
+  const double bl = (row && t > 0) ? e.S.beta[(size_t)(t - 1) * Nc + o] : 0.0;
+  const double br = (row && t < k - 1) ? e.S.beta[(size_t)t * Nc + o] : 0.0;
+  double yr = 0.0, yi = 0.0, amax = 0.0;
+  const int M = cheb_expm_e1_wave_gtab(k, a, bl, br, e.tau, e.jtab + (size_t)o * TDFE_JTAB_STRIDE, yr, yi, &amax);
+  if (row) {
+    e.S.y[((size_t)o * e.k_max + t) * 2 + 0] = yr;
+    e.S.y[((size_t)o * e.k_max + t) * 2 + 1] = yi;
+  }
+  if (t == 0) {
+    e.S.ext[2 * o + 0] = amax;
+    e.S.ext[2 * o + 1] = (double)M;
+  }
+}
+
 // Three-term step in two reads.  The operator pass of vector j accumulates
 // s_j^2 Hbar w_j (s_0 Hbar w_0 for j = 0) onto a buffer that this kernel
 // seeded with -q_{j-1}, so that on entry Hq = (Hbar q_j - beta_{j-1} q_{j-1}) / m_j
@@ -125,13 +165,18 @@ template <typename T>
 __global__ void __launch_bounds__(RED_THREADS)
     update_kernel(T* __restrict__ hq, const T* __restrict__ wa, T* __restrict__ wn, int C, int64_t nrows,
                   const double* alpha_j, const double* s_j, const double* m_j, const int* status,
-                  double* __restrict__ partial, const int* done) {
+                  double* __restrict__ partial, const int* done, SmallExp se) {
   __shared__ double sred[RED_THREADS];
   if (*done) return;
+  if ((int)blockIdx.x < se.nblk) {
+    small_exp_block(se);
+    return;
+  }
+  const int bid = (int)blockIdx.x - se.nblk;  // streaming block index, 0..RED_BLOCKS-1
   const int Cp = (C <= 1) ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : (C <= 32 ? 32 : 64)))));
   const int col = threadIdx.x % Cp;
   const int rlane = threadIdx.x / Cp;
-  const int rstride = (RED_THREADS / Cp) * gridDim.x;
+  const int rstride = (RED_THREADS / Cp) * (gridDim.x - se.nblk);
   double acc = 0.0;
   if (col < C) {
     const int o = col >> 1;
@@ -139,7 +184,7 @@ __global__ void __launch_bounds__(RED_THREADS)
     const double s = live ? s_j[o] : 0.0;
     const double ca = live ? alpha_j[o] * s : 0.0;
     const double cm = live ? (m_j ? m_j[o] : 1.0) : 0.0;
-    for (int64_t r = (int64_t)blockIdx.x * (RED_THREADS / Cp) + rlane; r < nrows; r += rstride) {
+    for (int64_t r = (int64_t)bid * (RED_THREADS / Cp) + rlane; r < nrows; r += rstride) {
       const int64_t i = r * C + col;
       const double a = (double)wa[i];
       const double v = cm * (double)hq[i] - ca * a;
@@ -151,7 +196,7 @@ __global__ void __launch_bounds__(RED_THREADS)
   }
   block_col_sum(acc, Cp, sred, sred);
   __syncthreads();
-  if (threadIdx.x < C) partial[(int64_t)blockIdx.x * C + threadIdx.x] = sred[threadIdx.x];
+  if (threadIdx.x < C) partial[(int64_t)bid * C + threadIdx.x] = sred[threadIdx.x];
 }
 
 // out[o] = f( sum_b partial[b][2o] + partial[b][2o+1] ), one block per orbital, fixed order.
@@ -194,7 +239,8 @@ __global__ void __launch_bounds__(RED_THREADS)
 __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int M,
                           double amax,
                           double bk, double ylr, double yli, double yr, double yi, const double* Lyr,
-                          const double* Lyi, int nthreads, int* err_flag, int* host_flag, int gen) {
+                          const double* Lyi, int nthreads, int* err_flag, int* host_flag, int gen,
+                          bool y_in_place = false) {
   const int t = threadIdx.x;
   int fin = 0;
   if (M < 0) {
@@ -212,7 +258,7 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
     // mixed precision: no tighter than the storage precision of the basis allows
     const bool conv = (eps <= fmax(tol, tol_rel * S.nrm[o])) || happy;
     const bool stop = conv || k >= k_max;
-    if (stop) {
+    if (stop && !y_in_place) {
       if (Lyr == nullptr) {
         if (t < k) {
           S.y[((size_t)o * k_max + t) * 2 + 0] = yr;
@@ -279,16 +325,12 @@ __global__ void __launch_bounds__(CHK_THREADS)
 
 // beta_k = ||w_k|| from the update partials, the scale 1/beta_k of the next
 // basis vector, and -- for k <= one wavefront -- the stop test of the same
-// orbital in the same launch (the first wavefront; the others leave after the
-// reduction)
+// orbital, on the small exponential the update kernel has left in its result
+// slot and ext
 __global__ void __launch_bounds__(RED_THREADS)
     beta_check_kernel(const double* __restrict__ partial, int64_t nblocks, int C, Scal S, int Nc, int k, int k_max,
                       double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen) {
   __shared__ double sred[RED_THREADS];
-  __shared__ double J[TDFE_MAX_BESSEL + 2];
-  __shared__ double sa[CHK_THREADS], sb[CHK_THREADS];
-  __shared__ int Ms;
-  __shared__ double invs;
   if (*S.done) return;
   const int o = blockIdx.x;
   const int t = threadIdx.x;
@@ -300,26 +342,19 @@ __global__ void __launch_bounds__(RED_THREADS)
     if (t < s) sred[t] += sred[t + s];
     __syncthreads();
   }
+  if (t != 0) return;
   const double bk = sqrt(sred[0]);
-  if (t == 0) {
-    const double sc = bk > 0.0 ? 1.0 / bk : 0.0;
-    S.beta[(size_t)(k - 1) * Nc + o] = bk;
-    S.scale[(size_t)k * Nc + o] = sc;
-    S.cs[(size_t)k * Nc + o] = sc * sc;
-  }
-  if (S.status[o] != 0 || t >= CHK_THREADS) return;
-  if (t < k) {
-    sa[t] = S.alpha[(size_t)t * Nc + o];
-    sb[t] = t < k - 1 ? S.beta[(size_t)t * Nc + o] : bk;
-  }
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-  double amax = 0.0, yr = 0.0, yi = 0.0;
-  const int M = cheb_expm_e1_wave<true>(k, sa, sb, tau, J, &Ms, &invs, yr, yi, &amax);
-  const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
-  stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, bk, ylr, yli, yr, yi, nullptr, nullptr, CHK_THREADS,
-            err_flag, host_flag, gen);
+  const double sc = bk > 0.0 ? 1.0 / bk : 0.0;
+  S.beta[(size_t)(k - 1) * Nc + o] = bk;
+  S.scale[(size_t)k * Nc + o] = sc;
+  S.cs[(size_t)k * Nc + o] = sc * sc;
+  if (S.status[o] != 0) return;
+  const double amax = S.ext[2 * o + 0];
+  const int M = (int)S.ext[2 * o + 1];
+  const double ylr = S.y[((size_t)o * k_max + k - 1) * 2 + 0];
+  const double yli = S.y[((size_t)o * k_max + k - 1) * 2 + 1];
+  stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, bk, ylr, yli, 0.0, 0.0, nullptr, nullptr, 1, err_flag,
+            host_flag, gen, true);
 }
 
 // z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk
@@ -452,10 +487,11 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     const double* m = k >= 2 ? S.beta + (size_t)(k - 2) * Nc : (const double*)nullptr;
     hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial, groups, C,
                        S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (double*)nullptr, m, (const int*)S.done);
-    hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS), dim3(RED_THREADS), 0, c->stream, Hq, (const T*)wk,
-                       W + (int64_t)k * vstride, C, nd, (const double*)(S.alpha + (size_t)(k - 1) * Nc),
+    SmallExp se{S, Nc, k, K, k <= CHK_THREADS ? Nc : 0, tau, c->jtab};
+    hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS + se.nblk), dim3(RED_THREADS), 0, c->stream, Hq,
+                       (const T*)wk, W + (int64_t)k * vstride, C, nd, (const double*)(S.alpha + (size_t)(k - 1) * Nc),
                        (const double*)(S.scale + (size_t)(k - 1) * Nc), m, (const int*)S.status, c->partial,
-                       (const int*)S.done);
+                       (const int*)S.done, se);
     // beta_k, the scale 1/beta_k of the next basis vector and the stop test
     if (k <= CHK_THREADS) {
       hipLaunchKernelGGL(beta_check_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial,
@@ -596,7 +632,7 @@ static int chunk_size(const tdfe_ctx* c, int n_orb) {
 // deferred-result slot `slot` (0 or 1) in the scalar block, past the Lanczos
 // scalars of a full chunk and before the occupations
 static double* result_slot(tdfe_ctx* c, int slot) {
-  const size_t base = (size_t)(6 * c->k_max + 6) * c->n_orb_max;
+  const size_t base = (size_t)(6 * c->k_max + 8) * c->n_orb_max;  // carve_scal takes 6 k_max + 8 per orbital
   return c->scal + base + (size_t)slot * (3 * c->n_orb_max + 1);
 }
 

@@ -12,6 +12,7 @@
 #include <cstdlib>
 #include <cstring>
 
+#include "tdfe_cheb.h"
 #include "tdfe_internal.h"
 #include "tdfe_rule1d.h"
 
@@ -214,6 +215,7 @@ void carve(tdfe_ctx* c, char* base) {
   c->n_partial = (std::max<int64_t>(ne, 4096) + 8) * std::max(cols, 8);
   c->partial = k.take<double>(c->n_partial);
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
+  c->jtab = k.take<double>((size_t)std::max(c->chunk_orb, 1) * TDFE_JTAB_STRIDE);
   c->counters = k.take<unsigned>(256);
   // FP32 copy of M^-1/2 for the mixed path's operator (placed last)
   c->minv32 = c->precision == TDFE_FP64 ? k.take<float>(1) : k.take<float>(nd);
