@@ -72,8 +72,13 @@ def test_density_and_dipole_match_oracle():
     assert np.abs(mu - scf.dipole(m, ref)).max() < 1e-12 * np.abs(mu).max()
 
 
+# the last three: tau |T| large enough that the Chebyshev series of the small
+# exponential runs past one 64-term register chunk (about 70, 100 and 150
+# terms), converging at k = 42 and 63 (the in-update evaluation) and k = 102
+# (the stop-test kernel's own evaluation beyond k = 64)
 @pytest.mark.parametrize("which,n_orb,tau", [("cfg1", 1, 0.05), ("cfg2_small", 3, 0.05), ("cfg2_small", 3, -0.025),
-                                             ("cfg3_small", 2, 0.05)])
+                                             ("cfg3_small", 2, 0.05), ("cfg1", 1, 0.5), ("cfg1", 1, 1.0),
+                                             ("cfg1", 2, -2.0)])
 def test_lanczos_expm_matches_oracle(which, n_orb, tau):
     cfg = {"cfg1": W.CONFIGS[1], "cfg2_small": _cfg2_small(n_orb), "cfg3_small": _cfg3_small(n_orb)}[which]
     ctx = gpu_context(cfg, n_orb=n_orb)
