@@ -280,6 +280,24 @@ def test_magnus_with_field_matches_oracle():
     assert rel(g.cpu().numpy(), st.psibar) < 1e-10
 
 
+def test_full_size_lanczos_samples_match_oracle():
+    """The benchmark mesh (16^3 cells, p = 5) and launch configuration (all 8
+    orbitals in one Krylov chunk, FP64 lane-pair operator, tau = dt): two of
+    the eight propagated orbitals against the oracle's own Lanczos runs."""
+    cfg = W.CONFIGS[2]
+    ctx = gpu_context(cfg)
+    g = gpu_initial_state(ctx, cfg)
+    ks, errs = ctx.lanczos_expm(g, cfg.dt, cfg.tol)
+    m, vq = oracle_mesh(cfg)
+    x = W.initial_psibar(cfg, m.dof_xyz, m.M)
+    cols = [0, 5]
+    z, kref, _ = lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), x[:, cols], cfg.dt, cfg.tol)
+    assert rel(g.cpu().numpy()[:, cols], z) < 1e-10
+    assert all(abs(ks[c] - k) <= 1 for c, k in zip(cols, kref))
+    assert max(errs) <= cfg.tol
+    ctx.close()
+
+
 def test_full_size_step_conserves_norm_and_charge():
     cfg = W.CONFIGS[2]
     ctx = gpu_context(cfg)
