@@ -357,25 +357,59 @@ __global__ void __launch_bounds__(RED_THREADS)
             host_flag, gen, true);
 }
 
-// z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk
+// z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk.
+// One thread per (row, orbital); the coefficients y_j s_j of the block's
+// orbitals are staged in LDS in tiles of COMB_JT iterations (kcap: an upper
+// bound of every orbital's k, the iterations enqueued), and four basis
+// vectors are loaded per round so that several loads are in flight per lane.
+constexpr int COMB_JT = 32;
 template <typename T>
-__global__ void combine_kernel(const T* __restrict__ W, int64_t stride_vec, int C, int64_t nrows, Scal S, int Nc,
-                               int k_max, double* __restrict__ out, int ld_out, int col0) {
+__global__ void __launch_bounds__(256)
+    combine_kernel(const T* __restrict__ W, int64_t stride_vec, int C, int64_t nrows, Scal S, int Nc, int k_max,
+                   int kcap, double* __restrict__ out, int ld_out, int col0) {
+  __shared__ double2 sa[COMB_JT * (TDFE_MAX_COLS / 2)];
   const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int o = (int)(idx % Nc);
   const int64_t r = idx / Nc;
-  if (r >= nrows) return;
-  const int kc = S.kconv[o];
+  const bool live = r < nrows;
+  const int kc = live ? S.kconv[o] : 0;
+  const T* __restrict__ w = W + (live ? r : 0) * C + 2 * o;
   double zr = 0.0, zi = 0.0;
-  for (int j = 0; j < kc; ++j) {
-    const double s = S.scale[(size_t)j * Nc + o];
-    const double ar = S.y[((size_t)o * k_max + j) * 2 + 0] * s;
-    const double ai = S.y[((size_t)o * k_max + j) * 2 + 1] * s;
-    const T* w = W + j * stride_vec + r * C + 2 * o;
-    const double qr = (double)w[0], qi = (double)w[1];
-    zr += ar * qr - ai * qi;
-    zi += ar * qi + ai * qr;
+  for (int j0 = 0; j0 < kcap; j0 += COMB_JT) {
+    const int jt = min(COMB_JT, kcap - j0);
+    __syncthreads();
+    for (int i = threadIdx.x; i < jt * Nc; i += blockDim.x) {
+      const int jj = j0 + i / Nc, oo = i % Nc;
+      const double sc = S.scale[(size_t)jj * Nc + oo];
+      sa[i] = make_double2(S.y[((size_t)oo * k_max + jj) * 2 + 0] * sc, S.y[((size_t)oo * k_max + jj) * 2 + 1] * sc);
+    }
+    __syncthreads();
+    const int je = min(kc - j0, jt);  // this orbital's iterations in the tile (none if <= 0)
+    int jj = 0;
+    for (; jj + 4 <= je; jj += 4) {
+      double qr[4], qi[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const T* q = w + (int64_t)(j0 + jj + u) * stride_vec;
+        qr[u] = (double)q[0];
+        qi[u] = (double)q[1];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double2 a = sa[(jj + u) * Nc + o];
+        zr += a.x * qr[u] - a.y * qi[u];
+        zi += a.x * qi[u] + a.y * qr[u];
+      }
+    }
+    for (; jj < je; ++jj) {
+      const T* q = w + (int64_t)(j0 + jj) * stride_vec;
+      const double qr = (double)q[0], qi = (double)q[1];
+      const double2 a = sa[jj * Nc + o];
+      zr += a.x * qr - a.y * qi;
+      zi += a.x * qi + a.y * qr;
+    }
   }
+  if (!live) return;
   const double nr = S.nrm[o];
   out[r * ld_out + col0 + 2 * o] = nr * zr;
   out[r * ld_out + col0 + 2 * o + 1] = nr * zi;
@@ -517,7 +551,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   {
     const int64_t n = nd * Nc;
     hipLaunchKernelGGL((combine_kernel<T>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, (const T*)W,
-                       vstride, C, nd, S, Nc, K, out, ld, 2 * o0);
+                       vstride, C, nd, S, Nc, K, std::min(k_enq, K), out, ld, 2 * o0);
     TDFE_HIP(c, hipGetLastError());
   }
   if (defer_slot) {
