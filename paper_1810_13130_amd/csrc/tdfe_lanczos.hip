@@ -23,6 +23,9 @@
 //    (Jacobi-Anger coefficients 2 (-i)^m J_m(tau r), Bessel values by
 //    Miller's backward recurrence), one wavefront per orbital, rows across
 //    lanes.  It gives the same y as an eigendecomposition of T_k to ~1e-15.
+//    For k <= 64 it runs in leading blocks of the same iteration's update
+//    kernel (T_k is complete once alpha_k is known), so the stop test after
+//    the update is only a reduction and a comparison;
 //  * the host enqueues iterations ahead and polls a device "all converged"
 //    flag two iterations behind; iterations enqueued past convergence exit
 //    at their first instruction.
