@@ -190,17 +190,26 @@ __global__ void finalize4_kernel(const double* partial, int64_t nblocks, double*
 }
 
 // ------------------------------------------------------------------------------------------------
-// load vector c_j = sum_e sum_q varpi_q detJ_q rho_q N_j(x_q), all nodes (full grid)
+// load vector c_j = sum_e sum_q varpi_q detJ_q rho_q N_j(x_q), all nodes (full grid).
+// LOAD_CPB(N) cells per block, N^2 threads per cell (one 1D line of the cell
+// per thread and pass), so that the block fills whole wavefronts.
 // ------------------------------------------------------------------------------------------------
+constexpr int load_cpb(int N) { return (N * N * N * 16 <= 4096) ? 16 : 8; }
+
 template <int N>
-__global__ void __launch_bounds__(N* N) load_kernel(const double* rho, const double* wdet, const double* tab,
-                                                     double* cload, int ncx, int ncy, int p, int Nx, int Ny, int weighted) {
+__global__ void __launch_bounds__(load_cpb(N) * N * N)
+    load_kernel(const double* rho, const double* wdet, const double* tab, double* cload, int64_t n_cell, int ncx,
+                int ncy, int p, int Nx, int Ny, int weighted) {
   constexpr int VOL = N * N * N;
-  __shared__ double sU[VOL];
+  constexpr int CPB = load_cpb(N);
+  __shared__ double sU[CPB * VOL];
   __shared__ double sB[N * N];
-  const int t = threadIdx.x;
-  const int64_t cell = blockIdx.x;
-  if (t < N * N) sB[t] = tab[TAB_B + (t / N) * TDFE_MAXN + (t % N)];
+  const int slot = threadIdx.x / (N * N);
+  const int t = threadIdx.x % (N * N);
+  const int64_t cell = (int64_t)blockIdx.x * CPB + slot;
+  const bool ok = cell < n_cell;
+  double* U = sU + slot * VOL;
+  if (threadIdx.x < N * N) sB[threadIdx.x] = tab[TAB_B + (threadIdx.x / N) * TDFE_MAXN + (threadIdx.x % N)];
   __syncthreads();
   const int cx = (int)(cell % ncx), cy = (int)((cell / ncx) % ncy), cz = (int)(cell / ((int64_t)ncx * ncy));
   double r1[N];
@@ -208,40 +217,43 @@ __global__ void __launch_bounds__(N* N) load_kernel(const double* rho, const dou
     const int a = t % N, b = t / N;
 #pragma unroll
     for (int c = 0; c < N; ++c) {
-      const int64_t g = cell * VOL + a + N * (b + N * c);
-      r1[c] = weighted ? wdet[g] * rho[g] : rho[g];
+      const int64_t g = (ok ? cell : 0) * VOL + a + N * (b + N * c);
+      r1[c] = ok ? (weighted ? wdet[g] * rho[g] : rho[g]) : 0.0;
     }
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       double s = 0;
 #pragma unroll
-      for (int c = 0; c < N; ++c) s += tab[TAB_B + c * TDFE_MAXN + k] * r1[c];
-      sU[(k * N + b) * N + a] = s;
+      for (int c = 0; c < N; ++c) s += sB[c * N + k] * r1[c];
+      U[(k * N + b) * N + a] = s;
     }
   }
   __syncthreads();
   {
     const int a = t % N, k = t / N;
 #pragma unroll
-    for (int b = 0; b < N; ++b) r1[b] = sU[(k * N + b) * N + a];
+    for (int b = 0; b < N; ++b) r1[b] = U[(k * N + b) * N + a];
 #pragma unroll
     for (int j = 0; j < N; ++j) {
       double s = 0;
 #pragma unroll
       for (int b = 0; b < N; ++b) s += sB[b * N + j] * r1[b];
-      sU[(k * N + j) * N + a] = s;
+      U[(k * N + j) * N + a] = s;
     }
   }
   __syncthreads();
+  if (!ok) return;
   {
-    const int j = t % N, k = t / N;
+    // last pass with x across lanes: each atomic instruction touches N
+    // consecutive nodes per z line instead of one node per lane
+    const int i = t % N, k = t / N;
 #pragma unroll
-    for (int a = 0; a < N; ++a) r1[a] = sU[(k * N + j) * N + a];
+    for (int a = 0; a < N; ++a) r1[a] = sB[a * N + i];
 #pragma unroll
-    for (int i = 0; i < N; ++i) {
+    for (int j = 0; j < N; ++j) {
       double s = 0;
 #pragma unroll
-      for (int a = 0; a < N; ++a) s += sB[a * N + i] * r1[a];
+      for (int a = 0; a < N; ++a) s += r1[a] * U[(k * N + j) * N + a];
       const int64_t node = (int64_t)(cx * p + i) + (int64_t)Nx * ((int64_t)(cy * p + j) + (int64_t)Ny * (cz * p + k));
       unsafeAtomicAdd(cload + node, s);
     }
@@ -857,8 +869,10 @@ tdfe_status launch_density_n(tdfe_ctx* c, DensParams& P) {
 template <int N>
 tdfe_status launch_load_interp(tdfe_ctx* c, int which, const double* in, const double* rho, int flag, double* out) {
   if (which == 0) {
-    hipLaunchKernelGGL((load_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, in, c->wdet, c->tab,
-                       out, c->ncx, c->ncy, c->p, c->Nx, c->Ny, flag);
+    constexpr int CPB = load_cpb(N);
+    hipLaunchKernelGGL((load_kernel<N>), dim3((unsigned)((c->n_cell + CPB - 1) / CPB)), dim3(CPB * N * N), 0,
+                       c->stream, in, c->wdet, c->tab, out, (int64_t)c->n_cell, c->ncx, c->ncy, c->p, c->Nx, c->Ny,
+                       flag);
   } else {
     hipLaunchKernelGGL((interp_xc_kernel<N>), dim3((unsigned)c->n_cell), dim3(N * N), 0, c->stream, in, rho,
                        c->tab, out, in != nullptr ? 1 : 0, flag, c->ncx, c->ncy, c->p, c->Nx, c->Ny);
