@@ -26,9 +26,12 @@
 //    For k <= 64 it runs in leading blocks of the same iteration's update
 //    kernel (T_k is complete once alpha_k is known), so the stop test after
 //    the update is only a reduction and a comparison;
-//  * the host enqueues iterations ahead and polls a device "all converged"
-//    flag two iterations behind; iterations enqueued past convergence exit
-//    at their first instruction.
+//  * the host enqueues iterations ahead, paced by a progress word the stop
+//    test stores into pinned memory (no event per iteration: its queue
+//    marker would drain the device before every operator launch), and stops
+//    at a device "all converged" flag; iterations enqueued past convergence
+//    exit at their first instruction.
+#include <chrono>
 #include <cmath>
 
 #include "tdfe_cheb.h"
@@ -299,14 +302,26 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
   }
 }
 
+// progress of the recurrence for the host's look-ahead: (generation, k) in
+// one pinned word, stored without ordering (the host only uses it to pace
+// its launches; results travel through the done flag and the readbacks)
+constexpr int PROGRESS_KBITS = 11;  // k <= 1024
+__device__ __forceinline__ void post_progress(unsigned* progress, int gen, int k) {
+  if (progress)
+    __hip_atomic_store(progress, ((unsigned)gen << PROGRESS_KBITS) | (unsigned)k, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 __global__ void __launch_bounds__(CHK_THREADS)
     check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int* err_flag,
-                 int* host_flag, int gen) {
+                 int* host_flag, int gen, unsigned* progress) {
   __shared__ ChebLds L;
   __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
   const int o = blockIdx.x;
   const int t = threadIdx.x;
-  if (*S.done || S.status[o] != 0) return;
+  if (*S.done) return;
+  if (o == 0 && t == 0) post_progress(progress, gen, k);
+  if (S.status[o] != 0) return;
   for (int j = t; j < k; j += CHK_THREADS) {
     sa[j] = S.alpha[(size_t)j * Nc + o];
     sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
@@ -332,7 +347,8 @@ __global__ void __launch_bounds__(CHK_THREADS)
 // slot and ext
 __global__ void __launch_bounds__(RED_THREADS)
     beta_check_kernel(const double* __restrict__ partial, int64_t nblocks, int C, Scal S, int Nc, int k, int k_max,
-                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen) {
+                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen,
+                      unsigned* progress) {
   __shared__ double sred[RED_THREADS];
   if (*S.done) return;
   const int o = blockIdx.x;
@@ -351,6 +367,7 @@ __global__ void __launch_bounds__(RED_THREADS)
   S.beta[(size_t)(k - 1) * Nc + o] = bk;
   S.scale[(size_t)k * Nc + o] = sc;
   S.cs[(size_t)k * Nc + o] = sc * sc;
+  if (o == 0) post_progress(progress, gen, k);
   if (S.status[o] != 0) return;
   const double amax = S.ext[2 * o + 0];
   const int M = (int)S.ext[2 * o + 1];
@@ -494,10 +511,16 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   TDFE_HIP(c, hipHostGetDevicePointer((void**)&dflag, (void*)(c->poll + 32), 0));
   hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc, dflag, gen);
   TDFE_HIP(c, hipGetLastError());
+  // the recurrence's progress word (pinned): read by the host to stay LOOK
+  // iterations ahead of the device.  An event recorded per iteration would do
+  // the same but drains the queue before the next operator launch (about
+  // 5 us per iteration on this device).
+  volatile unsigned* hprog = (volatile unsigned*)(c->poll + 34);
+  unsigned* dprog = nullptr;
+  TDFE_HIP(c, hipHostGetDevicePointer((void**)&dprog, (void*)(c->poll + 34), 0));
+  const unsigned gtag = (unsigned)gen & ((1u << (32 - PROGRESS_KBITS)) - 1u);
 
   const int LOOK = 2;
-  const int RING = 8;
-  TDFE_TRY(tdfe_poll_events(c));
   int k_enq = 0;
   for (int k = 1; k <= K; ++k) {
     k_enq = k;
@@ -532,19 +555,38 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     // beta_k, the scale 1/beta_k of the next basis vector and the stop test
     if (k <= CHK_THREADS) {
       hipLaunchKernelGGL(beta_check_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial,
-                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag, gen);
+                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag, gen, dprog);
     } else {
       hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
                          (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 3, S.scale + (size_t)k * Nc,
                          S.cs + (size_t)k * Nc, (const double*)nullptr, (const int*)S.done);
       hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
-                         err_flag, dflag, gen);
+                         err_flag, dflag, gen, dprog);
     }
     TDFE_HIP(c, hipGetLastError());
-    TDFE_HIP(c, hipEventRecord(c->evs[k % RING], c->stream));
     if (k > LOOK) {
-      const int kk = k - LOOK;
-      TDFE_HIP(c, hipEventSynchronize(c->evs[kk % RING]));
+      // wait until iteration k - LOOK has passed its stop test or the set is
+      // done.  The progress word only paces the launches: after every 2 ms
+      // without it the stream is queried (a query puts a marker into the
+      // queue, which costs the device a drain, so it is kept off the normal
+      // path), and if the stream has drained the loop goes on
+      const unsigned want = (unsigned)(k - LOOK);
+      auto t_last = std::chrono::steady_clock::now();
+      for (int spin = 1;; ++spin) {
+        if (*hflag == gen) break;
+        const unsigned v = *hprog;
+        if ((v >> PROGRESS_KBITS) == gtag && (v & ((1u << PROGRESS_KBITS) - 1u)) >= want) break;
+        if ((spin & 255) == 0) {
+          const auto now = std::chrono::steady_clock::now();
+          if (now - t_last > std::chrono::milliseconds(2)) {
+            const hipError_t q = hipStreamQuery(c->stream);
+            if (q == hipSuccess) break;
+            if (q != hipErrorNotReady) return tdfe_fail(c, TDFE_EDEVICE, "Lanczos: %s", hipGetErrorString(q));
+            t_last = now;
+          }
+        }
+        __builtin_ia32_pause();
+      }
       if (*hflag == gen) break;
     }
   }
