@@ -719,6 +719,9 @@ void jacobi_eigen(std::vector<double> A, int n, std::vector<double>& lam, std::v
           U[(size_t)k * n + p] = cs * ukp - sn * ukq;
           U[(size_t)k * n + q] = sn * ukp + cs * ukq;
         }
+        // the rotation annihilates a_pq: store the zero rather than the
+        // rounding residue, or the off-diagonal sum never meets the stop test
+        A[(size_t)p * n + q] = A[(size_t)q * n + p] = 0.0;
       }
   }
   lam.resize(n);
