@@ -4,8 +4,9 @@
 // coefficients 2 (-i sgn(s))^m J_m(|s| r), Bessel values by Miller's backward
 // recurrence normalised with J_0 + 2 sum J_2m = 1, and the three-term
 // recurrence v_{m+1} = 2 X v_m - v_{m-1}, X = (T - c)/r, v_0 = e_1, rows across
-// lanes.  cheb_expm_e1 and the default cheb_expm_e1_wave use workgroup
-// barriers, so every thread of the workgroup calls them.
+// lanes.  cheb_expm_e1 and cheb_expm_e1_wave use workgroup barriers, so every
+// thread of the workgroup calls them; cheb_expm_e1_wave_gtab involves one
+// wavefront only.
 #pragma once
 #include <hip/hip_runtime.h>
 
