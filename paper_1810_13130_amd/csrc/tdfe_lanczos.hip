@@ -26,8 +26,8 @@
 //    For k <= 64 it runs in leading blocks of the same iteration's update
 //    kernel (T_k is complete once alpha_k is known), so the stop test after
 //    the update is only a reduction and a comparison;
-//  * the host enqueues iterations ahead, paced by a progress word the stop
-//    test stores into pinned memory (no event per iteration: its queue
+//  * the host enqueues iterations ahead, paced by a progress word the update
+//    kernels store into pinned memory (no event per iteration: its queue
 //    marker would drain the device before every operator launch), and stops
 //    at a device "all converged" flag; iterations enqueued past convergence
 //    exit at their first instruction.
@@ -125,6 +125,20 @@ __global__ void __launch_bounds__(RED_THREADS)
   if (threadIdx.x < C) partial[(int64_t)blockIdx.x * C + threadIdx.x] = sred[threadIdx.x];
 }
 
+// progress of the recurrence for the host's look-ahead: (generation, k) in
+// one pinned word, stored without ordering (the host only uses it to pace
+// its launches; results travel through the done flag and the readbacks).
+// The update kernel of iteration k posts k - 1 when it starts, that is once
+// iteration k - 1 has passed its stop test without finishing the set: after
+// the set is done nothing is posted, and the host, waiting for a word that
+// does not come, is already polling the done flag when it is raised.
+constexpr int PROGRESS_KBITS = 11;  // k <= 1024
+__device__ __forceinline__ void post_progress(unsigned* progress, int gen, int k) {
+  if (progress)
+    __hip_atomic_store(progress, ((unsigned)gen << PROGRESS_KBITS) | (unsigned)k, __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+}
+
 // The small exponential of iteration k (k <= one wavefront) rides on the
 // update kernel of the same iteration: T_k needs alpha_1..alpha_k and
 // beta_1..beta_{k-1}, all known when the update starts, and only the stop
@@ -139,6 +153,8 @@ struct SmallExp {
   int nblk;  // leading blocks that evaluate the small exponential (0: none)
   double tau;
   double* jtab;  // [Nc][TDFE_JTAB_STRIDE] Bessel tables
+  unsigned* progress;  // pinned progress word (may be null)
+  int gen;
 };
 
 __device__ void small_exp_block(const SmallExp& e) {
@@ -174,6 +190,7 @@ __global__ void __launch_bounds__(RED_THREADS)
                   double* __restrict__ partial, const int* done, SmallExp se) {
   __shared__ double sred[RED_THREADS];
   if (*done) return;
+  if (blockIdx.x == 0 && threadIdx.x == 0) post_progress(se.progress, se.gen, se.k - 1);
   if ((int)blockIdx.x < se.nblk) {
     small_exp_block(se);
     return;
@@ -302,26 +319,14 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
   }
 }
 
-// progress of the recurrence for the host's look-ahead: (generation, k) in
-// one pinned word, stored without ordering (the host only uses it to pace
-// its launches; results travel through the done flag and the readbacks)
-constexpr int PROGRESS_KBITS = 11;  // k <= 1024
-__device__ __forceinline__ void post_progress(unsigned* progress, int gen, int k) {
-  if (progress)
-    __hip_atomic_store(progress, ((unsigned)gen << PROGRESS_KBITS) | (unsigned)k, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_SYSTEM);
-}
-
 __global__ void __launch_bounds__(CHK_THREADS)
     check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int* err_flag,
-                 int* host_flag, int gen, unsigned* progress) {
+                 int* host_flag, int gen) {
   __shared__ ChebLds L;
   __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
   const int o = blockIdx.x;
   const int t = threadIdx.x;
-  if (*S.done) return;
-  if (o == 0 && t == 0) post_progress(progress, gen, k);
-  if (S.status[o] != 0) return;
+  if (*S.done || S.status[o] != 0) return;
   for (int j = t; j < k; j += CHK_THREADS) {
     sa[j] = S.alpha[(size_t)j * Nc + o];
     sb[j] = S.beta[(size_t)j * Nc + o];  // sb[k-1] = beta_k (not part of T_k)
@@ -347,8 +352,7 @@ __global__ void __launch_bounds__(CHK_THREADS)
 // slot and ext
 __global__ void __launch_bounds__(RED_THREADS)
     beta_check_kernel(const double* __restrict__ partial, int64_t nblocks, int C, Scal S, int Nc, int k, int k_max,
-                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen,
-                      unsigned* progress) {
+                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen) {
   __shared__ double sred[RED_THREADS];
   if (*S.done) return;
   const int o = blockIdx.x;
@@ -367,7 +371,6 @@ __global__ void __launch_bounds__(RED_THREADS)
   S.beta[(size_t)(k - 1) * Nc + o] = bk;
   S.scale[(size_t)k * Nc + o] = sc;
   S.cs[(size_t)k * Nc + o] = sc * sc;
-  if (o == 0) post_progress(progress, gen, k);
   if (S.status[o] != 0) return;
   const double amax = S.ext[2 * o + 0];
   const int M = (int)S.ext[2 * o + 1];
@@ -511,8 +514,8 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   TDFE_HIP(c, hipHostGetDevicePointer((void**)&dflag, (void*)(c->poll + 32), 0));
   hipLaunchKernelGGL(zero_norm_kernel, dim3(1), dim3(64), 0, c->stream, S, Nc, dflag, gen);
   TDFE_HIP(c, hipGetLastError());
-  // the recurrence's progress word (pinned): read by the host to stay LOOK
-  // iterations ahead of the device.  An event recorded per iteration would do
+  // the recurrence's progress word (pinned, posted by the update kernels):
+  // read by the host to stay LOOK iterations ahead of the device.  An event recorded per iteration would do
   // the same but drains the queue before the next operator launch (about
   // 5 us per iteration on this device).
   volatile unsigned* hprog = (volatile unsigned*)(c->poll + 34);
@@ -547,7 +550,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     const double* m = k >= 2 ? S.beta + (size_t)(k - 2) * Nc : (const double*)nullptr;
     hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial, groups, C,
                        S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (double*)nullptr, m, (const int*)S.done);
-    SmallExp se{S, Nc, k, K, k <= CHK_THREADS ? Nc : 0, tau, c->jtab};
+    SmallExp se{S, Nc, k, K, k <= CHK_THREADS ? Nc : 0, tau, c->jtab, dprog, gen};
     hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS + se.nblk), dim3(RED_THREADS), 0, c->stream, Hq,
                        (const T*)wk, W + (int64_t)k * vstride, C, nd, (const double*)(S.alpha + (size_t)(k - 1) * Nc),
                        (const double*)(S.scale + (size_t)(k - 1) * Nc), m, (const int*)S.status, c->partial,
@@ -555,21 +558,22 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     // beta_k, the scale 1/beta_k of the next basis vector and the stop test
     if (k <= CHK_THREADS) {
       hipLaunchKernelGGL(beta_check_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial,
-                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag, gen, dprog);
+                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag, gen);
     } else {
       hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
                          (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 3, S.scale + (size_t)k * Nc,
                          S.cs + (size_t)k * Nc, (const double*)nullptr, (const int*)S.done);
       hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
-                         err_flag, dflag, gen, dprog);
+                         err_flag, dflag, gen);
     }
     TDFE_HIP(c, hipGetLastError());
     if (k > LOOK) {
-      // wait until iteration k - LOOK has passed its stop test or the set is
-      // done.  The progress word only paces the launches: after every 2 ms
-      // without it the stream is queried (a query puts a marker into the
-      // queue, which costs the device a drain, so it is kept off the normal
-      // path), and if the stream has drained the loop goes on
+      // wait until iteration k - LOOK has passed its stop test (posted when
+      // the next update starts) or the set is done.  The progress word only
+      // paces the launches: after every 2 ms without it the stream is queried
+      // (a query puts a marker into the queue, which costs the device a
+      // drain, so it is kept off the normal path), and if the stream has
+      // drained the loop goes on
       const unsigned want = (unsigned)(k - LOOK);
       auto t_last = std::chrono::steady_clock::now();
       for (int spin = 1;; ++spin) {
