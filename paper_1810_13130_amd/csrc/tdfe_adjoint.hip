@@ -33,6 +33,7 @@
 // recomputed once and its steps are reversed from its stored states.
 #include <algorithm>
 #include <cmath>
+#include <thread>
 #include <vector>
 
 #include "tdfe_internal.h"
@@ -412,9 +413,11 @@ void small_matrix(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, 
     }
     tdfe_sym_eigen(T, k, th, U);
   };
-  for (int o = 0; o < Nc; ++o) {
+  // orbitals are independent (disjoint output blocks): spread them over a
+  // few host threads, the device waits for this step
+  auto one = [&](int o) {
     const int kx = X.k[o], kz = Z.k[o];
-    if (kx == 0 || kz == 0 || !(X.nrm[o] > 0.0) || !(Z.nrm[o] > 0.0)) continue;
+    if (kx == 0 || kz == 0 || !(X.nrm[o] > 0.0) || !(Z.nrm[o] > 0.0)) return;
     kk[o] = kz;
     kk[Nc + o] = kx;
     std::vector<double> thx, Ux, thz, Uz;
@@ -454,7 +457,19 @@ void small_matrix(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, 
         Co[((size_t)j * ks + l) * 2 + 0] = nn * sr;
         Co[((size_t)j * ks + l) * 2 + 1] = nn * si;
       }
+  };
+  const int nt = std::max(1, std::min({Nc, 8, (int)std::thread::hardware_concurrency()}));
+  if (nt == 1) {
+    for (int o = 0; o < Nc; ++o) one(o);
+    return;
   }
+  std::vector<std::thread> pool;
+  for (int w = 1; w < nt; ++w)
+    pool.emplace_back([&, w] {
+      for (int o = w; o < Nc; o += nt) one(o);
+    });
+  for (int o = 0; o < Nc; o += nt) one(o);
+  for (auto& th : pool) th.join();
 }
 
 struct Grad {
