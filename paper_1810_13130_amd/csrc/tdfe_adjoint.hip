@@ -33,6 +33,7 @@
 // recomputed once and its steps are reversed from its stored states.
 #include <algorithm>
 #include <cmath>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -464,11 +465,18 @@ void small_matrix(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, 
     return;
   }
   std::vector<std::thread> pool;
-  for (int w = 1; w < nt; ++w)
-    pool.emplace_back([&, w] {
-      for (int o = w; o < Nc; o += nt) one(o);
-    });
+  int started = 1;  // workers 1..started-1 run; the caller takes the rest
+  try {
+    for (int w = 1; w < nt; ++w, ++started)
+      pool.emplace_back([&, w] {
+        for (int o = w; o < Nc; o += nt) one(o);
+      });
+  } catch (const std::system_error&) {
+    // no more threads available: the orbitals of unstarted workers run here
+  }
   for (int o = 0; o < Nc; o += nt) one(o);
+  for (int w = started; w < nt; ++w)
+    for (int o = w; o < Nc; o += nt) one(o);
   for (auto& th : pool) th.join();
 }
 
