@@ -173,20 +173,20 @@ __global__ void __launch_bounds__(N* N* CB) density_kernel(DensParams P) {
 }
 
 // sum of [nblocks][4] partials in a fixed order
+// (one block per value, launched with 4 blocks; the same order as a serial
+// pass over the four values)
 __global__ void finalize4_kernel(const double* partial, int64_t nblocks, double* out) {
   __shared__ double sred[256];
-  for (int v = 0; v < 4; ++v) {
-    double acc = 0.0;
-    for (int64_t b = threadIdx.x; b < nblocks; b += 256) acc += partial[b * 4 + v];
-    sred[threadIdx.x] = acc;
-    __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
-      if (threadIdx.x < s) sred[threadIdx.x] += sred[threadIdx.x + s];
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) out[v] = sred[0];
+  const int v = blockIdx.x;
+  double acc = 0.0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += 256) acc += partial[b * 4 + v];
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < s) sred[threadIdx.x] += sred[threadIdx.x + s];
     __syncthreads();
   }
+  if (threadIdx.x == 0) out[v] = sred[0];
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -1324,7 +1324,7 @@ tdfe_status tdfe_scf_potential(tdfe_ctx* c, const void* psibar, int n_orb, doubl
 tdfe_status tdfe_scf_potential_async(tdfe_ctx* c, const void* psibar, int n_orb, double* W, const void** host_red) {
   TDFE_TRY(tdfe_density_dev(c, psibar, n_orb, c->rho, c->partial));
   double* red = c->partial + c->n_cell * 4;
-  hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
+  hipLaunchKernelGGL(finalize4_kernel, dim3(4), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
   TDFE_HIP(c, hipGetLastError());
   if (c->hartree) {
     TDFE_TRY(tdfe_zero(c, c->cload, c->n_nodes * sizeof(double)));
@@ -1489,7 +1489,7 @@ tdfe_status tdfe_dipole(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* 
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "dipole before bind_workspace");
   TDFE_TRY(tdfe_density_dev(c, dev_psibar, n_orb, c->rho, c->partial));
   double* red = c->partial + c->n_cell * 4;
-  hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
+  hipLaunchKernelGGL(finalize4_kernel, dim3(4), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
   TDFE_HIP(c, hipGetLastError());
   const void* hr = nullptr;
   TDFE_TRY(tdfe_readback(c, red, 4 * sizeof(double), 2304, &hr));
@@ -1546,7 +1546,7 @@ static tdfe_status magnus_step_impl(tdfe_ctx* c, void* dev_psibar, int n_orb, do
     if (rep || (batch && batch->red_dst)) {
       TDFE_TRY(tdfe_density_dev(c, dev_psibar, n_orb, c->rho, c->partial));
       double* red = c->partial + c->n_cell * 4;
-      hipLaunchKernelGGL(finalize4_kernel, dim3(1), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
+      hipLaunchKernelGGL(finalize4_kernel, dim3(4), dim3(256), 0, c->stream, c->partial, c->n_cell, red);
       TDFE_HIP(c, hipGetLastError());
       if (batch && batch->red_dst) {
         hipLaunchKernelGGL(copy4_kernel, dim3(1), dim3(64), 0, c->stream, (const double*)red, batch->red_dst);
