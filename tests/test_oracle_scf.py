@@ -90,7 +90,52 @@ def test_xc_potential_is_derivative_of_energy(rs):
 def test_pz81_branches_join_at_rs_1():
     lo = scf.pz_eps_c(np.array([1.0 - 1e-12]))[0]
     hi = scf.pz_eps_c(np.array([1.0]))[0]
-    assert abs(lo - hi) < 1e-4
+    # the parametrisation joins its two branches at r_s = 1 (printed constants:
+    # a gap of 3.2e-5 Ha); a digit changed in B, D, gamma, beta_1 or beta_2 moves
+    # one branch by more than 1e-3
+    assert abs(lo - hi) < 5e-5
     assert -0.07 < hi < -0.05
     # correlation vanishes in the zero-density limit
     assert scf.correlation_potential(np.array([0.0]))[0] == 0.0
+
+
+def test_pz81_high_density_limit_is_the_rpa_logarithm():
+    # As r_s -> 0 the correlation energy of the uniform gas goes as
+    # A ln r_s + B + o(1) with A = (1 - ln 2) / pi^2 (the random-phase
+    # logarithm, exact in this limit).  The slope in ln r_s of the oracle's
+    # eps_c between r_s = 1e-8 and 1e-6 recovers A up to the C r_s ln r_s and
+    # D r_s terms (< 1e-6 here); the printed constant 0.0311 rounds the exact
+    # 0.0310907.
+    a_exact = (1.0 - np.log(2.0)) / np.pi ** 2
+    e1, e2 = scf.pz_eps_c(np.array([1e-8, 1e-6]))
+    slope = (e2 - e1) / np.log(100.0)
+    assert abs(slope - a_exact) < 3e-5
+
+
+def test_pz81_first_derivative_is_continuous_at_rs_1():
+    # The small-r_s branch's C and D were fixed so that eps_c and d eps_c/d r_s
+    # are continuous where the branches meet.  One-sided central differences
+    # of the oracle's eps_c on each branch (not its analytic derivative):
+    # the printed constants leave a gap of 1.3e-5 Ha per bohr; C = 0.0200
+    # instead of 0.0020 (or A = 0.0131) opens one of 1.8e-2.
+    h = 1e-4
+    lo_pts = np.array([1.0 - 3 * h, 1.0 - h])
+    hi_pts = np.array([1.0 + h, 1.0 + 3 * h])
+    d_lo = np.diff(scf.pz_eps_c(lo_pts))[0] / (2 * h)   # derivative at 1 - 2h
+    d_hi = np.diff(scf.pz_eps_c(hi_pts))[0] / (2 * h)   # derivative at 1 + 2h
+    # second derivatives are O(0.05), so the two sample points add < 2e-5
+    assert abs(d_lo - d_hi) < 5e-5
+    # and the analytic derivative the potential uses matches each branch
+    assert abs(scf.pz_deps_c(np.array([1.0 - 2 * h]))[0] - d_lo) < 1e-8
+    assert abs(scf.pz_deps_c(np.array([1.0 + 2 * h]))[0] - d_hi) < 1e-8
+
+
+def test_pz81_low_density_limit_approaches_the_wigner_crystal():
+    # At large r_s the electrons crystallise: the bcc Wigner lattice energy is
+    # -0.89593 / r_s Ha per electron, of which exchange is -0.45817 / r_s, so
+    # correlation tends to -0.43776 / r_s.  The parametrisation's large-r_s form
+    # gamma / (beta_2 r_s) = -0.4268 / r_s lies within 2.5% of it; a digit
+    # changed in gamma or beta_2 moves it by more than 10%.
+    rs = 1e8
+    lim = scf.pz_eps_c(np.array([rs]))[0] * rs
+    assert abs(lim / -0.43776 - 1.0) < 0.04
