@@ -186,9 +186,30 @@ tdfe_status tdfe_apply_H_add_f32(tdfe_ctx* ctx, const void* dev_psibar_c64, void
  * stop tolerance of orbital alpha is max(tol, 16 * 2^-24 * ||psibar_alpha||):
  * FP32 basis vectors cannot support a tighter estimate.  host_k [n_orb] and
  * host_err [n_orb] (may be NULL) receive the final dimension and error estimate.
- * Returns TDFE_ENOCONV (psibar holds the k_max iterate) if k_max is reached. */
+ * Returns TDFE_ENOCONV (psibar holds the k_max iterate) if k_max is reached.
+ * Returns TDFE_ENONFINITE if an orbital's FP64 norm ||psibar_alpha|| is NaN or
+ * Inf (a non-finite entry), or if a recurrence coefficient (alpha_k, beta_k)
+ * or the error estimate becomes non-finite: that orbital stops at once and
+ * its output columns are not finite; the other orbitals are propagated as
+ * usual.  ENONFINITE takes precedence over ENOCONV. */
 tdfe_status tdfe_lanczos_expm(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double tau, double tol,
                               int* host_k, double* host_err);
+
+/* scf_fields: the density-dependent potential of the given orbitals, without
+ * propagating them (Eq. VKS): rho of psibar (as tdfe_density), the Hartree
+ * potential phi from K phi = 4 pi c, c_j = int rho N_j, with phi = f =
+ * sum Z/|r - R| at the boundary nodes (Eqs. Poisson, VHDiscretePoisson;
+ * exact fast diagonalisation on box meshes, Jacobi-PCG to pcg_tol on curved
+ * ones, warm-started from and updating the context's last phi, as magnus_step
+ * does), and W = V_H + V_xc at the Gauss points.
+ *   dev_phi: [Nx Ny Nz] FP64 device, every node of the grid (boundary values
+ *            included), node (I,J,K) at I + Nx (J + Ny K); or NULL.
+ *   dev_w:   [n_cell][nq^3] FP64 device; or NULL (at least one is given).
+ * The Magnus extrapolation history is not touched.  Synchronises the stream.
+ * Errors: TDFE_ESTATE before set_scf (or with neither Hartree nor XC on),
+ * TDFE_EINVAL for dev_phi without Hartree, TDFE_ENOCONV / TDFE_ENONFINITE
+ * from the PCG solve. */
+tdfe_status tdfe_scf_fields(tdfe_ctx* ctx, const void* dev_psibar, int n_orb, double* dev_phi, double* dev_w);
 
 /* density at the Gauss points, rho_q = sum_alpha f_alpha |psi_alpha(x_q)|^2,
  * psi = M^-1/2 psibar interpolated with the GLL basis (Sec. TDKS equations).
@@ -252,7 +273,9 @@ tdfe_status tdfe_set_midpoint(tdfe_ctx* ctx, const tdfe_midpoint_desc* m);
  * psibar is updated in place; rep may be NULL.  The call synchronises its
  * stream once, at the end, to collect the Lanczos convergence status (and the
  * report); a device-side failure found there (TDFE_EINVAL for a Chebyshev
- * table overflow) is returned after psibar has been written. */
+ * table overflow, TDFE_ENONFINITE for a non-finite orbital norm, Lanczos
+ * coefficient or density, as in tdfe_lanczos_expm) is returned after psibar
+ * has been written. */
 tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double dt, double field_E,
                              double tol, tdfe_step_report* rep);
 
@@ -267,8 +290,10 @@ tdfe_status tdfe_magnus_step(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double 
  * propagations (in k_corr_max / k_corr_sum; per-step predictor and corrector
  * are not separated in the batched mode), largest error estimate, and the
  * last step's dipole and charge.  TDFE_ENOCONV if any Lanczos run reached
- * k_max (all steps are still taken); other errors stop the run at the step
- * that failed.  psibar is updated in place. */
+ * k_max (all steps are still taken); TDFE_ENONFINITE (checked at the end of
+ * the batch, before ENOCONV) if any Lanczos run met a non-finite norm or
+ * coefficient; other errors stop the run at the step that failed.  psibar is
+ * updated in place. */
 tdfe_status tdfe_propagate(tdfe_ctx* ctx, void* dev_psibar, int n_orb, int n_steps, double dt, const double* host_E,
                            double tol, double* dev_mu, tdfe_step_report* rep);
 
@@ -364,6 +389,7 @@ tdfe_status tdfe_adaptive_axes_query(const tdfe_adapt_desc* d, size_t* bytes);
 tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
                                int max_cells, double* host_axes, int* host_ncell, double* host_E);
 
+
 /* gradient_query: device workspace bytes that tdfe_dipole_gradient needs for
  * n_orb orbitals, n_steps steps, a state checkpoint every checkpoint_every
  * steps and Krylov bases of up to k_store vectors (a multiple of 8, at most
@@ -393,7 +419,9 @@ tdfe_status tdfe_gradient_query(tdfe_ctx* ctx, int n_orb, int n_steps, int check
  *    at tdfe_fe_mesh_setup); Hartree needs a box mesh;
  *    XC must be none or LDA exchange.
  *  - TDFE_EINVAL if a Lanczos run needs more than k_store vectors,
- *    TDFE_ENOCONV if one does not converge within k_max.
+ *    TDFE_ENOCONV if one does not converge within k_max, TDFE_ENONFINITE
+ *    if psibar0 has a non-finite entry (its norm is not finite) or a Lanczos
+ *    coefficient or the gradient becomes non-finite.
  *  Synchronises the stream. */
 tdfe_status tdfe_dipole_gradient(tdfe_ctx* ctx, const void* dev_psibar0, int n_orb, int n_steps,
                                  const double* host_E, double dt, double tol, int checkpoint_every,

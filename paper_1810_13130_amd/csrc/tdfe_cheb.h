@@ -26,12 +26,18 @@ struct ChebLds {
   int M;
 };
 
-// Bessel values J_0..J_M(z) into J (by the calling lane); returns M or -1.
+// Bessel values J_0..J_M(z) into J (by the calling lane); returns M, -1 if z
+// exceeds the table, or -2 if z is not finite (an Inf in T).  z is bounded
+// before it is converted to an integer, so no term count can overflow.
 // Miller's backward recurrence runs in registers (the table is only written);
 // the values are left unnormalised and *inv receives 1 / (J_0 + 2 sum J_2m),
 // which callers apply to the Chebyshev coefficients.
+#define TDFE_CHEB_NONFINITE (-2)
 __device__ inline int cheb_bessel(double z, double* J, double* inv) {
   int M = 0;
+  *inv = 1.0;
+  if (isnan(z) || isinf(z)) return TDFE_CHEB_NONFINITE;
+  if (z > 2.0 * TDFE_MAX_BESSEL) return -1;
   if (z > 1e-300) {
     M = (int)ceil(z + 10.0 * cbrt(z) + 20.0);
     int ms = M + 20 + (int)(2.0 * sqrt((double)M));
@@ -105,7 +111,7 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   const double jn = *invs;
   yr = 0.0;
   yi = 0.0;
-  if (M < 0) return -1;
+  if (M < 0) return M;
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
   const double ac = row ? a - cc : 0.0;
@@ -151,7 +157,8 @@ __device__ __forceinline__ double lane_read(double v, int lane) {
 // and each term takes its coefficient by a lane read.  Called by one full
 // wavefront (lanes 0..63, all active, no other wavefront of the workgroup
 // involved).  a, bl, br: row t of T (diagonal, left and right off-diagonal;
-// zero for rows t >= k).  Returns M, or -1 if |s| r exceeds the table.
+// zero for rows t >= k).  Returns M, -1 if |s| r exceeds the table, or
+// TDFE_CHEB_NONFINITE.
 __device__ inline int cheb_expm_e1_wave_gtab(int k, double a, double bl, double br, double s, double* Jg,
                                              double& yr, double& yi, double* amax) {
   const int t = threadIdx.x;
@@ -176,7 +183,7 @@ __device__ inline int cheb_expm_e1_wave_gtab(int k, double a, double bl, double 
   const double jn = lane_read(inv0, 0);
   yr = 0.0;
   yi = 0.0;
-  if (M < 0) return -1;
+  if (M < 0) return M;
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
   const double ac = row ? a - cc : 0.0;
@@ -214,7 +221,8 @@ __device__ inline int cheb_expm_e1_wave_gtab(int k, double a, double bl, double 
   return M;
 }
 
-// returns the number of terms M (>= 0) or -1 if |s| r exceeds the Bessel table;
+// returns the number of terms M (>= 0), -1 if |s| r exceeds the Bessel table or
+// TDFE_CHEB_NONFINITE if it is not finite;
 // *amax receives max_j |sa[j]|
 __device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, double s, ChebLds& L, double* amax) {
   const int t = threadIdx.x;
@@ -248,7 +256,7 @@ __device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, do
   __syncthreads();
   const int M = L.M;
   const double jn = L.inv;
-  if (M < 0) return -1;
+  if (M < 0) return M;
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
   for (int j = t; j < k; j += TDFE_CHEB_THREADS) {

@@ -268,8 +268,10 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
   int fin = 0;
   if (M < 0) {
     if (t == 0) {
-      S.status[o] = 3;
-      atomicOr(err_flag, 1);
+      // 3: |tau| ||T_k|| beyond the Bessel table (TDFE_EINVAL); 4: T_k not finite
+      const bool nf = M == TDFE_CHEB_NONFINITE;
+      S.status[o] = nf ? 4 : 3;
+      if (!nf) atomicOr(err_flag, 1);
       if (atomicAdd(S.nconv, 1) + 1 == Nc) {
         *S.done = 1;
         fin = 1;
@@ -280,7 +282,10 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
     const bool happy = bk <= 1e-14 * amax;
     // mixed precision: no tighter than the storage precision of the basis allows
     const bool conv = (eps <= fmax(tol, tol_rel * S.nrm[o])) || happy;
-    const bool stop = conv || k >= k_max;
+    // a NaN or Inf in beta_k or in the small exponential ends the orbital at
+    // once (status 4, reported as TDFE_ENONFINITE) instead of running to k_max
+    const bool nonfinite = !isfinite(eps);
+    const bool stop = conv || nonfinite || k >= k_max;
     if (stop && !y_in_place) {
       if (Lyr == nullptr) {
         if (t < k) {
@@ -298,7 +303,7 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
       S.err[o] = eps;
       if (stop) {
         S.kconv[o] = k;
-        S.status[o] = conv ? 1 : 2;
+        S.status[o] = nonfinite ? 4 : (conv ? 1 : 2);
         S.scale[(size_t)k * Nc + o] = 0.0;  // freezes the orbital in later operator passes
         S.cs[(size_t)k * Nc + o] = 0.0;
         if (atomicAdd(S.nconv, 1) + 1 == Nc) {
@@ -451,11 +456,15 @@ __global__ void init_scal_kernel(Scal S, int Nc) {
   }
 }
 
-// orbitals with zero norm are finished before the first iteration
+// orbitals with zero norm are finished before the first iteration; a
+// non-finite norm (a NaN or Inf entry in the orbital) finishes the orbital
+// with status 4, which the host reports as TDFE_ENONFINITE
 __global__ void zero_norm_kernel(Scal S, int Nc, int* host_flag, int gen) {
   const int o = threadIdx.x;
-  if (o < Nc && !(S.nrm[o] > 0.0)) {
-    S.status[o] = 1;
+  const double nr = o < Nc ? S.nrm[o] : 1.0;
+  const bool bad = !isfinite(nr);
+  if (o < Nc && (bad || !(nr > 0.0))) {
+    S.status[o] = bad ? 4 : 1;
     S.kconv[o] = 0;
     if (atomicAdd(S.nconv, 1) + 1 == Nc) {
       *S.done = 1;
@@ -732,7 +741,7 @@ tdfe_status tdfe_lanczos_results(tdfe_ctx* c, const void* host, int n_orb, doubl
                                  int* ksum_out, double* errmax_out) {
   const volatile double* h = (const volatile double*)host;
   const int nm = c->n_orb_max;
-  int kmax = 0, ksum = 0, bad = 0;
+  int kmax = 0, ksum = 0, bad = 0, nonfinite = 0;
   double emax = 0.0;
   for (int o = 0; o < n_orb; ++o) {
     const int k = (int)h[o];
@@ -740,10 +749,12 @@ tdfe_status tdfe_lanczos_results(tdfe_ctx* c, const void* host, int n_orb, doubl
     ksum += k;
     emax = std::max(emax, (double)h[2 * nm + o]);
     if ((int)h[nm + o] == 2) bad = 1;
+    if ((int)h[nm + o] == 4) nonfinite = 1;
   }
   if (kmax_out) *kmax_out = kmax;
   if (ksum_out) *ksum_out = ksum;
   if (errmax_out) *errmax_out = emax;
+  if (nonfinite) return tdfe_fail(c, TDFE_ENONFINITE, "Lanczos: non-finite norm or recurrence coefficient");
   if (h[3 * nm] != 0.0) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
   if (bad) return tdfe_fail(c, TDFE_ENOCONV, "Lanczos reached k_max=%d without eps <= %g", c->k_max, tol);
   return TDFE_OK;
@@ -779,19 +790,21 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
     if (s != TDFE_OK) return s;
   }
   if (slot) return TDFE_OK;
-  int kmax = 0, ksum = 0, bad = 0;
+  int kmax = 0, ksum = 0, bad = 0, nonfinite = 0;
   double emax = 0.0;
   for (int o = 0; o < n_orb; ++o) {
     kmax = std::max(kmax, ks[o]);
     ksum += ks[o];
     emax = std::max(emax, es[o]);
     if (st[o] == 2) bad = 1;
+    if (st[o] == 4) nonfinite = 1;
     if (k_out) k_out[o] = ks[o];
     if (err_out) err_out[o] = es[o];
   }
   if (kmax_out) *kmax_out = kmax;
   if (ksum_out) *ksum_out = ksum;
   if (errmax_out) *errmax_out = emax;
+  if (nonfinite) return tdfe_fail(c, TDFE_ENONFINITE, "Lanczos: non-finite norm or recurrence coefficient");
   if (bad) return tdfe_fail(c, TDFE_ENOCONV, "Lanczos reached k_max=%d without eps <= %g", c->k_max, tol);
   return TDFE_OK;
 }

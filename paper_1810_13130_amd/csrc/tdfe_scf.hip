@@ -370,6 +370,7 @@ __global__ void accum_results_kernel(const double* slot, int n_orb, int nm, doub
     acc[1] += k;
     acc[2] = fmax(acc[2], slot[2 * nm + o]);
     if (slot[nm + o] == 2.0) acc[3] = 1.0;
+    if (slot[nm + o] == 4.0) acc[5] = 1.0;
   }
   if (slot[3 * nm] != 0.0) acc[4] = 1.0;
 }
@@ -1476,6 +1477,22 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   return TDFE_OK;
 }
 
+tdfe_status tdfe_scf_fields(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* dev_phi, double* dev_w) {
+  if (!c || !dev_psibar || (!dev_phi && !dev_w)) return TDFE_EINVAL;
+  if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "scf_fields: n_orb out of range");
+  if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "scf_fields before bind_workspace");
+  if (!c->have_scf) return tdfe_fail(c, TDFE_ESTATE, "scf_fields before set_scf");
+  if (dev_phi && !c->hartree) return tdfe_fail(c, TDFE_EINVAL, "scf_fields: phi requested without Hartree");
+  // W goes to the caller's array, or to the midpoint slot that every Magnus
+  // step recomputes before reading it; the W history is not touched
+  TDFE_TRY(tdfe_scf_potential(c, dev_psibar, n_orb, dev_w ? dev_w : c->wh, nullptr, nullptr));
+  if (dev_phi)
+    TDFE_HIP(c, hipMemcpyAsync(dev_phi, c->phi, (size_t)c->n_nodes * sizeof(double), hipMemcpyDeviceToDevice,
+                               c->stream));
+  TDFE_HIP(c, hipStreamSynchronize(c->stream));
+  return TDFE_OK;
+}
+
 tdfe_status tdfe_density(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* dev_rho_q) {
   if (!c || !dev_psibar || !dev_rho_q) return TDFE_EINVAL;
   if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "density: n_orb out of range");
@@ -1508,7 +1525,8 @@ tdfe_status tdfe_dipole(tdfe_ctx* c, const void* dev_psibar, int n_orb, double* 
 // its Lanczos results are folded into acc on the device and its {charge,
 // mu} (when red_dst is set) copied to red_dst
 struct StepBatch {
-  double* acc;      // [8]: max k, sum k, max error estimate, not-converged flag, table-overflow flag
+  double* acc;      // [8]: max k, sum k, max error estimate, not-converged flag, table-overflow flag,
+                    // non-finite flag
   double* red_dst;  // [4] or null
 };
 
@@ -1742,6 +1760,7 @@ tdfe_status tdfe_propagate(tdfe_ctx* c, void* dev_psibar, int n_orb, int n_steps
   if (rep) TDFE_TRY(tdfe_readback(c, dev_mu ? dev_mu + 4 * (size_t)(n_steps - 1) : acc + 8, 4 * sizeof(double), 3712, &hm));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
   const volatile double* a = (const volatile double*)ha;
+  bool charge_finite = true;
   if (rep) {
     tdfe_step_report r{};
     // the predictor and corrector runs are folded together
@@ -1755,8 +1774,10 @@ tdfe_status tdfe_propagate(tdfe_ctx* c, void* dev_psibar, int n_orb, int n_steps
     r.mu[1] = m[2];
     r.mu[2] = m[3];
     *rep = r;
-    if (!std::isfinite(r.charge)) return tdfe_fail(c, TDFE_ENONFINITE, "propagate: non-finite density");
+    charge_finite = std::isfinite(r.charge);
   }
+  if (a[5] != 0.0) return tdfe_fail(c, TDFE_ENONFINITE, "propagate: non-finite norm or Lanczos coefficient");
+  if (!charge_finite) return tdfe_fail(c, TDFE_ENONFINITE, "propagate: non-finite density");
   if (a[4] != 0.0) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
   if (a[3] != 0.0) return tdfe_fail(c, TDFE_ENOCONV, "propagate: a Lanczos run reached k_max=%d without eps <= %g",
                                     c->k_max, tol);

@@ -99,6 +99,7 @@ SIGNATURES = {
     "tdfe_apply_H_add_f32": [_P, _P, _P, ctypes.c_int],
     "tdfe_lanczos_expm": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _IP, _DP],
     "tdfe_density": [_P, _P, ctypes.c_int, _P],
+    "tdfe_scf_fields": [_P, _P, ctypes.c_int, _P, _P],
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
     "tdfe_magnus_step": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                          ctypes.POINTER(StepReport)],
@@ -166,6 +167,7 @@ class Context:
         self.h = h
         self.n_dof, self.n_cell, self.n_quad, self.ws_bytes = self.query()
         self.p, self.nq = p, d.nq
+        self.n_nodes = int(np.prod([c * p + 1 for c in ncell]))
         self.n_orb_max = n_orb_max
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
@@ -327,6 +329,17 @@ class Context:
         self._check(self.lib.tdfe_density(self.h, _ptr(psibar), n, _ptr(out)))
         return out
 
+    def scf_fields(self, psibar, phi=True, w=True):
+        """(phi over every grid node or None, W = V_H + V_xc at the Gauss points
+        [n_cell][nq^3] or None) of the density of psibar; nothing is propagated."""
+        import torch
+        n = self._orb(psibar)
+        ph = torch.empty(self.n_nodes, dtype=torch.float64, device="cuda") if phi else None
+        wq = torch.empty((self.n_cell, self.n_quad // self.n_cell), dtype=torch.float64, device="cuda") if w else None
+        self._check(self.lib.tdfe_scf_fields(self.h, _ptr(psibar), n, _ptr(ph) if ph is not None else None,
+                                             _ptr(wq) if wq is not None else None))
+        return ph, wq
+
     def dipole(self, psibar):
         n = self._orb(psibar)
         mu = (ctypes.c_double * 3)()
@@ -468,16 +481,21 @@ def power_spectrum(mu, dt, omega):
     return out
 
 
-def adaptive_axes(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=4096):
-    """Vertex coordinates (x, y, z axes) of the graded rectilinear mesh whose
-    spacing follows the a priori element size h(r); returns (axes, E)."""
-    import torch
-    lib = load()
+def _adapt_desc(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples):
     keep = [np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1)) for v in (R, Z, s_orb, a_pot)]
     d = AdaptDesc()
     d.p, d.lo, d.hi, d.n_atoms = p, lo, hi, len(keep[1])
     d.R, d.Z, d.s_orb, d.a_pot = (k.ctypes.data_as(_DP) for k in keep)
     d.n_elem, d.samples = float(n_elem), samples
+    return d, keep
+
+
+def adaptive_axes(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=4096):
+    """Vertex coordinates (x, y, z axes) of the graded rectilinear mesh whose
+    spacing follows the a priori element size h(r); returns (axes, E)."""
+    import torch
+    lib = load()
+    d, keep = _adapt_desc(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples)
     nb = ctypes.c_size_t()
     s = lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb))
     if s != OK:
@@ -492,7 +510,9 @@ def adaptive_axes(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=
                                axes.ctypes.data_as(_DP), nc, ctypes.byref(E))
     if s != OK:
         raise TdfeError(s, "adaptive_axes failed")
+    del keep
     return [axes[a, :nc[a] + 1].copy() for a in range(3)], E.value
+
 
 
 def rectilinear_vertices(ax, ay, az):
