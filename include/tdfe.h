@@ -115,7 +115,19 @@ typedef struct {
   int n_orb;                /* orbitals the occupations refer to */
   double pcg_tol;           /* relative residual for curved meshes (box meshes solve exactly) */
   int pcg_maxit;
+  int pcg_precond;          /* curved meshes: TDFE_PCG_FDM (0, default) or TDFE_PCG_JACOBI */
 } tdfe_scf_desc;
+
+/* Hartree solve on curved meshes: conjugate gradients on K phi = 4 pi c to
+ * the relative residual pcg_tol, warm-started from the previous phi.  The
+ * preconditioner is either the inverse diagonal of K (TDFE_PCG_JACOBI) or
+ * TDFE_PCG_FDM: the exact inverse, by fast diagonalisation, of the stiffness
+ * of a rectilinear stand-in mesh whose vertex coordinates along each axis are
+ * the means of the true ones over the other two indices (on smoothly graded
+ * meshes 20-30 iterations instead of the hundreds Jacobi needs).  Both stop at
+ * the same residual test; box meshes always solve exactly. */
+#define TDFE_PCG_FDM 0
+#define TDFE_PCG_JACOBI 1
 
 /* set_scf: density-dependent part of V_KS.  Resets the extrapolation history. */
 tdfe_status tdfe_set_scf(tdfe_ctx* ctx, const tdfe_scf_desc* s);

@@ -36,7 +36,10 @@ struct tdfe_ctx {
   double D[TDFE_MAXN * TDFE_MAXN];       // D[a*n+i] = l_i'(eta_a)
   double Dg[TDFE_MAXN * TDFE_MAXN];      // Dg[a*nq+b] = derivative at eta_a of the Gauss-point Lagrange basis b
   std::vector<double> vertices;          // (ncx+1)(ncy+1)(ncz+1)*3
-  std::vector<double> ax_x, ax_y, ax_z;  // box grids: vertex coordinates along each axis
+  // box grids: the vertex coordinates along each axis; curved grids (after
+  // set_scf with Hartree): their means over the other two indices, the
+  // rectilinear stand-in mesh of the Hartree preconditioner
+  std::vector<double> ax_x, ax_y, ax_z;
 
   // ---- workspace ------------------------------------------------------------
   char* ws = nullptr;
@@ -100,6 +103,7 @@ struct tdfe_ctx {
   int occ_ver = 0, occ_dev_ver = -1, occ_dev_n = -1;  // device copy of the occupations is current when equal
   double pcg_tol = 1e-13;
   int pcg_maxit = 5000;
+  int pcg_precond = TDFE_PCG_FDM;  // curved meshes: CG preconditioner
   int last_poisson_iters = 0;
   double fdir[3] = {0.0, 0.0, 1.0};  // field direction d: V_field = -E_n (d . r)
   int mid_mode = TDFE_MIDPOINT_PC, mid_order = 1;  // midpoint Hamiltonian of the Magnus step

@@ -789,12 +789,12 @@ void fdm_axis(const tdfe_ctx* c, const std::vector<double>& ax, std::vector<doub
     }
 }
 
-tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
-  // rhs = 4 pi c_interior - (K f)_interior ; phi_interior = K^-1 rhs
+// t0 <- K_box^-1 t0 (interior vectors; t1 is scratch): the six 1D transforms
+// and the diagonal scaling of the fast diagonalisation of the rectilinear
+// stiffness built from the axes of tdfe_fdm_setup
+tdfe_status fdm_passes(tdfe_ctx* c) {
   const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
   const int64_t nd = c->n_dof;
-  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->cload,
-                     with_lift ? (const double*)c->lift : (const double*)nullptr, 4.0 * M_PI, c->t0, c->Nx, c->Ny, c->Nz);
   const double* Sx = c->fdmS;
   const double* Sy = Sx + (size_t)n1x * n1x;
   const double* Sz = Sy + (size_t)n1y * n1y;
@@ -855,10 +855,32 @@ tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
   TDFE_TRY(pass(c->t1, c->t0, 2, 0, false));
   TDFE_TRY(pass(c->t0, c->t1, 1, 0, false));
   TDFE_TRY(pass(c->t1, c->t0, 0, 0, false));
+  return TDFE_OK;
+}
+
+// box meshes: the exact Hartree solve, phi_interior = K^-1 (4 pi c - (K f))_interior
+tdfe_status fdm_solve(tdfe_ctx* c, bool with_lift, double* phi_full) {
+  const int64_t nd = c->n_dof;
+  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->cload,
+                     with_lift ? (const double*)c->lift : (const double*)nullptr, 4.0 * M_PI, c->t0, c->Nx, c->Ny, c->Nz);
+  TDFE_TRY(fdm_passes(c));
   hipLaunchKernelGGL(scatter_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->t0, phi_full, c->Nx, c->Ny,
                      c->Nz);
   TDFE_HIP(c, hipGetLastError());
   c->last_poisson_iters = 0;
+  return TDFE_OK;
+}
+
+// curved meshes: the PCG preconditioner z = K_box^-1 r on full-grid vectors
+// (interior entries; the boundary entries of z are left as they are, zero)
+tdfe_status fdm_precondition(tdfe_ctx* c, const double* r_full, double* z_full) {
+  const int64_t nd = c->n_dof;
+  hipLaunchKernelGGL(gather_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, r_full, (const double*)nullptr,
+                     1.0, c->t0, c->Nx, c->Ny, c->Nz);
+  TDFE_TRY(fdm_passes(c));
+  hipLaunchKernelGGL(scatter_interior_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, c->t0, z_full, c->Nx, c->Ny,
+                     c->Nz);
+  TDFE_HIP(c, hipGetLastError());
   return TDFE_OK;
 }
 
@@ -1058,28 +1080,32 @@ __device__ void block_sum3(double v0, double v1, double v2, double* out) {
   }
 }
 
-// r = b - Ap (interior), z = D^-1 r, p = z, Ap = 0; partials of r.z, r.r, b.b
+// r = b - Ap (interior), Ap = 0; Jacobi (jacobi != 0): z = D^-1 r, p = z;
+// partials of r.z (0 without Jacobi: the preconditioner pass fills it), r.r, b.b
 __global__ void __launch_bounds__(EW) pcg_start_kernel(const double* b, double* r, double* z, double* pv, double* Ap,
-                                                       const double* dinv, int64_t n, double* partial) {
+                                                       const double* dinv, int jacobi, int64_t n, double* partial) {
   double rz = 0, rr = 0, bb = 0;
   for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < n; i += (int64_t)gridDim.x * EW) {
     const double di = dinv[i];
     const double ri = di != 0.0 ? b[i] - Ap[i] : 0.0;  // dinv is 0 exactly on the boundary
-    const double zi = di * ri;
     r[i] = ri;
-    z[i] = zi;
-    pv[i] = zi;
     Ap[i] = 0.0;
-    rz += ri * zi;
+    if (jacobi) {
+      const double zi = di * ri;
+      z[i] = zi;
+      pv[i] = zi;
+      rz += ri * zi;
+    }
     rr += ri * ri;
     bb += b[i] * b[i];
   }
   block_sum3(rz, rr, bb, partial + blockIdx.x * 3);
 }
 
-// x += alpha p, r -= alpha Ap (interior), z = D^-1 r, Ap = 0; partials of r.z, r.r
+// x += alpha p, r -= alpha Ap (interior), Ap = 0; Jacobi: z = D^-1 r;
+// partials of r.z (0 without Jacobi), r.r
 __global__ void __launch_bounds__(EW) pcg_update_kernel(double* x, double* r, double* z, const double* pv, double* Ap,
-                                                        const double* dinv, const double* S, int64_t n,
+                                                        const double* dinv, int jacobi, const double* S, int64_t n,
                                                         double* partial, const int* done) {
   if (*done) return;
   const double alpha = S[3];
@@ -1089,14 +1115,33 @@ __global__ void __launch_bounds__(EW) pcg_update_kernel(double* x, double* r, do
     const double pi = pv[i];
     x[i] += alpha * pi;
     const double ri = di != 0.0 ? r[i] - alpha * Ap[i] : 0.0;
-    const double zi = di * ri;
     r[i] = ri;
-    z[i] = zi;
     Ap[i] = 0.0;
-    rz += ri * zi;
+    if (jacobi) {
+      const double zi = di * ri;
+      z[i] = zi;
+      rz += ri * zi;
+    }
     rr += ri * ri;
   }
   block_sum3(rz, rr, 0.0, partial + blockIdx.x * 3);
+}
+
+// the r.z slot of the update partials, after the preconditioner pass wrote z
+// (same grid and stride as pcg_update_kernel, so the fixed-order sums match)
+__global__ void __launch_bounds__(EW) pcg_rz_kernel(const double* r, const double* z, int64_t n, double* partial,
+                                                    const int* done) {
+  if (done && *done) return;
+  double rz = 0;
+  for (int64_t i = (int64_t)blockIdx.x * EW + threadIdx.x; i < n; i += (int64_t)gridDim.x * EW) rz += r[i] * z[i];
+  __shared__ double sred[EW];
+  sred[threadIdx.x] = rz;
+  __syncthreads();
+  for (int s = EW / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) sred[threadIdx.x] += sred[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x * 3] = sred[0];
 }
 
 // p = z + beta p
@@ -1228,12 +1273,26 @@ tdfe_status pcg_solve(tdfe_ctx* c) {
     a.done_flag = energy ? flags : nullptr;
     return tdfe_launch_apply(c, a);
   };
+  // preconditioner: Jacobi (z = D^-1 r inside the update kernels) or the fast
+  // diagonalisation of the rectilinear stand-in mesh (a pass of its own)
+  const int jacobi = c->pcg_precond == TDFE_PCG_JACOBI ? 1 : 0;
+  auto precondition = [&](const int* done) -> tdfe_status {
+    if (jacobi) return TDFE_OK;
+    TDFE_TRY(fdm_precondition(c, r, z));
+    hipLaunchKernelGGL(pcg_rz_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, (const double*)r, (const double*)z, nn,
+                       part, done);
+    TDFE_HIP(c, hipGetLastError());
+    return TDFE_OK;
+  };
   hipLaunchKernelGGL(pcg_rhs_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, c->cload, (const double*)c->lift,
                      (const double*)c->phi, x, c->Nx, c->Ny, c->Nz);
   TDFE_TRY(tdfe_zero(c, Ap, nn * sizeof(double)));
+  if (!jacobi) TDFE_TRY(tdfe_zero(c, z, nn * sizeof(double)));  // boundary entries stay zero
   TDFE_TRY(apply_K(x, false, nullptr));
   hipLaunchKernelGGL(pcg_start_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, (const double*)c->cload, r, z, pv, Ap,
-                     (const double*)c->dinvK, nn, part);
+                     (const double*)c->dinvK, jacobi, nn, part);
+  TDFE_TRY(precondition(nullptr));
+  if (!jacobi) TDFE_HIP(c, hipMemcpyAsync(pv, z, nn * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   volatile int* hflag = c->poll + 40;  // nothing on the stream writes it now
   *hflag = 0;
   int* dflag = nullptr;
@@ -1251,7 +1310,8 @@ tdfe_status pcg_solve(tdfe_ctx* c) {
       hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, groups, 1, 1, S,
                          flags, c->pcg_tol, c->pcg_maxit, dflag);
       hipLaunchKernelGGL(pcg_update_kernel, dim3(PCG_BLOCKS), dim3(EW), 0, c->stream, x, r, z, (const double*)pv, Ap,
-                         (const double*)c->dinvK, (const double*)S, nn, part, (const int*)flags);
+                         (const double*)c->dinvK, jacobi, (const double*)S, nn, part, (const int*)flags);
+      TDFE_TRY(precondition(flags));
       hipLaunchKernelGGL(pcg_scalar_kernel, dim3(1), dim3(EW), 0, c->stream, (const double*)part, (int64_t)PCG_BLOCKS,
                          3, 2, S, flags, c->pcg_tol, c->pcg_maxit, dflag);
       hipLaunchKernelGGL(pcg_direction_kernel, dim3(nblk(nn)), dim3(EW), 0, c->stream, (const double*)z, pv,
@@ -1435,6 +1495,33 @@ tdfe_status tdfe_set_midpoint(tdfe_ctx* c, const tdfe_midpoint_desc* m) {
   return TDFE_OK;
 }
 
+// rectilinear stand-in of a curved grid for the Hartree preconditioner: the
+// mean vertex coordinate of every logical plane along each axis; if a mean
+// sequence is not increasing (a folded map), a uniform one between its ends
+static void stand_in_axes(tdfe_ctx* c) {
+  const int nc[3] = {c->ncx, c->ncy, c->ncz};
+  std::vector<double>* out[3] = {&c->ax_x, &c->ax_y, &c->ax_z};
+  for (int d = 0; d < 3; ++d) {
+    std::vector<double>& ax = *out[d];
+    ax.assign(nc[d] + 1, 0.0);
+    std::vector<double> cnt(nc[d] + 1, 0.0);
+    for (int k = 0; k <= c->ncz; ++k)
+      for (int j = 0; j <= c->ncy; ++j)
+        for (int i = 0; i <= c->ncx; ++i) {
+          const int m = d == 0 ? i : (d == 1 ? j : k);
+          ax[m] += c->vertices[(((size_t)k * (c->ncy + 1) + j) * (c->ncx + 1) + i) * 3 + d];
+          cnt[m] += 1.0;
+        }
+    for (int m = 0; m <= nc[d]; ++m) ax[m] /= cnt[m];
+    bool inc = true;
+    for (int m = 1; m <= nc[d]; ++m) inc = inc && ax[m] > ax[m - 1];
+    if (!inc) {
+      const double a = ax[0], b = ax[nc[d]] > a ? ax[nc[d]] : a + nc[d];
+      for (int m = 0; m <= nc[d]; ++m) ax[m] = a + (b - a) * m / nc[d];
+    }
+  }
+}
+
 tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   if (!c || !s) return TDFE_EINVAL;
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "set_scf before bind_workspace");
@@ -1442,6 +1529,8 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   if (s->n_nuclei < 0 || (s->n_nuclei > 0 && (!s->Z || !s->R))) return tdfe_fail(c, TDFE_EINVAL, "set_scf: nuclei");
   if (s->n_orb < 0 || s->n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "set_scf: n_orb");
   if (s->hartree && !c->box && !(s->pcg_tol > 0.0)) return tdfe_fail(c, TDFE_EINVAL, "set_scf: pcg_tol");
+  if (s->pcg_precond != TDFE_PCG_FDM && s->pcg_precond != TDFE_PCG_JACOBI)
+    return tdfe_fail(c, TDFE_EINVAL, "set_scf: pcg_precond");
   c->hartree = s->hartree ? 1 : 0;
   c->xc = s->xc;
   c->nucZ.assign(s->Z, s->Z + s->n_nuclei);
@@ -1452,6 +1541,7 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
     for (int o = 0; o < s->n_orb; ++o) c->occ[o] = s->occupation[o];
   c->pcg_tol = s->pcg_tol;
   c->pcg_maxit = s->pcg_maxit;
+  c->pcg_precond = s->pcg_precond;
   if (c->hartree) {
     std::vector<double> zr(4 * std::max(1, s->n_nuclei));
     for (int a = 0; a < s->n_nuclei; ++a) {
@@ -1467,10 +1557,15 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
     TDFE_HIP(c, hipGetLastError());
     TDFE_TRY(tdfe_compute_lift(c));
     TDFE_HIP(c, hipStreamSynchronize(c->stream));
-    if (c->box)
+    if (c->box) {
       TDFE_TRY(tdfe_fdm_setup(c));
-    else
+    } else {
       TDFE_TRY(stiffness_diag(c));
+      if (c->pcg_precond == TDFE_PCG_FDM) {
+        stand_in_axes(c);
+        TDFE_TRY(tdfe_fdm_setup(c));
+      }
+    }
   }
   c->have_scf = c->hartree || c->xc != TDFE_XC_NONE;
   c->scf_init = false;

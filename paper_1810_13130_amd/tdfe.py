@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libtdfe.so")
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED_FP32 = 0, 1
 XC_NONE, XC_X, XC_XC = 0, 1, 2
+PCG_FDM, PCG_JACOBI = 0, 1
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "ESTATE", -6: "ENONFINITE"}
 
 
@@ -37,7 +38,7 @@ class ScfDesc(ctypes.Structure):
     _fields_ = [("hartree", ctypes.c_int), ("xc", ctypes.c_int), ("n_nuclei", ctypes.c_int),
                 ("Z", ctypes.POINTER(ctypes.c_double)), ("R", ctypes.POINTER(ctypes.c_double)),
                 ("occupation", ctypes.POINTER(ctypes.c_double)), ("n_orb", ctypes.c_int),
-                ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int)]
+                ("pcg_tol", ctypes.c_double), ("pcg_maxit", ctypes.c_int), ("pcg_precond", ctypes.c_int)]
 
 
 class StepReport(ctypes.Structure):
@@ -222,7 +223,8 @@ class Context:
         self._check(self.lib.tdfe_set_potential(self.h, _ptr(v)))
 
     def set_scf(self, hartree=False, xc=XC_NONE, Z=(), R=(), occupation=None, n_orb=0, pcg_tol=1e-13,
-                pcg_maxit=5000):
+                pcg_maxit=5000, pcg_precond=None):
+        """pcg_precond (curved meshes): PCG_FDM (default) or PCG_JACOBI."""
         s = ScfDesc()
         s.hartree = int(bool(hartree))
         s.xc = xc
@@ -241,6 +243,7 @@ class Context:
             s.n_orb = n_orb
         s.pcg_tol = pcg_tol
         s.pcg_maxit = pcg_maxit
+        s.pcg_precond = PCG_FDM if pcg_precond is None else pcg_precond
         self._check(self.lib.tdfe_set_scf(self.h, ctypes.byref(s)))
 
     def projector_query(self, n_proj):

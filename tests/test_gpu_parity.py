@@ -230,14 +230,18 @@ def test_magnus_scf_predictor_corrector_matches_oracle(n_orb):
     assert rel(g.cpu().numpy(), st.psibar) < 1e-10
 
 
+@pytest.mark.parametrize("precond", ["fdm", "jacobi"])
 @pytest.mark.parametrize("xc", ["x", "xc"])
-def test_magnus_scf_on_graded_mesh_matches_oracle(xc):
-    """Curved (trilinear) cells: Hartree by the GPU's Jacobi-PCG, exchange or
-    exchange + PZ81 correlation, predictor-corrector steps."""
+def test_magnus_scf_on_graded_mesh_matches_oracle(xc, precond):
+    """Curved (trilinear) cells: Hartree by the GPU's CG (preconditioned by the
+    rectilinear stand-in's fast diagonalisation, or Jacobi as the oracle),
+    exchange or exchange + PZ81 correlation, predictor-corrector steps."""
+    from paper_1810_13130_amd import tdfe
     cfg = _cfg3_small(n_orb=3)
     ctx = gpu_context(cfg, n_orb=3)
     Z, R = W.atoms(cfg)
-    ctx.set_scf(hartree=True, xc={"x": 1, "xc": 2}[xc], Z=Z, R=R, n_orb=3, pcg_tol=1e-14, pcg_maxit=5000)
+    ctx.set_scf(hartree=True, xc={"x": 1, "xc": 2}[xc], Z=Z, R=R, n_orb=3, pcg_tol=1e-14, pcg_maxit=5000,
+                pcg_precond={"fdm": tdfe.PCG_FDM, "jacobi": tdfe.PCG_JACOBI}[precond])
     g = gpu_initial_state(ctx, cfg)
     m, vq = oracle_mesh(cfg)
     sysm = System(m, vq, hartree=True, xc=xc, Z=Z, R=R, tol=1e-12, pcg_tol=1e-14)
@@ -251,12 +255,14 @@ def test_magnus_scf_on_graded_mesh_matches_oracle(xc):
     assert rel(g.cpu().numpy(), st.psibar) < 1e-10
 
 
-def test_pcg_not_converging_is_reported():
+@pytest.mark.parametrize("precond", ["fdm", "jacobi"])
+def test_pcg_not_converging_is_reported(precond):
     from paper_1810_13130_amd import tdfe
     cfg = _cfg3_small(n_orb=2)
     ctx = gpu_context(cfg, n_orb=2)
     Z, R = W.atoms(cfg)
-    ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=2, pcg_tol=1e-14, pcg_maxit=3)
+    ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=2, pcg_tol=1e-14, pcg_maxit=1,
+                pcg_precond={"fdm": tdfe.PCG_FDM, "jacobi": tdfe.PCG_JACOBI}[precond])
     g = gpu_initial_state(ctx, cfg)
     with pytest.raises(tdfe.TdfeError) as e:
         ctx.magnus_step(g, cfg.dt, 0.0, 1e-12)
