@@ -1,20 +1,29 @@
 """Benchmark: second-order Magnus steps per second on one MI355X.
 
-Workload (default): 16^3 box cells on [-10,10]^3, order p = 5 (493,039 DoFs),
-8 complex orbitals, 4 Gaussian-well atoms, Hartree + LDA exchange, kick 1e-3
-along z, dt = 0.05, Lanczos tolerance 1e-10 -- the pseudopotential-like
-molecule workload.  One step = the whole hot path: predictor Lanczos
-exp(-i dt/2 Hbar), density, Hartree, XC, corrector Lanczos exp(-i dt Hbar),
-density, Hartree, XC, dipole.  Inputs are resident on the GPU before timing.
+Headline workload: the graded molecule -- 31^3 trilinear cells on
+[-16,16]^3 graded towards 16 Gaussian-well atoms (cells 0.25 to 2 bohr),
+order p = 6 (6,331,625 DoFs), 32 complex orbitals, Hartree + LDA exchange and
+PZ81 correlation, kick 1e-3 along z, dt = 0.05, Lanczos tolerance 1e-10.  One
+step = the whole hot path: predictor Lanczos exp(-i dt/2 Hbar), density,
+Hartree, XC, corrector Lanczos exp(-i dt Hbar), density, Hartree, XC, dipole.
+Inputs are resident on the GPU before timing; the timed steps run in one
+tdfe_propagate call.
 
-Prints ONE JSON line (rank 0).  Besides the contract fields it reports the
-operator kernel's roofline position (per-launch duration measured with HIP
-events on the library's stream), its throughput in GDoF-orbitals/s, and a
-bounded CPU-oracle baseline measured on this host.
+Prints ONE JSON line.  Besides the contract fields: the mixed-precision path
+(FP32 operator and Krylov storage, FP64 scalars) with its dipole error against
+the FP64 trajectory and its speedup both at equal nominal tolerance and
+against FP64 run at the mixed path's effective stop tolerance; the operator
+kernel's position on the HBM roofline (launch duration from HIP events on the
+library's stream, in the step's own launch shape); the pseudopotential-like
+box workload (16^3 cells, p = 5, 8 orbitals) as an extra; and the CPU oracle
+timed on this host (a subprocess that runs beside the GPU legs).
 """
 import argparse
+import hashlib
 import json
 import os
+import platform
+import subprocess
 import sys
 import time
 
@@ -26,42 +35,50 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 FP64_VECTOR_PEAK_TFLOPS = 78.6   # 256 CU x 4 SIMD x 16 lanes x 2 flop x 2.4 GHz
 FP32_VECTOR_PEAK_TFLOPS = 157.3
+MIXED_TOL_FLOOR = 16.0 * 2.0 ** -24  # the mixed path's stop floor per unit ||psibar_alpha||
 
 
-def apply_work(n, nq, n_cell, n_dof, n_orb, elem_bytes=8):
-    """Algorithmic work of one Hbar apply on n_orb complex orbitals.
-
-    bytes: read psibar and write Hbar psibar once (2 x 2 real numbers per
-    DoF-orbital), the weighted potential once per Gauss point, M^-1/2 once
-    per DoF.  flops: per cell and real column 12 one-dimensional passes of
-    n^4 multiply-adds (3 interpolations, 3 collocation derivatives, their 6
-    transposes) plus ~7 n^3 pointwise.
-    """
-    bytes_ = n_dof * n_orb * 2 * elem_bytes * 2 + n_cell * nq ** 3 * elem_bytes + n_dof * 8
-    flops = n_cell * 2 * n_orb * (24 * n ** 4 + 7 * n ** 3)
-    return bytes_, flops
+def apply_bytes(n_dof, n_cell, n_quad, n_orb, elem_bytes, curved):
+    """Algorithmic HBM bytes of one Hbar launch on n_orb complex orbitals:
+    read psibar and write Hbar psibar once (2 reals each per DoF-orbital), the
+    weighted potential once per Gauss point, M^-1/2 once per DoF (all in the
+    kernel's precision), and on curved cells the 8 corner vertices per cell
+    (FP64) from which the metric is recomputed."""
+    b = n_dof * n_orb * 2 * elem_bytes * 2 + n_quad * elem_bytes + n_dof * elem_bytes
+    if curved:
+        b += n_cell * 24 * 8
+    return b
 
 
-# sources of the box-cell operator kernels (the lane-pair FP64 kernel and the
-# plane FP32 kernel) whose counters profiles/ holds
-OPERATOR_SOURCES = ("tdfe_apply_box.hip", "tdfe_apply_pair.hip", "tdfe_fold.h", "tdfe_rule1d.h")
+def apply_flops(n, n_cell, n_orb):
+    """Flops of one launch as the kernels execute them: per cell and real
+    column 12 one-dimensional passes with even/odd folded tables (n^4 / 2
+    multiply-adds each) plus ~7 n^3 pointwise; the per-point metric of curved
+    cells is not counted."""
+    return n_cell * 2 * n_orb * (12 * n ** 4 + 7 * n ** 3)
 
 
-def operator_source_hash():
-    import hashlib
+# the operator sources of the kernels the committed counter summaries cover
+OPERATOR_SOURCES = {"curved": ("tdfe_apply_curved.hip", "tdfe_fold.h", "tdfe_rule1d.h"),
+                    "box": ("tdfe_apply_box.hip", "tdfe_apply_pair.hip", "tdfe_fold.h", "tdfe_rule1d.h")}
+TRAFFIC_PROFILES = {"curved": "operator_graded_31x31x31_p6_hbm_bytes.md",
+                    "box": "operator_16x16x16_p5_8orb_hbm_bytes.md"}
+
+
+def operator_source_hash(kind):
     h = hashlib.sha256()
-    for name in OPERATOR_SOURCES:
+    for name in OPERATOR_SOURCES[kind]:
         with open(os.path.join(ROOT, "paper_1810_13130_amd", "csrc", name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def profiled_traffic(label):
-    """HBM bytes per operator launch from the committed rocprofv3 counter summary,
-    or None when the operator sources have changed since the counters were taken."""
-    prof = os.path.join(ROOT, "profiles", "operator_16x16x16_p5_8orb_hbm_bytes.md")
+def profiled_traffic(kind, label):
+    """HBM bytes per operator launch from the committed rocprofv3 counter
+    summary, or None when the operator sources have changed since the
+    counters were taken."""
     try:
-        text = open(prof).read()
+        text = open(os.path.join(ROOT, "profiles", TRAFFIC_PROFILES[kind])).read()
     except OSError:
         return None
     vals = {}
@@ -69,10 +86,136 @@ def profiled_traffic(label):
         if "=" in line and not line.startswith("|"):
             k, v = (x.strip() for x in line.split("=", 1))
             vals[k] = v
-    if vals.get("source_sha256_prefix") != operator_source_hash():
+    if vals.get("source_sha256_prefix") != operator_source_hash(kind):
         return None
     v = vals.get(f"traffic_bytes_per_launch.{label}")
     return float(v) if v is not None else None
+
+
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"os_cpu_count": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_worker(cfg_id):
+    """The CPU oracle on this host (run in a subprocess beside the GPU legs):
+    (1) real oracle Magnus steps of the harmonic trap, all 20 steps, with the
+    BLAS pool's threads and with one thread; (2) a bounded sample of the
+    headline workload on its full mesh: two Krylov iterations of one orbital's
+    propagation, two iterations of the Hartree Jacobi-PCG, the density of two
+    orbitals and the XC potential -- per-unit times that the parent scales by
+    the iteration counts it measures."""
+    import threadpoolctl
+    import workloads as W
+    from oracle import lanczos, operators as op, scf
+    from oracle.magnus import State, System, magnus_step
+    from oracle.mesh import Mesh
+    info = threadpoolctl.threadpool_info()
+    threads = max([i.get("num_threads", 1) for i in info] + [1])
+    out = {"threads": threads, **cpu_info()}
+    c1 = W.CONFIGS[1]
+
+    def trap_steps():
+        m1 = Mesh(c1.p, c1.ncell, W.vertices(c1), c1.nq)
+        s1 = System(m1, W.external_potential(c1, m1.quad_xyz), tol=c1.tol)
+        st = State(s1, W.initial_psibar(c1, m1.dof_xyz, m1.M))
+        t = time.perf_counter()
+        for _ in range(c1.steps):
+            magnus_step(s1, st, c1.dt)
+        return c1.steps / (time.perf_counter() - t)
+
+    out["trap_steps_per_s"] = trap_steps()
+    with threadpoolctl.threadpool_limits(1):
+        out["trap_steps_per_s_1thread"] = trap_steps()
+    cfg = W.CONFIGS[cfg_id]
+    t = time.perf_counter()
+    m = Mesh(cfg.p, cfg.ncell, W.vertices(cfg), cfg.nq)
+    vq = W.external_potential(cfg, m.quad_xyz)
+    psi = W.initial_psibar(W.scaled(cfg, n_orb=2), m.dof_xyz, m.M)
+    out["setup_s"] = time.perf_counter() - t
+
+    def krylov_its(n):
+        t0 = time.perf_counter()
+        try:
+            lanczos.lanczos_expm_vec(lambda v: op.apply_Hbar(m, vq, v), psi[:, 0], cfg.dt, 1e-300, k_max=n)
+        except lanczos.NotConverged:
+            pass
+        return (time.perf_counter() - t0) / n
+
+    out["krylov_it_s"] = krylov_its(2)
+    with threadpoolctl.threadpool_limits(1):
+        out["krylov_it_s_1thread"] = krylov_its(1)
+    t0 = time.perf_counter()
+    rho = scf.density(m, psi)
+    out["density_per_orbital_s"] = (time.perf_counter() - t0) / psi.shape[1]
+    t0 = time.perf_counter()
+    scf.xc_potential(rho, cfg.xc)
+    out["xc_s"] = time.perf_counter() - t0
+    if cfg.hartree:
+        # one PCG iteration: the difference of a 3-iteration and a 1-iteration
+        # solve (each also forms the load vector, the initial residual and the
+        # interpolation to the Gauss points)
+        Z, R = W.atoms(cfg)
+        h = scf.Hartree(m, Z, R, tol=1e-300, maxit=1)
+        ts = []
+        for its in (1, 3):
+            h.maxit = its
+            h.phi0[:] = 0.0
+            t0 = time.perf_counter()
+            try:
+                h.solve(rho)
+            except RuntimeError:
+                pass
+            ts.append(time.perf_counter() - t0)
+        out["pcg_it_s"] = max(ts[1] - ts[0], 0.0) / 2
+    out["n_dof"] = int(m.n_dof)
+    out["wall_s"] = time.perf_counter() - t
+    print(json.dumps(out), flush=True)
+
+
+def start_cpu_worker(cfg_id):
+    return subprocess.Popen([sys.executable, os.path.abspath(__file__), "--cpu-worker", "--config", str(cfg_id)],
+                            stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)
+
+
+def cpu_baseline(proc, cfg, counts, timeout_s=900):
+    """Oracle Magnus steps/s on the headline workload from the worker's sample,
+    scaled by the counts of the GPU's FP64 run of the same steps (Krylov
+    iterations per step over all orbitals; Jacobi-PCG iterations per step, the
+    oracle's own solver run on the GPU from the same states)."""
+    try:
+        so, se = proc.communicate(timeout=timeout_s)
+        w = json.loads(so.strip().splitlines()[-1])
+    except Exception as e:  # the baseline is reported, never required
+        proc.kill()
+        return {"error": f"oracle sample failed: {e}"}
+    K, P, N = counts["krylov_its_per_step"], counts.get("jacobi_pcg_its_per_step", 0.0), cfg.n_orb
+    step = (K * w["krylov_it_s"] + P * w.get("pcg_it_s", 0.0) + 2 * N * w["density_per_orbital_s"] + 2 * w["xc_s"])
+    step1 = step * w["krylov_it_s_1thread"] / w["krylov_it_s"]
+    return {
+        "value": 1.0 / step, "unit": "Magnus steps/s", "cores": w["threads"], "kind": "oracle",
+        "os_cpu_count": w["os_cpu_count"], "cpu_model": w["cpu_model"],
+        "value_1thread_est": 1.0 / step1,
+        "apply_H_gdof_orb_per_s": w["n_dof"] / w["krylov_it_s"] / 1e9,
+        "trap_steps_per_s": w["trap_steps_per_s"], "trap_steps_per_s_1thread": w["trap_steps_per_s_1thread"],
+        "sample": (f"oracle (numpy/scipy FP64) on this host, {w['threads']} BLAS threads: timed pieces of a "
+                   f"{cfg.name} step on its full mesh -- 2 Krylov iterations of one orbital "
+                   f"({w['krylov_it_s']:.2f} s/it; 1 thread {w['krylov_it_s_1thread']:.2f} s/it), "
+                   f"Hartree Jacobi-PCG iterations ({w.get('pcg_it_s', 0.0):.2f} s/it), the density of 2 "
+                   f"orbitals ({w['density_per_orbital_s']:.2f} s/orbital), XC ({w['xc_s']:.2f} s) -- scaled "
+                   f"by this run's counts per step: {K:.0f} Krylov its (GPU FP64, same recurrence), {P:.0f} "
+                   f"Jacobi-PCG its (the oracle's solver and tolerance, run on the GPU from the same states), "
+                   f"{2 * N} orbital densities: {step:.0f} s per step.  Also real oracle steps: the harmonic trap's "
+                   f"20 Magnus steps at {w['trap_steps_per_s']:.2f} steps/s ({w['trap_steps_per_s_1thread']:.2f} "
+                   f"on 1 thread).  Mesh set-up ({w['setup_s']:.0f} s) not counted."),
+    }
 
 
 def adjoint_rate(n_steps=20):
@@ -100,39 +243,6 @@ def adjoint_rate(n_steps=20):
     return {"workload": cfg.name, "steps": n_steps, "value": n_steps / wall,
             "unit": "Magnus steps/s (forward + reverse, gradient w.r.t. every E_n)",
             "wall_s": wall, "L": L, "grad_norm": float(np.linalg.norm(g))}
-
-
-def graded_apply(reps=3):
-    """Operator on curved (trilinear) cells: the graded workload (31^3 cells, p = 6,
-    6,331,625 DoFs, 32 orbitals), FP64 and FP32 launches."""
-    import torch
-    import workloads as W
-    from paper_1810_13130_amd import tdfe
-    cfg = W.CONFIGS[3]
-    out = {"workload": cfg.name}
-    for prec, name in ((tdfe.FP64, "f64"), (tdfe.MIXED_FP32, "f32")):
-        ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=cfg.n_orb, k_max=4, precision=prec)
-        xq = ctx.quad_coords().cpu().numpy()
-        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
-        dt_ = torch.complex128 if prec == tdfe.FP64 else torch.complex64
-        f = ctx.apply_H_add if prec == tdfe.FP64 else ctx.apply_H_add_f32
-        x = torch.randn(ctx.n_dof, cfg.n_orb, dtype=dt_, device="cuda")
-        y = torch.zeros_like(x)
-        f(x, y)
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(reps):
-            f(x, y)
-        e1.record()
-        torch.cuda.synchronize()
-        ms = e0.elapsed_time(e1) / reps
-        out[name + "_launch_ms"] = ms
-        out[name + "_gdof_orb_per_s"] = ctx.n_dof * cfg.n_orb / (ms * 1e-3) / 1e9
-        del x, y
-        ctx.close()
-        torch.cuda.empty_cache()
-    return out
 
 
 def nonlocal_term(n_steps=30, reps=50):
@@ -340,80 +450,189 @@ def adaptive_mesh(n_elem=1728, n_steps=10):
             "wall_s": time.perf_counter() - t}
 
 
-def cpu_oracle_baseline(cfg, ks_total):
-    """Bounded sample of the CPU oracle on this host, scaled to steps/s."""
-    import threadpoolctl
-    import workloads as W
-    from oracle import lanczos, operators as op, scf
-    from oracle.mesh import Mesh
+class Workload:
+    """One seeded workload on the GPU: the host-side inputs (vertices, V_ext at
+    the Gauss points, the initial psibar) are formed once and shared by every
+    context of the run (FP64 and mixed contexts have the same nodes and M)."""
+
+    def __init__(self, cfg):
+        import workloads as W
+        self.W = W
+        self.cfg = cfg
+        self.V = W.vertices(cfg)
+        self.vq = None
+        self.psi0 = None
+
+    def context(self, precision, pcg_precond=None):
+        import torch
+        from paper_1810_13130_amd import tdfe
+        cfg, W = self.cfg, self.W
+        ctx = tdfe.Context(cfg.p, cfg.ncell, self.V, n_orb_max=cfg.n_orb, k_max=cfg.k_max, precision=precision)
+        if self.vq is None:
+            xq = ctx.quad_coords().cpu().numpy()
+            self.vq = torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1))
+            self.psi0 = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
+                                                          ctx.mass_diag().cpu().numpy()))
+        ctx.set_potential(self.vq.cuda())
+        if cfg.hartree or cfg.xc != "none":
+            Z, R = W.atoms(cfg)
+            ctx.set_scf(hartree=cfg.hartree, xc={"none": 0, "x": 1, "xc": 2}[cfg.xc], Z=Z, R=R, n_orb=cfg.n_orb,
+                        pcg_tol=cfg.pcg_tol, pcg_precond=pcg_precond)
+        return ctx, self.psi0.cuda()
+
+
+def close(ctx):
+    import torch
+    ctx.close()
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+
+
+def run_steps(ctx, psi, cfg, tol, steps, warmup):
+    """warm-up steps one call each, then the timed steps in one tdfe_propagate
+    call (no host synchronisation between steps); per-step dipoles of all
+    steps from the reports and the device record"""
+    import torch
+    mus, kw = [], 0
+    for _ in range(warmup):
+        rep = ctx.magnus_step(psi, cfg.dt, 0.0, tol)
+        mus.append(rep["mu"])
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    m = Mesh(cfg.p, cfg.ncell, W.vertices(cfg), cfg.nq)
-    vq = W.external_potential(cfg, m.quad_xyz)
-    psi = W.initial_psibar(cfg, m.dof_xyz, m.M)
-    # (a) Lanczos propagations of two orbitals, one at a time: cost per Krylov iteration
-    t = time.perf_counter()
-    ks = []
-    for o in range(2):
-        _, k_o, _ = lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), psi[:, o:o + 1], cfg.dt, cfg.tol)
-        ks.append(k_o[0])
-    t_it = (time.perf_counter() - t) / sum(ks)
-    # (b) 20 iterations of the oracle's Hartree PCG: cost per PCG iteration
-    Z, R = W.atoms(cfg)
-    h = scf.Hartree(m, Z, R, tol=1e-13, maxit=20)
-    rho = scf.density(m, psi)
-    t = time.perf_counter()
-    try:
-        h.solve(rho)
-    except RuntimeError:
-        pass
-    t_cg = (time.perf_counter() - t) / 20
-    # (c) one density evaluation
-    t = time.perf_counter()
-    scf.density(m, psi)
-    t_rho = time.perf_counter() - t
-    # the oracle's own warm-started config-2 Hartree solves take ~357 iterations
-    # to reach 1e-13 (measured with the oracle on this workload)
-    pcg_its = 357
-    step = ks_total * t_it + 2 * pcg_its * t_cg + 2 * t_rho
-    info = threadpoolctl.threadpool_info()
-    threads = max([i.get("num_threads", 1) for i in info] + [1])
-    return {
-        "value": 1.0 / step, "unit": "Magnus steps/s", "cores": threads, "kind": "oracle",
-        "apply_H_gdof_orb_per_s": m.n_dof / t_it / 1e9,
-        "sample": (f"oracle on this host: Lanczos propagations of 2 orbitals ({sum(ks)} its, {t_it*1e3:.0f} ms/it), "
-                   f"20 Hartree PCG its ({t_cg*1e3:.0f} ms/it), 1 density ({t_rho:.2f} s); step = "
-                   f"{ks_total} Krylov its + 2x{pcg_its} PCG its + 2 densities = {step:.1f} s; "
-                   f"sample wall {time.perf_counter()-t0:.1f} s"),
-    }
+    rec, tot = ctx.propagate(psi, steps, cfg.dt, None, tol)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    mus.extend(rec[:, 1:].cpu().numpy())
+    return {"wall": wall, "steps_per_s": steps / wall, "krylov_its_per_step": tot["k_corr_sum"] / steps,
+            "poisson_its_last_solve": tot["poisson_iters"], "mu": np.array(mus)}
+
+
+def time_apply(ctx, n_orb, fp32, reps):
+    """average duration of one operator launch on n_orb orbitals, from HIP
+    events recorded on the library's stream (the current torch stream)"""
+    import torch
+    dt_ = torch.complex64 if fp32 else torch.complex128
+    x = torch.randn(ctx.n_dof, n_orb, dtype=dt_, device="cuda")
+    y = torch.zeros_like(x)
+    f = ctx.apply_H_add_f32 if fp32 else ctx.apply_H_add
+    for _ in range(3):
+        f(x, y)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        f(x, y)
+    e1.record()
+    torch.cuda.synchronize()
+    del x, y
+    return e0.elapsed_time(e1) / 1e3 / reps
+
+
+def roofline(ctx, cfg, n_orb, t_launch, fp32, kernel, curved):
+    eb = 4 if fp32 else 8
+    by = apply_bytes(ctx.n_dof, ctx.n_cell, ctx.n_quad, n_orb, eb, curved)
+    fl = apply_flops(cfg.p + 1, ctx.n_cell, n_orb)
+    kind = "curved" if curved else "box"
+    alu_peak = FP32_VECTOR_PEAK_TFLOPS if fp32 else FP64_VECTOR_PEAK_TFLOPS
+    return {"bound": "hbm", "achieved": by / t_launch / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": by / t_launch / 1e9 / HBM_PEAK_GBS,
+            "traffic": profiled_traffic(kind, ("fp32" if fp32 else "fp64") + f"_{n_orb}orb"),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-kernel calibrated)",
+            "kernel": kernel, "launch_orbitals": n_orb, "launch_us": t_launch * 1e6,
+            "algorithmic_bytes": by, "bytes_per_dof_orb": by / (ctx.n_dof * n_orb),
+            "executed_flops": fl, "alu_frac": fl / t_launch / 1e12 / alu_peak,
+            "alu_peak_tflops": alu_peak}
+
+
+def dipole_errors(mu, ref):
+    n = min(len(mu), len(ref))
+    d = np.abs(mu[:n] - ref[:n]).max()
+    induced = np.abs(ref[:n] - ref[0]).max()
+    return float(d / np.abs(ref[:n]).max()), float(d / max(induced, 1e-300)), n
+
+
+def workload_legs(cfg, steps, warmup, apply_reps, curved, matched=True, jacobi_count=False):
+    """FP64, mixed and (optionally) FP64 at the mixed path's effective stop
+    tolerance on one workload; operator launches in the step's shape."""
+    from paper_1810_13130_amd import tdfe
+    wl = Workload(cfg)
+    res = {}
+    ctx, psi = wl.context(tdfe.FP64)
+    chunk64 = ctx.krylov_chunk(cfg.n_orb)
+    r64 = run_steps(ctx, psi, cfg, cfg.tol, steps, warmup)
+    t_chunk = time_apply(ctx, chunk64, False, apply_reps)
+    t_full = time_apply(ctx, cfg.n_orb, False, max(3, apply_reps // 4))
+    kname = "cplane_kernel<double,7,16,CPB> (trilinear cells)" if curved else "pair_kernel<double,6,16,1> (box cells)"
+    res["f64"] = {**{k: v for k, v in r64.items() if k != "mu"}, "chunk_orbitals": chunk64,
+                  "roofline": roofline(ctx, cfg, chunk64, t_chunk, False, kname, curved),
+                  "apply_H_gdof_orb_per_s": ctx.n_dof * cfg.n_orb / t_full / 1e9, "apply_full_ms": t_full * 1e3}
+    res["n_dof"], res["n_cell"] = ctx.n_dof, ctx.n_cell
+    if jacobi_count:
+        # the oracle's Hartree solver (Jacobi-PCG at the same tolerance) from the
+        # same states: one step to restart the history, then one step counted
+        Z, R = wl.W.atoms(cfg)
+        ctx.set_scf(hartree=cfg.hartree, xc={"none": 0, "x": 1, "xc": 2}[cfg.xc], Z=Z, R=R, n_orb=cfg.n_orb,
+                    pcg_tol=cfg.pcg_tol, pcg_precond=tdfe.PCG_JACOBI)
+        ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+        rj = ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+        res["jacobi_pcg_its_per_solve"] = rj["poisson_iters"]
+    close(ctx)
+    ctx, psi = wl.context(tdfe.MIXED_FP32)
+    chunk32 = ctx.krylov_chunk(cfg.n_orb)
+    r32 = run_steps(ctx, psi, cfg, cfg.tol, steps, warmup)
+    t_chunk32 = time_apply(ctx, chunk32, True, apply_reps)
+    t_full32 = time_apply(ctx, cfg.n_orb, True, max(3, apply_reps // 4))
+    kname32 = kname.replace("double", "float")
+    e, e_ind, n = dipole_errors(r32["mu"], r64["mu"])
+    res["mixed"] = {**{k: v for k, v in r32.items() if k != "mu"}, "chunk_orbitals": chunk32,
+                    "dipole_rel_err": e, "dipole_err_rel_induced": e_ind, "steps_compared": n,
+                    "speedup_vs_f64_same_tol": r32["steps_per_s"] / r64["steps_per_s"],
+                    "roofline": roofline(ctx, cfg, chunk32, t_chunk32, True,
+                                         kname32 if curved else "plane_kernel<float,6,16,2> (box cells)", curved),
+                    "apply_H_gdof_orb_per_s": ctx.n_dof * cfg.n_orb / t_full32 / 1e9, "apply_full_ms": t_full32 * 1e3}
+    close(ctx)
+    if matched:
+        tol_m = max(cfg.tol, MIXED_TOL_FLOOR)  # ||psibar_alpha|| = 1 (orthonormal orbitals)
+        ctx, psi = wl.context(tdfe.FP64)
+        rm = run_steps(ctx, psi, cfg, tol_m, steps, warmup)
+        em, em_ind, _ = dipole_errors(rm["mu"], r64["mu"])
+        res["f64_matched_tol"] = {**{k: v for k, v in rm.items() if k != "mu"}, "tol": tol_m,
+                                  "dipole_rel_err": em, "dipole_err_rel_induced": em_ind}
+        res["mixed"]["speedup_vs_f64_matched_tol"] = r32["steps_per_s"] / rm["steps_per_s"]
+        close(ctx)
+    return res
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=100)
-    ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", type=int, default=2)
-    ap.add_argument("--apply-reps", type=int, default=100)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", type=int, default=3)
+    ap.add_argument("--apply-reps", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-mixed", action="store_true")
-    ap.add_argument("--no-adjoint", action="store_true")
-    ap.add_argument("--no-graded", action="store_true")
-    ap.add_argument("--no-nonlocal", action="store_true")
-    ap.add_argument("--no-spectra", action="store_true")
-    ap.add_argument("--no-midpoint", action="store_true")
-    ap.add_argument("--no-adaptive", action="store_true")
+    ap.add_argument("--no-matched", action="store_true")
+    ap.add_argument("--no-extras", action="store_true", help="skip the box workload and the extension legs")
+    ap.add_argument("--apply-only", action="store_true",
+                    help="only the operator launches of the headline workload (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
+    ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_worker:
+        cpu_worker(args.config)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "runs on one GPU: the orbital-sharded multi-GPU layout is described, not implemented",
                           "n_gpus": args.gpus}))
         sys.exit(2)
+    import workloads as W
+    cfg = W.CONFIGS[args.config]
+    curved = cfg.graded
+    cpu = None if (args.no_cpu_baseline or args.apply_only) else start_cpu_worker(args.config)
 
     import torch
-    import workloads as W
     from paper_1810_13130_amd import tdfe
-
     torch.cuda.set_device(0)
     if args.copy_calibration:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
@@ -421,157 +640,56 @@ def main():
         a.fill_(1.0)
         b.copy_(a)
         torch.cuda.synchronize()
-    cfg = W.CONFIGS[args.config]
-    n_orb = cfg.n_orb
+        del a, b
+    if args.apply_only:
+        wl = Workload(cfg)
+        for prec, fp32 in ((tdfe.FP64, False), (tdfe.MIXED_FP32, True)):
+            ctx, _ = wl.context(prec)
+            n = ctx.krylov_chunk(cfg.n_orb)
+            t = time_apply(ctx, n, fp32, args.apply_reps)
+            print(json.dumps({"precision": "f32" if fp32 else "f64", "launch_orbitals": n, "launch_us": t * 1e6}),
+                  flush=True)
+            close(ctx)
+        return
 
-    def make(precision):
-        ctx = tdfe.Context(cfg.p, cfg.ncell, W.vertices(cfg), n_orb_max=n_orb, k_max=cfg.k_max,
-                           precision=precision)
-        xq = ctx.quad_coords().cpu().numpy()
-        ctx.set_potential(torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1)).cuda())
-        if cfg.hartree or cfg.xc != "none":
-            Z, R = W.atoms(cfg)
-            ctx.set_scf(hartree=cfg.hartree, xc={"none": 0, "x": 1, "xc": 2}[cfg.xc], Z=Z, R=R, n_orb=n_orb)
-        psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
-                                                ctx.mass_diag().cpu().numpy())).cuda()
-        return ctx, psi
-
-    def run(precision):
-        """warm-up steps one call each, then the timed steps in one
-        tdfe_propagate call (no host synchronisation between steps); the
-        per-step dipoles come back from the device record"""
-        ctx, psi = make(precision)
-        mus = []
-        for _ in range(args.warmup):
-            mus.append(ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)["mu"])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        rec, tot = ctx.propagate(psi, args.steps, cfg.dt, None, cfg.tol)
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        mus.extend(rec[:, 1:].cpu().numpy())
-        return ctx, wall, tot["k_corr_sum"], np.array(mus)
-
-    def per_call_rate(ctx, n=None):
-        """the same steps driven by one magnus_step call each (a host
-        synchronisation at the end of every step)"""
-        n = n or args.steps
-        psi = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
-                                                ctx.mass_diag().cpu().numpy())).cuda()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(n):
-            ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol, report=False)
-        torch.cuda.synchronize()
-        return n / (time.perf_counter() - t0)
-
-    def time_apply(ctx, fp32):
-        dt_ = torch.complex64 if fp32 else torch.complex128
-        x = torch.randn(ctx.n_dof, n_orb, dtype=dt_, device="cuda")
-        y = torch.zeros_like(x)
-        f = ctx.apply_H_add_f32 if fp32 else ctx.apply_H_add
-        for _ in range(5):
-            f(x, y)
-        e0 = torch.cuda.Event(enable_timing=True)
-        e1 = torch.cuda.Event(enable_timing=True)
-        torch.cuda.synchronize()
-        e0.record()
-        for _ in range(args.apply_reps):
-            f(x, y)
-        e1.record()
-        torch.cuda.synchronize()
-        return e0.elapsed_time(e1) / 1e3 / args.apply_reps
-
-    def roofline(ctx, t_apply, elem_bytes, alu_peak, label):
-        by, fl = apply_work(cfg.p + 1, cfg.nq, ctx.n_cell, ctx.n_dof, n_orb, elem_bytes)
-        t_hbm = by / (HBM_PEAK_GBS * 1e9)
-        t_alu = fl / (alu_peak * 1e12)
-        if t_alu >= t_hbm:
-            roof = {"bound": "alu", "achieved": fl / t_apply / 1e12, "peak": alu_peak, "unit": "TFLOP/s"}
-        else:
-            roof = {"bound": "hbm", "achieved": by / t_apply / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s"}
-        roof["frac"] = roof["achieved"] / roof["peak"]
-        roof["traffic"] = profiled_traffic("fp64" if elem_bytes == 8 else "fp32")
-        roof["traffic_unit"] = "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"
-        roof["kernel"] = label
-        roof["launch_us"] = t_apply * 1e6
-        roof["algorithmic_bytes"] = by
-        roof["algorithmic_flops"] = fl
-        roof["hbm_frac"] = (by / t_apply / 1e9) / HBM_PEAK_GBS
-        roof["alu_frac"] = (fl / t_apply / 1e12) / alu_peak
-        return roof
-
-    ctx, dt_wall, ks_total, mu64 = run(tdfe.FP64)
-    steps_per_s = args.steps / dt_wall
-    per_call = per_call_rate(ctx)
-    # the paper's production Krylov tolerance (1e-8) on the same workload, FP64
-    prod = None
-    if cfg.tol != 1e-8:
-        psi_p = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
-                                                  ctx.mass_diag().cpu().numpy())).cuda()
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        _, tot_p = ctx.propagate(psi_p, args.steps, cfg.dt, None, 1e-8, record=False)
-        torch.cuda.synchronize()
-        prod = {"tol": 1e-8, "steps_per_s": args.steps / (time.perf_counter() - t0),
-                "krylov_its_per_step": tot_p["k_corr_sum"] / args.steps}
-    t_apply = time_apply(ctx, False)
-    roof = roofline(ctx, t_apply, 8, FP64_VECTOR_PEAK_TFLOPS, "pair_kernel<double,6,16,1> (Hbar, 16^3 p=5, 8 orbitals)")
-    gdof = ctx.n_dof * n_orb / t_apply / 1e9
-    n_dof, n_cell = ctx.n_dof, ctx.n_cell
-    ctx.close()
-    del ctx
-    torch.cuda.empty_cache()
-
-    mixed = None
-    if not args.no_mixed:
-        ctxm, wall_m, ks_m, mu32 = run(tdfe.MIXED_FP32)
-        per_call_m = per_call_rate(ctxm)
-        t_apply_m = time_apply(ctxm, True)
-        err = float(np.abs(mu32 - mu64).max() / np.abs(mu64).max())
-        dmu = mu64 - mu64[0]
-        err_induced = float(np.abs(mu32 - mu64).max() / max(np.abs(dmu).max(), 1e-300))
-        mixed = {"value": args.steps / wall_m, "unit": "Magnus steps/s", "ms_per_step": 1e3 * wall_m / args.steps,
-                 "dtype": "f32 operator + Krylov storage, f64 scalars/orbitals",
-                 "lanczos_tol": f"max({cfg.tol:g}, 16 * 2^-24 * ||psibar_alpha||) per orbital (FP32 storage floor)",
-                 "speedup_vs_f64": (args.steps / wall_m) / steps_per_s,
-                 "per_call_steps_per_s": per_call_m,
-                 "dipole_rel_err": err, "dipole_err_rel_induced": err_induced,
-                 "steps_compared": len(mu64), "krylov_its_per_step": ks_m / args.steps,
-                 "apply_H_gdof_orb_per_s": ctxm.n_dof * n_orb / t_apply_m / 1e9,
-                 "roofline": roofline(ctxm, t_apply_m, 4, FP32_VECTOR_PEAK_TFLOPS,
-                                      "plane_kernel<float,6,16,2> (Hbar, 16^3 p=5, 8 orbitals)")}
-        ctxm.close()
-
+    res = workload_legs(cfg, args.steps, args.warmup, args.apply_reps, curved, matched=not args.no_matched,
+                        jacobi_count=curved and cfg.hartree)
+    f64 = res["f64"]
+    counts = {"krylov_its_per_step": f64["krylov_its_per_step"]}
+    if "jacobi_pcg_its_per_solve" in res:
+        counts["jacobi_pcg_its_per_step"] = 2.0 * res["jacobi_pcg_its_per_solve"]
+    hartree = ("none" if not cfg.hartree else
+               ("CG with the fast diagonalisation of the axis-averaged rectilinear mesh as preconditioner, "
+                f"relative residual {cfg.pcg_tol:g}" if curved else "fast diagonalisation (exact)"))
     out = {
         "metric": "Magnus steps/sec and apply_H GDoF-orbitals/s, FP64 vs mixed at dipole err<=1e-5",
-        "value": steps_per_s, "unit": "Magnus steps/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": 1e3 * dt_wall / args.steps, "higher_is_better": True,
+        "value": f64["steps_per_s"], "unit": "Magnus steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": 1e3 * f64["wall"] / args.steps, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
-        "config": {"workload": cfg.name, "n_dof": n_dof, "n_cell": n_cell, "p": cfg.p,
-                   "n_orb": n_orb, "dt": cfg.dt, "tol": cfg.tol, "krylov_its_per_step": ks_total / args.steps,
-                   "hartree": "fast diagonalisation (exact)", "xc": cfg.xc},
-        "apply_H_gdof_orb_per_s": gdof,
-        "per_call_steps_per_s": per_call,
-        "production_tolerance": prod,
-        "timed_region": "one tdfe_propagate call of the timed steps (per_call_steps_per_s: one magnus_step call per step)",
-        "roofline": roof,
-        "mixed": mixed,
+        "config": {"workload": cfg.name, "n_dof": res["n_dof"], "n_cell": res["n_cell"], "p": cfg.p,
+                   "n_orb": cfg.n_orb, "dt": cfg.dt, "tol": cfg.tol, "krylov_its_per_step": f64["krylov_its_per_step"],
+                   "krylov_chunk_orbitals": f64["chunk_orbitals"], "hartree": hartree,
+                   "hartree_its_last_solve": f64["poisson_its_last_solve"],
+                   "jacobi_pcg_its_per_solve": res.get("jacobi_pcg_its_per_solve"), "xc": cfg.xc},
+        "apply_H_gdof_orb_per_s": f64["apply_H_gdof_orb_per_s"],
+        "apply_H_gdof_orb_per_s_mixed": res["mixed"]["apply_H_gdof_orb_per_s"],
+        "timed_region": "one tdfe_propagate call of the timed steps; warm-up steps one magnus_step call each",
+        "roofline": f64["roofline"],
+        "mixed": {"value": res["mixed"]["steps_per_s"], "unit": "Magnus steps/s",
+                  "dtype": "f32 operator + Krylov storage, f64 recurrence scalars / small exponential / orbitals",
+                  "lanczos_tol": f"max({cfg.tol:g}, 16 * 2^-24 * ||psibar_alpha||) per orbital (FP32 storage floor)",
+                  **{k: v for k, v in res["mixed"].items() if k not in ("steps_per_s", "wall")}},
+        "f64_matched_tol": res.get("f64_matched_tol"),
     }
-    if not args.no_adjoint:
-        out["adjoint"] = adjoint_rate()
-    if not args.no_graded:
-        out["graded_apply"] = graded_apply()
-    if not args.no_nonlocal:
-        out["nonlocal"] = nonlocal_term()
-    if not args.no_spectra:
-        out["field_and_spectra"] = field_and_spectra()
-    if not args.no_midpoint:
-        out["midpoint"] = midpoint_modes()
-    if not args.no_adaptive:
-        out["adaptive_mesh"] = adaptive_mesh()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_oracle_baseline(cfg, int(round(ks_total / args.steps)))
+    if not args.no_extras:
+        c2 = W.CONFIGS[2]
+        r2 = workload_legs(c2, 100, 5, 100, False, matched=True)
+        out["box_workload"] = {"workload": c2.name, **r2}
+        for name, fn in (("adjoint", adjoint_rate), ("nonlocal", nonlocal_term), ("field_and_spectra", field_and_spectra),
+                         ("midpoint", midpoint_modes), ("adaptive_mesh", adaptive_mesh)):
+            out[name] = fn()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu_baseline(cpu, cfg, counts)
     print(json.dumps(out), flush=True)
 
 

@@ -84,6 +84,12 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
 tdfe_status tdfe_query(const tdfe_ctx* ctx, int64_t* n_dof, int64_t* n_cell, int64_t* n_quad,
                        size_t* workspace_bytes);
 
+/* krylov_chunk: orbitals per Krylov chunk for a call on n_orb orbitals (the
+ * operator launches of lanczos_expm and magnus_step cover one chunk, 2 *chunk
+ * real columns, at a time); chunks are sized so that (k_max + 2) basis
+ * vectors fit the memory limit stated at tdfe_fe_mesh_setup.  Host only. */
+tdfe_status tdfe_krylov_chunk(const tdfe_ctx* ctx, int n_orb, int* chunk);
+
 /* binds a caller-owned device buffer of >= workspace_bytes (256-byte aligned)
  * and computes the device-side geometry and the diagonal overlap
  * M_jj = sum_e w_i w_j w_k det J_e(node) (GLL quadrature, Sec. spectral FE). */

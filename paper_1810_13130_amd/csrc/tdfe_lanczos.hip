@@ -721,6 +721,12 @@ static int chunk_size(const tdfe_ctx* c, int n_orb) {
   return best;
 }
 
+extern "C" tdfe_status tdfe_krylov_chunk(const tdfe_ctx* c, int n_orb, int* chunk) {
+  if (!c || !chunk || n_orb < 1 || n_orb > c->n_orb_max) return TDFE_EINVAL;
+  *chunk = chunk_size(c, n_orb);
+  return TDFE_OK;
+}
+
 // deferred-result slot `slot` (0 or 1) in the scalar block, past the Lanczos
 // scalars of a full chunk and before the occupations
 static double* result_slot(tdfe_ctx* c, int slot) {

@@ -100,6 +100,7 @@ SIGNATURES = {
     "tdfe_apply_H_add_f32": [_P, _P, _P, ctypes.c_int],
     "tdfe_lanczos_expm": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _IP, _DP],
     "tdfe_density": [_P, _P, ctypes.c_int, _P],
+    "tdfe_krylov_chunk": [_P, ctypes.c_int, _IP],
     "tdfe_scf_fields": [_P, _P, ctypes.c_int, _P, _P],
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
     "tdfe_magnus_step": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -182,9 +183,13 @@ class Context:
         return s
 
     def close(self):
+        """destroy the context and drop its workspace (the memory returns to
+        torch's caching allocator at once, not when this object is collected)"""
         if getattr(self, "h", None):
             self.lib.tdfe_destroy(self.h)
             self.h = None
+        self.workspace = None
+        self._nl_store = None
 
     def __del__(self):
         try:
@@ -331,6 +336,12 @@ class Context:
             out = torch.empty((self.n_cell, self.n_quad // self.n_cell), dtype=torch.float64, device="cuda")
         self._check(self.lib.tdfe_density(self.h, _ptr(psibar), n, _ptr(out)))
         return out
+
+    def krylov_chunk(self, n_orb):
+        """orbitals per Krylov chunk (one operator launch) for a call on n_orb orbitals"""
+        k = ctypes.c_int()
+        self._check(self.lib.tdfe_krylov_chunk(self.h, n_orb, ctypes.byref(k)))
+        return k.value
 
     def scf_fields(self, psibar, phi=True, w=True):
         """(phi over every grid node or None, W = V_H + V_xc at the Gauss points
