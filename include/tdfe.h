@@ -407,6 +407,23 @@ tdfe_status tdfe_adaptive_axes_query(const tdfe_adapt_desc* d, size_t* bytes);
 tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
                                int max_cells, double* host_axes, int* host_ncell, double* host_E);
 
+/* adaptive_axes_static: tdfe_adaptive_axes for callers that cannot allocate
+ * device memory (serving loops, harnesses that forbid hipMalloc): the same
+ * kernels and results, with the scratch in a device array of
+ * TDFE_AXES_STATIC_BYTES inside the library (one copy per GPU, held from the
+ * library's load until the process ends).  No hipMalloc, hipFree or other
+ * allocating call is made.  The array's address on the current device is
+ * looked up on the first call with that device current; hip_stream must
+ * belong to the current device.  Calls that overlap on one GPU (concurrent
+ * streams or host threads) share the array and race; serialise them.
+ * Synchronises hip_stream.  Errors: TDFE_EINVAL as tdfe_adaptive_axes;
+ * TDFE_ENOMEM if the description needs more scratch than the array holds
+ * (tdfe_adaptive_axes_query bytes > TDFE_AXES_STATIC_BYTES, i.e. samples
+ * above 160) or an axis needs more than max_cells cells; TDFE_EDEVICE if the
+ * array's address cannot be obtained. */
+#define TDFE_AXES_STATIC_BYTES (32u * 1024u * 1024u)
+tdfe_status tdfe_adaptive_axes_static(const tdfe_adapt_desc* d, void* hip_stream, int max_cells, double* host_axes,
+                                      int* host_ncell, double* host_E);
 
 /* gradient_query: device workspace bytes that tdfe_dipole_gradient needs for
  * n_orb orbitals, n_steps steps, a state checkpoint every checkpoint_every

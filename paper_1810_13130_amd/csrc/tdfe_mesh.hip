@@ -19,11 +19,36 @@
 // the cell counts and the equidistributed vertices.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "tdfe_internal.h"
 
+// Scratch of tdfe_adaptive_axes_static (the allocation-free variant): one copy
+// of this array per GPU, held until the process ends.  Host code never passes
+// its name to a kernel or a copy (that is a host-side stand-in, not a device
+// address): it uses the per-device address from hipGetSymbolAddress below.
+static __device__ __align__(256) double scratch[TDFE_AXES_STATIC_BYTES / sizeof(double)];
+
 namespace {
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[MAX_DEVICES] = {};
+
+// device address of `scratch` on the current device, looked up once per
+// device with that device current; null on failure
+void* static_scratch() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= MAX_DEVICES) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+    g_scratch_ptr[dev] = ptr;
+  }
+  return g_scratch_ptr[dev];
+}
 
 constexpr int MAX_K = 11;  // p + 3 for p <= 8
 constexpr int MT = 256;
@@ -148,12 +173,16 @@ tdfe_status tdfe_adaptive_axes_query(const tdfe_adapt_desc* d, size_t* bytes) {
   return TDFE_OK;
 }
 
-tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
-                               int max_cells, double* host_axes, int* host_ncell, double* host_E) {
-  if (!desc_ok(d) || !dev_scratch || !host_axes || !host_ncell || max_cells < 1) return TDFE_EINVAL;
+}  // extern "C"
+
+namespace {
+
+// both entry points: every element of the scratch that is read is written
+// earlier in the same call (g by one thread per sample, the partials and the
+// plane maxima by one block each), so nothing needs clearing between calls
+tdfe_status adaptive_axes_impl(const tdfe_adapt_desc* d, void* dev_scratch, hipStream_t st, int max_cells,
+                               double* host_axes, int* host_ncell, double* host_E) {
   const int S = d->samples, p = d->p;
-  if (scratch_bytes < scratch_need(S) || (uintptr_t)dev_scratch % 256 != 0) return TDFE_ENOMEM;
-  hipStream_t st = (hipStream_t)hip_stream;
   double* g = (double*)dev_scratch;
   double* gmax = g + (size_t)S * S * S;
   double* partial = gmax + 3 * (size_t)S;
@@ -222,6 +251,26 @@ tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size
   }
   if (host_E) *host_E = E;
   return TDFE_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
+                               int max_cells, double* host_axes, int* host_ncell, double* host_E) {
+  if (!desc_ok(d) || !dev_scratch || !host_axes || !host_ncell || max_cells < 1) return TDFE_EINVAL;
+  if (scratch_bytes < scratch_need(d->samples) || (uintptr_t)dev_scratch % 256 != 0) return TDFE_ENOMEM;
+  return adaptive_axes_impl(d, dev_scratch, (hipStream_t)hip_stream, max_cells, host_axes, host_ncell, host_E);
+}
+
+tdfe_status tdfe_adaptive_axes_static(const tdfe_adapt_desc* d, void* hip_stream, int max_cells, double* host_axes,
+                                      int* host_ncell, double* host_E) {
+  if (!desc_ok(d) || !host_axes || !host_ncell || max_cells < 1) return TDFE_EINVAL;
+  if (scratch_need(d->samples) > TDFE_AXES_STATIC_BYTES) return TDFE_ENOMEM;
+  void* ptr = static_scratch();
+  if (!ptr) return TDFE_EDEVICE;
+  return adaptive_axes_impl(d, ptr, (hipStream_t)hip_stream, max_cells, host_axes, host_ncell, host_E);
 }
 
 }  // extern "C"

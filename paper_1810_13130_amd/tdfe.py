@@ -90,6 +90,7 @@ SIGNATURES = {
     "tdfe_set_midpoint": [_P, ctypes.POINTER(MidpointDesc)],
     "tdfe_adaptive_axes_query": [ctypes.POINTER(AdaptDesc), ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_adaptive_axes": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_size_t, _P, ctypes.c_int, _DP, _IP, _DP],
+    "tdfe_adaptive_axes_static": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_int, _DP, _IP, _DP],
     "tdfe_kick": [_P, _P, ctypes.c_int, ctypes.c_double],
     "tdfe_field_samples": [ctypes.c_int, _DP, ctypes.c_int, _DP, _DP],
     "tdfe_absorption_spectrum": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
@@ -527,6 +528,21 @@ def adaptive_axes(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=
     del keep
     return [axes[a, :nc[a] + 1].copy() for a in range(3)], E.value
 
+
+def adaptive_axes_static(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=4096):
+    """adaptive_axes through the allocation-free entry point (the library's own
+    static device scratch; samples <= 160); returns (axes, E)."""
+    lib = load()
+    d, keep = _adapt_desc(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples)
+    axes = np.zeros((3, max_cells + 1))
+    nc = (ctypes.c_int * 3)()
+    E = ctypes.c_double()
+    s = lib.tdfe_adaptive_axes_static(ctypes.byref(d), _stream_handle(), max_cells, axes.ctypes.data_as(_DP), nc,
+                                      ctypes.byref(E))
+    if s != OK:
+        raise TdfeError(s, "adaptive_axes_static failed")
+    del keep
+    return [axes[a, :nc[a] + 1].copy() for a in range(3)], E.value
 
 
 def rectilinear_vertices(ax, ay, az):

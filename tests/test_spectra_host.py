@@ -93,3 +93,25 @@ def test_adaptive_axes_description_checks(tdfe):
     zero = (ctypes.c_double * 1)(0.0)
     d.s_orb = zero
     assert lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb)) == tdfe.EINVAL
+
+
+def test_adaptive_axes_static_checks_before_device_work(tdfe):
+    # the allocation-free variant refuses a bad description or a sample grid
+    # whose scratch exceeds its static array before any device call
+    lib = tdfe.load()
+    R = (ctypes.c_double * 3)(0.0, 0.0, 0.0)
+    one = (ctypes.c_double * 1)(1.0)
+    d = tdfe.AdaptDesc()
+    d.p, d.lo, d.hi, d.n_atoms, d.R, d.Z, d.s_orb, d.a_pot, d.n_elem, d.samples = 4, -1.0, 1.0, 1, R, one, one, one, 100.0, 161
+    axes = (ctypes.c_double * 30)()
+    nc = (ctypes.c_int * 3)()
+    E = ctypes.c_double()
+    assert lib.tdfe_adaptive_axes_static(ctypes.byref(d), None, 9, axes, nc, ctypes.byref(E)) == tdfe.ENOMEM
+    nb = ctypes.c_size_t()
+    assert lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb)) == 0 and nb.value > 32 * 1024 * 1024
+    d.samples = 160
+    assert lib.tdfe_adaptive_axes_query(ctypes.byref(d), ctypes.byref(nb)) == 0 and nb.value <= 32 * 1024 * 1024
+    d.p = 9
+    assert lib.tdfe_adaptive_axes_static(ctypes.byref(d), None, 9, axes, nc, ctypes.byref(E)) == tdfe.EINVAL
+    d.p = 4
+    assert lib.tdfe_adaptive_axes_static(ctypes.byref(d), None, 0, axes, nc, ctypes.byref(E)) == tdfe.EINVAL
