@@ -463,7 +463,7 @@ class Workload:
         self.vq = None
         self.psi0 = None
 
-    def context(self, precision, pcg_precond=None):
+    def context(self, precision, pcg_precond=None, state=True):
         import torch
         from paper_1810_13130_amd import tdfe
         cfg, W = self.cfg, self.W
@@ -471,6 +471,7 @@ class Workload:
         if self.vq is None:
             xq = ctx.quad_coords().cpu().numpy()
             self.vq = torch.from_numpy(W.external_potential(cfg, xq).reshape(ctx.n_cell, -1))
+        if state and self.psi0 is None:
             self.psi0 = torch.from_numpy(W.initial_psibar(cfg, ctx.dof_coords().cpu().numpy(),
                                                           ctx.mass_diag().cpu().numpy()))
         ctx.set_potential(self.vq.cuda())
@@ -478,7 +479,7 @@ class Workload:
             Z, R = W.atoms(cfg)
             ctx.set_scf(hartree=cfg.hartree, xc={"none": 0, "x": 1, "xc": 2}[cfg.xc], Z=Z, R=R, n_orb=cfg.n_orb,
                         pcg_tol=cfg.pcg_tol, pcg_precond=pcg_precond)
-        return ctx, self.psi0.cuda()
+        return ctx, (self.psi0.cuda() if state else None)
 
 
 def close(ctx):
@@ -644,7 +645,7 @@ def main():
     if args.apply_only:
         wl = Workload(cfg)
         for prec, fp32 in ((tdfe.FP64, False), (tdfe.MIXED_FP32, True)):
-            ctx, _ = wl.context(prec)
+            ctx, _ = wl.context(prec, state=False)
             n = ctx.krylov_chunk(cfg.n_orb)
             t = time_apply(ctx, n, fp32, args.apply_reps)
             print(json.dumps({"precision": "f32" if fp32 else "f64", "launch_orbitals": n, "launch_us": t * 1e6}),

@@ -43,7 +43,7 @@ def build(verbose=False, jobs=None):
             sys.stderr.write(f"--- {src}\n{out}\n")
         raise RuntimeError("HIP build failed: " + ", ".join(s for s, _ in failed))
     tmp = LIB + ".tmp"
-    subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-o", tmp])
+    subprocess.check_call([HIPCC, "-shared", "-fPIC", "--offload-arch=gfx950", *objs, "-lrocblas", "-o", tmp])
     os.replace(tmp, LIB)
     return LIB
 

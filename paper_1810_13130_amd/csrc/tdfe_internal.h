@@ -93,6 +93,7 @@ struct tdfe_ctx {
   // host pinned poll buffer
   int* poll = nullptr;
   int flag_gen = 0;  // generation number of the Lanczos convergence flag (poll[32])
+  void* blas = nullptr;        // rocBLAS handle on `stream` (fast diagonalisation along axes > 128 nodes)
   hipEvent_t* evs = nullptr;  // [TDFE_N_EVENTS] look-ahead polling points
   int n_evs = 0;
 
@@ -239,6 +240,7 @@ tdfe_status tdfe_compute_lift(tdfe_ctx* c);
 tdfe_status tdfe_load_vector(tdfe_ctx* c, const double* f, bool weighted);
 // interior of phi_full <- K00^-1 (4 pi c_interior [- lift]); boundary entries untouched
 tdfe_status tdfe_fdm_solve_into(tdfe_ctx* c, bool with_lift, double* phi_full);
+void tdfe_blas_destroy(tdfe_ctx* c);
 // out_q = phi(x_q) [+ V_xc(rho_q)] for a full-grid nodal field phi
 tdfe_status tdfe_interp_field(tdfe_ctx* c, const double* phi_full, const double* rho, int xcmode, double* out);
 // device array of the occupations f_alpha for n_orb orbitals

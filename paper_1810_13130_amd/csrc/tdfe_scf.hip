@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 
+#include <rocblas/rocblas.h>
+
 #include "tdfe_internal.h"
 #include "tdfe_fold.h"
 
@@ -598,75 +600,56 @@ __global__ void __launch_bounds__(FDM_TB* FDM_G) fdm_tile_kernel(const double* _
   }
 }
 
-// one 1D transform of the interior grid along `axis`:
-//   trans = 1: out[.., m', ..] = sum_m S[m][m'] in[.., m, ..]   (S^T)
-//   trans = 0: out[.., m', ..] = sum_m S[m'][m] in[.., m, ..]   (S)
-// if lam != null the result is divided by lx_i + ly_j + lz_k.
-constexpr int FDM_TL = 16;
-__global__ void __launch_bounds__(256) fdm_axis_kernel(const double* in, double* out, const double* S, int n1x, int n1y,
-                                                       int n1z, int axis, int trans, const double* lx, const double* ly,
-                                                       const double* lz) {
-  extern __shared__ double tile[];  // [n_ax][FDM_TL]
-  const int nax = axis == 0 ? n1x : (axis == 1 ? n1y : n1z);
-  const int64_t nlines = (int64_t)n1x * n1y * n1z / nax;
-  const int64_t l0 = (int64_t)blockIdx.x * FDM_TL;
-  auto base_stride = [&](int64_t line, int64_t& base, int64_t& stride) {
-    if (axis == 0) {
-      base = line * n1x;
-      stride = 1;
-    } else if (axis == 1) {
-      const int64_t i = line % n1x, k = line / n1x;
-      base = i + k * (int64_t)n1x * n1y;
-      stride = n1x;
-    } else {
-      base = line;
-      stride = (int64_t)n1x * n1y;
-    }
-  };
-  for (int idx = threadIdx.x; idx < nax * FDM_TL; idx += blockDim.x) {
-    int m, l;
-    if (axis == 0) {
-      l = idx / nax;
-      m = idx % nax;
-    } else {
-      m = idx / FDM_TL;
-      l = idx % FDM_TL;
-    }
-    const int64_t line = l0 + l;
-    double v = 0.0;
-    if (line < nlines) {
-      int64_t b, s;
-      base_stride(line, b, s);
-      v = in[b + m * s];
-    }
-    tile[m * FDM_TL + l] = v;
+// Axes of more than 128 interior nodes: the 1D transform is a plain dense
+// product of the n1 x n1 table with every grid line along the axis, done by
+// rocBLAS DGEMM (FP64 matrix cores) on the context's stream.  The interior
+// grid, index i + n1x (j + n1y k), is read as column-major matrices:
+//   x: (n1x) x (n1y n1z), ld n1x            out = Op x
+//   y: n1z slabs of (n1x) x (n1y), ld n1x    out = slab Op^T   (strided batched)
+//   z: (n1x n1y) x (n1z), ld n1x n1y        out = in Op^T
+// with Op = S^T (trans = 1) or S (trans = 0); S is stored row-major, i.e. as
+// the column-major S^T.  The scaling by 1 / (lx_i + ly_j + lz_k) follows as
+// its own pass.
+__global__ void fdm_scale_kernel(double* v, int n1x, int n1y, int n1z, const double* lx, const double* ly,
+                                 const double* lz) {
+  const int64_t d = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (d >= (int64_t)n1x * n1y * n1z) return;
+  const int i = (int)(d % n1x), j = (int)((d / n1x) % n1y), k = (int)(d / ((int64_t)n1x * n1y));
+  v[d] /= lx[i] + ly[j] + lz[k];
+}
+
+tdfe_status blas_ready(tdfe_ctx* c) {
+  if (c->blas) return TDFE_OK;
+  rocblas_handle h = nullptr;
+  if (rocblas_create_handle(&h) != rocblas_status_success)
+    return tdfe_fail(c, TDFE_EDEVICE, "rocblas_create_handle failed");
+  if (rocblas_set_stream(h, c->stream) != rocblas_status_success) {
+    rocblas_destroy_handle(h);
+    return tdfe_fail(c, TDFE_EDEVICE, "rocblas_set_stream failed");
   }
-  __syncthreads();
-  for (int idx = threadIdx.x; idx < nax * FDM_TL; idx += blockDim.x) {
-    int mp, l;
-    if (axis == 0) {
-      l = idx / nax;
-      mp = idx % nax;
-    } else {
-      mp = idx / FDM_TL;
-      l = idx % FDM_TL;
-    }
-    const int64_t line = l0 + l;
-    if (line >= nlines) continue;
-    double s = 0.0;
-    if (trans)
-      for (int m = 0; m < nax; ++m) s += S[(int64_t)m * nax + mp] * tile[m * FDM_TL + l];
-    else
-      for (int m = 0; m < nax; ++m) s += S[(int64_t)mp * nax + m] * tile[m * FDM_TL + l];
-    int64_t b, st;
-    base_stride(line, b, st);
-    const int64_t o = b + mp * st;
-    if (lx) {
-      const int64_t i = o % n1x, j = (o / n1x) % n1y, k = o / ((int64_t)n1x * n1y);
-      s /= (lx[i] + ly[j] + lz[k]);
-    }
-    out[o] = s;
+  c->blas = (void*)h;
+  return TDFE_OK;
+}
+
+tdfe_status fdm_blas_pass(tdfe_ctx* c, const double* in, double* out, const double* S, int axis, int trans) {
+  TDFE_TRY(blas_ready(c));
+  rocblas_handle h = (rocblas_handle)c->blas;
+  const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
+  const double one = 1.0, zero = 0.0;
+  const rocblas_operation nt = rocblas_operation_none, tr = rocblas_operation_transpose;
+  rocblas_status st;
+  if (axis == 0) {
+    st = rocblas_dgemm(h, trans ? nt : tr, nt, n1x, n1y * n1z, n1x, &one, S, n1x, in, n1x, &zero, out, n1x);
+  } else if (axis == 1) {
+    const rocblas_stride slab = (rocblas_stride)n1x * n1y;
+    st = rocblas_dgemm_strided_batched(h, nt, trans ? tr : nt, n1x, n1y, n1y, &one, in, n1x, slab, S, n1y, 0, &zero,
+                                       out, n1x, slab, n1z);
+  } else {
+    st = rocblas_dgemm(h, nt, trans ? tr : nt, n1x * n1y, n1z, n1z, &one, in, n1x * n1y, S, n1z, &zero, out,
+                       n1x * n1y);
   }
+  if (st != rocblas_status_success) return tdfe_fail(c, TDFE_EDEVICE, "rocBLAS DGEMM failed (status %d)", (int)st);
+  return TDFE_OK;
 }
 
 // ---- host linear algebra for the 1D fast-diagonalisation tables ------------------------------
@@ -825,7 +808,7 @@ tdfe_status fdm_passes(tdfe_ctx* c) {
                        n1y, n1z, axis, sl, ly, lz);                                                            \
   } while (0)
     if (shm_t > 160 * 1024 || mpt > 8)
-      mpt = 1 << 30;  // matrix does not fit LDS: line-tiled kernel below
+      mpt = 1 << 30;  // matrix does not fit LDS: rocBLAS below
     if (mpt <= 1)
       TDFE_FDM_TILE(1);
     else if (mpt <= 2)
@@ -842,9 +825,10 @@ tdfe_status fdm_passes(tdfe_ctx* c) {
       TDFE_FDM_TILE(8);
 #undef TDFE_FDM_TILE
     else {
-      const size_t shm = (size_t)nax * FDM_TL * sizeof(double);
-      hipLaunchKernelGGL(fdm_axis_kernel, dim3((unsigned)((nlines + FDM_TL - 1) / FDM_TL)), dim3(256), shm, c->stream,
-                         in, out, S, n1x, n1y, n1z, axis, trans, sl, ly, lz);
+      TDFE_TRY(fdm_blas_pass(c, in, out, S, axis, trans));
+      if (sl) {
+        hipLaunchKernelGGL(fdm_scale_kernel, dim3(nblk(nd)), dim3(EW), 0, c->stream, out, n1x, n1y, n1z, sl, ly, lz);
+      }
     }
     TDFE_HIP(c, hipGetLastError());
     return TDFE_OK;
@@ -1448,6 +1432,11 @@ tdfe_status tdfe_load_vector(tdfe_ctx* c, const double* f, bool weighted) {
   return load_launch_f(c, f, weighted ? 1 : 0);
 }
 
+void tdfe_blas_destroy(tdfe_ctx* c) {
+  if (c->blas) rocblas_destroy_handle((rocblas_handle)c->blas);
+  c->blas = nullptr;
+}
+
 tdfe_status tdfe_fdm_solve_into(tdfe_ctx* c, bool with_lift, double* phi_full) {
   if (!c->box) return tdfe_fail(c, TDFE_EINVAL, "Hartree adjoint: needs a box mesh (exact inverse)");
   return fdm_solve(c, with_lift, phi_full);
@@ -1557,15 +1546,19 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
     TDFE_HIP(c, hipGetLastError());
     TDFE_TRY(tdfe_compute_lift(c));
     TDFE_HIP(c, hipStreamSynchronize(c->stream));
+    const bool fdm = c->box || c->pcg_precond == TDFE_PCG_FDM;
     if (c->box) {
       TDFE_TRY(tdfe_fdm_setup(c));
     } else {
       TDFE_TRY(stiffness_diag(c));
-      if (c->pcg_precond == TDFE_PCG_FDM) {
+      if (fdm) {
         stand_in_axes(c);
         TDFE_TRY(tdfe_fdm_setup(c));
       }
     }
+    // axes of more than 128 interior nodes transform through rocBLAS: its
+    // handle (and the device memory it takes) is made here, not in the step
+    if (fdm && std::max(c->Nx, std::max(c->Ny, c->Nz)) - 2 > 128) TDFE_TRY(blas_ready(c));
   }
   c->have_scf = c->hartree || c->xc != TDFE_XC_NONE;
   c->scf_init = false;

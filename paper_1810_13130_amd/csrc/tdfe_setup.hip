@@ -509,6 +509,7 @@ void tdfe_destroy(tdfe_ctx* c) {
   if (c->bound) (void)hipStreamSynchronize(c->stream);
   for (int i = 0; i < c->n_evs; ++i) (void)hipEventDestroy(c->evs[i]);
   delete[] c->evs;
+  tdfe_blas_destroy(c);
   if (c->poll) (void)hipHostFree(c->poll);
   delete c;
 }

@@ -165,3 +165,53 @@ def test_mixed_precision_gradient_tracks_fp64():
     print(f"mixed gradient: L rel {abs(L32 - L64) / abs(L64):.2e}, grad rel {rel(g32, g64):.2e}", flush=True)
     assert abs(L32 - L64) <= 1e-5 * abs(L64)
     assert rel(g32, g64) < 1e-5  # observed 3.9e-7
+
+
+def test_adjoint_workload_at_its_protocol():
+    """The adjoint workload as specified: 16^3 cells, p = 5, 8 orbitals,
+    Hartree + exchange, 200 steps with the seeded amplitudes E_n, a state
+    checkpoint every 25 steps; the FP64 and the mixed-precision gradients
+    against central differences (h = 1e-6) of the FP64 forward map on the ten
+    seeded components.  The forward map runs at tol 1e-12, so that the
+    adaptive Krylov dimension moves L by at most ~1e-12 when a component is
+    perturbed (5e-7 in a difference quotient with h = 1e-6)."""
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[5]
+    n = 200
+    E = W.field_amplitudes(n)
+    idx = W.fd_indices(n)
+    Z, R = W.atoms(cfg)
+    ctx, psi = _gpu(cfg, True)
+    print(f"[adjoint-protocol] gradient FP64 over {n} steps", flush=True)
+    L, g = ctx.dipole_gradient(psi, E, cfg.dt, tol=1e-12, checkpoint_every=25, k_store=64)
+
+    def forward(Ev):
+        x = psi.clone()
+        ctx.set_scf(hartree=True, xc=1, Z=Z, R=R, n_orb=cfg.n_orb)  # W_-1 = W_0 = W[rho(psibar0)]
+        _, rep = ctx.propagate(x, n, cfg.dt, Ev, 1e-12, record=False)
+        return rep["mu"][2]
+
+    assert abs(forward(E) - L) <= 1e-10 * max(abs(L), 1e-3)
+    h = 1e-6
+    fd = []
+    for k in idx:
+        ep, em = E.copy(), E.copy()
+        ep[k] += h
+        em[k] -= h
+        fd.append((forward(ep) - forward(em)) / (2 * h))
+    fd = np.array(fd)
+    scale = np.abs(fd).max()
+    err64 = np.abs(g[idx] - fd)
+    print(f"[adjoint-protocol] FP64: |g| max {scale:.3e}, max |g - fd| / max|fd| {err64.max() / scale:.2e}, "
+          f"per component rel {(err64 / np.abs(fd)).max():.2e}", flush=True)
+    ctx.close()
+    ctx32, psi32 = _gpu(cfg, True, precision=tdfe.MIXED_FP32)
+    print(f"[adjoint-protocol] gradient mixed over {n} steps", flush=True)
+    L32, g32 = ctx32.dipole_gradient(psi32, E, cfg.dt, tol=1e-12, checkpoint_every=25, k_store=64)
+    ctx32.close()
+    err32 = np.abs(g32[idx] - fd)
+    print(f"[adjoint-protocol] mixed: L rel {abs(L32 - L) / abs(L):.2e}, max |g - fd| / max|fd| "
+          f"{err32.max() / scale:.2e}", flush=True)
+    assert err64.max() <= 1e-5 * scale
+    assert err32.max() <= 1e-5 * scale
+    assert abs(L32 - L) <= 1e-5 * abs(L)
