@@ -53,6 +53,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
   __shared__ T sX[CPB * VOL * CB];
   __shared__ T sV[CPB * VOL];
   __shared__ T sG[CPB * VOL * 6];
+  __shared__ T sM[CPB * VOL];
   __shared__ double sRed[THREADS];
   if (P.done && *P.done) return;
 
@@ -84,7 +85,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     MV = (const MT*)P.minv;
   else
     MV = (const MT*)P.minv32;
-  T cs = (T)1;
+  T cs = act ? (T)1 : (T)0;
   if (P.colscale && act) cs = (T)P.colscale[colg >> 1];
 
   // block staging in three steps, so that a wave waits for memory once and
@@ -110,6 +111,30 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
     }
   }
   const int64_t c0 = (int64_t)group * CPB;
+  // per-node scale of the block's cells, staged once per block (the column
+  // lanes of a plane share it): M^-1/2 on DoFs (1 without the Loewdin
+  // scaling) and 0 on Dirichlet nodes and past the last cell, which zeroes
+  // their gathered values and their scattered contributions
+  constexpr int NM = NV;
+  T mr[NM];
+#pragma unroll
+  for (int k = 0; k < NM; ++k) {
+    const int q = t + k * THREADS;
+    const int64_t ce = c0 + q / VOL;
+    const int r = q % VOL;
+    bool in = q < CPB * VOL && ce < P.n_cell;
+    int64_t idx = 0;
+    if (in) {
+      const int ex = (int)(ce % P.ncx), ey = (int)((ce / P.ncx) % P.ncy), ez = (int)(ce / ((int64_t)P.ncx * P.ncy));
+      const int I = ex * P.p + r % N, Jn = ey * P.p + (r / N) % N, K = ez * P.p + r / (N * N);
+      if (!P.fullgrid) {
+        in = I > 0 && I < P.Nx - 1 && Jn > 0 && Jn < P.Ny - 1 && K > 0 && K < P.Nz - 1;
+        idx = (int64_t)(I - 1) + (int64_t)(P.Nx - 2) * ((int64_t)(Jn - 1) + (int64_t)(P.Ny - 2) * (K - 1));
+      }
+    }
+    const T mval = MV[(in && P.lowdin) ? idx : 0];
+    mr[k] = in ? (P.lowdin ? mval : (T)1) : (T)0;
+  }
   T vr[NV];
 #pragma unroll
   for (int k = 0; k < NV; ++k) {
@@ -211,7 +236,10 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         const int q = t + k * THREADS;
-        if (q < CPB * VOL) sV[q] = vr[k];
+        if (q < CPB * VOL) {
+          sV[q] = vr[k];
+          sM[q] = mr[k];
+        }
       }
 #pragma unroll
       for (int k = 0; k < NCR; ++k) {
@@ -221,18 +249,47 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       __syncthreads();
       compute_metric();
     }
-    T u[N][N], mv[N][N];  // [i][k]: gathered values and M^-1/2, all loads in flight together
+    // The gather reads through a buffer resource that starts at the block's
+    // first node row: nodes outside the array (the Dirichlet planes at the
+    // domain faces) have negative offsets or offsets past the end and read
+    // 0; Dirichlet nodes inside its range (I = 0 or Nx-1, which alias a
+    // neighbouring row's DoF) read a value that the zero in sM cancels.  No
+    // address is selected and no value is masked.  The range is kept below
+    // 2^31 bytes, so every negative 32-bit offset is out of range; a block
+    // spans at most (n-1)(1 + row + plane) rows, far below that.
+    T u[N][N];  // [i][k]: gathered values, all loads in flight together
+    {
+      // the resource is built from the block's first cell (the lowest rows
+      // any of its cells touches) and made explicitly wave-uniform
+      const int64_t rows = P.fullgrid ? (int64_t)P.Nx * P.Ny * P.Nz : (int64_t)NxI * NyI * (P.Nz - 2);
+      const int bx = (int)(c0 % P.ncx), by = (int)((c0 / P.ncx) % P.ncy), bz = (int)(c0 / ((int64_t)P.ncx * P.ncy));
+      const int64_t first = P.fullgrid ? (int64_t)bx * P.p + (int64_t)P.Nx * ((int64_t)by * P.p +
+                                                                              (int64_t)P.Ny * bz * P.p)
+                                       : (int64_t)(bx * P.p - 1) + (int64_t)NxI * ((int64_t)(by * P.p - 1) +
+                                                                                 (int64_t)NyI * (bz * P.p - 1));
+      const int64_t base = first > 0 ? first : 0;
+      const int64_t bytes = (rows - base) * P.ld * (int64_t)sizeof(T);
+      const uint64_t addr = (uint64_t)(uintptr_t)(X + base * P.ld);
+      const uint32_t alo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+      const uint32_t ahi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+      const int nrec = __builtin_amdgcn_readfirstlane((int)(bytes < 0x7fffffff ? bytes : 0x7fffffff));
+      const __amdgpu_buffer_rsrc_t rx = __builtin_amdgcn_make_buffer_rsrc(
+          (void*)(uintptr_t)(((uint64_t)ahi << 32) | alo), 0, nrec, 0x00020000);
+      const int ldb = P.ld * (int)sizeof(T);
+      const int64_t kst = nk * ldb;
+      const int64_t off0 = ((n0 - base) * P.ld + colg) * (int64_t)sizeof(T);
 #pragma unroll
-    for (int k = 0; k < N; ++k)
+      for (int k = 0; k < N; ++k) {
+        const int ok = (int)(off0 + k * kst);
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        // every load is issued from a valid address (masked entries read
-        // element 0 and are zeroed), so the gather has no branches
-        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
-        const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
-        u[i][k] = X[nd * P.ld + colg * (ok ? 1 : 0)];
-        mv[i][k] = MV[P.lowdin ? nd : 0];
+        for (int i = 0; i < N; ++i) {
+          if constexpr (sizeof(T) == 8)
+            u[i][k] = __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(rx, ok + i * ldb, 0, 0));
+          else
+            u[i][k] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(rx, ok + i * ldb, 0, 0));
+        }
       }
+    }
     // keep the scaling below from being interleaved with the loads (which
     // would make each load wait for its own value)
     __builtin_amdgcn_sched_barrier(0);
@@ -240,7 +297,10 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
       for (int k = 0; k < NV; ++k) {
         const int q = t + k * THREADS;
-        if (q < CPB * VOL) sV[q] = vr[k];
+        if (q < CPB * VOL) {
+          sV[q] = vr[k];
+          sM[q] = mr[k];
+        }
       }
 #pragma unroll
       for (int k = 0; k < NCR; ++k) {
@@ -253,10 +313,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 #pragma unroll
     for (int k = 0; k < N; ++k)
 #pragma unroll
-      for (int i = 0; i < N; ++i) {
-        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
-        u[i][k] = ok ? u[i][k] * (P.lowdin ? mv[i][k] * cs : cs) : (T)0;
-      }
+      for (int i = 0; i < N; ++i) u[i][k] *= sM[slot * VOL + i + N * (pl + N * k)] * cs;
 #pragma unroll
     for (int k = 0; k < N; ++k) {
       T line[N], o1[N], o2[N];
@@ -424,19 +481,17 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
       // one wait per line covers them
       T ml[N];
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
-        const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
-        ml[k] = MV[P.lowdin ? nd : 0];
-      }
+      for (int k = 0; k < N; ++k) ml[k] = sM[slot * VOL + i + N * (pl + N * k)];
       T o[N];
       eo<T, N, 1>(FS.Bt, h[i], o);
+      // imask / kmask depend on the cell only, so these branches are uniform
+      // whenever a wave holds one cell; act and the plane's own row test are
+      // folded into imask
+      if ((imask >> i) & 1u) {
+        T* yrow = Y + ((n0 + i) * P.ld + colg);
 #pragma unroll
-      for (int k = 0; k < N; ++k) {
-        const bool ok = ((imask >> i) & (kmask >> k) & 1u) != 0;
-        const int64_t nd = ok ? n0 + i + (int64_t)k * nk : 0;
-        const T val = P.lowdin ? o[k] * ml[k] : o[k];
-        if (ok) unsafeAtomicAdd(Y + (nd * P.ld + colg), val);
+        for (int k = 0; k < N; ++k)
+          if ((kmask >> k) & 1u) unsafeAtomicAdd(yrow + (int64_t)k * nk * P.ld, o[k] * ml[k]);
       }
     }
   }
@@ -456,7 +511,7 @@ __global__ void __launch_bounds__(CPB * N * CB) __attribute__((amdgpu_waves_per_
 template <typename T, int N, int CB>
 constexpr int cplane_lds(int cpb) {
   constexpr int VOL = N * N * N;
-  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) * 7 + cpb * N * CB * 8 + cpb * 24 * 8;
+  return cpb * VOL * CB * (int)sizeof(T) + cpb * VOL * (int)sizeof(T) * 8 + cpb * N * CB * 8 + cpb * 24 * 8;
 }
 
 // cells per block: at most 512 threads; the metric makes a cell's LDS about
