@@ -229,6 +229,22 @@ tdfe_status tdfe_lanczos_expm(tdfe_ctx* ctx, void* dev_psibar, int n_orb, double
  * from the PCG solve. */
 tdfe_status tdfe_scf_fields(tdfe_ctx* ctx, const void* dev_psibar, int n_orb, double* dev_phi, double* dev_w);
 
+/* tridiag_expm: the small exponential of the Lanczos approximation (Eq. zk),
+ * y = exp(-i tau T) e_1 for one real symmetric tridiagonal T of order k
+ * (1 <= k <= 1024): diagonal dev_alpha[k], off-diagonal dev_beta[k-1]
+ * (FP64 device; dev_beta may be NULL for k = 1); dev_y [k] complex128
+ * interleaved (device).  The same evaluation the Lanczos stop test uses: a
+ * Chebyshev series on the Gershgorin interval [c - r, c + r] of T with
+ * Jacobi-Anger coefficients 2 (-i)^m J_m(|tau| r), about |tau| r terms, for
+ * |tau| r up to about 6.5e4.  No context; dev_scratch (>= the queried bytes,
+ * 256-byte aligned) holds the Bessel table.  Synchronises hip_stream;
+ * *host_terms (may be NULL) receives the number of terms.  Errors: EINVAL for
+ * bad arguments or |tau| r beyond the table, ENOMEM for a small or misaligned
+ * scratch, ENONFINITE for an Inf or NaN spread of T. */
+tdfe_status tdfe_tridiag_expm_query(int k, size_t* bytes);
+tdfe_status tdfe_tridiag_expm(const double* dev_alpha, const double* dev_beta, int k, double tau, double* dev_y,
+                              void* dev_scratch, size_t scratch_bytes, void* hip_stream, int* host_terms);
+
 /* density at the Gauss points, rho_q = sum_alpha f_alpha |psi_alpha(x_q)|^2,
  * psi = M^-1/2 psibar interpolated with the GLL basis (Sec. TDKS equations).
  * dev_rho_q: [n_cell][nq^3] FP64 device. */

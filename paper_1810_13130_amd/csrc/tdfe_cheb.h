@@ -4,21 +4,23 @@
 // coefficients 2 (-i sgn(s))^m J_m(|s| r), Bessel values by Miller's backward
 // recurrence normalised with J_0 + 2 sum J_2m = 1, and the three-term
 // recurrence v_{m+1} = 2 X v_m - v_{m-1}, X = (T - c)/r, v_0 = e_1, rows across
-// lanes.  cheb_expm_e1 and cheb_expm_e1_wave use workgroup barriers, so every
-// thread of the workgroup calls them; cheb_expm_e1_wave_gtab involves one
-// wavefront only.
+// lanes.  cheb_expm_e1 and cheb_expm_e1_wave run on a one-wavefront
+// workgroup and use its barriers; cheb_expm_e1_wave_gtab involves one
+// wavefront of a larger workgroup only.  Every path reads its Bessel
+// coefficients from a per-orbital table in global memory.
 #pragma once
 #include <hip/hip_runtime.h>
 
 #define TDFE_CHEB_THREADS 64
-#define TDFE_MAX_BESSEL 6144
+// largest Bessel table: |s| r up to about 6.5e4 (the all-electron-like
+// workload's smallest cells reach a few 1e4 at its dt)
+#define TDFE_MAX_BESSEL 65536
 #define TDFE_KCAP 1024
-// per-wavefront Bessel table in global memory for cheb_expm_e1_wave_gtab:
-// the table plus two register chunks of padding for the look-ahead load
+// per-orbital Bessel table in global memory (every evaluation path): the
+// table plus two register chunks of padding for the look-ahead load
 #define TDFE_JTAB_STRIDE (TDFE_MAX_BESSEL + 2 + 2 * TDFE_CHEB_THREADS)
 
 struct ChebLds {
-  double J[TDFE_MAX_BESSEL + 2];
   double bufA[TDFE_KCAP], bufB[TDFE_KCAP];
   double yr[TDFE_KCAP], yi[TDFE_KCAP];
   double red[3 * TDFE_CHEB_THREADS];
@@ -82,11 +84,19 @@ __device__ __forceinline__ double lane_next(double v) {
   return __hiloint2double(hi, lo);
 }
 
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
+  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
+  return __hiloint2double(hi, lo);
+}
+
 // Same result for k <= TDFE_CHEB_THREADS, one row per lane of a single
 // wavefront: the Chebyshev vectors stay in registers and the tridiagonal
 // neighbours come from DPP lane shifts, so a term costs no LDS round trip.
-// Lane j returns row j of y in (yr, yi) (zero for j >= k).  J is an LDS
-// table of TDFE_MAX_BESSEL + 2 entries, Ms / invs LDS scalars.
+// Lane j returns row j of y in (yr, yi) (zero for j >= k).  J is the
+// orbital's global table of TDFE_JTAB_STRIDE entries, Ms / invs LDS scalars;
+// every lane keeps 64 consecutive coefficients in one register and each term
+// takes its own by a lane read.
 __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* sb, double s, double* J, int* Ms,
                                         double* invs, double& yr, double& yi, double* amax) {
   const int t = threadIdx.x;
@@ -106,6 +116,8 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
   const double z = fabs(s) * rr;
   if (t == 0) *Ms = cheb_bessel(z, J, invs);
+  // lane 0's table stores complete and are visible to every lane's loads
+  __threadfence();
   __syncthreads();
   const int M = *Ms;
   const double jn = *invs;
@@ -115,20 +127,26 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
   const double ac = row ? a - cc : 0.0;
+  double jr = J[t];
+  double jnx = J[TDFE_CHEB_THREADS + t];
   double vp = (t == 0) ? 1.0 : 0.0;
-  yr = jn * J[0] * vp;
+  yr = jn * lane_read(jr, 0) * vp;
   if (M >= 1) {
     double left = lane_prev(vp), right = lane_next(vp);
     double vc = (ac * vp + bl * left + br * right) * invr;
-    yi += -2.0 * sgn * jn * J[1] * vc;
+    yi += -2.0 * sgn * jn * lane_read(jr, 1) * vc;
     for (int mm = 2; mm <= M; ++mm) {
+      if ((mm & (TDFE_CHEB_THREADS - 1)) == 0) {
+        jr = jnx;
+        jnx = J[mm + TDFE_CHEB_THREADS + t];  // < TDFE_JTAB_STRIDE since mm <= M < TDFE_MAX_BESSEL
+      }
       left = lane_prev(vc);
       right = lane_next(vc);
       const double w = ac * vc + bl * left + br * right;
       const double vn = 2.0 * w * invr - vp;
       vp = vc;
       vc = vn;
-      const double cj = 2.0 * jn * J[mm];
+      const double cj = 2.0 * jn * lane_read(jr, mm & (TDFE_CHEB_THREADS - 1));
       const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
       if (ph == 0) yr += cj * vn;
       else if (ph == 1) yi -= sgn * cj * vn;
@@ -141,12 +159,6 @@ __device__ inline int cheb_expm_e1_wave(int k, const double* sa, const double* s
   yr = a0 * pr - b0 * pim;
   yi = a0 * pim + b0 * pr;
   return M;
-}
-
-__device__ __forceinline__ double lane_read(double v, int lane) {
-  const int lo = __builtin_amdgcn_readlane(__double2loint(v), lane);
-  const int hi = __builtin_amdgcn_readlane(__double2hiint(v), lane);
-  return __hiloint2double(hi, lo);
 }
 
 // The same series as cheb_expm_e1_wave, with the same arithmetic in the same
@@ -221,10 +233,13 @@ __device__ inline int cheb_expm_e1_wave_gtab(int k, double a, double bl, double 
   return M;
 }
 
-// returns the number of terms M (>= 0), -1 if |s| r exceeds the Bessel table or
-// TDFE_CHEB_NONFINITE if it is not finite;
-// *amax receives max_j |sa[j]|
-__device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, double s, ChebLds& L, double* amax) {
+// k up to TDFE_KCAP rows on ONE wavefront (rows t, t + 64, ... per lane, the
+// Chebyshev vectors in LDS); the coefficients come from the orbital's global
+// table Jg as in cheb_expm_e1_wave.  Returns the number of terms M (>= 0),
+// -1 if |s| r exceeds the Bessel table or TDFE_CHEB_NONFINITE if it is not
+// finite; *amax receives max_j |sa[j]|
+__device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, double s, ChebLds& L, double* Jg,
+                                   double* amax) {
   const int t = threadIdx.x;
   double lo = 1e300, hi = -1e300, am = 0.0;
   for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
@@ -252,16 +267,21 @@ __device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, do
   *amax = L.red[2 * TDFE_CHEB_THREADS];
   const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
   const double z = fabs(s) * rr;
-  if (t == 0) L.M = cheb_bessel(z, L.J, &L.inv);
+  if (t == 0) L.M = cheb_bessel(z, Jg, &L.inv);
+  // lane 0's table stores complete and are visible to every lane's loads
+  __threadfence();
   __syncthreads();
   const int M = L.M;
   const double jn = L.inv;
   if (M < 0) return M;
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
+  double jr = Jg[t];
+  double jnx = Jg[TDFE_CHEB_THREADS + t];
+  const double J0 = lane_read(jr, 0), J1 = lane_read(jr, 1);
   for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
     L.bufA[j] = (j == 0) ? 1.0 : 0.0;
-    L.yr[j] = jn * L.J[0] * L.bufA[j];
+    L.yr[j] = jn * J0 * L.bufA[j];
     L.yi[j] = 0.0;
   }
   __syncthreads();
@@ -274,11 +294,15 @@ __device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, do
       if (j < k - 1) w += sb[j] * prev[j + 1];
       w *= invr;
       cur[j] = w;
-      L.yi[j] += -2.0 * sgn * jn * L.J[1] * w;
+      L.yi[j] += -2.0 * sgn * jn * J1 * w;
     }
     __syncthreads();
     for (int mm = 2; mm <= M; ++mm) {
-      const double cj = 2.0 * jn * L.J[mm];
+      if ((mm & (TDFE_CHEB_THREADS - 1)) == 0) {
+        jr = jnx;
+        jnx = Jg[mm + TDFE_CHEB_THREADS + t];  // < TDFE_JTAB_STRIDE since mm <= M < TDFE_MAX_BESSEL
+      }
+      const double cj = 2.0 * jn * lane_read(jr, mm & (TDFE_CHEB_THREADS - 1));
       const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
       for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
         double w = (sa[j] - cc) * cur[j];

@@ -326,7 +326,7 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
 
 __global__ void __launch_bounds__(CHK_THREADS)
     check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int* err_flag,
-                 int* host_flag, int gen) {
+                 int* host_flag, int gen, double* jtab) {
   __shared__ ChebLds L;
   __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
   const int o = blockIdx.x;
@@ -340,12 +340,12 @@ __global__ void __launch_bounds__(CHK_THREADS)
   double amax = 0.0;
   if (k <= CHK_THREADS) {
     double yr = 0.0, yi = 0.0;
-    const int M = cheb_expm_e1_wave(k, sa, sb, tau, L.J, &L.M, &L.inv, yr, yi, &amax);
+    const int M = cheb_expm_e1_wave(k, sa, sb, tau, jtab + (size_t)o * TDFE_JTAB_STRIDE, &L.M, &L.inv, yr, yi, &amax);
     const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
     stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], ylr, yli, yr, yi, nullptr, nullptr,
               CHK_THREADS, err_flag, host_flag, gen);
   } else {
-    const int M = cheb_expm_e1(k, sa, sb, tau, L, &amax);
+    const int M = cheb_expm_e1(k, sa, sb, tau, L, jtab + (size_t)o * TDFE_JTAB_STRIDE, &amax);
     stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], L.yr[k - 1], L.yi[k - 1], 0.0, 0.0, L.yr,
               L.yi, CHK_THREADS, err_flag, host_flag, gen);
   }
@@ -573,7 +573,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
                          (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 3, S.scale + (size_t)k * Nc,
                          S.cs + (size_t)k * Nc, (const double*)nullptr, (const int*)S.done);
       hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
-                         err_flag, dflag, gen);
+                         err_flag, dflag, gen, c->jtab);
     }
     TDFE_HIP(c, hipGetLastError());
     if (k > LOOK) {
@@ -719,6 +719,70 @@ static int chunk_size(const tdfe_ctx* c, int n_orb) {
     }
   }
   return best;
+}
+
+// y = exp(-i tau T) e_1 for one tridiagonal T given on the device (the small
+// exponential of the Lanczos stop test, on its own): one wavefront, the same
+// series and Bessel table as check_kernel
+__global__ void __launch_bounds__(CHK_THREADS)
+    tridiag_expm_kernel(const double* alpha, const double* beta, int k, double tau, double* y, double* jtab,
+                        int* status) {
+  __shared__ ChebLds L;
+  __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
+  const int t = threadIdx.x;
+  for (int j = t; j < k; j += CHK_THREADS) {
+    sa[j] = alpha[j];
+    sb[j] = j < k - 1 ? beta[j] : 0.0;
+  }
+  __syncthreads();
+  double amax = 0.0;
+  int M;
+  if (k <= CHK_THREADS) {
+    double yr = 0.0, yi = 0.0;
+    M = cheb_expm_e1_wave(k, sa, sb, tau, jtab, &L.M, &L.inv, yr, yi, &amax);
+    if (M >= 0 && t < k) {
+      y[2 * t] = yr;
+      y[2 * t + 1] = yi;
+    }
+  } else {
+    M = cheb_expm_e1(k, sa, sb, tau, L, jtab, &amax);
+    if (M >= 0)
+      for (int j = t; j < k; j += CHK_THREADS) {
+        y[2 * j] = L.yr[j];
+        y[2 * j + 1] = L.yi[j];
+      }
+  }
+  if (t == 0) *status = M;
+}
+
+extern "C" tdfe_status tdfe_tridiag_expm_query(int k, size_t* bytes) {
+  if (!bytes || k < 1 || k > TDFE_KCAP) return TDFE_EINVAL;
+  *bytes = (size_t)(TDFE_JTAB_STRIDE + 8) * sizeof(double);
+  return TDFE_OK;
+}
+
+extern "C" tdfe_status tdfe_tridiag_expm(const double* dev_alpha, const double* dev_beta, int k, double tau,
+                                         double* dev_y, void* dev_scratch, size_t scratch_bytes, void* hip_stream,
+                                         int* host_terms) {
+  if (!dev_alpha || !dev_y || !dev_scratch || k < 1 || k > TDFE_KCAP || (k > 1 && !dev_beta) || !std::isfinite(tau))
+    return TDFE_EINVAL;
+  size_t need = 0;
+  TDFE_TRY(tdfe_tridiag_expm_query(k, &need));
+  if (scratch_bytes < need || (uintptr_t)dev_scratch % 256 != 0) return TDFE_ENOMEM;
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* jtab = (double*)dev_scratch;
+  int* dstatus = (int*)(jtab + TDFE_JTAB_STRIDE);
+  hipLaunchKernelGGL(tridiag_expm_kernel, dim3(1), dim3(CHK_THREADS), 0, st, dev_alpha, dev_beta, k, tau, dev_y, jtab,
+                     dstatus);
+  if (hipGetLastError() != hipSuccess) return TDFE_EDEVICE;
+  int M = 0;
+  if (hipMemcpyAsync(&M, dstatus, sizeof(int), hipMemcpyDeviceToHost, st) != hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess)
+    return TDFE_EDEVICE;
+  if (host_terms) *host_terms = M;
+  if (M == TDFE_CHEB_NONFINITE) return TDFE_ENONFINITE;
+  if (M < 0) return TDFE_EINVAL;
+  return TDFE_OK;
 }
 
 extern "C" tdfe_status tdfe_krylov_chunk(const tdfe_ctx* c, int n_orb, int* chunk) {

@@ -91,6 +91,8 @@ SIGNATURES = {
     "tdfe_adaptive_axes_query": [ctypes.POINTER(AdaptDesc), ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_adaptive_axes": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_size_t, _P, ctypes.c_int, _DP, _IP, _DP],
     "tdfe_adaptive_axes_static": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_int, _DP, _IP, _DP],
+    "tdfe_tridiag_expm_query": [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "tdfe_tridiag_expm": [_P, _P, ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_size_t, _P, _IP],
     "tdfe_kick": [_P, _P, ctypes.c_int, ctypes.c_double],
     "tdfe_field_samples": [ctypes.c_int, _DP, ctypes.c_int, _DP, _DP],
     "tdfe_absorption_spectrum": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double, _P,
@@ -543,6 +545,30 @@ def adaptive_axes_static(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max
         raise TdfeError(s, "adaptive_axes_static failed")
     del keep
     return [axes[a, :nc[a] + 1].copy() for a in range(3)], E.value
+
+
+def tridiag_expm(alpha, beta, tau):
+    """y = exp(-i tau T) e_1 on the GPU for the tridiagonal T (numpy alpha[k],
+    beta[k-1]); returns (y as a complex128 numpy array, number of series terms)."""
+    import torch
+    lib = load()
+    k = len(alpha)
+    nb = ctypes.c_size_t()
+    s = lib.tdfe_tridiag_expm_query(k, ctypes.byref(nb))
+    if s != OK:
+        raise TdfeError(s, "tridiag_expm: bad order")
+    a = torch.from_numpy(np.ascontiguousarray(alpha, dtype=np.float64)).cuda()
+    b = torch.from_numpy(np.ascontiguousarray(np.asarray(beta, dtype=np.float64).reshape(-1))).cuda() if k > 1 else None
+    y = torch.empty(k, dtype=torch.complex128, device="cuda")
+    scratch = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    m = ctypes.c_int()
+    s = lib.tdfe_tridiag_expm(_ptr(a), _ptr(b) if b is not None else None, k, float(tau), _ptr(y),
+                              ctypes.c_void_p(base + off), nb.value, _stream_handle(), ctypes.byref(m))
+    if s != OK:
+        raise TdfeError(s, "tridiag_expm failed")
+    return y.cpu().numpy(), m.value
 
 
 def rectilinear_vertices(ax, ay, az):

@@ -115,3 +115,17 @@ def test_adaptive_axes_static_checks_before_device_work(tdfe):
     assert lib.tdfe_adaptive_axes_static(ctypes.byref(d), None, 9, axes, nc, ctypes.byref(E)) == tdfe.EINVAL
     d.p = 4
     assert lib.tdfe_adaptive_axes_static(ctypes.byref(d), None, 0, axes, nc, ctypes.byref(E)) == tdfe.EINVAL
+
+
+def test_tridiag_expm_checks_before_device_work(tdfe):
+    lib = tdfe.load()
+    nb = ctypes.c_size_t()
+    assert lib.tdfe_tridiag_expm_query(0, ctypes.byref(nb)) == tdfe.EINVAL
+    assert lib.tdfe_tridiag_expm_query(1025, ctypes.byref(nb)) == tdfe.EINVAL
+    assert lib.tdfe_tridiag_expm_query(1024, ctypes.byref(nb)) == 0 and nb.value > 8 * 65536
+    fake = ctypes.c_void_p(4096)
+    m = ctypes.c_int()
+    # a scratch below the queried size is refused before any launch
+    assert lib.tdfe_tridiag_expm(fake, fake, 10, 0.1, fake, fake, 16, None, ctypes.byref(m)) == tdfe.ENOMEM
+    assert lib.tdfe_tridiag_expm(fake, None, 10, 0.1, fake, fake, nb.value, None, ctypes.byref(m)) == tdfe.EINVAL
+    assert lib.tdfe_tridiag_expm(fake, fake, 10, float("inf"), fake, fake, nb.value, None, None) == tdfe.EINVAL
