@@ -34,6 +34,7 @@
 #include <algorithm>
 #include <cmath>
 #include <system_error>
+#include <atomic>
 #include <thread>
 #include <vector>
 
@@ -401,8 +402,10 @@ tdfe_status CaptureHook::after_loop(tdfe_ctx* c, const void* W, int64_t vstride,
 }
 
 // C for every orbital from the forward (x) and adjoint (z) Krylov records
-void small_matrix(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, double tau, std::vector<double>& Cm,
-                  std::vector<int>& kk) {
+// returns false if a host allocation failed (in the caller or on a worker
+// thread); every started thread has been joined by then
+bool small_matrix_impl(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, double tau,
+                       std::vector<double>& Cm, std::vector<int>& kk) {
   Cm.assign((size_t)Nc * ks * ks * 2, 0.0);
   kk.assign(2 * Nc, 0);
   auto eig = [&](const KrylovRecord& R, int o, std::vector<double>& th, std::vector<double>& U) {
@@ -462,22 +465,38 @@ void small_matrix(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, 
   const int nt = std::max(1, std::min({Nc, 8, (int)std::thread::hardware_concurrency()}));
   if (nt == 1) {
     for (int o = 0; o < Nc; ++o) one(o);
-    return;
+    return true;
   }
+  std::atomic<bool> failed{false};
+  auto share = [&](int w) {
+    try {
+      for (int o = w; o < Nc; o += nt) one(o);
+    } catch (...) {
+      failed = true;
+    }
+  };
   std::vector<std::thread> pool;
   int started = 1;  // workers 1..started-1 run; the caller takes the rest
   try {
-    for (int w = 1; w < nt; ++w, ++started)
-      pool.emplace_back([&, w] {
-        for (int o = w; o < Nc; o += nt) one(o);
-      });
-  } catch (const std::system_error&) {
-    // no more threads available: the orbitals of unstarted workers run here
+    pool.reserve(nt - 1);
+    for (int w = 1; w < nt; ++w, ++started) pool.emplace_back(share, w);
+  } catch (...) {
+    // no more threads (or no room for their handles): the orbitals of
+    // unstarted workers run here
   }
-  for (int o = 0; o < Nc; o += nt) one(o);
-  for (int w = started; w < nt; ++w)
-    for (int o = w; o < Nc; o += nt) one(o);
+  share(0);
+  for (int w = started; w < nt; ++w) share(w);
   for (auto& th : pool) th.join();
+  return !failed;
+}
+
+bool small_matrix(const KrylovRecord& X, const KrylovRecord& Z, int Nc, int ks, double tau, std::vector<double>& Cm,
+                  std::vector<int>& kk) {
+  try {
+    return small_matrix_impl(X, Z, Nc, ks, tau, Cm, kk);
+  } catch (...) {
+    return false;
+  }
 }
 
 struct Grad {
@@ -558,7 +577,8 @@ struct Grad {
 
   // Vb for the exponential recorded in X (forward) and Zr (adjoint run with -tau)
   tdfe_status potential_cotangent(const KrylovRecord& X, double tau, double* Vb) {
-    small_matrix(X, Zr, n_orb, g.ks, tau, Cm_host, kk_host);
+    if (!small_matrix(X, Zr, n_orb, g.ks, tau, Cm_host, kk_host))
+      return tdfe_fail(c, TDFE_ENOMEM, "gradient: host allocation failed in the small-matrix step");
     double* Cm = (double*)(base + g.o_cm);
     int* kk = (int*)(base + g.o_k);
     TDFE_HIP(c, hipMemcpyAsync(Cm, Cm_host.data(), Cm_host.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
