@@ -15,8 +15,10 @@ the FP64 trajectory and its speedup both at equal nominal tolerance and
 against FP64 run at the mixed path's effective stop tolerance; the operator
 kernel's position on the HBM roofline (launch duration from HIP events on the
 library's stream, in the step's own launch shape); the pseudopotential-like
-box workload (16^3 cells, p = 5, 8 orbitals) as an extra; and the CPU oracle
-timed on this host (a subprocess that runs beside the GPU legs).
+box workload (16^3 cells, p = 5, 8 orbitals) and two mixed steps of the
+all-electron-like workload (39^3 cells, p = 7, 20 M DoFs, 24 orbitals) as
+extras; and the CPU oracle timed on this host (a subprocess that runs beside
+the GPU legs).
 """
 import argparse
 import hashlib
@@ -552,6 +554,69 @@ def dipole_errors(mu, ref):
     return float(d / np.abs(ref[:n]).max()), float(d / max(induced, 1e-300)), n
 
 
+def hartree_solves(reps=3):
+    """The Hartree solve of the graded workload on its own (31^3 trilinear
+    cells, p = 6, 6.5 M nodes): CG to relative residual 1e-13, preconditioned
+    by the fast diagonalisation of the axis-averaged rectilinear stand-in
+    (rocBLAS DGEMM passes) and by Jacobi, from a cold start and then warm
+    started from the previous solution; time per solve and iterations."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.scaled(W.CONFIGS[3], n_orb=2)
+    wl = Workload(cfg)
+    out = {"workload": cfg.name + " (density of 2 orbitals)"}
+    for name, pc in (("fdm", tdfe.PCG_FDM), ("jacobi", tdfe.PCG_JACOBI)):
+        ctx, psi = wl.context(tdfe.FP64, pcg_precond=pc)
+        res = []
+        for r in range(reps):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            ctx.scf_fields(psi, phi=False)
+            torch.cuda.synchronize()
+            res.append(time.perf_counter() - t)
+        rep = ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+        out[name] = {"cold_solve_s": res[0], "warm_solve_s": float(np.median(res[1:])),
+                     "its_per_solve_in_a_step": rep["poisson_iters"]}
+        close(ctx)
+    return out
+
+
+def ae_steps(n_steps=2):
+    """The all-electron-like workload at full size (39^3 graded trilinear
+    cells down to ~0.02 bohr at the nuclei, p = 7, 20,123,648 DoFs, 24
+    orbitals, smoothed Coulomb wells Z in {6,7,8}, Hartree + exchange +
+    correlation, kick 1e-3, dt 0.005, k_max 512) on the mixed path: the
+    Krylov basis in FP32, chunked to the device memory (k_max + 2 vectors
+    per orbital), recurrence scalars and the small exponential in FP64.  The
+    first step also forms W_0.  Step times, Krylov dimensions, charge."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[4]
+    t0 = time.perf_counter()
+    wl = Workload(cfg)
+    ctx, psi = wl.context(tdfe.MIXED_FP32)
+    out = {"workload": cfg.name, "n_dof": ctx.n_dof, "n_orb": cfg.n_orb, "k_max": cfg.k_max, "dt": cfg.dt,
+           "tol": cfg.tol, "krylov_chunk_orbitals": ctx.krylov_chunk(cfg.n_orb), "setup_s": None, "steps": []}
+    torch.cuda.synchronize()
+    out["setup_s"] = time.perf_counter() - t0
+    for _ in range(n_steps):
+        t = time.perf_counter()
+        try:
+            rep = ctx.magnus_step(psi, cfg.dt, 0.0, cfg.tol)
+        except tdfe.TdfeError as e:
+            out["steps"].append({"error": str(e), "wall_s": time.perf_counter() - t})
+            break
+        torch.cuda.synchronize()
+        out["steps"].append({"wall_s": time.perf_counter() - t, "k_pred_max": rep["k_pred_max"],
+                             "k_corr_max": rep["k_corr_max"], "k_pred_sum": rep["k_pred_sum"],
+                             "k_corr_sum": rep["k_corr_sum"], "err_max": rep["err_max"],
+                             "hartree_its": rep["poisson_iters"], "charge": rep["charge"], "mu": list(rep["mu"])})
+    close(ctx)
+    return out
+
+
 def workload_legs(cfg, steps, warmup, apply_reps, curved, matched=True, jacobi_count=False):
     """FP64, mixed and (optionally) FP64 at the mixed path's effective stop
     tolerance on one workload; operator launches in the step's shape."""
@@ -618,6 +683,8 @@ def main():
                     help="only the operator launches of the headline workload (for counter runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
+    ap.add_argument("--legs", default=None,
+                    help="comma list of extra legs to run alone (ae, box, adjoint, nonlocal, spectra, midpoint, adaptive)")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -630,7 +697,7 @@ def main():
     import workloads as W
     cfg = W.CONFIGS[args.config]
     curved = cfg.graded
-    cpu = None if (args.no_cpu_baseline or args.apply_only) else start_cpu_worker(args.config)
+    cpu = None if (args.no_cpu_baseline or args.apply_only or args.legs) else start_cpu_worker(args.config)
 
     import torch
     from paper_1810_13130_amd import tdfe
@@ -642,6 +709,12 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
+    legs = {"ae": ae_steps, "hartree": hartree_solves, "adjoint": adjoint_rate, "nonlocal": nonlocal_term, "spectra": field_and_spectra,
+            "midpoint": midpoint_modes, "adaptive": adaptive_mesh,
+            "box": lambda: {"workload": W.CONFIGS[2].name, **workload_legs(W.CONFIGS[2], 100, 5, 100, False)}}
+    if args.legs:
+        print(json.dumps({name: legs[name]() for name in args.legs.split(",")}), flush=True)
+        return
     if args.apply_only:
         wl = Workload(cfg)
         for prec, fp32 in ((tdfe.FP64, False), (tdfe.MIXED_FP32, True)):
@@ -686,6 +759,8 @@ def main():
         c2 = W.CONFIGS[2]
         r2 = workload_legs(c2, 100, 5, 100, False, matched=True)
         out["box_workload"] = {"workload": c2.name, **r2}
+        out["ae_workload"] = ae_steps()
+        out["hartree_graded"] = hartree_solves()
         for name, fn in (("adjoint", adjoint_rate), ("nonlocal", nonlocal_term), ("field_and_spectra", field_and_spectra),
                          ("midpoint", midpoint_modes), ("adaptive_mesh", adaptive_mesh)):
             out[name] = fn()
