@@ -1,14 +1,15 @@
 """GPU parity of the operator on trilinear (curved) cells, every supported order.
 
-The curved-cell operator has two kernels: the plane-ownership kernel (two or
-more real columns at orders p <= 7) and the line-ownership kernel (one
-column, p = 8, or on request).  Each order is
-checked against the FP64 oracle on a small graded mesh with an uneven cell
+The curved-cell operator has three kernels for two or more real columns at
+orders p <= 7 -- lane pairs sharing a plane (the FP64 default), plane
+ownership (the FP32 default) -- and the line-ownership kernel (one column,
+p = 8, or on request).  Each order is checked in both of the first two
+kernels against the FP64 oracle on a small graded mesh with an uneven cell
 count per axis and an orbital count that selects a different column-block
 width (ragged column chunks included), in FP64 (1e-12) and in FP32 storage
-(2e-6, 1e-5 at p >= 7); the two kernels are compared with each other; and one
+(2e-6, 1e-5 at p >= 7); the kernels are compared with each other; and one
 predictor-corrector SCF step at p = 6 runs the one-column stiffness products
-(full node grid, no M^-1/2) of the Jacobi-PCG Hartree solve.
+(full node grid, no M^-1/2) of the CG Hartree solve.
 """
 import numpy as np
 import pytest
@@ -31,8 +32,10 @@ def _graded(p, n_orb, ncell=(2, 3, 2)):
     return W.scaled(W.CONFIGS[3], ncell=ncell, p=p, n_orb=n_orb)
 
 
+@pytest.mark.parametrize("variant", ["pair", "plane"])
 @pytest.mark.parametrize("p", sorted(ORBS))
-def test_curved_operator_fp64_every_order(p):
+def test_curved_operator_fp64_every_order(p, variant, monkeypatch):
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", variant)
     n_orb = ORBS[p]
     cfg = _graded(p, n_orb)
     ctx = gpu_context(cfg, n_orb=n_orb, k_max=4)
@@ -42,8 +45,10 @@ def test_curved_operator_fp64_every_order(p):
     assert rel(y, op.apply_Hbar(m, vq, x)) < 1e-12
 
 
+@pytest.mark.parametrize("variant", ["pair", "plane"])
 @pytest.mark.parametrize("p", sorted(ORBS))
-def test_curved_operator_fp32_every_order(p):
+def test_curved_operator_fp32_every_order(p, variant, monkeypatch):
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", variant)
     n_orb = ORBS[p]
     cfg = _graded(p, n_orb)
     ctx = gpu_context(cfg, n_orb=n_orb, k_max=4, precision=MIXED)
@@ -56,13 +61,17 @@ def test_curved_operator_fp32_every_order(p):
 
 
 @pytest.mark.parametrize("p", [3, 6])
-def test_plane_and_line_kernels_agree_on_curved_cells(p, monkeypatch):
+def test_pair_plane_and_line_kernels_agree_on_curved_cells(p, monkeypatch):
     cfg = _graded(p, 5)
     x = torch.from_numpy(W.random_block(_n_dof(cfg), 5, 300 + p)).cuda()
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", "plane")
     y_plane = gpu_context(cfg, n_orb=5, k_max=4).apply_H(x).cpu().numpy()
+    monkeypatch.setenv("TDFE_APPLY_VARIANT", "pair")
+    y_pair = gpu_context(cfg, n_orb=5, k_max=4).apply_H(x).cpu().numpy()
     monkeypatch.setenv("TDFE_APPLY_VARIANT", "line")
     y_line = gpu_context(cfg, n_orb=5, k_max=4).apply_H(x).cpu().numpy()
     assert rel(y_plane, y_line) < 1e-13
+    assert rel(y_pair, y_line) < 1e-13
 
 
 def _n_dof(cfg):
@@ -85,3 +94,20 @@ def test_scf_step_on_curved_cells_at_p6_matches_oracle():
     assert np.abs(rep["mu"] - ref["dipole"]).max() < 1e-10 * np.abs(ref["dipole"]).max()
     assert abs(rep["charge"] - ref["charge"]) < 1e-10 * abs(ref["charge"])
     assert rel(g.cpu().numpy(), st.psibar) < 1e-10
+
+
+def test_pair_and_plane_agree_at_the_graded_launch_shape(monkeypatch):
+    """The graded molecule's full mesh (31^3 cells, p = 6) at the FP64 step's
+    launch shape (a Krylov chunk of 8 orbitals = 16 real columns): the
+    lane-pair and the plane kernel agree to rounding."""
+    cfg = W.scaled(W.CONFIGS[3], n_orb=8)
+    x = None
+    out = {}
+    for variant in ("pair", "plane"):
+        monkeypatch.setenv("TDFE_APPLY_VARIANT", variant)
+        ctx = gpu_context(cfg, n_orb=8, k_max=4)
+        if x is None:
+            x = torch.from_numpy(W.random_block(ctx.n_dof, 8, 77)).cuda()
+        out[variant] = ctx.apply_H(x).cpu().numpy()
+        ctx.close()
+    assert rel(out["pair"], out["plane"]) < 1e-13
