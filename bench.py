@@ -518,8 +518,15 @@ def time_apply(ctx, n_orb, fp32, reps):
     x = torch.randn(ctx.n_dof, n_orb, dtype=dt_, device="cuda")
     y = torch.zeros_like(x)
     f = ctx.apply_H_add_f32 if fp32 else ctx.apply_H_add
-    for _ in range(3):
+    # warm up for at least 50 ms of launches (clocks settle; a propagation
+    # runs thousands of launches back to back)
+    t_w = time.perf_counter()
+    for i in range(1000):
         f(x, y)
+        if i >= 2 and i % 4 == 3:
+            torch.cuda.synchronize()
+            if time.perf_counter() - t_w > 0.05:
+                break
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()

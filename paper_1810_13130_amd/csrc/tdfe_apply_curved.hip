@@ -628,18 +628,22 @@ __device__ __forceinline__ void zpair(const ZSplit& F, const T* in, T* out, T sg
   T x[HZ], own[HZ], oth[H];
 #pragma unroll
   for (int k = 0; k < HZ; ++k) x[k] = sg * in[k];
+  // (entries that are exactly zero -- the middle row of B for odd n, the
+  // centre of Dg -- are skipped at compile time)
 #pragma unroll
   for (int c = 0; c < HZ; ++c) {
     T a = 0;
 #pragma unroll
-    for (int k = 0; k < HZ; ++k) a += (T)F.own[c * CP_HZ + k] * x[k];
+    for (int k = 0; k < HZ; ++k)
+      if (F.own[c * CP_HZ + k] != 0.0) a += (T)F.own[c * CP_HZ + k] * x[k];
     own[c] = a;
   }
 #pragma unroll
   for (int c = 0; c < H; ++c) {
     T b = 0;
 #pragma unroll
-    for (int k = 0; k < HZ; ++k) b += (T)F.oth[c * CP_HZ + k] * x[k];
+    for (int k = 0; k < HZ; ++k)
+      if (F.oth[c * CP_HZ + k] != 0.0) b += (T)F.oth[c * CP_HZ + k] * x[k];
     oth[c] = b;
   }
 #pragma unroll

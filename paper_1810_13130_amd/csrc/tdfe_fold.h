@@ -91,15 +91,19 @@ __device__ __forceinline__ void eo(const Folded<FT>& F, const T* in, T* out) {
     e[i] = in[i] + in[N - 1 - i];
     o[i] = in[i] - in[N - 1 - i];
   }
+  // coefficients that are exactly zero (for odd N the middle row of B, whose
+  // middle Gauss point is a GLL node, and the middle column of B^T) are
+  // skipped: the tables are compile-time constants, so the tests fold away
 #pragma unroll
   for (int a = 0; a < H; ++a) {
     T Pv = 0, Qv = 0;
 #pragma unroll
     for (int i = 0; i < H; ++i) {
-      Pv += (T)F.E[a * EO_MAX_H + i] * e[i];
-      Qv += (T)F.O[a * EO_MAX_H + i] * o[i];
+      if (F.E[a * EO_MAX_H + i] != 0) Pv += (T)F.E[a * EO_MAX_H + i] * e[i];
+      if (F.O[a * EO_MAX_H + i] != 0) Qv += (T)F.O[a * EO_MAX_H + i] * o[i];
     }
-    if constexpr (N & 1) Pv += (T)F.mc[a] * in[H];
+    if constexpr (N & 1)
+      if (F.mc[a] != 0) Pv += (T)F.mc[a] * in[H];
     out[a] = Pv + Qv;
     out[N - 1 - a] = S > 0 ? Pv - Qv : Qv - Pv;
   }
@@ -107,11 +111,13 @@ __device__ __forceinline__ void eo(const Folded<FT>& F, const T* in, T* out) {
     T m = 0;
     if constexpr (S > 0) {
 #pragma unroll
-      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * e[i];
-      m += (T)F.mr[H] * in[H];
+      for (int i = 0; i < H; ++i)
+        if (F.mr[i] != 0) m += (T)F.mr[i] * e[i];
+      if (F.mr[H] != 0) m += (T)F.mr[H] * in[H];
     } else {
 #pragma unroll
-      for (int i = 0; i < H; ++i) m += (T)F.mr[i] * o[i];
+      for (int i = 0; i < H; ++i)
+        if (F.mr[i] != 0) m += (T)F.mr[i] * o[i];
     }
     out[H] = m;
   }
