@@ -116,6 +116,17 @@ class Mesh:
         return x, det, Ginv
 
     # -- convenience -----------------------------------------------------
+    def nodes_from_dofs(self, u):
+        """Values at every node from DoF values (boundary nodes 0)."""
+        u = np.asarray(u)
+        out = np.zeros((self.n_nodes,) + u.shape[1:], dtype=u.dtype)
+        out[self.dof_nodes] = u
+        return out
+
+    def dofs_from_nodes(self, y):
+        """Rows of a node array that belong to DoFs."""
+        return np.asarray(y)[self.dof_nodes]
+
     @property
     def dof_xyz(self):
         return self.node_xyz[self.dof_nodes]

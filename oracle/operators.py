@@ -59,15 +59,17 @@ def _assemble(mesh, y_e):
 
 def apply_H(mesh, vq, u):
     """(H u) on the DoFs; u: (n_dof, ...) FE coefficients (real or complex).
+    The mesh maps DoF values to node values (``nodes_from_dofs``: placement,
+    or the hanging-node constraints of an octree mesh) and back (its
+    transpose).
 
     vq: potential at the Gauss points in the (n_cell, nq^3) layout with the x
     index fastest, or None for the kinetic part alone.
     """
-    u_nodes = np.zeros((mesh.n_nodes,) + u.shape[1:], dtype=u.dtype)
-    u_nodes[mesh.dof_nodes] = u
+    u_nodes = mesh.nodes_from_dofs(u)
     v = None if vq is None else mesh.to_cell_quad(vq)
     y = _cell_operator(mesh, _cell_values(mesh, u_nodes), v, 0.5)
-    return _assemble(mesh, y)[mesh.dof_nodes]
+    return mesh.dofs_from_nodes(_assemble(mesh, y))
 
 
 def apply_Hbar(mesh, vq, psibar):
@@ -121,6 +123,9 @@ def _dense(mesh, vq, kin):
 def dense_H(mesh, vq):
     """Dense H restricted to the DoFs (tiny meshes only)."""
     A = _dense(mesh, vq, 0.5)
+    if hasattr(mesh, "C"):  # hanging-node constraints: C^T A C
+        C = mesh.C.toarray()
+        return C.T @ A @ C
     return A[np.ix_(mesh.dof_nodes, mesh.dof_nodes)]
 
 

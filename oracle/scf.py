@@ -25,9 +25,7 @@ def quad_values(mesh, u_dof_or_nodes, nodes=False):
     if nodes:
         u_nodes = u_dof_or_nodes
     else:
-        u = u_dof_or_nodes
-        u_nodes = np.zeros((mesh.n_nodes,) + u.shape[1:], dtype=u.dtype)
-        u_nodes[mesh.dof_nodes] = u
+        u_nodes = mesh.nodes_from_dofs(u_dof_or_nodes)
     B = mesh.ref.B
     return np.einsum("ai,bj,ck,eijk...->eabc...", B, B, B, u_nodes[mesh.cell_nodes], optimize=True)
 
