@@ -441,6 +441,70 @@ tdfe_status tdfe_adaptive_axes(const tdfe_adapt_desc* d, void* dev_scratch, size
 tdfe_status tdfe_adaptive_axes_static(const tdfe_adapt_desc* d, void* hip_stream, int max_cells, double* host_axes,
                                       int* host_ncell, double* host_E);
 
+/* Octree meshes with hanging nodes (Sec. "Efficient spatio-temporal
+ * discretization": adaptive hexahedra that follow h(r) = E g(r)^(-1/(p+3))
+ * of Eq. OptimalMeshSize).  Cell (level q, i, j, k) is the cube of edge
+ * (hi - lo) / (n0 2^q) with lowest corner lo + (i, j, k) times that edge.
+ *
+ * octree_leaves: [lo, hi]^3 starts as n0^3 cubes; a cube of edge s is split
+ * into its 8 octants while s > E (largest g over its 27 sample points:
+ * corners, edge and face midpoints, centre)^(-1/(p+3)), at most max_level
+ * times (E and g as for tdfe_adaptive_axes: E from the samples^3 grid); then
+ * leaves that share a face, an edge or a corner are brought within one level
+ * of each other by splitting the coarser.  g runs on the GPU, the decisions on
+ * the host.  host_leaves receives n_leaf rows {q, i, j, k} in ascending
+ * lexicographic order, host_E the constant E.  octree_leaves_query gives the
+ * scratch bytes for max_leaves.  Synchronises hip_stream.  EINVAL for a bad
+ * description (as tdfe_adaptive_axes, or n0 outside 1..64, max_level outside
+ * 0..10); ENOMEM if the scratch is too small or the tree needs more than
+ * max_leaves leaves. */
+tdfe_status tdfe_octree_leaves_query(const tdfe_adapt_desc* d, int max_leaves, size_t* bytes);
+tdfe_status tdfe_octree_leaves(const tdfe_adapt_desc* d, int n0, int max_level, void* dev_scratch,
+                               size_t scratch_bytes, void* hip_stream, int max_leaves, int* host_leaves,
+                               int* host_n_leaf, double* host_E);
+
+/* fe_octree_setup: a context on the leaves of an octree (any leaf list that
+ * tiles [lo, hi]^3 with neighbours -- across faces, edges and corners --
+ * within one level; e.g. from tdfe_octree_leaves), in place of
+ * tdfe_fe_mesh_setup.  Order-p GLL nodes of all leaves are merged by
+ * position; a node on the closed boundary of a leaf that does not own it
+ * (hanging) takes that leaf's polynomial value there (the tensor Lagrange
+ * interpolant of its face or edge nodes), chains of such constraints are
+ * substituted and masters on the domain boundary (Dirichlet) drop out.  The
+ * DoFs are the remaining interior nodes, numbered by position (x slowest,
+ * then y, then z); C maps DoF values to all nodes.  The overlap is lumped:
+ * M_d = sum over nodes m of C_md N_m with N_m the GLL-rule mass of node m,
+ * which keeps the GLL quadrature of every function of the constrained space
+ * exact, and Hbar = M^-1/2 C^T H_nodes C M^-1/2.  Cells are numbered in the
+ * order given; per-point arrays are [n_cell][nq^3] as for other meshes.
+ * Supported afterwards: query, bind_workspace, dof_coords, quad_coords,
+ * mass_diag, set_potential, apply_H, apply_H_add, lanczos_expm, density,
+ * dipole, kick, set_field_direction, and magnus_step / propagate with a
+ * fixed potential plus the field (set_scf may set occupations only).  EINVAL
+ * from set_scf with Hartree or XC, set_projectors with projectors,
+ * gradient_query and dipole_gradient; apply_H_add_f32 needs a mixed context,
+ * which octree meshes do not have.  The device arrays (cell node lists, C and
+ * C^T, two node work arrays of min(64, max(2 chunk, 2 n_orb_max)) columns)
+ * live in the workspace.  EINVAL for p outside 1..8, n0 outside 1..64,
+ * max_level outside 0..10, leaves that do not tile the domain or are not
+ * balanced, precision other than TDFE_FP64, or a non-positive lumped
+ * overlap. */
+typedef struct {
+  int p;             /* element order, 1..8 */
+  double lo, hi;     /* domain [lo, hi]^3 */
+  int n0;            /* root cubes per axis */
+  int max_level;     /* finest level any leaf may have */
+  int n_leaf;
+  const int* leaves; /* HOST [n_leaf][4] = {q, i, j, k} */
+  int n_orb_max;
+  int k_max;
+  int precision;     /* TDFE_FP64 */
+} tdfe_octree_desc;
+tdfe_status tdfe_fe_octree_setup(const tdfe_octree_desc* d, void* hip_stream, tdfe_ctx** out);
+/* octree_info: counts of an octree context: all nodes, hanging nodes and
+ * non-zeros of C (any pointer may be NULL); EINVAL on other contexts. */
+tdfe_status tdfe_octree_info(const tdfe_ctx* ctx, int64_t* n_nodes, int64_t* n_hanging, int64_t* nnz);
+
 /* gradient_query: device workspace bytes that tdfe_dipole_gradient needs for
  * n_orb orbitals, n_steps steps, a state checkpoint every checkpoint_every
  * steps and Krylov bases of up to k_store vectors (a multiple of 8, at most

@@ -712,6 +712,7 @@ struct Grad {
 tdfe_status grad_checks(tdfe_ctx* c, int n_orb, int n_steps, int ckpt, int k_store) {
   if (!c) return TDFE_EINVAL;
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "gradient before bind_workspace");
+  if (c->octree) return tdfe_fail(c, TDFE_EINVAL, "gradient: not on octree meshes");
   if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "gradient: n_orb out of range");
   if (n_orb > c->chunk_orb) return tdfe_fail(c, TDFE_EINVAL, "gradient: orbitals must fit one Lanczos chunk");
   if (n_steps < 1 || ckpt < 1) return tdfe_fail(c, TDFE_EINVAL, "gradient: n_steps and checkpoint_every must be >= 1");

@@ -595,6 +595,7 @@ int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
 }
 
 static tdfe_status launch_local(tdfe_ctx* c, const ApplyArgs& a) {
+  if (c->octree) return tdfe_launch_apply_octree(c, a);
   // the FP32 copy of the potential exists in mixed contexts only
   if (a.fp32 && c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply: FP32 launch in an FP64 context");
   // default policy, from measurements on the benchmark and graded workloads:

@@ -119,6 +119,30 @@ struct tdfe_ctx {
   int64_t nl_line_dofs = 0;                             // DoFs on those lines (x ranges)
   int64_t nl_packed = 0;             // stored entries of Cbar
   int64_t nl_box_dofs = 0;           // DoFs in the groups' boxes (summed over groups)
+
+  // ---- octree meshes (tdfe_octree.hip) -------------------------------------------------------
+  // host tables built at setup and copied into the workspace at bind; n_nodes
+  // counts every merged GLL node (hanging and boundary ones included)
+  bool octree = false;
+  int oct_w = 0;  // real columns of the node work arrays
+  int64_t oct_hanging = 0;
+  std::vector<int> oct_cn_h;                 // [n_cell][n^3] node of every cell node (x fastest)
+  std::vector<double> oct_s_h;               // [n_cell] cube edge
+  std::vector<int> oct_eptr_h, oct_ecol_h;   // C: rows over nodes (DoF columns)
+  std::vector<double> oct_eval_h;
+  std::vector<int> oct_rptr_h, oct_rcol_h;   // C^T: rows over DoFs (node columns)
+  std::vector<double> oct_rval_h;
+  std::vector<double> oct_m_h, oct_dofxyz_h, oct_xq_h, oct_wdet_h;
+  int* oct_cn = nullptr;
+  double* oct_s = nullptr;
+  int* oct_eptr = nullptr;
+  int* oct_ecol = nullptr;
+  double* oct_eval = nullptr;
+  int* oct_rptr = nullptr;
+  int* oct_rcol = nullptr;
+  double* oct_rval = nullptr;
+  double* oct_xf = nullptr;  // [n_nodes][oct_w] expanded input
+  double* oct_yf = nullptr;  // [n_nodes][oct_w] per-node output before C^T
 };
 
 // error helpers ----------------------------------------------------------------
@@ -249,6 +273,15 @@ tdfe_status tdfe_occ_dev(tdfe_ctx* c, int n_orb, const double** dev);
 tdfe_status tdfe_assemble_vw(tdfe_ctx* c, const double* A, double ca, const double* B, double cb, double E);
 // host symmetric eigen-decomposition A = U diag(lam) U^T (row-major n x n, U[i*n+k] = k-th vector)
 void tdfe_sym_eigen(const std::vector<double>& A, int n, std::vector<double>& lam, std::vector<double>& U);
+
+// octree meshes (tdfe_octree.hip): the operator as C^T (cell operators) C in
+// the Loewdin scaling, the density at the Gauss points with the same 4
+// partial sums per cell as the structured density kernel, and the upload of
+// the host tables at bind
+tdfe_status tdfe_launch_apply_octree(tdfe_ctx* c, const ApplyArgs& a);
+tdfe_status tdfe_octree_density(tdfe_ctx* c, const double* psibar, int n_orb, const double* occ, double* rho,
+                                double* partial4);
+tdfe_status tdfe_octree_bind(tdfe_ctx* c);
 
 // workspace carving (tdfe_setup.hip)
 int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols);

@@ -20,6 +20,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <set>
 #include <vector>
 
 #include "tdfe_internal.h"
@@ -83,6 +84,27 @@ __device__ double dbar(const double* pt, const double* R, double s, double A, in
   return fabs(A) * pow(s, -k) * multi_sum(Hx, Hy, Hz, k) * exp(-0.5 * (ux * ux + uy * uy + uz * uz));
 }
 
+// g at one point: the sum over atoms above
+__device__ double weight_at(const double* pt, const AtomParams* atoms, int n_atoms, int p) {
+  double v = 0.0;
+  for (int a = 0; a < n_atoms; ++a) {
+    const AtomParams A = atoms[a];
+    const double amp = pow(M_PI * A.s * A.s, -0.75);
+    v += 2.0 * dbar(pt, A.R, A.s, amp, p + 1) + dbar(pt, A.R, A.s, amp, p + 3);
+    v += dbar(pt, A.R, A.a, A.Z, p + 1);
+  }
+  return v;
+}
+
+// g at n given points (octree refinement)
+__global__ void __launch_bounds__(MT)
+    point_weight_kernel(const AtomParams* atoms, int n_atoms, int p, const double* pts, int64_t n, double* g) {
+  const int64_t idx = (int64_t)blockIdx.x * MT + threadIdx.x;
+  if (idx >= n) return;
+  const double pt[3] = {pts[3 * idx], pts[3 * idx + 1], pts[3 * idx + 2]};
+  g[idx] = weight_at(pt, atoms, n_atoms, p);
+}
+
 __global__ void __launch_bounds__(MT)
     size_weight_kernel(const AtomParams* atoms, int n_atoms, int p, double lo, double step, double hi, int S,
                        double* g) {
@@ -92,14 +114,7 @@ __global__ void __launch_bounds__(MT)
   const int k = (int)(idx % S), j = (int)((idx / S) % S), i = (int)(idx / ((int64_t)S * S));
   auto coord = [&](int m) { return m == S - 1 ? hi : lo + m * step; };
   const double pt[3] = {coord(i), coord(j), coord(k)};  // sample (i, j, k) = (x, y, z), z fastest
-  double v = 0.0;
-  for (int a = 0; a < n_atoms; ++a) {
-    const AtomParams A = atoms[a];
-    const double amp = pow(M_PI * A.s * A.s, -0.75);
-    v += 2.0 * dbar(pt, A.R, A.s, amp, p + 1) + dbar(pt, A.R, A.s, amp, p + 3);
-    v += dbar(pt, A.R, A.a, A.Z, p + 1);
-  }
-  g[idx] = v;
+  g[idx] = weight_at(pt, atoms, n_atoms, p);
 }
 
 // partial[b] = sum over a grid-stride share of w_i w_j w_k g^{3/(p+3)} (trapezoid weights / step^3)
@@ -271,6 +286,173 @@ tdfe_status tdfe_adaptive_axes_static(const tdfe_adapt_desc* d, void* hip_stream
   void* ptr = static_scratch();
   if (!ptr) return TDFE_EDEVICE;
   return adaptive_axes_impl(d, ptr, (hipStream_t)hip_stream, max_cells, host_axes, host_ncell, host_E);
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------------------
+// octree leaves following h(r): E from the samples^3 grid as above, g at the
+// 27 sample points of every cube of a level on the GPU, split decisions and
+// the 2:1 balance on the host
+// ------------------------------------------------------------------------------------------------
+namespace {
+
+size_t octree_scratch_need(int S, int max_leaves) {
+  const size_t pts = (size_t)TDFE_MAX_ATOMS_MESH * 8 * sizeof(double) + (size_t)max_leaves * 27 * 4 * sizeof(double) + 1024;
+  return std::max(scratch_need(S), pts);
+}
+
+struct LeafKey {
+  int q, i, j, k;
+  bool operator<(const LeafKey& o) const {
+    if (q != o.q) return q < o.q;
+    if (i != o.i) return i < o.i;
+    if (j != o.j) return j < o.j;
+    return k < o.k;
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+tdfe_status tdfe_octree_leaves_query(const tdfe_adapt_desc* d, int max_leaves, size_t* bytes) {
+  if (!desc_ok(d) || !bytes || max_leaves < 1) return TDFE_EINVAL;
+  *bytes = octree_scratch_need(d->samples, max_leaves);
+  return TDFE_OK;
+}
+
+tdfe_status tdfe_octree_leaves(const tdfe_adapt_desc* d, int n0, int max_level, void* dev_scratch,
+                               size_t scratch_bytes, void* hip_stream, int max_leaves, int* host_leaves,
+                               int* host_n_leaf, double* host_E) {
+  if (!desc_ok(d) || !dev_scratch || !host_leaves || !host_n_leaf || max_leaves < 1) return TDFE_EINVAL;
+  if (n0 < 1 || n0 > 64 || max_level < 0 || max_level > 10) return TDFE_EINVAL;
+  if (scratch_bytes < octree_scratch_need(d->samples, max_leaves) || (uintptr_t)dev_scratch % 256 != 0)
+    return TDFE_ENOMEM;
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int S = d->samples, p = d->p;
+  std::vector<AtomParams> ha(d->n_atoms);
+  for (int a = 0; a < d->n_atoms; ++a) {
+    for (int c = 0; c < 3; ++c) ha[a].R[c] = d->R[3 * a + c];
+    ha[a].Z = d->Z[a];
+    ha[a].s = d->s_orb[a];
+    ha[a].a = d->a_pot[a];
+  }
+  // E^3 = (trapezoid integral of g^{3/(p+3)} on the samples) / N_elem
+  double E = 0.0;
+  {
+    double* g = (double*)dev_scratch;
+    double* partial = g + (size_t)S * S * S + 3 * (size_t)S;
+    AtomParams* atoms = (AtomParams*)(partial + SUM_BLOCKS);
+    const double step = (d->hi - d->lo) / (S - 1);
+    const int64_t n = (int64_t)S * S * S;
+    if (hipMemcpyAsync(atoms, ha.data(), ha.size() * sizeof(AtomParams), hipMemcpyHostToDevice, st) != hipSuccess)
+      return TDFE_EDEVICE;
+    hipLaunchKernelGGL(size_weight_kernel, dim3((unsigned)((n + MT - 1) / MT)), dim3(MT), 0, st,
+                       (const AtomParams*)atoms, d->n_atoms, p, d->lo, step, d->hi, S, g);
+    hipLaunchKernelGGL(count_partial_kernel, dim3(SUM_BLOCKS), dim3(MT), 0, st, (const double*)g, S, p, partial);
+    if (hipGetLastError() != hipSuccess) return TDFE_EDEVICE;
+    std::vector<double> hp(SUM_BLOCKS);
+    if (hipMemcpyAsync(hp.data(), partial, hp.size() * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return TDFE_EDEVICE;
+    double sum = 0.0;
+    for (double v : hp) sum += v;
+    E = std::cbrt(sum * step * step * step / d->n_elem);
+    if (!(E > 0.0) || !std::isfinite(E)) return TDFE_EINVAL;
+  }
+  // refinement, level by level
+  AtomParams* atoms = (AtomParams*)dev_scratch;
+  double* pts = (double*)dev_scratch + (size_t)TDFE_MAX_ATOMS_MESH * 8;
+  double* gp = pts + (size_t)max_leaves * 27 * 3;
+  if (hipMemcpyAsync(atoms, ha.data(), ha.size() * sizeof(AtomParams), hipMemcpyHostToDevice, st) != hipSuccess)
+    return TDFE_EDEVICE;
+  std::set<LeafKey> leaves;
+  for (int i = 0; i < n0; ++i)
+    for (int j = 0; j < n0; ++j)
+      for (int k = 0; k < n0; ++k) leaves.insert({0, i, j, k});
+  if ((int64_t)leaves.size() > max_leaves) return TDFE_ENOMEM;
+  const double frac[3] = {0.0, 0.5, 1.0};
+  auto split = [&](const LeafKey& c) {
+    leaves.erase(c);
+    for (int dd = 0; dd < 8; ++dd)
+      leaves.insert({c.q + 1, 2 * c.i + (dd & 1), 2 * c.j + ((dd >> 1) & 1), 2 * c.k + (dd >> 2)});
+  };
+  for (int q = 0; q < max_level; ++q) {
+    std::vector<LeafKey> cells;
+    for (const auto& c : leaves)
+      if (c.q == q) cells.push_back(c);
+    if (cells.empty()) continue;
+    const double s = (d->hi - d->lo) / (double)(n0 << q);
+    std::vector<double> hpts(cells.size() * 27 * 3);
+    for (size_t e = 0; e < cells.size(); ++e) {
+      const double org[3] = {d->lo + s * cells[e].i, d->lo + s * cells[e].j, d->lo + s * cells[e].k};
+      int m = 0;
+      for (int fx = 0; fx < 3; ++fx)
+        for (int fy = 0; fy < 3; ++fy)
+          for (int fz = 0; fz < 3; ++fz, ++m) {
+            hpts[(e * 27 + m) * 3 + 0] = org[0] + s * frac[fx];
+            hpts[(e * 27 + m) * 3 + 1] = org[1] + s * frac[fy];
+            hpts[(e * 27 + m) * 3 + 2] = org[2] + s * frac[fz];
+          }
+    }
+    const int64_t np = (int64_t)cells.size() * 27;
+    std::vector<double> hg(np);
+    if (hipMemcpyAsync(pts, hpts.data(), hpts.size() * sizeof(double), hipMemcpyHostToDevice, st) != hipSuccess)
+      return TDFE_EDEVICE;
+    hipLaunchKernelGGL(point_weight_kernel, dim3((unsigned)((np + MT - 1) / MT)), dim3(MT), 0, st,
+                       (const AtomParams*)atoms, d->n_atoms, p, (const double*)pts, np, gp);
+    if (hipGetLastError() != hipSuccess) return TDFE_EDEVICE;
+    if (hipMemcpyAsync(hg.data(), gp, np * sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        hipStreamSynchronize(st) != hipSuccess)
+      return TDFE_EDEVICE;
+    for (size_t e = 0; e < cells.size(); ++e) {
+      double gmax = 0.0;
+      for (int m = 0; m < 27; ++m) gmax = std::max(gmax, hg[e * 27 + m]);
+      const double h = gmax > 0.0 ? E * std::pow(gmax, -1.0 / (p + 3)) : INFINITY;
+      if (s > h) {
+        if ((int64_t)leaves.size() + 7 > max_leaves) return TDFE_ENOMEM;
+        split(cells[e]);
+      }
+    }
+  }
+  // 2:1 balance across faces, edges and corners
+  while (true) {
+    std::set<LeafKey> to_split;
+    for (const auto& c : leaves) {
+      if (c.q < 2) continue;
+      const int nm = n0 << c.q;
+      for (int dx = -1; dx <= 1; ++dx)
+        for (int dy = -1; dy <= 1; ++dy)
+          for (int dz = -1; dz <= 1; ++dz) {
+            if (!dx && !dy && !dz) continue;
+            const int a = c.i + dx, b = c.j + dy, cc = c.k + dz;
+            if (a < 0 || b < 0 || cc < 0 || a >= nm || b >= nm || cc >= nm) continue;
+            for (int q = c.q - 2; q >= 0; --q) {
+              const int sh = c.q - q;
+              const LeafKey anc{q, a >> sh, b >> sh, cc >> sh};
+              if (leaves.count(anc)) {
+                to_split.insert(anc);
+                break;
+              }
+            }
+          }
+    }
+    if (to_split.empty()) break;
+    if ((int64_t)leaves.size() + 7 * (int64_t)to_split.size() > max_leaves) return TDFE_ENOMEM;
+    for (const auto& c : to_split) split(c);
+  }
+  int64_t m = 0;
+  for (const auto& c : leaves) {
+    host_leaves[4 * m + 0] = c.q;
+    host_leaves[4 * m + 1] = c.i;
+    host_leaves[4 * m + 2] = c.j;
+    host_leaves[4 * m + 3] = c.k;
+    ++m;
+  }
+  *host_n_leaf = (int)m;
+  if (host_E) *host_E = E;
+  return TDFE_OK;
 }
 
 }  // extern "C"

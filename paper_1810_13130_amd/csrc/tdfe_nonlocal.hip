@@ -577,6 +577,7 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
   if (n_proj < 0 || n_proj > TDFE_MAX_PROJ)
     return tdfe_fail(c, TDFE_EINVAL, "set_projectors: n_proj outside [0, %d]", TDFE_MAX_PROJ);
   if (n_proj > 0 && (!dev_u || !dev_dv || !dev_store)) return tdfe_fail(c, TDFE_EINVAL, "set_projectors: null pointer");
+  if (n_proj > 0 && c->octree) return tdfe_fail(c, TDFE_EINVAL, "set_projectors: not on octree meshes");
   if (n_proj > 0 && (uintptr_t)dev_store % 256 != 0)
     return tdfe_fail(c, TDFE_EINVAL, "set_projectors: store not 256-byte aligned");
   const NlLayout L = nl_layout(c, n_proj, (char*)dev_store);

@@ -1327,6 +1327,11 @@ tdfe_status pcg_solve(tdfe_ctx* c) {
 
 // density at the Gauss points into rho (device) and 4 partial sums per cell
 tdfe_status tdfe_density_dev(tdfe_ctx* c, const void* psibar, int n_orb, double* rho, double* partial4) {
+  if (c->octree) {
+    const double* occ = nullptr;
+    TDFE_TRY(upload_occ(c, n_orb, (double**)&occ));
+    return tdfe_octree_density(c, (const double*)psibar, n_orb, occ, rho, partial4);
+  }
   DensParams P{};
   P.psi = (const double*)psibar;
   P.cols = 2 * n_orb;
@@ -1517,6 +1522,8 @@ tdfe_status tdfe_set_scf(tdfe_ctx* c, const tdfe_scf_desc* s) {
   if (s->xc < TDFE_XC_NONE || s->xc > TDFE_XC_XC) return tdfe_fail(c, TDFE_EINVAL, "set_scf: bad xc mode");
   if (s->n_nuclei < 0 || (s->n_nuclei > 0 && (!s->Z || !s->R))) return tdfe_fail(c, TDFE_EINVAL, "set_scf: nuclei");
   if (s->n_orb < 0 || s->n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "set_scf: n_orb");
+  if (c->octree && (s->hartree || s->xc != TDFE_XC_NONE))
+    return tdfe_fail(c, TDFE_EINVAL, "set_scf: octree meshes take no Hartree or exchange-correlation term");
   if (s->hartree && !c->box && !(s->pcg_tol > 0.0)) return tdfe_fail(c, TDFE_EINVAL, "set_scf: pcg_tol");
   if (s->pcg_precond != TDFE_PCG_FDM && s->pcg_precond != TDFE_PCG_JACOBI)
     return tdfe_fail(c, TDFE_EINVAL, "set_scf: pcg_precond");

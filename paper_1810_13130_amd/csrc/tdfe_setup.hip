@@ -204,8 +204,8 @@ void carve(tdfe_ctx* c, char* base) {
   const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
   c->fdmS = k.take<double>(2 * ((size_t)n1x * n1x + (size_t)n1y * n1y + (size_t)n1z * n1z));
   c->fdmL = k.take<double>((size_t)n1x + n1y + n1z);
-  c->pcg = c->box ? k.take<double>(1) : k.take<double>(5 * nn);
-  c->dinvK = c->box ? k.take<double>(1) : k.take<double>(nn);
+  c->pcg = (c->box || c->octree) ? k.take<double>(1) : k.take<double>(5 * nn);
+  c->dinvK = (c->box || c->octree) ? k.take<double>(1) : k.take<double>(nn);
   c->pcgs = k.take<double>(16);
   const int cols = 2 * c->chunk_orb;
   c->krylov = k.take<char>((size_t)(c->k_max + 1) * nd * cols * elem_bytes(c));
@@ -217,6 +217,19 @@ void carve(tdfe_ctx* c, char* base) {
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
   c->jtab = k.take<double>((size_t)std::max(c->chunk_orb, 1) * TDFE_JTAB_STRIDE);
   c->counters = k.take<unsigned>(256);
+  // octree meshes: cell node lists, cube edges, C and C^T, node work arrays
+  if (c->octree) {
+    c->oct_cn = k.take<int>(c->oct_cn_h.size());
+    c->oct_s = k.take<double>(c->oct_s_h.size());
+    c->oct_eptr = k.take<int>(c->oct_eptr_h.size());
+    c->oct_ecol = k.take<int>(c->oct_ecol_h.size());
+    c->oct_eval = k.take<double>(c->oct_eval_h.size());
+    c->oct_rptr = k.take<int>(c->oct_rptr_h.size());
+    c->oct_rcol = k.take<int>(c->oct_rcol_h.size());
+    c->oct_rval = k.take<double>(c->oct_rval_h.size());
+    c->oct_xf = k.take<double>((size_t)nn * c->oct_w);
+    c->oct_yf = k.take<double>((size_t)nn * c->oct_w);
+  }
   // FP32 copy of M^-1/2 for the mixed path's operator (placed last)
   c->minv32 = c->precision == TDFE_FP64 ? k.take<float>(1) : k.take<float>(nd);
   c->ws_need = k.off + 256;
@@ -224,6 +237,56 @@ void carve(tdfe_ctx* c, char* base) {
   c->nodexyz_ptr = nodexyz;
 }
 }  // namespace
+
+namespace {
+
+// reference element tables (the same constexpr rule the operator kernels
+// evaluate at compile time)
+void init_tables(tdfe_ctx* c) {
+  const tdfe1d::Rule R = tdfe1d::make_rule(c->p);
+  static_assert(tdfe1d::MAXN == TDFE_MAXN, "table stride");
+  std::memcpy(c->xi, R.xi, sizeof c->xi);
+  std::memcpy(c->w, R.w, sizeof c->w);
+  std::memcpy(c->eta, R.eta, sizeof c->eta);
+  std::memcpy(c->wq, R.wq, sizeof c->wq);
+  std::memcpy(c->B, R.B, sizeof c->B);
+  std::memcpy(c->D, R.D, sizeof c->D);
+  std::memcpy(c->Dg, R.Dg, sizeof c->Dg);
+}
+
+void init_variant(tdfe_ctx* c) {
+  const char* v = std::getenv("TDFE_APPLY_VARIANT");
+  c->variant = 0;
+  if (v && std::strcmp(v, "line") == 0) c->variant = TDFE_VARIANT_LINE;
+  if (v && std::strcmp(v, "pair") == 0) c->variant = TDFE_VARIANT_PAIR;
+  if (v && std::strcmp(v, "plane") == 0) c->variant = TDFE_VARIANT_PLANE;
+}
+
+// Krylov chunk: as many orbitals as fit in 60% of the device memory free at
+// creation (about 170 GB on an idle 288 GB device; 128 GB if it cannot be queried)
+void init_chunk(tdfe_ctx* c) {
+  const size_t eb = c->precision == TDFE_FP64 ? 8 : 4;
+  const double per_orb = (double)(c->k_max + 2) * (double)c->n_dof * 2.0 * (double)eb;
+  double basis_bytes = 128e9;
+  {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) basis_bytes = 0.6 * (double)free_b;
+    else (void)hipGetLastError();
+  }
+  int chunk = (int)std::min<double>(c->n_orb_max, std::floor(basis_bytes / per_orb));
+  if (chunk > TDFE_MAX_COLS / 2) chunk = TDFE_MAX_COLS / 2;
+  {
+    // optional cap (tests use it to run several chunks on small meshes)
+    const char* v = std::getenv("TDFE_MAX_CHUNK_ORB");
+    if (v && std::atoi(v) > 0) chunk = std::min(chunk, std::atoi(v));
+  }
+  if (chunk < 1) chunk = 1;
+  c->chunk_orb = chunk;
+}
+
+}  // namespace
+
+tdfe_status tdfe_octree_configure(tdfe_ctx* c, const tdfe_octree_desc* d);
 
 extern "C" {
 
@@ -265,19 +328,7 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
   const size_t nv = (size_t)(c->ncx + 1) * (c->ncy + 1) * (c->ncz + 1) * 3;
   c->vertices.assign(d->vertices, d->vertices + nv);
 
-  // reference element tables (the same constexpr rule the operator kernels
-  // evaluate at compile time)
-  {
-    const tdfe1d::Rule R = tdfe1d::make_rule(c->p);
-    static_assert(tdfe1d::MAXN == TDFE_MAXN, "table stride");
-    std::memcpy(c->xi, R.xi, sizeof c->xi);
-    std::memcpy(c->w, R.w, sizeof c->w);
-    std::memcpy(c->eta, R.eta, sizeof c->eta);
-    std::memcpy(c->wq, R.wq, sizeof c->wq);
-    std::memcpy(c->B, R.B, sizeof c->B);
-    std::memcpy(c->D, R.D, sizeof c->D);
-    std::memcpy(c->Dg, R.Dg, sizeof c->Dg);
-  }
+  init_tables(c);
 
   // rectilinear (box) detection: x depends only on the x index, etc.
   auto V = [&](int i, int j, int k, int dd) {
@@ -302,33 +353,48 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
       if (!(c->ax_z[i] > c->ax_z[i - 1])) box = false;
   }
   c->box = box;
-  {
-    const char* v = std::getenv("TDFE_APPLY_VARIANT");
-    c->variant = 0;
-    if (v && std::strcmp(v, "line") == 0) c->variant = TDFE_VARIANT_LINE;
-    if (v && std::strcmp(v, "pair") == 0) c->variant = TDFE_VARIANT_PAIR;
-    if (v && std::strcmp(v, "plane") == 0) c->variant = TDFE_VARIANT_PLANE;
-  }
+  init_variant(c);
+  init_chunk(c);
+  carve(c, nullptr);
+  *out = c;
+  return TDFE_OK;
+}
 
-  // Krylov chunk: as many orbitals as fit in 60% of the device memory free at
-  // creation (about 170 GB on an idle 288 GB device; 128 GB if it cannot be queried)
-  const size_t eb = c->precision == TDFE_FP64 ? 8 : 4;
-  const double per_orb = (double)(c->k_max + 2) * (double)c->n_dof * 2.0 * (double)eb;
-  double basis_bytes = 128e9;
-  {
-    size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) basis_bytes = 0.6 * (double)free_b;
-    else (void)hipGetLastError();
+tdfe_status tdfe_fe_octree_setup(const tdfe_octree_desc* d, void* hip_stream, tdfe_ctx** out) {
+  if (!d || !out) return TDFE_EINVAL;
+  *out = nullptr;
+  if (d->p < 1 || d->p > 8) return TDFE_EINVAL;
+  if (!(d->hi > d->lo) || !std::isfinite(d->lo) || !std::isfinite(d->hi)) return TDFE_EINVAL;
+  if (d->n0 < 1 || d->n0 > 64 || d->max_level < 0 || d->max_level > 10) return TDFE_EINVAL;
+  if (d->n_leaf < 1 || !d->leaves) return TDFE_EINVAL;
+  if (d->n_orb_max < 1 || d->n_orb_max > 4096) return TDFE_EINVAL;
+  if (d->k_max < 1 || d->k_max > 1024) return TDFE_EINVAL;
+  if (d->precision != TDFE_FP64) return TDFE_EINVAL;
+  tdfe_ctx* c = new tdfe_ctx();
+  c->p = d->p;
+  c->n = d->p + 1;
+  c->nq = d->p + 1;
+  c->octree = true;
+  c->box = false;
+  // the structured-grid fields keep the smallest valid values (their arrays
+  // are not used on octree meshes)
+  c->ncx = c->ncy = c->ncz = 1;
+  c->Nx = c->Ny = c->Nz = 3;
+  c->n_cell = d->n_leaf;
+  c->n_quad = c->n_cell * c->nq * c->nq * c->nq;
+  c->n_orb_max = d->n_orb_max;
+  c->k_max = d->k_max;
+  c->precision = d->precision;
+  c->stream = (hipStream_t)hip_stream;
+  init_tables(c);
+  const tdfe_status st = tdfe_octree_configure(c, d);
+  if (st != TDFE_OK) {
+    delete c;
+    return st;
   }
-  int chunk = (int)std::min<double>(c->n_orb_max, std::floor(basis_bytes / per_orb));
-  if (chunk > TDFE_MAX_COLS / 2) chunk = TDFE_MAX_COLS / 2;
-  {
-    // optional cap (tests use it to run several chunks on small meshes)
-    const char* v = std::getenv("TDFE_MAX_CHUNK_ORB");
-    if (v && std::atoi(v) > 0) chunk = std::min(chunk, std::atoi(v));
-  }
-  if (chunk < 1) chunk = 1;
-  c->chunk_orb = chunk;
+  init_variant(c);
+  init_chunk(c);
+  c->oct_w = std::min(TDFE_MAX_COLS, std::max(2 * c->chunk_orb, 2 * c->n_orb_max));
   carve(c, nullptr);
   *out = c;
   return TDFE_OK;
@@ -340,6 +406,19 @@ tdfe_status tdfe_query(const tdfe_ctx* c, int64_t* n_dof, int64_t* n_cell, int64
   if (n_cell) *n_cell = c->n_cell;
   if (n_quad) *n_quad = c->n_quad;
   if (ws) *ws = c->ws_need;
+  return TDFE_OK;
+}
+
+static tdfe_status finish_bind(tdfe_ctx* c) {
+  // pinned poll buffer for the Lanczos convergence flags
+  if (!c->poll) {
+    TDFE_HIP(c, hipHostMalloc((void**)&c->poll, 4096 * sizeof(int), hipHostMallocDefault));
+    std::memset(c->poll, 0, 4096 * sizeof(int));  // flags compare against generation numbers >= 1
+  }
+  c->bound = true;
+  c->have_potential = false;
+  c->have_scf = false;
+  c->scf_init = false;
   return TDFE_OK;
 }
 
@@ -372,6 +451,11 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
         tab[TAB_W3Q + a + c->nq * (b + c->nq * cc)] = c->wq[a] * c->wq[b] * c->wq[cc];
   TDFE_HIP(c, hipMemcpyAsync(c->tab, tab.data(), TAB_SIZE * sizeof(double), hipMemcpyHostToDevice, c->stream));
 
+  if (c->octree) {
+    TDFE_TRY(tdfe_octree_bind(c));
+    TDFE_HIP(c, hipMemsetAsync(c->counters, 0, 256 * sizeof(unsigned), c->stream));
+    return finish_bind(c);
+  }
   // cell corners (and per-cell box metric)
   std::vector<double> cor((size_t)c->n_cell * 24), geo((size_t)c->n_cell * 4);
   auto V = [&](int i, int j, int k, int dd) {
@@ -453,16 +537,7 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
   TDFE_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, c->stream));
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
   if (hbad) return tdfe_fail(c, TDFE_EINVAL, "mesh has a non-positive Jacobian");
-  // pinned poll buffer for the Lanczos convergence flags
-  if (!c->poll) {
-    TDFE_HIP(c, hipHostMalloc((void**)&c->poll, 4096 * sizeof(int), hipHostMallocDefault));
-    std::memset(c->poll, 0, 4096 * sizeof(int));  // flags compare against generation numbers >= 1
-  }
-  c->bound = true;
-  c->have_potential = false;
-  c->have_scf = false;
-  c->scf_init = false;
-  return TDFE_OK;
+  return finish_bind(c);
 }
 
 tdfe_status tdfe_dof_coords(tdfe_ctx* c, double* dev_xyz) {

@@ -61,6 +61,12 @@ class AdaptDesc(ctypes.Structure):
                 ("n_elem", ctypes.c_double), ("samples", ctypes.c_int)]
 
 
+class OctreeDesc(ctypes.Structure):
+    _fields_ = [("p", ctypes.c_int), ("lo", ctypes.c_double), ("hi", ctypes.c_double), ("n0", ctypes.c_int),
+                ("max_level", ctypes.c_int), ("n_leaf", ctypes.c_int), ("leaves", ctypes.POINTER(ctypes.c_int)),
+                ("n_orb_max", ctypes.c_int), ("k_max", ctypes.c_int), ("precision", ctypes.c_int)]
+
+
 class MidpointDesc(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int), ("order", ctypes.c_int), ("sc_tol", ctypes.c_double),
                 ("sc_maxit", ctypes.c_int)]
@@ -91,6 +97,11 @@ SIGNATURES = {
     "tdfe_adaptive_axes_query": [ctypes.POINTER(AdaptDesc), ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_adaptive_axes": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_size_t, _P, ctypes.c_int, _DP, _IP, _DP],
     "tdfe_adaptive_axes_static": [ctypes.POINTER(AdaptDesc), _P, ctypes.c_int, _DP, _IP, _DP],
+    "tdfe_octree_leaves_query": [ctypes.POINTER(AdaptDesc), ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
+    "tdfe_octree_leaves": [ctypes.POINTER(AdaptDesc), ctypes.c_int, ctypes.c_int, _P, ctypes.c_size_t, _P,
+                           ctypes.c_int, _IP, _IP, _DP],
+    "tdfe_fe_octree_setup": [ctypes.POINTER(OctreeDesc), _P, ctypes.POINTER(_P)],
+    "tdfe_octree_info": [_P, _I64P, _I64P, _I64P],
     "tdfe_tridiag_expm_query": [ctypes.c_int, ctypes.POINTER(ctypes.c_size_t)],
     "tdfe_tridiag_expm": [_P, _P, ctypes.c_int, ctypes.c_double, _P, _P, ctypes.c_size_t, _P, _IP],
     "tdfe_kick": [_P, _P, ctypes.c_int, ctypes.c_double],
@@ -170,14 +181,44 @@ class Context:
         if s != OK:
             raise TdfeError(s, "fe_mesh_setup rejected the mesh description")
         self.h = h
-        self.n_dof, self.n_cell, self.n_quad, self.ws_bytes = self.query()
         self.p, self.nq = p, d.nq
         self.n_nodes = int(np.prod([c * p + 1 for c in ncell]))
+        self._bind(n_orb_max)
+
+    def _bind(self, n_orb_max):
+        import torch
+        self.n_dof, self.n_cell, self.n_quad, self.ws_bytes = self.query()
         self.n_orb_max = n_orb_max
         self.workspace = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device="cuda")
         base = self.workspace.data_ptr()
         off = (-base) % 256
         self._check(self.lib.tdfe_bind_workspace(self.h, ctypes.c_void_p(base + off), self.ws_bytes))
+
+    @classmethod
+    def octree(cls, p, lo, hi, n0, max_level, leaves, n_orb_max, k_max=128, stream=None):
+        """A context on the leaves ({q, i, j, k} rows) of an octree over
+        [lo, hi]^3 with hanging-node constraints (tdfe_fe_octree_setup)."""
+        self = cls.__new__(cls)
+        self.lib = load()
+        lv = np.ascontiguousarray(np.asarray(leaves, dtype=np.int32).reshape(-1, 4))
+        self._leaves = lv
+        d = OctreeDesc()
+        d.p, d.lo, d.hi, d.n0, d.max_level = p, lo, hi, n0, max_level
+        d.n_leaf = len(lv)
+        d.leaves = lv.ctypes.data_as(_IP)
+        d.n_orb_max, d.k_max, d.precision = n_orb_max, k_max, FP64
+        self._stream = stream if stream is not None else _stream_handle()
+        h = ctypes.c_void_p()
+        s = self.lib.tdfe_fe_octree_setup(ctypes.byref(d), self._stream, ctypes.byref(h))
+        if s != OK:
+            raise TdfeError(s, "fe_octree_setup rejected the octree")
+        self.h = h
+        self.p, self.nq = p, p + 1
+        nn, nh, nz = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        self._check(self.lib.tdfe_octree_info(self.h, ctypes.byref(nn), ctypes.byref(nh), ctypes.byref(nz)))
+        self.n_nodes, self.n_hanging, self.constraint_nnz = nn.value, nh.value, nz.value
+        self._bind(n_orb_max)
+        return self
 
     # -- plumbing ---------------------------------------------------------------
     def _check(self, s):
@@ -529,6 +570,31 @@ def adaptive_axes(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=
         raise TdfeError(s, "adaptive_axes failed")
     del keep
     return [axes[a, :nc[a] + 1].copy() for a in range(3)], E.value
+
+
+def octree_leaves(p, lo, hi, R, Z, s_orb, a_pot, n_elem, n0, max_level, samples=129, max_leaves=200000):
+    """Leaves ({q, i, j, k} rows, sorted) of the balanced octree whose cubes
+    follow the a priori element size h(r); returns (leaves, E)."""
+    import torch
+    lib = load()
+    d, keep = _adapt_desc(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples)
+    nb = ctypes.c_size_t()
+    s = lib.tdfe_octree_leaves_query(ctypes.byref(d), max_leaves, ctypes.byref(nb))
+    if s != OK:
+        raise TdfeError(s, "octree_leaves: bad description")
+    scratch = torch.empty(nb.value + 256, dtype=torch.uint8, device="cuda")
+    base = scratch.data_ptr()
+    off = (-base) % 256
+    out = np.zeros((max_leaves, 4), dtype=np.int32)
+    n = ctypes.c_int()
+    E = ctypes.c_double()
+    s = lib.tdfe_octree_leaves(ctypes.byref(d), n0, max_level, ctypes.c_void_p(base + off), nb.value,
+                               _stream_handle(), max_leaves, out.ctypes.data_as(_IP), ctypes.byref(n),
+                               ctypes.byref(E))
+    if s != OK:
+        raise TdfeError(s, "octree_leaves failed")
+    del keep
+    return out[:n.value].copy(), E.value
 
 
 def adaptive_axes_static(p, lo, hi, R, Z, s_orb, a_pot, n_elem, samples=129, max_cells=4096):
