@@ -452,6 +452,74 @@ def adaptive_mesh(n_elem=1728, n_steps=10):
             "wall_s": time.perf_counter() - t}
 
 
+def octree_mesh(n_elem=1728.0, n_steps=10, n0=4, max_level=3):
+    """Octree mesh with hanging nodes from the a priori element size against
+    a uniform mesh with about the same DoF count: the induced dipole of the
+    benchmark workload's recipe with its potential held fixed (4 atoms, 8
+    orbitals, kick, p = 5; octree contexts take no Hartree term) over 10
+    steps, each against a 32^3-cell uniform reference; and the octree
+    operator's rate."""
+    import torch
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    base = W.CONFIGS[2]
+    Z, R = W.atoms(base)
+
+    def run(ctx):
+        xq = ctx.quad_coords().cpu().numpy()
+        ctx.set_potential(torch.from_numpy(W.external_potential(base, xq).reshape(ctx.n_cell, -1)).cuda())
+        psi = torch.from_numpy(W.initial_psibar(base, ctx.dof_coords().cpu().numpy(),
+                                                ctx.mass_diag().cpu().numpy())).cuda()
+        mu = [ctx.dipole(psi)[0][2]]
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(n_steps):
+            mu.append(ctx.magnus_step(psi, base.dt, 0.0, base.tol)["mu"][2])
+        torch.cuda.synchronize()
+        mu = np.array(mu)
+        return mu - mu[0], time.perf_counter() - t
+
+    t0 = time.perf_counter()
+    leaves, E = tdfe.octree_leaves(base.p, base.lo, base.hi, R, Z, [1.0] * len(Z), [0.5] * len(Z), n_elem, n0,
+                                   max_level, samples=129)
+    t_leaves = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    oc = tdfe.Context.octree(base.p, base.lo, base.hi, n0, max_level, leaves, n_orb_max=base.n_orb, k_max=base.k_max)
+    t_setup = time.perf_counter() - t0
+    d_oct, w_oct = run(oc)
+    t_apply = time_apply(oc, base.n_orb, False, 20)
+    res_oct = {"leaves": int(len(leaves)), "levels": np.bincount(leaves[:, 0]).tolist(), "n_dof": oc.n_dof,
+               "hanging_nodes": oc.n_hanging, "constraint_nnz": oc.constraint_nnz, "E": E,
+               "leaves_s": t_leaves, "setup_s": t_setup, "steps_per_s": n_steps / w_oct,
+               "apply_us": t_apply * 1e6, "apply_H_gdof_orb_per_s": oc.n_dof * base.n_orb / t_apply / 1e9}
+    nd_oct = oc.n_dof
+    oc.close()
+    torch.cuda.empty_cache()
+    n1 = max(2, int(round((nd_oct ** (1.0 / 3.0) + 1.0) / base.p)))
+
+    def uniform(nc):
+        return tdfe.Context(base.p, (nc, nc, nc), W.box_vertices(base.lo, base.hi, (nc, nc, nc)),
+                            n_orb_max=base.n_orb, k_max=base.k_max)
+
+    ref_ctx = uniform(32)
+    ref, _ = run(ref_ctx)
+    nd_ref = ref_ctx.n_dof
+    ref_ctx.close()
+    torch.cuda.empty_cache()
+    uc = uniform(n1)
+    d_uni, w_uni = run(uc)
+    nd_uni = uc.n_dof
+    uc.close()
+    torch.cuda.empty_cache()
+    scale = np.abs(ref).max()
+    res_oct["induced_dipole_rel_err"] = float(np.abs(d_oct - ref).max() / scale)
+    return {"workload": base.name + f" recipe with a fixed potential, {n_steps} steps, p = {base.p}",
+            "reference": {"cells": [32, 32, 32], "n_dof": nd_ref},
+            "uniform": {"cells": [n1] * 3, "n_dof": nd_uni, "steps_per_s": n_steps / w_uni,
+                        "induced_dipole_rel_err": float(np.abs(d_uni - ref).max() / scale)},
+            "octree": res_oct}
+
+
 class Workload:
     """One seeded workload on the GPU: the host-side inputs (vertices, V_ext at
     the Gauss points, the initial psibar) are formed once and shared by every
@@ -691,7 +759,8 @@ def main():
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     ap.add_argument("--legs", default=None,
-                    help="comma list of extra legs to run alone (ae, box, adjoint, nonlocal, spectra, midpoint, adaptive)")
+                    help="comma list of extra legs to run alone (ae, box, hartree, adjoint, nonlocal, spectra, midpoint, "
+                         "adaptive, octree)")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -717,7 +786,7 @@ def main():
         torch.cuda.synchronize()
         del a, b
     legs = {"ae": ae_steps, "hartree": hartree_solves, "adjoint": adjoint_rate, "nonlocal": nonlocal_term, "spectra": field_and_spectra,
-            "midpoint": midpoint_modes, "adaptive": adaptive_mesh,
+            "midpoint": midpoint_modes, "adaptive": adaptive_mesh, "octree": octree_mesh,
             "box": lambda: {"workload": W.CONFIGS[2].name, **workload_legs(W.CONFIGS[2], 100, 5, 100, False)}}
     if args.legs:
         print(json.dumps({name: legs[name]() for name in args.legs.split(",")}), flush=True)
@@ -769,7 +838,8 @@ def main():
         out["ae_workload"] = ae_steps()
         out["hartree_graded"] = hartree_solves()
         for name, fn in (("adjoint", adjoint_rate), ("nonlocal", nonlocal_term), ("field_and_spectra", field_and_spectra),
-                         ("midpoint", midpoint_modes), ("adaptive_mesh", adaptive_mesh)):
+                         ("midpoint", midpoint_modes), ("adaptive_mesh", adaptive_mesh),
+                         ("octree_mesh", octree_mesh)):
             out[name] = fn()
     if cpu is not None:
         out["cpu_baseline"] = cpu_baseline(cpu, cfg, counts)
