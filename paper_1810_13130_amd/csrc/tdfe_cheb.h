@@ -21,7 +21,6 @@
 #define TDFE_JTAB_STRIDE (TDFE_MAX_BESSEL + 2 + 2 * TDFE_CHEB_THREADS)
 
 struct ChebLds {
-  double bufA[TDFE_KCAP], bufB[TDFE_KCAP];
   double yr[TDFE_KCAP], yi[TDFE_KCAP];
   double red[3 * TDFE_CHEB_THREADS];
   double inv;  // normalisation of the Bessel table
@@ -233,100 +232,135 @@ __device__ inline int cheb_expm_e1_wave_gtab(int k, double a, double bl, double 
   return M;
 }
 
-// k up to TDFE_KCAP rows on ONE wavefront (rows t, t + 64, ... per lane, the
-// Chebyshev vectors in LDS); the coefficients come from the orbital's global
-// table Jg as in cheb_expm_e1_wave.  Returns the number of terms M (>= 0),
-// -1 if |s| r exceeds the Bessel table or TDFE_CHEB_NONFINITE if it is not
-// finite; *amax receives max_j |sa[j]|
-__device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, double s, ChebLds& L, double* Jg,
-                                   double* amax) {
+// Same function for k > TDFE_CHEB_THREADS: R consecutive rows per lane of one
+// wavefront (lane t holds rows R t .. R t + R - 1), the Chebyshev vectors in
+// registers, the neighbours across lanes by DPP shifts, so that a term costs
+// no LDS round trip or barrier.  sa / sb: diagonal and off-diagonal (any
+// memory the wavefront can read); row R t + r of y is returned in yr[r],
+// yi[r] (zero past k).
+template <int R>
+__device__ inline int cheb_expm_e1_rows(int k, const double* sa, const double* sb, double s, double* Jg,
+                                        double (&yr)[R], double (&yi)[R], double* amax) {
   const int t = threadIdx.x;
+  double a[R], bl[R], br[R];
   double lo = 1e300, hi = -1e300, am = 0.0;
-  for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
-    double rad = 0.0;
-    if (j > 0) rad += fabs(sb[j - 1]);
-    if (j < k - 1) rad += fabs(sb[j]);
-    lo = fmin(lo, sa[j] - rad);
-    hi = fmax(hi, sa[j] + rad);
-    am = fmax(am, fabs(sa[j]));
-  }
-  L.red[t] = lo;
-  L.red[TDFE_CHEB_THREADS + t] = hi;
-  L.red[2 * TDFE_CHEB_THREADS + t] = am;
-  __syncthreads();
-  for (int w = TDFE_CHEB_THREADS / 2; w > 0; w >>= 1) {
-    if (t < w) {
-      L.red[t] = fmin(L.red[t], L.red[t + w]);
-      L.red[TDFE_CHEB_THREADS + t] = fmax(L.red[TDFE_CHEB_THREADS + t], L.red[TDFE_CHEB_THREADS + t + w]);
-      L.red[2 * TDFE_CHEB_THREADS + t] = fmax(L.red[2 * TDFE_CHEB_THREADS + t], L.red[2 * TDFE_CHEB_THREADS + t + w]);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = R * t + r;
+    const bool row = j < k;
+    a[r] = row ? sa[j] : 0.0;
+    bl[r] = (row && j > 0) ? sb[j - 1] : 0.0;
+    br[r] = (row && j < k - 1) ? sb[j] : 0.0;
+    if (row) {
+      lo = fmin(lo, a[r] - fabs(bl[r]) - fabs(br[r]));
+      hi = fmax(hi, a[r] + fabs(bl[r]) + fabs(br[r]));
+      am = fmax(am, fabs(a[r]));
     }
-    __syncthreads();
   }
-  lo = L.red[0];
-  hi = L.red[TDFE_CHEB_THREADS];
-  *amax = L.red[2 * TDFE_CHEB_THREADS];
+  for (int off = TDFE_CHEB_THREADS / 2; off > 0; off >>= 1) {
+    lo = fmin(lo, __shfl_xor(lo, off));
+    hi = fmax(hi, __shfl_xor(hi, off));
+    am = fmax(am, __shfl_xor(am, off));
+  }
+  *amax = am;
   const double cc = 0.5 * (lo + hi), rr = 0.5 * (hi - lo);
   const double z = fabs(s) * rr;
-  if (t == 0) L.M = cheb_bessel(z, Jg, &L.inv);
+  int m0 = 0;
+  double inv0 = 0.0;
+  if (t == 0) m0 = cheb_bessel(z, Jg, &inv0);
   // lane 0's table stores complete and are visible to every lane's loads
   __threadfence();
-  __syncthreads();
-  const int M = L.M;
-  const double jn = L.inv;
+  const int M = __builtin_amdgcn_readfirstlane(m0);
+  const double jn = lane_read(inv0, 0);
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    yr[r] = 0.0;
+    yi[r] = 0.0;
+  }
   if (M < 0) return M;
   const double sgn = s >= 0.0 ? 1.0 : -1.0;
   const double invr = rr > 0.0 ? 1.0 / rr : 0.0;
+  double ac[R], vp[R], vc[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    ac[r] = (R * t + r < k) ? a[r] - cc : 0.0;
+    vp[r] = (t == 0 && r == 0) ? 1.0 : 0.0;
+  }
   double jr = Jg[t];
   double jnx = Jg[TDFE_CHEB_THREADS + t];
-  const double J0 = lane_read(jr, 0), J1 = lane_read(jr, 1);
-  for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
-    L.bufA[j] = (j == 0) ? 1.0 : 0.0;
-    L.yr[j] = jn * J0 * L.bufA[j];
-    L.yi[j] = 0.0;
-  }
-  __syncthreads();
-  double* prev = L.bufA;
-  double* cur = L.bufB;
+  yr[0] = jn * lane_read(jr, 0) * vp[0];
   if (M >= 1) {
-    for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
-      double w = (sa[j] - cc) * prev[j];
-      if (j > 0) w += sb[j - 1] * prev[j - 1];
-      if (j < k - 1) w += sb[j] * prev[j + 1];
-      w *= invr;
-      cur[j] = w;
-      L.yi[j] += -2.0 * sgn * jn * J1 * w;
+    {
+      const double left = lane_prev(vp[R - 1]), right = lane_next(vp[0]);
+      const double J1 = lane_read(jr, 1);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double l = r > 0 ? vp[r - 1] : left, rt = r < R - 1 ? vp[r + 1] : right;
+        vc[r] = (ac[r] * vp[r] + bl[r] * l + br[r] * rt) * invr;
+        yi[r] += -2.0 * sgn * jn * J1 * vc[r];
+      }
     }
-    __syncthreads();
     for (int mm = 2; mm <= M; ++mm) {
       if ((mm & (TDFE_CHEB_THREADS - 1)) == 0) {
         jr = jnx;
         jnx = Jg[mm + TDFE_CHEB_THREADS + t];  // < TDFE_JTAB_STRIDE since mm <= M < TDFE_MAX_BESSEL
       }
+      const double left = lane_prev(vc[R - 1]), right = lane_next(vc[0]);
+      double vn[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double l = r > 0 ? vc[r - 1] : left, rt = r < R - 1 ? vc[r + 1] : right;
+        const double w = ac[r] * vc[r] + bl[r] * l + br[r] * rt;
+        vn[r] = 2.0 * w * invr - vp[r];
+      }
       const double cj = 2.0 * jn * lane_read(jr, mm & (TDFE_CHEB_THREADS - 1));
       const int ph = mm & 3;  // (-i sgn)^m : 1, -i sgn, -1, +i sgn
-      for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
-        double w = (sa[j] - cc) * cur[j];
-        if (j > 0) w += sb[j - 1] * cur[j - 1];
-        if (j < k - 1) w += sb[j] * cur[j + 1];
-        const double v2 = 2.0 * w * invr - prev[j];
-        prev[j] = v2;
-        if (ph == 0) L.yr[j] += cj * v2;
-        else if (ph == 1) L.yi[j] -= sgn * cj * v2;
-        else if (ph == 2) L.yr[j] -= cj * v2;
-        else L.yi[j] += sgn * cj * v2;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        vp[r] = vc[r];
+        vc[r] = vn[r];
+        if (ph == 0) yr[r] += cj * vn[r];
+        else if (ph == 1) yi[r] -= sgn * cj * vn[r];
+        else if (ph == 2) yr[r] -= cj * vn[r];
+        else yi[r] += sgn * cj * vn[r];
       }
-      __syncthreads();
-      double* tmp = prev;
-      prev = cur;
-      cur = tmp;
     }
   }
   const double pr = cos(s * cc), pim = -sin(s * cc);
-  for (int j = t; j < k; j += TDFE_CHEB_THREADS) {
-    const double a = L.yr[j], b = L.yi[j];
-    L.yr[j] = a * pr - b * pim;
-    L.yi[j] = a * pim + b * pr;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const double a0 = yr[r], b0 = yi[r];
+    yr[r] = a0 * pr - b0 * pim;
+    yi[r] = a0 * pim + b0 * pr;
+  }
+  return M;
+}
+
+template <int R>
+__device__ inline int cheb_rows_lds(int k, const double* sa, const double* sb, double s, ChebLds& L, double* Jg,
+                                    double* amax) {
+  double yr[R], yi[R];
+  const int M = cheb_expm_e1_rows<R>(k, sa, sb, s, Jg, yr, yi, amax);
+  const int t = threadIdx.x;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    const int j = R * t + r;
+    if (j < k) {
+      L.yr[j] = yr[r];
+      L.yi[j] = yi[r];
+    }
   }
   __syncthreads();
   return M;
+}
+
+// y = exp(-i s T) e_1 for TDFE_CHEB_THREADS < k <= TDFE_KCAP on one
+// wavefront, left in L.yr / L.yi (rows per lane by k: 2, 3, 4, 8 or 16)
+__device__ inline int cheb_expm_e1(int k, const double* sa, const double* sb, double s, ChebLds& L, double* Jg,
+                                   double* amax) {
+  if (k <= 2 * TDFE_CHEB_THREADS) return cheb_rows_lds<2>(k, sa, sb, s, L, Jg, amax);
+  if (k <= 3 * TDFE_CHEB_THREADS) return cheb_rows_lds<3>(k, sa, sb, s, L, Jg, amax);
+  if (k <= 4 * TDFE_CHEB_THREADS) return cheb_rows_lds<4>(k, sa, sb, s, L, Jg, amax);
+  if (k <= 8 * TDFE_CHEB_THREADS) return cheb_rows_lds<8>(k, sa, sb, s, L, Jg, amax);
+  return cheb_rows_lds<16>(k, sa, sb, s, L, Jg, amax);
 }

@@ -85,6 +85,7 @@ struct tdfe_ctx {
   void* hq = nullptr;         // [n_dof][cols] apply output
   void* half = nullptr;       // [n_dof][2 n_orb_max] predictor state (complex128)
   double* partial = nullptr;  // reduction partials
+  double* partial2 = nullptr; // [128][TDFE_MAX_COLS] first level of the two-level alpha reduction
   double* scal = nullptr;     // per-orbital Lanczos scalars
   double* jtab = nullptr;     // [chunk_orb][TDFE_JTAB_STRIDE] Bessel tables of the small exponential
   unsigned* counters = nullptr;

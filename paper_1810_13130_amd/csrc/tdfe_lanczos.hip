@@ -254,6 +254,34 @@ __global__ void __launch_bounds__(RED_THREADS)
   }
 }
 
+// first level of a two-level fixed-order sum of [nrows][C] partials: block b
+// sums its contiguous share of rows for every column into out[b][C] (the
+// second level is finalize_pairs_kernel over the ALPHA_SLICES rows of out)
+constexpr int ALPHA_SLICES = 128;
+__global__ void __launch_bounds__(RED_THREADS)
+    slice_sums_kernel(const double* __restrict__ partial, int64_t nrows, int C, double* __restrict__ out,
+                      const int* done) {
+  __shared__ double sred[RED_THREADS];
+  if (done && *done) return;
+  const int Cp = (C <= 1) ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : (C <= 32 ? 32 : 64)))));
+  const int col = threadIdx.x % Cp;
+  const int rl = threadIdx.x / Cp;
+  const int nl = RED_THREADS / Cp;
+  const int64_t per = (nrows + ALPHA_SLICES - 1) / ALPHA_SLICES;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = r0 + per < nrows ? r0 + per : nrows;
+  double acc = 0.0;
+  if (col < C)
+    for (int64_t r = r0 + rl; r < r1; r += nl) acc += partial[r * C + col];
+  sred[threadIdx.x] = acc;
+  __syncthreads();
+  if (rl == 0 && col < C) {
+    double s = 0.0;
+    for (int l = 0; l < nl; ++l) s += sred[l * Cp + col];
+    out[(int64_t)blockIdx.x * C + col] = s;
+  }
+}
+
 // ---------------------------------------------------------------------------------------------
 // small exponential and adaptive stop, one wavefront per orbital
 // ---------------------------------------------------------------------------------------------
@@ -557,8 +585,18 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     TDFE_TRY(tdfe_launch_apply(c, a));
     // m = beta_{k-2} for k >= 2 (the operator input was scaled by s^2, not s), 1 for k = 1
     const double* m = k >= 2 ? S.beta + (size_t)(k - 2) * Nc : (const double*)nullptr;
-    hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial, groups, C,
-                       S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (double*)nullptr, m, (const int*)S.done);
+    if (groups > 4 * ALPHA_SLICES) {
+      // many operator blocks: a first level over slices of rows (all columns
+      // at once), then the per-orbital sums over the slices
+      hipLaunchKernelGGL(slice_sums_kernel, dim3(ALPHA_SLICES), dim3(RED_THREADS), 0, c->stream,
+                         (const double*)c->partial, groups, C, c->partial2, (const int*)S.done);
+      hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial2,
+                         (int64_t)ALPHA_SLICES, C, S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (double*)nullptr,
+                         m, (const int*)S.done);
+    } else {
+      hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial, groups, C,
+                         S.alpha + (size_t)(k - 1) * Nc, 0, (double*)nullptr, (double*)nullptr, m, (const int*)S.done);
+    }
     SmallExp se{S, Nc, k, K, k <= CHK_THREADS ? Nc : 0, tau, c->jtab, dprog, gen};
     hipLaunchKernelGGL((update_kernel<T>), dim3(RED_BLOCKS + se.nblk), dim3(RED_THREADS), 0, c->stream, Hq,
                        (const T*)wk, W + (int64_t)k * vstride, C, nd, (const double*)(S.alpha + (size_t)(k - 1) * Nc),

@@ -214,6 +214,7 @@ void carve(tdfe_ctx* c, char* base) {
   // block partials of the operator kernels, plus rows appended after them (the nonlocal term's)
   c->n_partial = (std::max<int64_t>(ne, 4096) + 8) * std::max(cols, 8);
   c->partial = k.take<double>(c->n_partial);
+  c->partial2 = k.take<double>(128 * TDFE_MAX_COLS);
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
   c->jtab = k.take<double>((size_t)std::max(c->chunk_orb, 1) * TDFE_JTAB_STRIDE);
   c->counters = k.take<unsigned>(256);
