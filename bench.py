@@ -692,6 +692,42 @@ def ae_steps(n_steps=2):
     return out
 
 
+def matrix_core_engines(steps=100, warmup=5, reps=100):
+    """The box-cell workload (16^3 cells, p = 5, 8 orbitals, Hartree + LDA x)
+    with the cell operator's 1D contractions on each engine: the VALU kernels
+    of the FP64 and mixed paths and the matrix-core variants (FP64, FP32 and
+    split BF16 products): operator launch time in the step's shape, Magnus
+    steps/s and the dipole error against the FP64 VALU trajectory."""
+    import workloads as W
+    from paper_1810_13130_amd import tdfe
+    cfg = W.CONFIGS[2]
+    wl = Workload(cfg)
+    out = {"workload": cfg.name, "steps": steps}
+    ref = None
+    engines = (("f64_valu", tdfe.FP64, False, "pair_kernel<double,6,16,1>"),
+               ("f64_mfma", tdfe.FP64_MFMA, False, "mfma_box_kernel<FP64,6> (v_mfma_f64_16x16x4)"),
+               ("f32_valu", tdfe.MIXED_FP32, True, "plane_kernel<float,6,16,2>"),
+               ("f32_mfma", tdfe.FP32_MFMA, True, "mfma_box_kernel<FP32,6> (v_mfma_f32_16x16x4)"),
+               ("bf16x3_mfma", tdfe.BF16_MFMA, True, "mfma_box_kernel<BF16x3,6> (v_mfma_f32_16x16x16_bf16)"))
+    for name, prec, fp32, kernel in engines:
+        ctx, psi = wl.context(prec)
+        n = ctx.krylov_chunk(cfg.n_orb)
+        r = run_steps(ctx, psi, cfg, cfg.tol, steps, warmup)
+        t = time_apply(ctx, n, fp32, reps)
+        rec = {"kernel": kernel, "launch_us": t * 1e6, "launch_orbitals": n, "steps_per_s": r["steps_per_s"],
+               "krylov_its_per_step": r["krylov_its_per_step"],
+               "hbm_frac": apply_bytes(ctx.n_dof, ctx.n_cell, ctx.n_quad, n, 4 if fp32 else 8, False) / t / 1e9
+               / HBM_PEAK_GBS}
+        if ref is None:
+            ref = r["mu"]
+        else:
+            e, e_ind, m = dipole_errors(r["mu"], ref)
+            rec.update({"dipole_rel_err": e, "dipole_err_rel_induced": e_ind, "steps_compared": m})
+        out[name] = rec
+        close(ctx)
+    return out
+
+
 def workload_legs(cfg, steps, warmup, apply_reps, curved, matched=True, jacobi_count=False):
     """FP64, mixed and (optionally) FP64 at the mixed path's effective stop
     tolerance on one workload; operator launches in the step's shape."""
@@ -756,11 +792,14 @@ def main():
     ap.add_argument("--no-extras", action="store_true", help="skip the box workload and the extension legs")
     ap.add_argument("--apply-only", action="store_true",
                     help="only the operator launches of the headline workload (for counter runs)")
+    ap.add_argument("--engines", default="f64,mixed",
+                    help="with --apply-only: comma list of f64, mixed, f64_mfma, f32_mfma, bf16_mfma (the matrix-core "
+                         "variants need a box-cell workload, --config 2)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run a 1 GiB device copy first (reference kernel for HBM byte counters)")
     ap.add_argument("--legs", default=None,
                     help="comma list of extra legs to run alone (ae, box, hartree, adjoint, nonlocal, spectra, midpoint, "
-                         "adaptive, octree)")
+                         "adaptive, octree, mfma)")
     ap.add_argument("--cpu-worker", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     if args.cpu_worker:
@@ -786,19 +825,21 @@ def main():
         torch.cuda.synchronize()
         del a, b
     legs = {"ae": ae_steps, "hartree": hartree_solves, "adjoint": adjoint_rate, "nonlocal": nonlocal_term, "spectra": field_and_spectra,
-            "midpoint": midpoint_modes, "adaptive": adaptive_mesh, "octree": octree_mesh,
+            "midpoint": midpoint_modes, "adaptive": adaptive_mesh, "octree": octree_mesh, "mfma": matrix_core_engines,
             "box": lambda: {"workload": W.CONFIGS[2].name, **workload_legs(W.CONFIGS[2], 100, 5, 100, False)}}
     if args.legs:
         print(json.dumps({name: legs[name]() for name in args.legs.split(",")}), flush=True)
         return
     if args.apply_only:
         wl = Workload(cfg)
-        for prec, fp32 in ((tdfe.FP64, False), (tdfe.MIXED_FP32, True)):
+        engines = {"f64": (tdfe.FP64, False), "mixed": (tdfe.MIXED_FP32, True), "f64_mfma": (tdfe.FP64_MFMA, False),
+                   "f32_mfma": (tdfe.FP32_MFMA, True), "bf16_mfma": (tdfe.BF16_MFMA, True)}
+        for name in args.engines.split(","):
+            prec, fp32 = engines[name]
             ctx, _ = wl.context(prec, state=False)
             n = ctx.krylov_chunk(cfg.n_orb)
             t = time_apply(ctx, n, fp32, args.apply_reps)
-            print(json.dumps({"precision": "f32" if fp32 else "f64", "launch_orbitals": n, "launch_us": t * 1e6}),
-                  flush=True)
+            print(json.dumps({"precision": name, "launch_orbitals": n, "launch_us": t * 1e6}), flush=True)
             close(ctx)
         return
 
@@ -839,7 +880,7 @@ def main():
         out["hartree_graded"] = hartree_solves()
         for name, fn in (("adjoint", adjoint_rate), ("nonlocal", nonlocal_term), ("field_and_spectra", field_and_spectra),
                          ("midpoint", midpoint_modes), ("adaptive_mesh", adaptive_mesh),
-                         ("octree_mesh", octree_mesh)):
+                         ("octree_mesh", octree_mesh), ("matrix_cores", matrix_core_engines)):
             out[name] = fn()
     if cpu is not None:
         out["cpu_baseline"] = cpu_baseline(cpu, cfg, counts)

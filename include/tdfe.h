@@ -59,6 +59,21 @@ typedef struct tdfe_ctx tdfe_ctx;
 /* working precision of the cell contractions and Krylov storage */
 #define TDFE_FP64 0       /* everything FP64 (parity path) */
 #define TDFE_MIXED_FP32 1 /* FP32 contractions and Krylov storage; FP64 scalars */
+/* Matrix-core variants of the operator's 1D contractions (rectilinear box
+ * meshes only; tdfe_fe_mesh_setup returns TDFE_EINVAL for any other mesh).
+ * Storage, scalars and every other kernel are those of the base precision;
+ * only the H-bar launches of the cell operator change engine:
+ *   TDFE_FP32_MFMA: as TDFE_MIXED_FP32, contractions on FP32 matrix cores
+ *                   (v_mfma_f32_16x16x4), p <= 7;
+ *   TDFE_BF16_MFMA: as TDFE_MIXED_FP32, each contraction as three BF16
+ *                   matrix-core products of split operands (head x head +
+ *                   head x remainder + remainder x head, FP32 accumulation;
+ *                   about 2^-16 relative per product), p <= 7;
+ *   TDFE_FP64_MFMA: as TDFE_FP64, contractions on FP64 matrix cores
+ *                   (v_mfma_f64_16x16x4), p <= 6. */
+#define TDFE_FP32_MFMA 2
+#define TDFE_BF16_MFMA 3
+#define TDFE_FP64_MFMA 4
 
 typedef struct {
   int p;                  /* element order, 1..8 (Sec. spectral FE) */
@@ -67,7 +82,7 @@ typedef struct {
   const double* vertices; /* HOST, (ncx+1)(ncy+1)(ncz+1) x 3, x fastest */
   int n_orb_max;          /* largest orbital block passed to any call */
   int k_max;              /* Krylov dimension cap, 1..1024 */
-  int precision;          /* TDFE_FP64 or TDFE_MIXED_FP32 */
+  int precision;          /* TDFE_FP64, TDFE_MIXED_FP32 or a matrix-core variant */
 } tdfe_mesh_desc;
 
 /* fe_mesh_setup: reference element (GLL nodes/weights, Gauss rule, 1D

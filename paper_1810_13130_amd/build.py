@@ -7,6 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libtdfe.so")
 SOURCES = ["tdfe_setup.hip", "tdfe_apply.hip", "tdfe_apply_box.hip", "tdfe_apply_pair.hip", "tdfe_apply_curved.hip",
+           "tdfe_apply_mfma.hip",
            "tdfe_nonlocal.hip", "tdfe_spectra.hip", "tdfe_mesh.hip", "tdfe_octree.hip", "tdfe_lanczos.hip", "tdfe_scf.hip",
            "tdfe_adjoint.hip"]
 

@@ -597,13 +597,14 @@ int64_t tdfe_blocks_apply(const tdfe_ctx* c, int cols) {
 static tdfe_status launch_local(tdfe_ctx* c, const ApplyArgs& a) {
   if (c->octree) return tdfe_launch_apply_octree(c, a);
   // the FP32 copy of the potential exists in mixed contexts only
-  if (a.fp32 && c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply: FP32 launch in an FP64 context");
+  if (a.fp32 && !tdfe_fp32(c)) return tdfe_fail(c, TDFE_EINVAL, "apply: FP32 launch in an FP64 context");
   // default policy, from measurements on the benchmark and graded workloads:
   // box cells: the lane-pair kernel for FP64 at even n (two waves per SIMD;
   // 130 us against 170 us for the plane kernel at 16^3 cells, p = 5, 8
   // orbitals), the plane kernel otherwise; trilinear cells: the plane kernel
   // for two or more columns at p <= 7, the line kernel for one column and at
   // p = 8
+  if (c->mfma && tdfe_mfma_kernel_ok(c, a)) return tdfe_launch_apply_mfma(c, a);
   if (c->variant != TDFE_VARIANT_LINE) {
     if (c->box) {
       const bool pair = c->variant == TDFE_VARIANT_PAIR || (c->variant == 0 && !a.fp32);

@@ -26,6 +26,10 @@ struct tdfe_ctx {
   // (see tdfe_launch_apply), 1 "line" everywhere, 2 "pair" for box cells of
   // even n in both precisions, 3 "plane" kernels wherever they exist
   int variant = 0;
+  // the cell operator's contractions on the matrix cores (precision
+  // TDFE_FP32_MFMA, TDFE_BF16_MFMA or TDFE_FP64_MFMA; box meshes)
+  bool mfma = false;
+  double* mfma_tab = nullptr;  // [6][16][16] stacked 1D tables
   hipStream_t stream = nullptr;
   std::string err;
 
@@ -205,6 +209,14 @@ bool tdfe_curved_kernel_ok(const tdfe_ctx* c, int cols, bool fp32);
 #define TDFE_VARIANT_PAIR 2
 #define TDFE_VARIANT_PLANE 3
 tdfe_status tdfe_launch_apply_curved(tdfe_ctx* c, const ApplyArgs& a);
+// matrix-core variant for box cells (tdfe_apply_mfma.hip)
+bool tdfe_mfma_kernel_ok(const tdfe_ctx* c, const ApplyArgs& a);
+tdfe_status tdfe_launch_apply_mfma(tdfe_ctx* c, const ApplyArgs& a);
+void tdfe_mfma_tables(int p, double* out);  // host: [6][16][16]
+// FP32 Krylov storage and operator (mixed precision and its matrix-core variants)
+inline bool tdfe_fp32(const tdfe_ctx* c) {
+  return c->precision == TDFE_MIXED_FP32 || c->precision == TDFE_FP32_MFMA || c->precision == TDFE_BF16_MFMA;
+}
 // nonlocal term after the local kernel (tdfe_nonlocal.hip): Loewdin launches
 // on the DoF numbering only; appends one row to the energy partials
 tdfe_status tdfe_launch_nonlocal(tdfe_ctx* c, const ApplyArgs& a);

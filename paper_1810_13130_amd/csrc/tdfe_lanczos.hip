@@ -881,7 +881,7 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
   }
   std::vector<int> ks(n_orb), st(n_orb);
   std::vector<double> es(n_orb);
-  const void* v = c->precision == TDFE_FP64 ? (const void*)vw : (const void*)c->vw32;
+  const void* v = !tdfe_fp32(c) ? (const void*)vw : (const void*)c->vw32;
   // when the input is also the output, every chunk must read the input before
   // any chunk writes: the combination of a chunk only writes that chunk's
   // columns, and copy_in of a chunk only reads them, so chunk order is safe.
@@ -889,7 +889,7 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
   for (int o0 = 0; o0 < n_orb; o0 += csz) {
     const int Nc = std::min(csz, n_orb - o0);
     tdfe_status s;
-    if (c->precision == TDFE_FP64)
+    if (!tdfe_fp32(c))
       s = run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
                             es.data() + o0, st.data() + o0, hook, slot);
     else
@@ -952,7 +952,7 @@ tdfe_status tdfe_apply_H_add_f32(tdfe_ctx* c, const void* dev_psibar, void* dev_
   if (!c || !dev_psibar || !dev_out) return TDFE_EINVAL;
   if (n_orb < 1 || n_orb > c->n_orb_max) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32: n_orb out of range");
   if (dev_psibar == dev_out) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32: output aliases input");
-  if (c->precision != TDFE_MIXED_FP32) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32 needs a mixed-precision context");
+  if (!tdfe_fp32(c)) return tdfe_fail(c, TDFE_EINVAL, "apply_H_f32 needs a mixed-precision context");
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "apply_H_f32 before bind_workspace");
   if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "apply_H_f32 before set_potential");
   ApplyArgs a{};

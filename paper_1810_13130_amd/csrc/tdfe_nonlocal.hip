@@ -91,7 +91,7 @@ NlLayout nl_layout(const tdfe_ctx* c, int n_proj, char* base) {
   };
   const size_t np = (size_t)n_proj, mb = (size_t)nl_max_blocks(n_proj);
   L.cbar = (double*)take(np * c->n_dof * sizeof(double));
-  L.cbar32 = (float*)take(c->precision == TDFE_FP64 ? sizeof(float) : np * c->n_dof * sizeof(float));
+  L.cbar32 = (float*)take(!tdfe_fp32(c) ? sizeof(float) : np * c->n_dof * sizeof(float));
   L.E = (double*)take(np * sizeof(double));
   L.part = (double*)take(mb * NL_PCH * TDFE_MAX_COLS * sizeof(double));
   L.tE = (double*)take(np * TDFE_MAX_COLS * sizeof(double));
@@ -699,7 +699,7 @@ tdfe_status tdfe_set_projectors(tdfe_ctx* c, int n_proj, const double* dev_u, co
       const int64_t o = g.off + q * vol;
       hipLaunchKernelGGL(nl_pack_kernel, dim3((unsigned)((vol + 255) / 256)), dim3(256), 0, c->stream,
                          (const double*)L.dense, g, nxi, nyi, L.cbar + o,
-                         c->precision == TDFE_FP64 ? (float*)nullptr : L.cbar32 + o);
+                         !tdfe_fp32(c) ? (float*)nullptr : L.cbar32 + o);
       TDFE_HIP(c, hipGetLastError());
     }
   }

@@ -1457,7 +1457,7 @@ void tdfe_sym_eigen(const std::vector<double>& A, int n, std::vector<double>& la
 
 tdfe_status tdfe_assemble_vw(tdfe_ctx* c, const double* A, double ca, const double* B, double cb, double E) {
   const int64_t nqd = c->n_quad;
-  float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
+  float* v32 = !tdfe_fp32(c) ? nullptr : c->vw32;
   hipLaunchKernelGGL(assemble_vw_kernel, dim3(nblk(nqd)), dim3(EW), 0, c->stream, c->vext, c->xq, c->wdet, A, ca, B, cb,
                      (const double*)nullptr, 0.0, E * c->fdir[0], E * c->fdir[1], E * c->fdir[2], c->vw, v32, nqd);
   TDFE_HIP(c, hipGetLastError());
@@ -1634,7 +1634,7 @@ static tdfe_status magnus_step_impl(tdfe_ctx* c, void* dev_psibar, int n_orb, do
   if (!c->bound) return tdfe_fail(c, TDFE_ESTATE, "magnus_step before bind_workspace");
   if (!c->have_potential) return tdfe_fail(c, TDFE_ESTATE, "magnus_step before set_potential");
   const int64_t nqd = c->n_quad;
-  float* v32 = c->precision == TDFE_FP64 ? nullptr : c->vw32;
+  float* v32 = !tdfe_fp32(c) ? nullptr : c->vw32;
   tdfe_step_report r{};
   // the Lanczos results of the step (Krylov dimensions, error estimates,
   // convergence) and the dipole stay on the device until one readback and one

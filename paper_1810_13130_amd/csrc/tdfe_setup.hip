@@ -167,12 +167,13 @@ struct Carver {
   }
 };
 
-size_t elem_bytes(const tdfe_ctx* c) { return c->precision == TDFE_FP64 ? 8 : 4; }
+size_t elem_bytes(const tdfe_ctx* c) { return !tdfe_fp32(c) ? 8 : 4; }
 
 void carve(tdfe_ctx* c, char* base) {
   Carver k{base};
   const int64_t nd = c->n_dof, nqd = c->n_quad, nn = c->n_nodes, ne = c->n_cell;
   c->tab = k.take<double>(TAB_SIZE);
+  c->mfma_tab = c->mfma ? k.take<double>(6 * 256) : nullptr;
   c->minv = k.take<double>(nd);
   c->mdiag = k.take<double>(nd);
   c->dofxyz = k.take<double>(3 * nd);
@@ -232,7 +233,7 @@ void carve(tdfe_ctx* c, char* base) {
     c->oct_yf = k.take<double>((size_t)nn * c->oct_w);
   }
   // FP32 copy of M^-1/2 for the mixed path's operator (placed last)
-  c->minv32 = c->precision == TDFE_FP64 ? k.take<float>(1) : k.take<float>(nd);
+  c->minv32 = !tdfe_fp32(c) ? k.take<float>(1) : k.take<float>(nd);
   c->ws_need = k.off + 256;
   // node coordinates live right after dofxyz; keep the pointer in the ctx via fb's neighbour
   c->nodexyz_ptr = nodexyz;
@@ -266,7 +267,7 @@ void init_variant(tdfe_ctx* c) {
 // Krylov chunk: as many orbitals as fit in 60% of the device memory free at
 // creation (about 170 GB on an idle 288 GB device; 128 GB if it cannot be queried)
 void init_chunk(tdfe_ctx* c) {
-  const size_t eb = c->precision == TDFE_FP64 ? 8 : 4;
+  const size_t eb = !tdfe_fp32(c) ? 8 : 4;
   const double per_orb = (double)(c->k_max + 2) * (double)c->n_dof * 2.0 * (double)eb;
   double basis_bytes = 128e9;
   {
@@ -300,7 +301,7 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
   if (!d->vertices) return TDFE_EINVAL;
   if (d->n_orb_max < 1 || d->n_orb_max > 4096) return TDFE_EINVAL;
   if (d->k_max < 1 || d->k_max > 1024) return TDFE_EINVAL;
-  if (d->precision != TDFE_FP64 && d->precision != TDFE_MIXED_FP32) return TDFE_EINVAL;
+  if (d->precision < TDFE_FP64 || d->precision > TDFE_FP64_MFMA) return TDFE_EINVAL;
   const int64_t Nx = (int64_t)d->ncell[0] * d->p + 1, Ny = (int64_t)d->ncell[1] * d->p + 1,
                 Nz = (int64_t)d->ncell[2] * d->p + 1;
   if (Nx < 3 || Ny < 3 || Nz < 3) return TDFE_EINVAL;  // no interior node
@@ -354,6 +355,13 @@ tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_c
       if (!(c->ax_z[i] > c->ax_z[i - 1])) box = false;
   }
   c->box = box;
+  // matrix-core variants: box cells, p <= 7 (p <= 6 in FP64: three FP64 cell
+  // arrays of 16 columns fill the 160 KB of LDS)
+  c->mfma = c->precision == TDFE_FP32_MFMA || c->precision == TDFE_BF16_MFMA || c->precision == TDFE_FP64_MFMA;
+  if (c->mfma && (!box || c->p > (c->precision == TDFE_FP64_MFMA ? 6 : 7))) {
+    delete c;
+    return TDFE_EINVAL;
+  }
   init_variant(c);
   init_chunk(c);
   carve(c, nullptr);
@@ -451,6 +459,11 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
       for (int a = 0; a < c->nq; ++a)
         tab[TAB_W3Q + a + c->nq * (b + c->nq * cc)] = c->wq[a] * c->wq[b] * c->wq[cc];
   TDFE_HIP(c, hipMemcpyAsync(c->tab, tab.data(), TAB_SIZE * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  std::vector<double> mt(c->mfma ? 6 * 256 : 0);  // (the stream is synchronised before the host copies go)
+  if (c->mfma) {
+    tdfe_mfma_tables(c->p, mt.data());
+    TDFE_HIP(c, hipMemcpyAsync(c->mfma_tab, mt.data(), mt.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+  }
 
   if (c->octree) {
     TDFE_TRY(tdfe_octree_bind(c));
@@ -530,7 +543,7 @@ tdfe_status tdfe_bind_workspace(tdfe_ctx* c, void* dev, size_t bytes) {
   {
     const int64_t n = c->n_nodes;
     hipLaunchKernelGGL(node_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, c->stream, G,
-                       c->nodexyz_ptr, c->mdiag, c->minv, c->precision == TDFE_FP64 ? nullptr : c->minv32,
+                       c->nodexyz_ptr, c->mdiag, c->minv, !tdfe_fp32(c) ? nullptr : c->minv32,
                        c->dofxyz, bad);
     TDFE_HIP(c, hipGetLastError());
   }

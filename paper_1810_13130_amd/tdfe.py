@@ -17,6 +17,9 @@ LIB_PATH = os.path.join(_HERE, "libtdfe.so")
 
 OK, EINVAL, ENOMEM, EDEVICE, ENOCONV, ESTATE, ENONFINITE = 0, -1, -2, -3, -4, -5, -6
 FP64, MIXED_FP32 = 0, 1
+# matrix-core variants of the cell operator (box meshes): FP32 storage for the
+# first two (as MIXED_FP32), FP64 for the third
+FP32_MFMA, BF16_MFMA, FP64_MFMA = 2, 3, 4
 XC_NONE, XC_X, XC_XC = 0, 1, 2
 PCG_FDM, PCG_JACOBI = 0, 1
 _NAMES = {0: "OK", -1: "EINVAL", -2: "ENOMEM", -3: "EDEVICE", -4: "ENOCONV", -5: "ESTATE", -6: "ENONFINITE"}

@@ -65,6 +65,21 @@ def test_setup_rejects_bad_descriptions(lib, kw):
     assert s == tdfe.EINVAL and not h.value
 
 
+def test_matrix_core_precisions_need_box_cells_and_their_order_limit(lib):
+    from paper_1810_13130_amd import tdfe
+    curved = W.box_vertices(-1.0, 1.0, (2, 2, 2)).copy()
+    curved[1, 1, 1, 0] += 0.1  # one interior vertex moved: trilinear cells
+    for prec, p_max in ((tdfe.FP32_MFMA, 7), (tdfe.BF16_MFMA, 7), (tdfe.FP64_MFMA, 6)):
+        d, keep = _desc(tdfe, p=p_max, precision=prec)
+        s, h = _setup(lib, d)
+        assert s == tdfe.OK
+        lib.tdfe_destroy(h)
+        d, keep = _desc(tdfe, p=p_max + 1, precision=prec)
+        assert _setup(lib, d)[0] == tdfe.EINVAL
+        d, keep = _desc(tdfe, p=2, precision=prec, vertices=curved.reshape(-1))
+        assert _setup(lib, d)[0] == tdfe.EINVAL
+
+
 def test_setup_rejects_nonfinite_vertex(lib):
     from paper_1810_13130_amd import tdfe
     v = W.box_vertices(-1.0, 1.0, (2, 2, 2)).reshape(-1).copy()
