@@ -135,19 +135,26 @@ struct tdfe_ctx {
   std::vector<double> oct_s_h;               // [n_cell] cube edge
   std::vector<int> oct_eptr_h, oct_ecol_h;   // C: rows over nodes (DoF columns)
   std::vector<double> oct_eval_h;
-  std::vector<int> oct_rptr_h, oct_rcol_h;   // C^T: rows over DoFs (node columns)
-  std::vector<double> oct_rval_h;
   std::vector<double> oct_m_h, oct_dofxyz_h, oct_xq_h, oct_wdet_h;
   int* oct_cn = nullptr;
   double* oct_s = nullptr;
   int* oct_eptr = nullptr;
   int* oct_ecol = nullptr;
   double* oct_eval = nullptr;
-  int* oct_rptr = nullptr;
-  int* oct_rcol = nullptr;
-  double* oct_rval = nullptr;
-  double* oct_xf = nullptr;  // [n_nodes][oct_w] expanded input
-  double* oct_yf = nullptr;  // [n_nodes][oct_w] per-node output before C^T
+  double* oct_xf = nullptr;  // [n_nodes][oct_w] expanded input (density; the operator's hanging values)
+  double* oct_yf = nullptr;  // [n_nodes][oct_w] the operator's hanging-node output before C_h^T
+  // the operator's view: per cell node slot its DoF index, -1 (boundary, or a
+  // hanging node without interior masters: value 0) or -2 - h for hanging
+  // node h; the hanging nodes' node indices; C^T restricted to the hanging
+  // rows, by master DoF
+  std::vector<int> oct_cd_h, oct_hv_h, oct_mptr_h, oct_md_h, oct_mh_h;
+  std::vector<double> oct_mv_h;
+  int* oct_cd = nullptr;
+  int* oct_hv = nullptr;
+  int* oct_mptr = nullptr;
+  int* oct_md = nullptr;
+  int* oct_mh = nullptr;
+  double* oct_mv = nullptr;
 };
 
 // error helpers ----------------------------------------------------------------

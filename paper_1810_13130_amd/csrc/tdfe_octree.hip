@@ -11,10 +11,14 @@
 // of node m, so that Hbar = M^-1/2 C^T H_nodes C M^-1/2 (Eq.
 // TDKSMatVecStandard) keeps a diagonal M.
 //
-// Device (every operator application, Eq. DiscreteHamiltonian):
-//   expand  xf = C (cs M^-1/2 x)             one thread per (node, column)
-//   cells   yf += H_e xf_e                    one block per (cube, column block)
-//   reduce  y += M^-1/2 C^T yf                one thread per (DoF, column)
+// Device (every operator application, Eq. DiscreteHamiltonian), with C
+// split into its identity rows (DoF nodes) and the rows of hanging nodes:
+//   hexpand  xh = C_h (cs M^-1/2 x)           one thread per (hanging node, column)
+//   cells    per cube: gather DoF nodes from x (x cs M^-1/2), hanging nodes
+//            from xh, boundary nodes 0; H_e; scatter-add DoF nodes onto y
+//            (x M^-1/2), hanging nodes onto yh
+//   hreduce  y += M^-1/2 C_h^T yh             one thread per (master DoF, column)
+// The density expands every node (xf = C cs M^-1/2 x) and interpolates from xf.
 // The cell kernel keeps the cube's values in LDS and runs one 1D contraction
 // per thread and pass (x, y, z interpolation to the Gauss points, collocation
 // derivatives there, the diagonal metric of a cube, transposed passes back);
@@ -271,22 +275,6 @@ tdfe_status build_octree(tdfe_ctx* c, const tdfe_octree_desc* d) {
     c->oct_eptr_h[v + 1] = (int)c->oct_ecol_h.size();
   }
   if ((int64_t)c->oct_ecol_h.size() > ((int64_t)1 << 31) - 2) return tdfe_fail(c, TDFE_EINVAL, "octree: C too large");
-  // C^T by DoF rows (node order within a row)
-  c->oct_rptr_h.assign(ndof + 1, 0);
-  for (size_t j = 0; j < c->oct_ecol_h.size(); ++j) c->oct_rptr_h[c->oct_ecol_h[j] + 1]++;
-  for (int64_t dd = 0; dd < ndof; ++dd) c->oct_rptr_h[dd + 1] += c->oct_rptr_h[dd];
-  c->oct_rcol_h.assign(c->oct_ecol_h.size(), 0);
-  c->oct_rval_h.assign(c->oct_ecol_h.size(), 0.0);
-  {
-    std::vector<int> fill(c->oct_rptr_h.begin(), c->oct_rptr_h.end() - 1);
-    for (int64_t v = 0; v < nn; ++v)
-      for (int j = c->oct_eptr_h[v]; j < c->oct_eptr_h[v + 1]; ++j) {
-        const int dd = c->oct_ecol_h[j];
-        c->oct_rcol_h[fill[dd]] = (int)v;
-        c->oct_rval_h[fill[dd]] = c->oct_eval_h[j];
-        ++fill[dd];
-      }
-  }
   // unconstrained GLL mass of every node, then the row-sum lumped overlap
   const double unit = (d->hi - d->lo) / (double)top;
   std::vector<double> Mn(nn, 0.0);
@@ -330,6 +318,45 @@ tdfe_status build_octree(tdfe_ctx* c, const tdfe_octree_desc* d) {
   }
   c->oct_cn_h.resize(cn.size());
   for (size_t i = 0; i < cn.size(); ++i) c->oct_cn_h[i] = (int)cn[i];
+  // the operator's slot codes and the hanging rows of C^T by master DoF
+  std::vector<int64_t> hidx(nn, -1);
+  c->oct_hv_h.clear();
+  for (int64_t v = 0; v < nn; ++v)
+    if (hang[v] && c->oct_eptr_h[v + 1] > c->oct_eptr_h[v]) {
+      hidx[v] = (int64_t)c->oct_hv_h.size();
+      c->oct_hv_h.push_back((int)v);
+    }
+  c->oct_cd_h.resize(cn.size());
+  for (size_t i = 0; i < cn.size(); ++i) {
+    const int64_t v = cn[i];
+    c->oct_cd_h[i] = dof_of[v] >= 0 ? (int)dof_of[v] : (hidx[v] >= 0 ? (int)(-2 - hidx[v]) : -1);
+  }
+  {
+    std::vector<int> cnt(ndof, 0);
+    for (const int v : c->oct_hv_h)
+      for (int j = c->oct_eptr_h[v]; j < c->oct_eptr_h[v + 1]; ++j) ++cnt[c->oct_ecol_h[j]];
+    std::vector<int> slot(ndof, -1);
+    c->oct_md_h.clear();
+    c->oct_mptr_h.assign(1, 0);
+    for (int64_t dd = 0; dd < ndof; ++dd)
+      if (cnt[dd] > 0) {
+        slot[dd] = (int)c->oct_md_h.size();
+        c->oct_md_h.push_back((int)dd);
+        c->oct_mptr_h.push_back(c->oct_mptr_h.back() + cnt[dd]);
+      }
+    c->oct_mh_h.assign(c->oct_mptr_h.back(), 0);
+    c->oct_mv_h.assign(c->oct_mptr_h.back(), 0.0);
+    std::vector<int> fill(c->oct_mptr_h.begin(), c->oct_mptr_h.end() - 1);
+    for (size_t h = 0; h < c->oct_hv_h.size(); ++h) {
+      const int v = c->oct_hv_h[h];
+      for (int j = c->oct_eptr_h[v]; j < c->oct_eptr_h[v + 1]; ++j) {
+        const int k = slot[c->oct_ecol_h[j]];
+        c->oct_mh_h[fill[k]] = (int)h;
+        c->oct_mv_h[fill[k]] = c->oct_eval_h[j];
+        ++fill[k];
+      }
+    }
+  }
   c->n_nodes = nn;
   c->n_dof = ndof;
   c->oct_hanging = nh;
@@ -362,19 +389,62 @@ __global__ void __launch_bounds__(EW)
   if (yf) yf[v * W + col] = 0.0;
 }
 
-// y[d][col] += M^-1/2_d sum over the row of C^T
+// the hanging nodes' values for the operator: xh[h][col] = sum_j C_vj (cs
+// M^-1/2 x)_j for v = hv[h]; yh[h][col] = 0
 __global__ void __launch_bounds__(EW)
-    oct_reduce_kernel(double* __restrict__ y, int ld, int cols, const double* __restrict__ minv,
-                      const int* __restrict__ rptr, const int* __restrict__ rcol, const double* __restrict__ rval,
-                      int64_t nd, int W, const double* __restrict__ yf, const int* done) {
+    oct_hexpand_kernel(const double* __restrict__ x, int ld, int cols, const double* colscale,
+                       const double* __restrict__ minv, const int* __restrict__ hv, const int* __restrict__ eptr,
+                       const int* __restrict__ ecol, const double* __restrict__ eval, int64_t nh, int W,
+                       double* __restrict__ xh, double* __restrict__ yh, const int* done) {
   if (done && *done) return;
   const int64_t idx = (int64_t)blockIdx.x * EW + threadIdx.x;
-  if (idx >= nd * cols) return;
-  const int64_t dd = idx / cols;
+  if (idx >= nh * cols) return;
+  const int64_t h = idx / cols;
   const int col = (int)(idx % cols);
-  double acc = 0.0;
-  for (int j = rptr[dd]; j < rptr[dd + 1]; ++j) acc += rval[j] * yf[(int64_t)rcol[j] * W + col];
-  y[dd * ld + col] += (minv ? minv[dd] : 1.0) * acc;
+  const int v = hv[h];
+  // four independent partial sums keep four rows' loads in flight
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int j0 = eptr[v], j1 = eptr[v + 1];
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+      const int dd = ecol[j + u];
+      acc[u] += eval[j + u] * (minv ? minv[dd] : 1.0) * x[(int64_t)dd * ld + col];
+    }
+  }
+  for (; j < j1; ++j) {
+    const int dd = ecol[j];
+    acc[0] += eval[j] * (minv ? minv[dd] : 1.0) * x[(int64_t)dd * ld + col];
+  }
+  double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
+  if (colscale) sum *= colscale[col >> 1];
+  xh[h * W + col] = sum;
+  yh[h * W + col] = 0.0;
+}
+
+// y[d][col] += M^-1/2_d sum_h C_hd yh[h][col] over the master DoFs of hanging nodes
+__global__ void __launch_bounds__(EW)
+    oct_hreduce_kernel(double* __restrict__ y, int ld, int cols, const double* __restrict__ minv,
+                       const int* __restrict__ mptr, const int* __restrict__ md, const int* __restrict__ mh,
+                       const double* __restrict__ mv, int64_t nmd, int W, const double* __restrict__ yh,
+                       const int* done) {
+  if (done && *done) return;
+  const int64_t idx = (int64_t)blockIdx.x * EW + threadIdx.x;
+  if (idx >= nmd * cols) return;
+  const int64_t k = idx / cols;
+  const int col = (int)(idx % cols);
+  // four independent partial sums keep four rows' loads in flight
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int j0 = mptr[k], j1 = mptr[k + 1];
+  int j = j0;
+  for (; j + 4 <= j1; j += 4) {
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc[u] += mv[j + u] * yh[(int64_t)mh[j + u] * W + col];
+  }
+  for (; j < j1; ++j) acc[0] += mv[j] * yh[(int64_t)mh[j] * W + col];
+  const int dd = md[k];
+  y[(int64_t)dd * ld + col] += (minv ? minv[dd] : 1.0) * ((acc[0] + acc[1]) + (acc[2] + acc[3]));
 }
 
 // one 1D pass: the thread's line along axis AX of src, times the folded
@@ -402,10 +472,15 @@ __device__ __forceinline__ void line_pass(const double* src, double* dst, const 
 }
 
 struct OctCellParams {
-  const double* xf;
-  double* yf;
+  const double* x;         // DoF input, [n_dof][ld] from the launch's first column
+  double* y;               // DoF output (accumulated), same layout
+  int ld;
+  const double* minv;      // M^-1/2 per DoF or null
+  const double* colscale;  // per orbital of the launch or null
+  const double* xh;        // hanging-node input [n_h][W]
+  double* yh;              // hanging-node output [n_h][W]
   int W, cols, cols_total, col0, nchunks;
-  const int* cn;      // [n_cell][n^3]
+  const int* cd;      // [n_cell][n^3] slot codes
   const double* s;    // [n_cell]
   const double* vw;   // [n_cell][nq^3] or null
   double kin;
@@ -429,16 +504,33 @@ __global__ void __launch_bounds__(N* N* CB) oct_cell_kernel(OctCellParams P) {
   const int chunk = blockIdx.x % P.nchunks;
   const int colg = chunk * CB + col;
   const bool ok = colg < P.cols;
-  const int* cnode = P.cn + cell * VOL;
+  // the cube's slot codes and per-slot M^-1/2, staged once per block
+  __shared__ int sCode[VOL];
+  __shared__ double sM[VOL];
+  for (int q = t; q < VOL; q += T) {
+    const int cq = P.cd[cell * VOL + q];
+    sCode[q] = cq;
+    sM[q] = (cq >= 0 && P.minv) ? P.minv[cq] : 1.0;
+  }
+  __syncthreads();
   auto L = [&](int x, int y, int z) { return ((z * N + y) * N + x) * CB + col; };
-  // gather: the thread's x-line (y, z) = (line % N, line / N)
+  const int cg = ok ? colg : 0;
+  // gather: the thread's x-line (y, z) = (line % N, line / N); DoFs straight
+  // from the input (x M^-1/2 x column scale), hanging nodes from their
+  // expanded values, boundary nodes 0
   {
     const int y = line % N, z = line / N;
+    const double cs = P.colscale ? P.colscale[cg >> 1] : 1.0;
     double v[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
-      const int64_t g = (int64_t)cnode[(z * N + y) * N + i] * P.W + (ok ? colg : 0);
-      v[i] = P.xf[g];
+      const int q = sCode[(z * N + y) * N + i];
+      double val = 0.0;
+      if (q >= 0)
+        val = P.x[(int64_t)q * P.ld + cg] * (sM[(z * N + y) * N + i] * cs);
+      else if (q <= -2)
+        val = P.xh[(int64_t)(-2 - q) * P.W + cg];
+      v[i] = val;
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) sQ[L(i, y, z)] = ok ? v[i] : 0.0;
@@ -504,8 +596,13 @@ __global__ void __launch_bounds__(N* N* CB) oct_cell_kernel(OctCellParams P) {
     eo<double, N, 1>(FS.Bt, in, out);
     if (ok) {
 #pragma unroll
-      for (int i = 0; i < N; ++i)
-        unsafeAtomicAdd(P.yf + (int64_t)cnode[(z * N + y) * N + i] * P.W + colg, out[i]);
+      for (int i = 0; i < N; ++i) {
+        const int q = sCode[(z * N + y) * N + i];
+        if (q >= 0)
+          unsafeAtomicAdd(P.y + (int64_t)q * P.ld + colg, out[i] * sM[(z * N + y) * N + i]);
+        else if (q <= -2)
+          unsafeAtomicAdd(P.yh + (int64_t)(-2 - q) * P.W + colg, out[i]);
+      }
     }
   }
   if (P.energy) {
@@ -619,7 +716,7 @@ constexpr int oct_cb(int N) { return N <= 5 ? 16 : (N <= 7 ? 8 : 4); }
 template <int N>
 tdfe_status launch_cells(tdfe_ctx* c, OctCellParams& P) {
   constexpr int CB = oct_cb(N);
-  static_assert(3 * N * N * N * CB * 8 + N * N * CB * 8 <= 160 * 1024, "LDS");
+  static_assert(3 * N * N * N * CB * 8 + N * N * CB * 8 + N * N * N * 12 <= 160 * 1024, "LDS");
   P.nchunks = (P.cols + CB - 1) / CB;
   hipLaunchKernelGGL((oct_cell_kernel<N, CB>), dim3((unsigned)(c->n_cell * P.nchunks)), dim3(N * N * CB), 0,
                      c->stream, P);
@@ -663,22 +760,30 @@ tdfe_status tdfe_launch_apply_octree(tdfe_ctx* c, const ApplyArgs& a) {
   const double* x = (const double*)a.x;
   double* y = (double*)a.y;
   if (a.n_blocks_out) *a.n_blocks_out = c->n_cell;
+  const int64_t nh = (int64_t)c->oct_hv_h.size(), nmd = (int64_t)c->oct_md_h.size();
+  const double* minv = a.lowdin ? (const double*)c->minv : (const double*)nullptr;
   for (int col0 = 0; col0 < a.cols; col0 += W) {
     const int cols = std::min(W, a.cols - col0);
-    hipLaunchKernelGGL(oct_expand_kernel, dim3(nblk(c->n_nodes * cols)), dim3(EW), 0, c->stream, x + col0, a.ld,
-                       cols, a.colscale ? a.colscale + col0 / 2 : (const double*)nullptr,
-                       a.lowdin ? (const double*)c->minv : (const double*)nullptr, (const int*)c->oct_eptr,
-                       (const int*)c->oct_ecol, (const double*)c->oct_eval, c->n_nodes, W, c->oct_xf, c->oct_yf,
-                       a.done_flag);
-    TDFE_HIP(c, hipGetLastError());
+    const double* cs = a.colscale ? a.colscale + col0 / 2 : (const double*)nullptr;
+    if (nh > 0) {
+      hipLaunchKernelGGL(oct_hexpand_kernel, dim3(nblk(nh * cols)), dim3(EW), 0, c->stream, x + col0, a.ld, cols, cs,
+                         minv, (const int*)c->oct_hv, (const int*)c->oct_eptr, (const int*)c->oct_ecol,
+                         (const double*)c->oct_eval, nh, W, c->oct_xf, c->oct_yf, a.done_flag);
+      TDFE_HIP(c, hipGetLastError());
+    }
     OctCellParams P{};
-    P.xf = c->oct_xf;
-    P.yf = c->oct_yf;
+    P.x = x + col0;
+    P.y = y + col0;
+    P.ld = a.ld;
+    P.minv = minv;
+    P.colscale = cs;
+    P.xh = c->oct_xf;
+    P.yh = c->oct_yf;
     P.W = W;
     P.cols = cols;
     P.cols_total = a.cols;
     P.col0 = col0;
-    P.cn = c->oct_cn;
+    P.cd = c->oct_cd;
     P.s = c->oct_s;
     P.vw = a.vw;
     P.kin = a.kin;
@@ -686,11 +791,12 @@ tdfe_status tdfe_launch_apply_octree(tdfe_ctx* c, const ApplyArgs& a) {
     P.done = a.done_flag;
     P.n_cell = c->n_cell;
     TDFE_TRY(cells_launch(c, P));
-    hipLaunchKernelGGL(oct_reduce_kernel, dim3(nblk(c->n_dof * cols)), dim3(EW), 0, c->stream, y + col0, a.ld, cols,
-                       a.lowdin ? (const double*)c->minv : (const double*)nullptr, (const int*)c->oct_rptr,
-                       (const int*)c->oct_rcol, (const double*)c->oct_rval, c->n_dof, W, (const double*)c->oct_yf,
-                       a.done_flag);
-    TDFE_HIP(c, hipGetLastError());
+    if (nmd > 0) {
+      hipLaunchKernelGGL(oct_hreduce_kernel, dim3(nblk(nmd * cols)), dim3(EW), 0, c->stream, y + col0, a.ld, cols,
+                         minv, (const int*)c->oct_mptr, (const int*)c->oct_md, (const int*)c->oct_mh,
+                         (const double*)c->oct_mv, nmd, W, (const double*)c->oct_yf, a.done_flag);
+      TDFE_HIP(c, hipGetLastError());
+    }
   }
   return TDFE_OK;
 }
@@ -743,9 +849,12 @@ tdfe_status tdfe_octree_bind(tdfe_ctx* c) {
   TDFE_TRY(up(c->oct_eptr, c->oct_eptr_h.data(), c->oct_eptr_h.size() * sizeof(int)));
   TDFE_TRY(up(c->oct_ecol, c->oct_ecol_h.data(), c->oct_ecol_h.size() * sizeof(int)));
   TDFE_TRY(up(c->oct_eval, c->oct_eval_h.data(), c->oct_eval_h.size() * sizeof(double)));
-  TDFE_TRY(up(c->oct_rptr, c->oct_rptr_h.data(), c->oct_rptr_h.size() * sizeof(int)));
-  TDFE_TRY(up(c->oct_rcol, c->oct_rcol_h.data(), c->oct_rcol_h.size() * sizeof(int)));
-  TDFE_TRY(up(c->oct_rval, c->oct_rval_h.data(), c->oct_rval_h.size() * sizeof(double)));
+  TDFE_TRY(up(c->oct_cd, c->oct_cd_h.data(), c->oct_cd_h.size() * sizeof(int)));
+  TDFE_TRY(up(c->oct_hv, c->oct_hv_h.data(), c->oct_hv_h.size() * sizeof(int)));
+  TDFE_TRY(up(c->oct_mptr, c->oct_mptr_h.data(), c->oct_mptr_h.size() * sizeof(int)));
+  TDFE_TRY(up(c->oct_md, c->oct_md_h.data(), c->oct_md_h.size() * sizeof(int)));
+  TDFE_TRY(up(c->oct_mh, c->oct_mh_h.data(), c->oct_mh_h.size() * sizeof(int)));
+  TDFE_TRY(up(c->oct_mv, c->oct_mv_h.data(), c->oct_mv_h.size() * sizeof(double)));
   // the host vectors stay: a later bind to another workspace uploads them again
   TDFE_HIP(c, hipStreamSynchronize(c->stream));
   return TDFE_OK;

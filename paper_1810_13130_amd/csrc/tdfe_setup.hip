@@ -219,16 +219,19 @@ void carve(tdfe_ctx* c, char* base) {
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
   c->jtab = k.take<double>((size_t)std::max(c->chunk_orb, 1) * TDFE_JTAB_STRIDE);
   c->counters = k.take<unsigned>(256);
-  // octree meshes: cell node lists, cube edges, C and C^T, node work arrays
+  // octree meshes: cell node lists, cube edges, C, the operator's slot codes and hanging rows, node work arrays
   if (c->octree) {
     c->oct_cn = k.take<int>(c->oct_cn_h.size());
     c->oct_s = k.take<double>(c->oct_s_h.size());
     c->oct_eptr = k.take<int>(c->oct_eptr_h.size());
     c->oct_ecol = k.take<int>(c->oct_ecol_h.size());
     c->oct_eval = k.take<double>(c->oct_eval_h.size());
-    c->oct_rptr = k.take<int>(c->oct_rptr_h.size());
-    c->oct_rcol = k.take<int>(c->oct_rcol_h.size());
-    c->oct_rval = k.take<double>(c->oct_rval_h.size());
+    c->oct_cd = k.take<int>(c->oct_cd_h.size());
+    c->oct_hv = k.take<int>(c->oct_hv_h.size());
+    c->oct_mptr = k.take<int>(c->oct_mptr_h.size());
+    c->oct_md = k.take<int>(c->oct_md_h.size());
+    c->oct_mh = k.take<int>(c->oct_mh_h.size());
+    c->oct_mv = k.take<double>(c->oct_mv_h.size());
     c->oct_xf = k.take<double>((size_t)nn * c->oct_w);
     c->oct_yf = k.take<double>((size_t)nn * c->oct_w);
   }
