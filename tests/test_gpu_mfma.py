@@ -127,3 +127,18 @@ def test_bf16_split_magnus_dipole_error_is_reported():
     G = g.cpu().numpy().conj().T @ g.cpu().numpy()
     assert np.abs(G - np.eye(3)).max() < 1e-5
     ctx.close()
+
+
+def test_mfma_operators_at_the_benchmark_workload():
+    """The launch the engine benchmark times: 16^3 box cells, p = 5, 8 orbitals
+    (493,039 DoFs), every engine against one oracle application."""
+    cfg = W.CONFIGS[2]
+    m, vq = oracle_mesh(cfg)
+    x = W.random_block(m.n_dof, cfg.n_orb, 7)
+    ref = op.apply_Hbar(m, vq, x)
+    for prec in (FP64_MFMA, FP32_MFMA, BF16_MFMA):
+        ctx = gpu_context(cfg, precision=prec)
+        err = rel(_apply(ctx, prec, x), ref)
+        print(f"[mfma-full] {NAMES[prec]} relative error {err:.3e}", flush=True)
+        assert err < TOL[prec]
+        ctx.close()
