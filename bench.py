@@ -688,6 +688,14 @@ def ae_steps(n_steps=2):
                              "k_corr_max": rep["k_corr_max"], "k_pred_sum": rep["k_pred_sum"],
                              "k_corr_sum": rep["k_corr_sum"], "err_max": rep["err_max"],
                              "hartree_its": rep["poisson_iters"], "charge": rep["charge"], "mu": list(rep["mu"])})
+    # the FP32 operator at the step's launch shape (the Krylov chunk) and at 8
+    # orbitals, against the HBM roof
+    out["operator"] = []
+    for norb in sorted({out["krylov_chunk_orbitals"], 8}):
+        t = time_apply(ctx, norb, True, 10)
+        by = apply_bytes(ctx.n_dof, ctx.n_cell, ctx.n_quad, norb, 4, True)
+        out["operator"].append({"orbitals": norb, "launch_us": t * 1e6, "algorithmic_bytes": by,
+                                "hbm_frac": by / t / 1e9 / HBM_PEAK_GBS})
     close(ctx)
     return out
 
