@@ -601,9 +601,10 @@ static tdfe_status launch_local(tdfe_ctx* c, const ApplyArgs& a) {
   // default policy, from measurements on the benchmark and graded workloads:
   // box cells: the lane-pair kernel for FP64 at even n (two waves per SIMD;
   // 130 us against 170 us for the plane kernel at 16^3 cells, p = 5, 8
-  // orbitals), the plane kernel otherwise; trilinear cells: the plane kernel
-  // for two or more columns at p <= 7, the line kernel for one column and at
-  // p = 8
+  // orbitals), the plane kernel otherwise; trilinear cells, two or more
+  // columns at p <= 7: the lane-pair kernel for FP64 and for FP32 at p = 7,
+  // the plane kernel for FP32 below p = 7; the line kernel for one column and
+  // at p = 8
   if (c->mfma && tdfe_mfma_kernel_ok(c, a)) return tdfe_launch_apply_mfma(c, a);
   if (c->variant != TDFE_VARIANT_LINE) {
     if (c->box) {

@@ -1157,8 +1157,12 @@ tdfe_status launch_curved(tdfe_ctx* c, const ApplyArgs& a) {
     P.eta[i] = c->eta[i];
     P.wq[i] = c->wq[i];
   }
-  // lane pairs for FP64 (two waves per SIMD), plane ownership otherwise
-  const bool pair = c->variant == TDFE_VARIANT_PAIR || (c->variant == 0 && sizeof(T) == 8);
+  // lane pairs for FP64 (two waves per SIMD instead of one) and for FP32 at
+  // n = 8 (162 VGPRs against the plane kernel's 256: 1.75 against 1.98 ms per
+  // 2-orbital launch of the all-electron workload); plane ownership for FP32
+  // otherwise (at n = 7 both run two waves per SIMD and the pairs' duplicated
+  // z work loses: 2.24 against 1.50 ms per 16-orbital graded launch)
+  const bool pair = c->variant == TDFE_VARIANT_PAIR || (c->variant == 0 && (sizeof(T) == 8 || N == 8));
   if (pair) {
     switch (N) {
       case 2: return launch_cpair_n<T, 2>(c, P, a.n_blocks_out);
