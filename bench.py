@@ -136,6 +136,20 @@ def cpu_worker(cfg_id):
     out["trap_steps_per_s"] = trap_steps()
     with threadpoolctl.threadpool_limits(1):
         out["trap_steps_per_s_1thread"] = trap_steps()
+
+    def apply_rate(c, n_orb, reps):
+        # oracle H-bar applications on n_orb orbitals, DoF-orbitals per second
+        mc = Mesh(c.p, c.ncell, W.vertices(c), c.nq)
+        vc = W.external_potential(c, mc.quad_xyz)
+        xc = W.random_block(mc.n_dof, n_orb, 3)
+        op.apply_Hbar(mc, vc, xc)  # first call builds the mesh's cached tables
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            op.apply_Hbar(mc, vc, xc)
+        return mc.n_dof * n_orb * reps / (time.perf_counter() - t0)
+
+    out["apply_dof_orb_per_s_cfg1"] = apply_rate(c1, 1, 20)
+    out["apply_dof_orb_per_s_cfg2"] = apply_rate(W.CONFIGS[2], 8, 1)
     cfg = W.CONFIGS[cfg_id]
     t = time.perf_counter()
     m = Mesh(cfg.p, cfg.ncell, W.vertices(cfg), cfg.nq)
@@ -206,6 +220,8 @@ def cpu_baseline(proc, cfg, counts, timeout_s=900):
         "os_cpu_count": w["os_cpu_count"], "cpu_model": w["cpu_model"],
         "value_1thread_est": 1.0 / step1,
         "apply_H_gdof_orb_per_s": w["n_dof"] / w["krylov_it_s"] / 1e9,
+        "apply_H_gdof_orb_per_s_trap": w.get("apply_dof_orb_per_s_cfg1", 0.0) / 1e9,
+        "apply_H_gdof_orb_per_s_box_8orb": w.get("apply_dof_orb_per_s_cfg2", 0.0) / 1e9,
         "trap_steps_per_s": w["trap_steps_per_s"], "trap_steps_per_s_1thread": w["trap_steps_per_s_1thread"],
         "sample": (f"oracle (numpy/scipy FP64) on this host, {w['threads']} BLAS threads: timed pieces of a "
                    f"{cfg.name} step on its full mesh -- 2 Krylov iterations of one orbital "
