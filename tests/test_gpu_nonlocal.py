@@ -169,6 +169,29 @@ def test_fp32_operator_with_projectors_matches_oracle():
     assert rel(y.cpu().numpy(), _ref_apply(m, vq, CE, x)) < 2e-6
 
 
+@pytest.mark.parametrize("prec,bar", [(4, 1e-12), (2, 2e-6), (3, 1e-4)], ids=["fp64_mfma", "fp32_mfma", "bf16x3_mfma"])
+def test_matrix_core_operators_with_projectors_match_oracle(prec, bar):
+    """The nonlocal term after the matrix-core cell operator (box cells); the
+    bars are the engines' own operator bars (tests/test_gpu_mfma.py)."""
+    cfg = CASES["box_pair"](4)
+    ctx = gpu_context(cfg, n_orb=4, k_max=8, precision=prec)
+    _gpu_projectors(ctx, cfg)
+    m, vq = oracle_mesh(cfg)
+    CE = _oracle_projectors(m, cfg)
+    x = W.random_block(m.n_dof, 4, 43)
+    if prec == 4:
+        y = ctx.apply_H(torch.from_numpy(x).cuda()).cpu().numpy()
+    else:
+        xg = torch.from_numpy(x).to(torch.complex64).cuda()
+        yg = torch.zeros_like(xg)
+        ctx.apply_H_add_f32(xg, yg)
+        y = yg.cpu().numpy()
+    ref = _ref_apply(m, vq, CE, x)
+    assert rel(y, ref) < bar
+    # the term is far above the bar: a dropped term fails
+    assert rel(op.apply_Hbar(m, vq, x), ref) > 100 * bar
+
+
 def test_mixed_magnus_with_projectors_dipole_within_1e5():
     cfg = _cfg2(3)
     ctx = gpu_context(cfg, n_orb=3, precision=1)
