@@ -26,10 +26,14 @@ __device__ __forceinline__ void atomic_add(T* p, T v) {
   unsafeAtomicAdd(p, v);
 }
 
+// logical block of physical block p in a grid of G: the dispatcher hands
+// blocks to the 8 XCDs round robin (block p to XCD p mod 8), and XCD x takes
+// the contiguous logical range starting at x q + min(x, r) (q = G / 8,
+// r = G mod 8; q + 1 blocks for x < r), so that neighbouring cells, which
+// share nodes, run under one L2
 __device__ __forceinline__ int remap_block(int p, int G) {
-  // consecutive logical blocks on the same XCD (8 XCDs, round-robin dispatch)
-  if ((G & 7) == 0) return (p & 7) * (G >> 3) + (p >> 3);
-  return p;
+  const int q = G >> 3, r = G & 7, x = p & 7;
+  return x * q + min(x, r) + (p >> 3);
 }
 
 template <int N, int CB, int CPB, int GEOM>

@@ -75,9 +75,14 @@ __device__ __forceinline__ void flush_energy(double& e, T line) {
   if constexpr (sizeof(T) == 4) e += (double)line;
 }
 
+// logical block of physical block p in a grid of G: the dispatcher hands
+// blocks to the 8 XCDs round robin (block p to XCD p mod 8), and XCD x takes
+// the contiguous logical range starting at x q + min(x, r) (q = G / 8,
+// r = G mod 8; q + 1 blocks for x < r), so that neighbouring cells, which
+// share nodes, run under one L2
 __device__ __forceinline__ int remap_block(int p, int G) {
-  if ((G & 7) == 0) return (p & 7) * (G >> 3) + (p >> 3);
-  return p;
+  const int q = G >> 3, r = G & 7, x = p & 7;
+  return x * q + min(x, r) + (p >> 3);
 }
 
 // out[a] = sum_i A[a][i] in[i] by even/odd folding; A given folded (in any
