@@ -752,6 +752,22 @@ def matrix_core_engines(steps=100, warmup=5, reps=100):
     return out
 
 
+def curved_kernel_name(p, cols, fp32):
+    """Name of the trilinear-cell operator kernel a launch of `cols` real
+    columns runs (the library's default choice: lane pairs for FP64 and for
+    FP32 at p = 7, plane ownership for FP32 below; columns per block the next
+    power of two up to 16, at least 2 for lane pairs, or 32 for FP32 plane
+    launches of more than 16)."""
+    n = p + 1
+    pw = 1
+    while pw < cols:
+        pw *= 2
+    if not fp32 or n == 8:
+        t = "float" if fp32 else "double"
+        return f"cpair_kernel<{t},{n},{max(2, min(pw, 16))},CPB> (trilinear cells, lane pairs)"
+    return f"cplane_kernel<float,{n},{32 if cols > 16 else pw},CPB> (trilinear cells)"
+
+
 def workload_legs(cfg, steps, warmup, apply_reps, curved, matched=True, jacobi_count=False):
     """FP64, mixed and (optionally) FP64 at the mixed path's effective stop
     tolerance on one workload; operator launches in the step's shape."""
@@ -763,7 +779,7 @@ def workload_legs(cfg, steps, warmup, apply_reps, curved, matched=True, jacobi_c
     r64 = run_steps(ctx, psi, cfg, cfg.tol, steps, warmup)
     t_chunk = time_apply(ctx, chunk64, False, apply_reps)
     t_full = time_apply(ctx, cfg.n_orb, False, max(3, apply_reps // 4))
-    kname = "cplane_kernel<double,7,16,CPB> (trilinear cells)" if curved else "pair_kernel<double,6,16,1> (box cells)"
+    kname = curved_kernel_name(cfg.p, 2 * chunk64, False) if curved else "pair_kernel<double,6,16,1> (box cells)"
     res["f64"] = {**{k: v for k, v in r64.items() if k != "mu"}, "chunk_orbitals": chunk64,
                   "roofline": roofline(ctx, cfg, chunk64, t_chunk, False, kname, curved),
                   "apply_H_gdof_orb_per_s": ctx.n_dof * cfg.n_orb / t_full / 1e9, "apply_full_ms": t_full * 1e3}
@@ -783,7 +799,7 @@ def workload_legs(cfg, steps, warmup, apply_reps, curved, matched=True, jacobi_c
     r32 = run_steps(ctx, psi, cfg, cfg.tol, steps, warmup)
     t_chunk32 = time_apply(ctx, chunk32, True, apply_reps)
     t_full32 = time_apply(ctx, cfg.n_orb, True, max(3, apply_reps // 4))
-    kname32 = kname.replace("double", "float")
+    kname32 = curved_kernel_name(cfg.p, 2 * chunk32, True) if curved else None
     e, e_ind, n = dipole_errors(r32["mu"], r64["mu"])
     res["mixed"] = {**{k: v for k, v in r32.items() if k != "mu"}, "chunk_orbitals": chunk32,
                     "dipole_rel_err": e, "dipole_err_rel_induced": e_ind, "steps_compared": n,
