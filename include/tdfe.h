@@ -105,6 +105,23 @@ tdfe_status tdfe_query(const tdfe_ctx* ctx, int64_t* n_dof, int64_t* n_cell, int
  * vectors fit the memory limit stated at tdfe_fe_mesh_setup.  Host only. */
 tdfe_status tdfe_krylov_chunk(const tdfe_ctx* ctx, int n_orb, int* chunk);
 
+/* krylov_soft_chunk: the chunk and Krylov dimension limit that the next
+ * exponential of lanczos_expm, magnus_step or propagate on n_orb orbitals
+ * will use (the per-orbital adaptive dimension of Eq. AdaptiveLanczos does
+ * not change).  Once an exponential has run, chunks may be wider than
+ * krylov_chunk: w orbitals then share the basis memory of krylov_chunk
+ * orbitals, which holds (k_max + 1) krylov_chunk / w - 1 vectors past the
+ * first (*kcap); w is chosen so that *kcap is at least twice the largest
+ * Krylov dimension of the last exponential and at least 32.  An orbital
+ * that reaches *kcap unconverged sends its chunk back to k_max in chunks of
+ * krylov_chunk before the chunk writes its output: the result is the same,
+ * the exponential takes longer (and a soft-capped chunk waits for the device
+ * once, before its combination).  *chunk = krylov_chunk and *kcap = k_max
+ * when no wider chunk applies (no exponential yet, every orbital in one
+ * chunk, or the field gradient's runs).  Host only; EINVAL for a null pointer
+ * or n_orb outside 1..n_orb_max. */
+tdfe_status tdfe_krylov_soft_chunk(const tdfe_ctx* ctx, int n_orb, int* chunk, int* kcap);
+
 /* binds a caller-owned device buffer of >= workspace_bytes (256-byte aligned)
  * and computes the device-side geometry and the diagonal overlap
  * M_jj = sum_e w_i w_j w_k det J_e(node) (GLL quadrature, Sec. spectral FE). */

@@ -13,6 +13,9 @@
 
 // one Krylov chunk holds at most this many real columns (2 per orbital)
 #define TDFE_MAX_COLS 64
+// a soft-capped chunk runs only with a cap of at least this many vectors and
+// at least twice the largest Krylov dimension seen
+#define TDFE_SOFT_CAP_MIN 32
 
 struct tdfe_ctx {
   // ---- configuration -------------------------------------------------------
@@ -49,6 +52,11 @@ struct tdfe_ctx {
   char* ws = nullptr;
   size_t ws_bytes = 0, ws_need = 0;
   int chunk_orb = 0;  // orbitals per Krylov chunk
+  // widest chunk the workspace holds with a soft cap on the Krylov dimension:
+  // w orbitals fit (k_max + 1) chunk_orb / w - 1 basis vectors in the same
+  // memory (operator output, partials and Bessel tables sized for w)
+  int wide_orb = 0;
+  int k_seen = 0;  // largest Krylov dimension of the last exponentials (0: none yet)
 
   // device pointers into the workspace
   double* tab = nullptr;      // device copy of the 1D tables (see tab_* offsets)
@@ -85,13 +93,13 @@ struct tdfe_ctx {
   double* pcg = nullptr;      // 5 x [n_nodes] (r, z, p, Ap, x) for curved meshes
   double* dinvK = nullptr;    // [n_nodes] inverse stiffness diagonal (interior), 0 on boundary
   double* pcgs = nullptr;     // [16] CG scalars (rz, rr, bb, alpha, beta, pAp)
-  void* krylov = nullptr;     // (k_max+1) x [n_dof][cols]
-  void* hq = nullptr;         // [n_dof][cols] apply output
+  void* krylov = nullptr;     // (k_max+1) x [n_dof][2 chunk_orb]
+  void* hq = nullptr;         // [n_dof][2 max(chunk_orb, wide_orb)] apply output
   void* half = nullptr;       // [n_dof][2 n_orb_max] predictor state (complex128)
   double* partial = nullptr;  // reduction partials
   double* partial2 = nullptr; // [128][TDFE_MAX_COLS] first level of the two-level alpha reduction
   double* scal = nullptr;     // per-orbital Lanczos scalars
-  double* jtab = nullptr;     // [chunk_orb][TDFE_JTAB_STRIDE] Bessel tables of the small exponential
+  double* jtab = nullptr;     // [max(chunk_orb, wide_orb)][TDFE_JTAB_STRIDE] Bessel tables of the small exponential
   unsigned* counters = nullptr;
   int64_t n_partial = 0;
 
@@ -223,6 +231,13 @@ void tdfe_mfma_tables(int p, double* out);  // host: [6][16][16]
 // FP32 Krylov storage and operator (mixed precision and its matrix-core variants)
 inline bool tdfe_fp32(const tdfe_ctx* c) {
   return c->precision == TDFE_MIXED_FP32 || c->precision == TDFE_FP32_MFMA || c->precision == TDFE_BF16_MFMA;
+}
+// Krylov dimension that a chunk of w orbitals can reach in the basis memory
+// of chunk_orb orbitals at k_max: (k_max + 1) chunk_orb / w - 1 vectors past
+// the first, at most k_max
+inline int tdfe_soft_cap(const tdfe_ctx* c, int w) {
+  const long long v = (long long)(c->k_max + 1) * c->chunk_orb / (w > 0 ? w : 1) - 1;
+  return (int)(v < c->k_max ? v : c->k_max);
 }
 // nonlocal term after the local kernel (tdfe_nonlocal.hip): Loewdin launches
 // on the DoF numbering only; appends one row to the energy partials

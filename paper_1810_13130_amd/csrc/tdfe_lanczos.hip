@@ -329,7 +329,8 @@ __global__ void __launch_bounds__(RED_THREADS)
 // ---------------------------------------------------------------------------------------------
 // stop decision of orbital o after the small exponential (one wavefront, or
 // the whole block for the LDS path): error estimate, y at convergence, status
-__device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int M,
+__device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, int kcap, double tau, double tol, double tol_rel,
+                          int M,
                           double amax,
                           double bk, double ylr, double yli, double yr, double yi, const double* Lyr,
                           const double* Lyi, int nthreads, int* err_flag, int* host_flag, int gen,
@@ -355,7 +356,8 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
     // a NaN or Inf in beta_k or in the small exponential ends the orbital at
     // once (status 4, reported as TDFE_ENONFINITE) instead of running to k_max
     const bool nonfinite = !isfinite(eps);
-    const bool stop = conv || nonfinite || k >= k_max;
+    // kcap: the chunk's Krylov dimension limit (k_max, or a soft cap)
+    const bool stop = conv || nonfinite || k >= kcap;
     if (stop && !y_in_place) {
       if (Lyr == nullptr) {
         if (t < k) {
@@ -395,7 +397,7 @@ __device__ void stop_test(Scal S, int o, int Nc, int k, int k_max, double tau, d
 }
 
 __global__ void __launch_bounds__(CHK_THREADS)
-    check_kernel(Scal S, int Nc, int k, int k_max, double tau, double tol, double tol_rel, int* err_flag,
+    check_kernel(Scal S, int Nc, int k, int k_max, int kcap, double tau, double tol, double tol_rel, int* err_flag,
                  int* host_flag, int gen, double* jtab) {
   __shared__ ChebLds L;
   __shared__ double sa[TDFE_KCAP], sb[TDFE_KCAP];
@@ -412,12 +414,12 @@ __global__ void __launch_bounds__(CHK_THREADS)
     double yr = 0.0, yi = 0.0;
     const int M = cheb_expm_e1_wave(k, sa, sb, tau, jtab + (size_t)o * TDFE_JTAB_STRIDE, &L.M, &L.inv, yr, yi, &amax);
     const double ylr = __shfl(yr, k - 1), yli = __shfl(yi, k - 1);
-    stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], ylr, yli, yr, yi, nullptr, nullptr,
+    stop_test(S, o, Nc, k, k_max, kcap, tau, tol, tol_rel, M, amax, sb[k - 1], ylr, yli, yr, yi, nullptr, nullptr,
               CHK_THREADS, err_flag, host_flag, gen);
   } else {
     const int M = cheb_expm_e1(k, sa, sb, tau, L, jtab + (size_t)o * TDFE_JTAB_STRIDE, &amax);
-    stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, sb[k - 1], L.yr[k - 1], L.yi[k - 1], 0.0, 0.0, L.yr,
-              L.yi, CHK_THREADS, err_flag, host_flag, gen);
+    stop_test(S, o, Nc, k, k_max, kcap, tau, tol, tol_rel, M, amax, sb[k - 1], L.yr[k - 1], L.yi[k - 1], 0.0, 0.0,
+              L.yr, L.yi, CHK_THREADS, err_flag, host_flag, gen);
   }
 }
 
@@ -427,7 +429,7 @@ __global__ void __launch_bounds__(CHK_THREADS)
 // slot and ext
 __global__ void __launch_bounds__(RED_THREADS)
     beta_check_kernel(const double* __restrict__ partial, int64_t nblocks, int C, Scal S, int Nc, int k, int k_max,
-                      double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen) {
+                      int kcap, double tau, double tol, double tol_rel, int* err_flag, int* host_flag, int gen) {
   __shared__ double sred[RED_THREADS];
   if (*S.done) return;
   const int o = blockIdx.x;
@@ -451,8 +453,8 @@ __global__ void __launch_bounds__(RED_THREADS)
   const int M = (int)S.ext[2 * o + 1];
   const double ylr = S.y[((size_t)o * k_max + k - 1) * 2 + 0];
   const double yli = S.y[((size_t)o * k_max + k - 1) * 2 + 1];
-  stop_test(S, o, Nc, k, k_max, tau, tol, tol_rel, M, amax, bk, ylr, yli, 0.0, 0.0, nullptr, nullptr, 1, err_flag,
-            host_flag, gen, true);
+  stop_test(S, o, Nc, k, k_max, kcap, tau, tol, tol_rel, M, amax, bk, ylr, yli, 0.0, 0.0, nullptr, nullptr, 1,
+            err_flag, host_flag, gen, true);
 }
 
 // z = ||psi|| sum_j y_j s_j w_j, written into the complex128 output chunk.
@@ -562,10 +564,14 @@ __global__ void stash_results_kernel(const int* kconv, const int* status, const 
   if (threadIdx.x == 0 && *err_flag) slot[3 * n_max] = 1.0;
 }
 
+// One chunk of Nc orbitals.  Kc < k_max runs a soft-capped chunk (wider than
+// the basis memory holds at k_max): if an orbital reaches Kc unconverged, the
+// chunk ends before its combination (the input is untouched) with *restart
+// set, and the caller runs those orbitals again at k_max.
 template <typename T>
 tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out, int ld, int o0, int Nc,
                       double tau, double tol, int* k_out, double* err_out, int* status_out, LanczosHook* hook,
-                      double* defer_slot) {
+                      double* defer_slot, int Kc, bool* restart) {
   const int C = 2 * Nc;
   const int64_t nd = c->n_dof;
   const int64_t vstride = nd * C;
@@ -573,6 +579,12 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   T* Hq = (T*)c->hq;
   Scal S = carve_scal(c, Nc);
   const int K = c->k_max;
+  *restart = false;
+  // the basis holds (k_max + 1) vectors of 2 chunk_orb columns; the operator
+  // output and the Bessel tables max(chunk_orb, wide_orb) orbitals
+  if (Kc < 1 || Kc > K || (int64_t)(Kc + 1) * C > (int64_t)(K + 1) * 2 * c->chunk_orb ||
+      Nc > std::max(c->chunk_orb, c->wide_orb) || (Kc < K && hook))
+    return tdfe_fail(c, TDFE_EINVAL, "Lanczos chunk of %d orbitals with cap %d does not fit the workspace", Nc, Kc);
   int* err_flag = (int*)c->counters + 140;
   // FP32 basis vectors carry rounding of 2^-24 relative: a Krylov error
   // estimate below a small multiple of that (times ||psibar||) buys nothing
@@ -604,7 +616,7 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
 
   const int LOOK = 2;
   int k_enq = 0;
-  for (int k = 1; k <= K; ++k) {
+  for (int k = 1; k <= Kc; ++k) {
     k_enq = k;
     T* wk = W + (int64_t)(k - 1) * vstride;
     ApplyArgs a{};
@@ -648,12 +660,12 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
     // beta_k, the scale 1/beta_k of the next basis vector and the stop test
     if (k <= CHK_THREADS) {
       hipLaunchKernelGGL(beta_check_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, (const double*)c->partial,
-                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, tau, tol, tol_rel, err_flag, dflag, gen);
+                         (int64_t)RED_BLOCKS, C, S, Nc, k, K, Kc, tau, tol, tol_rel, err_flag, dflag, gen);
     } else {
       hipLaunchKernelGGL(finalize_pairs_kernel, dim3(Nc), dim3(RED_THREADS), 0, c->stream, c->partial,
                          (int64_t)RED_BLOCKS, C, S.beta + (size_t)(k - 1) * Nc, 3, S.scale + (size_t)k * Nc,
                          S.cs + (size_t)k * Nc, (const double*)nullptr, (const int*)S.done);
-      hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, tau, tol, tol_rel,
+      hipLaunchKernelGGL(check_kernel, dim3(Nc), dim3(CHK_THREADS), 0, c->stream, S, Nc, k, K, Kc, tau, tol, tol_rel,
                          err_flag, dflag, gen, c->jtab);
     }
     TDFE_HIP(c, hipGetLastError());
@@ -686,6 +698,15 @@ tdfe_status run_chunk(tdfe_ctx* c, const void* vw, const double* in, double* out
   }
   if (hook)
     TDFE_TRY(hook->after_loop(c, W, vstride, Nc, o0, S.scale, S.kconv, S.alpha, S.beta, S.nrm, k_enq, sizeof(T) == 4));
+  if (Kc < K) {
+    // soft cap: the states decide between the combination and a restart
+    const void* hs = nullptr;
+    TDFE_TRY(tdfe_readback(c, S.status, Nc * sizeof(int), 256, &hs));
+    TDFE_HIP(c, hipStreamSynchronize(c->stream));
+    for (int o = 0; o < Nc; ++o)
+      if (((const volatile int*)hs)[o] == 2) *restart = true;
+    if (*restart) return TDFE_OK;
+  }
   // combination
   {
     const int64_t n = nd * Nc;
@@ -779,8 +800,7 @@ tdfe_status tdfe_readback(tdfe_ctx* c, const void* dev_src, size_t bytes, size_t
 // (a launch on `cols` real columns costs about the next power of two up to 16,
 // then whole blocks of 16), with a small charge per chunk so that ties go to
 // fewer chunks.  32 orbitals with room for 9 run as 4 x 8, not 9 + 9 + 9 + 5.
-static int chunk_size(const tdfe_ctx* c, int n_orb) {
-  const int cap = c->chunk_orb;
+static int chunk_size_upto(int n_orb, int cap) {
   if (n_orb <= cap) return n_orb;
   auto padded = [](int cols) {
     if (cols > 16) return (cols + 15) / 16 * 16;
@@ -800,6 +820,25 @@ static int chunk_size(const tdfe_ctx* c, int n_orb) {
     }
   }
   return best;
+}
+
+static int chunk_size(const tdfe_ctx* c, int n_orb) { return chunk_size_upto(n_orb, c->chunk_orb); }
+
+// chunk and Krylov cap of the next exponential on n_orb orbitals: chunks wider
+// than the basis memory holds at k_max once an earlier exponential has shown
+// a Krylov dimension k_seen with a cap of at least 2 k_seen (and
+// TDFE_SOFT_CAP_MIN); otherwise the chunk at k_max
+static void soft_chunk(const tdfe_ctx* c, int n_orb, bool hooked, int* chunk, int* kcap) {
+  *chunk = chunk_size(c, n_orb);
+  *kcap = c->k_max;
+  if (hooked || c->k_seen <= 0 || n_orb <= c->chunk_orb || c->wide_orb <= c->chunk_orb) return;
+  const int need = std::max(2 * c->k_seen, TDFE_SOFT_CAP_MIN);
+  int wmax = c->chunk_orb;
+  for (int w = c->chunk_orb + 1; w <= std::min(n_orb, c->wide_orb); ++w)
+    if (tdfe_soft_cap(c, w) >= need) wmax = w;
+  if (wmax <= c->chunk_orb) return;
+  *chunk = chunk_size_upto(n_orb, wmax);
+  if (*chunk > c->chunk_orb) *kcap = tdfe_soft_cap(c, *chunk);
 }
 
 // y = exp(-i tau T) e_1 for one tridiagonal T given on the device (the small
@@ -872,6 +911,12 @@ extern "C" tdfe_status tdfe_krylov_chunk(const tdfe_ctx* c, int n_orb, int* chun
   return TDFE_OK;
 }
 
+extern "C" tdfe_status tdfe_krylov_soft_chunk(const tdfe_ctx* c, int n_orb, int* chunk, int* kcap) {
+  if (!c || !chunk || !kcap || n_orb < 1 || n_orb > c->n_orb_max) return TDFE_EINVAL;
+  soft_chunk(c, n_orb, false, chunk, kcap);
+  return TDFE_OK;
+}
+
 // deferred-result slot `slot` (0 or 1) in the scalar block, past the Lanczos
 // scalars of a full chunk and before the occupations
 static double* result_slot(tdfe_ctx* c, int slot) {
@@ -905,6 +950,7 @@ tdfe_status tdfe_lanczos_results(tdfe_ctx* c, const void* host, int n_orb, doubl
   if (kmax_out) *kmax_out = kmax;
   if (ksum_out) *ksum_out = ksum;
   if (errmax_out) *errmax_out = emax;
+  if (!bad && !nonfinite) c->k_seen = kmax;
   if (nonfinite) return tdfe_fail(c, TDFE_ENONFINITE, "Lanczos: non-finite norm or recurrence coefficient");
   if (h[3 * nm] != 0.0) return tdfe_fail(c, TDFE_EINVAL, "small exponential: |tau| ||T|| too large for the Chebyshev table");
   if (bad) return tdfe_fail(c, TDFE_ENOCONV, "Lanczos reached k_max=%d without eps <= %g", c->k_max, tol);
@@ -927,18 +973,30 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
   const void* v = !tdfe_fp32(c) ? (const void*)vw : (const void*)c->vw32;
   // when the input is also the output, every chunk must read the input before
   // any chunk writes: the combination of a chunk only writes that chunk's
-  // columns, and copy_in of a chunk only reads them, so chunk order is safe.
-  const int csz = chunk_size(c, n_orb);
+  // columns, and copy_in of a chunk only reads them, so chunk order is safe
+  // (a soft-capped chunk that restarts has not written its columns either).
+  auto run = [&](int o0, int Nc, int kc, bool* restart) {
+    if (!tdfe_fp32(c))
+      return run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
+                               es.data() + o0, st.data() + o0, hook, slot, kc, restart);
+    return run_chunk<float>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
+                            es.data() + o0, st.data() + o0, hook, slot, kc, restart);
+  };
+  int csz = 0, kcap = 0;
+  soft_chunk(c, n_orb, hook != nullptr, &csz, &kcap);
   for (int o0 = 0; o0 < n_orb; o0 += csz) {
     const int Nc = std::min(csz, n_orb - o0);
-    tdfe_status s;
-    if (!tdfe_fp32(c))
-      s = run_chunk<double>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
-                            es.data() + o0, st.data() + o0, hook, slot);
-    else
-      s = run_chunk<float>(c, v, (const double*)in, (double*)out, ld, o0, Nc, tau, tol, ks.data() + o0,
-                           es.data() + o0, st.data() + o0, hook, slot);
-    if (s != TDFE_OK) return s;
+    bool restart = false;
+    TDFE_TRY(run(o0, Nc, Nc > c->chunk_orb ? kcap : c->k_max, &restart));
+    if (!restart) continue;
+    // an orbital needs more than the soft cap: these orbitals again at k_max
+    // in chunks the basis holds, and no more soft caps below that dimension
+    c->k_seen = std::max(c->k_seen, kcap + 1);
+    const int sub = chunk_size(c, Nc);
+    for (int q0 = o0; q0 < o0 + Nc; q0 += sub) {
+      bool again = false;
+      TDFE_TRY(run(q0, std::min(sub, o0 + Nc - q0), c->k_max, &again));
+    }
   }
   if (slot) return TDFE_OK;
   int kmax = 0, ksum = 0, bad = 0, nonfinite = 0;
@@ -955,6 +1013,7 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
   if (kmax_out) *kmax_out = kmax;
   if (ksum_out) *ksum_out = ksum;
   if (errmax_out) *errmax_out = emax;
+  if (!bad && !nonfinite) c->k_seen = kmax;
   if (nonfinite) return tdfe_fail(c, TDFE_ENONFINITE, "Lanczos: non-finite norm or recurrence coefficient");
   if (bad) return tdfe_fail(c, TDFE_ENOCONV, "Lanczos reached k_max=%d without eps <= %g", c->k_max, tol);
   return TDFE_OK;

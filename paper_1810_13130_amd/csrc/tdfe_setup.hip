@@ -7,6 +7,7 @@
 // come from the constexpr rule of tdfe_rule1d.h (Newton iteration on the
 // Legendre three-term recurrence, barycentric Lagrange formulas), evaluated
 // here at run time; the per-point geometry and M are computed on the device.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdlib>
@@ -208,8 +209,8 @@ void carve(tdfe_ctx* c, char* base) {
   c->pcg = (c->box || c->octree) ? k.take<double>(1) : k.take<double>(5 * nn);
   c->dinvK = (c->box || c->octree) ? k.take<double>(1) : k.take<double>(nn);
   c->pcgs = k.take<double>(16);
-  const int cols = 2 * c->chunk_orb;
-  c->krylov = k.take<char>((size_t)(c->k_max + 1) * nd * cols * elem_bytes(c));
+  const int cols = 2 * std::max(c->chunk_orb, c->wide_orb);  // widest chunk's columns
+  c->krylov = k.take<char>((size_t)(c->k_max + 1) * nd * 2 * c->chunk_orb * elem_bytes(c));
   c->hq = k.take<char>((size_t)nd * cols * elem_bytes(c));
   c->half = k.take<double>((size_t)nd * 2 * c->n_orb_max);
   // block partials of the operator kernels, plus rows appended after them (the nonlocal term's)
@@ -217,7 +218,7 @@ void carve(tdfe_ctx* c, char* base) {
   c->partial = k.take<double>(c->n_partial);
   c->partial2 = k.take<double>(128 * TDFE_MAX_COLS);
   c->scal = k.take<double>((size_t)(8 * c->k_max + 32) * c->n_orb_max);
-  c->jtab = k.take<double>((size_t)std::max(c->chunk_orb, 1) * TDFE_JTAB_STRIDE);
+  c->jtab = k.take<double>((size_t)std::max({c->chunk_orb, c->wide_orb, 1}) * TDFE_JTAB_STRIDE);
   c->counters = k.take<unsigned>(256);
   // octree meshes: cell node lists, cube edges, C, the operator's slot codes and hanging rows, node work arrays
   if (c->octree) {
@@ -280,13 +281,23 @@ void init_chunk(tdfe_ctx* c) {
   }
   int chunk = (int)std::min<double>(c->n_orb_max, std::floor(basis_bytes / per_orb));
   if (chunk > TDFE_MAX_COLS / 2) chunk = TDFE_MAX_COLS / 2;
-  {
-    // optional cap (tests use it to run several chunks on small meshes)
-    const char* v = std::getenv("TDFE_MAX_CHUNK_ORB");
-    if (v && std::atoi(v) > 0) chunk = std::min(chunk, std::atoi(v));
-  }
+  // optional caps: TDFE_MAX_CHUNK_ORB on every chunk (tests use it to run
+  // several chunks on small meshes), TDFE_BASIS_CHUNK_ORB on the basis memory
+  // only, as on a device with less memory (soft-capped chunks stay possible)
+  const char* vmax = std::getenv("TDFE_MAX_CHUNK_ORB");
+  const int cap_all = vmax && std::atoi(vmax) > 0 ? std::atoi(vmax) : 0;
+  const char* vbas = std::getenv("TDFE_BASIS_CHUNK_ORB");
+  if (vbas && std::atoi(vbas) > 0) chunk = std::min(chunk, std::atoi(vbas));
+  if (cap_all) chunk = std::min(chunk, cap_all);
   if (chunk < 1) chunk = 1;
   c->chunk_orb = chunk;
+  // soft-capped chunks: every width whose cap keeps TDFE_SOFT_CAP_MIN vectors
+  int wide = chunk;
+  const int wlim = std::min(c->n_orb_max, TDFE_MAX_COLS / 2);
+  for (int w = chunk + 1; w <= wlim; ++w)
+    if (tdfe_soft_cap(c, w) >= TDFE_SOFT_CAP_MIN) wide = w;
+  if (cap_all) wide = std::min(wide, cap_all);
+  c->wide_orb = std::max(wide, chunk);
 }
 
 }  // namespace

@@ -118,6 +118,7 @@ SIGNATURES = {
     "tdfe_lanczos_expm": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, _IP, _DP],
     "tdfe_density": [_P, _P, ctypes.c_int, _P],
     "tdfe_krylov_chunk": [_P, ctypes.c_int, _IP],
+    "tdfe_krylov_soft_chunk": [_P, ctypes.c_int, _IP, _IP],
     "tdfe_scf_fields": [_P, _P, ctypes.c_int, _P, _P],
     "tdfe_dipole": [_P, _P, ctypes.c_int, _DP, _DP],
     "tdfe_magnus_step": [_P, _P, ctypes.c_int, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -389,6 +390,13 @@ class Context:
         k = ctypes.c_int()
         self._check(self.lib.tdfe_krylov_chunk(self.h, n_orb, ctypes.byref(k)))
         return k.value
+
+    def krylov_soft_chunk(self, n_orb):
+        """(chunk, Krylov dimension limit) of the next exponential on n_orb
+        orbitals: wider chunks under a soft cap once an exponential has run"""
+        k, cap = ctypes.c_int(), ctypes.c_int()
+        self._check(self.lib.tdfe_krylov_soft_chunk(self.h, n_orb, ctypes.byref(k), ctypes.byref(cap)))
+        return k.value, cap.value
 
     def scf_fields(self, psibar, phi=True, w=True):
         """(phi over every grid node or None, W = V_H + V_xc at the Gauss points

@@ -145,6 +145,38 @@ def test_query_sizes_and_call_order(lib):
     lib.tdfe_destroy(h)
 
 
+def test_soft_chunk_query_before_any_exponential(lib, monkeypatch):
+    """With the basis memory capped at two orbitals, eight orbitals run in
+    chunks of two at k_max until an exponential has shown its Krylov
+    dimension; the workspace holds the widest soft-capped chunk's operator
+    output (seven orbitals: (128 + 1) 2 / 7 - 1 = 35 >= 32 vectors)."""
+    from paper_1810_13130_amd import tdfe
+    sizes = {}
+    for env in ("TDFE_BASIS_CHUNK_ORB", "TDFE_MAX_CHUNK_ORB"):
+        monkeypatch.delenv("TDFE_BASIS_CHUNK_ORB", raising=False)
+        monkeypatch.delenv("TDFE_MAX_CHUNK_ORB", raising=False)
+        monkeypatch.setenv(env, "2")
+        d, keep = _desc(tdfe, p=2, nc=(2, 2, 2), k_max=128, n_orb=8)
+        s, h = _setup(lib, d)
+        assert s == tdfe.OK
+        ch, cap = ctypes.c_int(), ctypes.c_int()
+        assert lib.tdfe_krylov_chunk(h, 8, ctypes.byref(ch)) == 0 and ch.value == 2
+        assert lib.tdfe_krylov_soft_chunk(h, 8, ctypes.byref(ch), ctypes.byref(cap)) == 0
+        assert (ch.value, cap.value) == (2, 128)
+        assert lib.tdfe_krylov_soft_chunk(h, 0, ctypes.byref(ch), ctypes.byref(cap)) == tdfe.EINVAL
+        assert lib.tdfe_krylov_soft_chunk(h, 9, ctypes.byref(ch), ctypes.byref(cap)) == tdfe.EINVAL
+        assert lib.tdfe_krylov_soft_chunk(h, 8, None, ctypes.byref(cap)) == tdfe.EINVAL
+        assert lib.tdfe_krylov_soft_chunk(h, 8, ctypes.byref(ch), None) == tdfe.EINVAL
+        nd, nc, nq, ws = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t()
+        assert lib.tdfe_query(h, ctypes.byref(nd), ctypes.byref(nc), ctypes.byref(nq), ctypes.byref(ws)) == 0
+        sizes[env] = (ws.value, nd.value)
+        lib.tdfe_destroy(h)
+    assert lib.tdfe_krylov_soft_chunk(None, 8, ctypes.byref(ch), ctypes.byref(cap)) == tdfe.EINVAL
+    # the operator output for 7 orbitals instead of 2: at least 10 more columns per DoF
+    (wb, nd), (wm, _) = sizes["TDFE_BASIS_CHUNK_ORB"], sizes["TDFE_MAX_CHUNK_ORB"]
+    assert wb - wm >= 10 * nd * 8
+
+
 def test_null_arguments(lib):
     from paper_1810_13130_amd import tdfe
     assert lib.tdfe_fe_mesh_setup(None, None, None) == tdfe.EINVAL

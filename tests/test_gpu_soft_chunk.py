@@ -1,0 +1,97 @@
+"""Soft-capped Krylov chunks (wider chunks in the basis memory of narrower
+ones, Eq. AdaptiveLanczos's per-orbital dimension unchanged) against the
+oracle and against runs in plain chunks.
+
+The basis memory is capped at one orbital (TDFE_BASIS_CHUNK_ORB=1, as on a
+device that holds one orbital's basis at k_max = 100); four orbitals then
+run in chunks of two with a cap of (100 + 1) / 2 - 1 = 49 vectors once an
+exponential has shown its Krylov dimension.  On this mesh (4^3 box cells,
+p = 4) the oracle needs k = 9 at tau = 0.05 and k = 56 at tau = 6: the
+second exceeds the cap, so the chunk restarts at k_max.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from gpu_util import gpu_context, oracle_mesh, rel
+from oracle import lanczos, operators as op
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+K_MAX = 100
+
+
+def _cfg():
+    return W.scaled(W.CONFIGS[2], ncell=(4, 4, 4), p=4, n_orb=4)
+
+
+def _block(m, seed=9):
+    x = W.random_block(m.n_dof, 4, seed)
+    return x / np.linalg.norm(x, axis=0)
+
+
+def test_soft_chunk_widens_after_first_exponential_and_restarts_past_cap(monkeypatch):
+    monkeypatch.setenv("TDFE_BASIS_CHUNK_ORB", "1")
+    cfg = _cfg()
+    ctx = gpu_context(cfg, n_orb=4, k_max=K_MAX)
+    m, vq = oracle_mesh(cfg)
+    x = _block(m)
+    ref = lambda tau: lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), x, tau, 1e-12)
+    assert ctx.krylov_chunk(4) == 1
+    assert ctx.krylov_soft_chunk(4) == (1, K_MAX)  # no exponential yet
+    # 1: plain one-orbital chunks
+    g = torch.from_numpy(x).cuda()
+    ks, _ = ctx.lanczos_expm(g, 0.05, 1e-12)
+    z, kref, _ = ref(0.05)
+    assert rel(g.cpu().numpy(), z) < 1e-10 and max(ks) == max(kref) == 9
+    # 2: two-orbital chunks capped at 49 (at least 32 and twice k = 9)
+    assert ctx.krylov_soft_chunk(4) == (2, 49)
+    g = torch.from_numpy(x).cuda()
+    ks, errs = ctx.lanczos_expm(g, 0.05, 1e-12)
+    assert rel(g.cpu().numpy(), z) < 1e-10
+    assert all(abs(a - b) <= 1 for a, b in zip(ks, kref)) and max(errs) <= 1e-12
+    # 3: k = 56 exceeds the cap: every chunk restarts at k_max, same result
+    g = torch.from_numpy(x).cuda()
+    ks, errs = ctx.lanczos_expm(g, 6.0, 1e-12)
+    z6, kref6, _ = ref(6.0)
+    assert rel(g.cpu().numpy(), z6) < 1e-10
+    assert all(abs(a - b) <= 1 for a, b in zip(ks, kref6)) and max(errs) <= 1e-12
+    assert min(ks) > 49
+    # twice k = 56 is more than k_max: back to one-orbital chunks
+    assert ctx.krylov_soft_chunk(4) == (1, K_MAX)
+    ctx.close()
+
+
+@pytest.mark.parametrize("steps", [1, 3])
+def test_soft_chunk_magnus_and_propagate_match_plain_chunks(monkeypatch, steps):
+    """magnus_step (host-read results) and propagate (results kept on the
+    device until the end) with soft-capped chunks, one of which restarts in
+    the corrector (tau = dt = 6), against the same steps in one chunk."""
+    cfg = _cfg()
+    m, _ = oracle_mesh(cfg)
+    x = _block(m, seed=21)
+    out = []
+    for basis in ("1", None):
+        if basis:
+            monkeypatch.setenv("TDFE_BASIS_CHUNK_ORB", basis)
+        else:
+            monkeypatch.delenv("TDFE_BASIS_CHUNK_ORB", raising=False)
+        ctx = gpu_context(cfg, n_orb=4, k_max=K_MAX)
+        # a short exponential first, so that the next ones may widen
+        warm = torch.from_numpy(x).cuda()
+        ctx.lanczos_expm(warm, 0.01, 1e-12)
+        if basis:
+            assert ctx.krylov_soft_chunk(4)[0] > 1
+        g = torch.from_numpy(x).cuda()
+        if steps == 1:
+            rep = ctx.magnus_step(g, 6.0, 0.0, 1e-12)
+            mu = np.asarray(rep["mu"])
+        else:
+            rec, _ = ctx.propagate(g, steps, 6.0, tol=1e-12)
+            mu = rec.cpu().numpy() if hasattr(rec, "cpu") else np.asarray(rec)
+        out.append((g.cpu().numpy(), mu))
+        ctx.close()
+    (g1, mu1), (g2, mu2) = out
+    assert rel(g1, g2) < 1e-12
+    assert np.abs(mu1 - mu2).max() <= 1e-12 * max(1.0, np.abs(mu2).max())
