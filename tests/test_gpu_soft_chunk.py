@@ -31,36 +31,61 @@ def _block(m, seed=9):
     return x / np.linalg.norm(x, axis=0)
 
 
-def test_soft_chunk_widens_after_first_exponential_and_restarts_past_cap(monkeypatch):
+# FP64: tolerance 1e-12 (k = 9, then 56 at tau = 6), against the oracle.
+# Mixed: the FP32 basis stops at its floor 16 2^-24 (the oracle needs k = 5
+# at that tolerance, and 66 at tau = 10); tau = 0.05 is compared with the
+# oracle at the mixed path's 2e-6.  At tau = 10 each of the k iterations
+# stores a basis vector rounded to FP32 and may stop at the floor, so the
+# bar is k 16 2^-24 (6e-5 at k = 66) against the oracle and against the same
+# exponential in a context of plain one-orbital chunks (the launches the
+# restart runs; there only the order of the atomic additions differs)
+@pytest.mark.parametrize("mixed", [False, True])
+def test_soft_chunk_widens_after_first_exponential_and_restarts_past_cap(monkeypatch, mixed):
+    from paper_1810_13130_amd import tdfe
     monkeypatch.setenv("TDFE_BASIS_CHUNK_ORB", "1")
     cfg = _cfg()
-    ctx = gpu_context(cfg, n_orb=4, k_max=K_MAX)
+    ctx = gpu_context(cfg, n_orb=4, k_max=K_MAX, precision=tdfe.MIXED_FP32 if mixed else tdfe.FP64)
     m, vq = oracle_mesh(cfg)
     x = _block(m)
-    ref = lambda tau: lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), x, tau, 1e-12)
+    tol, bar, tau_big = (1e-10, 2e-6, 10.0) if mixed else (1e-12, 1e-10, 6.0)
+    ref = lambda tau: lanczos.lanczos_expm(lambda v: op.apply_Hbar(m, vq, v), x, tau, tol)
     assert ctx.krylov_chunk(4) == 1
     assert ctx.krylov_soft_chunk(4) == (1, K_MAX)  # no exponential yet
     # 1: plain one-orbital chunks
     g = torch.from_numpy(x).cuda()
-    ks, _ = ctx.lanczos_expm(g, 0.05, 1e-12)
+    ks, _ = ctx.lanczos_expm(g, 0.05, tol)
     z, kref, _ = ref(0.05)
-    assert rel(g.cpu().numpy(), z) < 1e-10 and max(ks) == max(kref) == 9
-    # 2: two-orbital chunks capped at 49 (at least 32 and twice k = 9)
+    assert rel(g.cpu().numpy(), z) < bar and max(ks) <= 16
+    if not mixed:
+        assert max(ks) == max(kref) == 9
+    # 2: two-orbital chunks capped at 49 (at least 32 and twice k)
     assert ctx.krylov_soft_chunk(4) == (2, 49)
     g = torch.from_numpy(x).cuda()
-    ks, errs = ctx.lanczos_expm(g, 0.05, 1e-12)
-    assert rel(g.cpu().numpy(), z) < 1e-10
-    assert all(abs(a - b) <= 1 for a, b in zip(ks, kref)) and max(errs) <= 1e-12
-    # 3: k = 56 exceeds the cap: every chunk restarts at k_max, same result
+    ks2, errs = ctx.lanczos_expm(g, 0.05, tol)
+    assert rel(g.cpu().numpy(), z) < bar and all(abs(a - b) <= 1 for a, b in zip(ks2, ks))
+    if not mixed:
+        assert all(abs(a - b) <= 1 for a, b in zip(ks2, kref)) and max(errs) <= 1e-12
+    # 3: k beyond the cap of 49: every chunk restarts at k_max, same result
     g = torch.from_numpy(x).cuda()
-    ks, errs = ctx.lanczos_expm(g, 6.0, 1e-12)
-    z6, kref6, _ = ref(6.0)
-    assert rel(g.cpu().numpy(), z6) < 1e-10
-    assert all(abs(a - b) <= 1 for a, b in zip(ks, kref6)) and max(errs) <= 1e-12
+    ks, errs = ctx.lanczos_expm(g, tau_big, tol)
     assert min(ks) > 49
-    # twice k = 56 is more than k_max: back to one-orbital chunks
+    zb, krefb, _ = ref(tau_big)
+    bar_big = max(ks) * 16 * 2.0**-24 if mixed else bar
+    assert rel(g.cpu().numpy(), zb) < bar_big
+    if not mixed:
+        assert all(abs(a - b) <= 1 for a, b in zip(ks, krefb)) and max(errs) <= 1e-12
+    # twice that k is more than k_max: back to one-orbital chunks
     assert ctx.krylov_soft_chunk(4) == (1, K_MAX)
     ctx.close()
+    if mixed:
+        monkeypatch.setenv("TDFE_MAX_CHUNK_ORB", "1")
+        plain = gpu_context(cfg, n_orb=4, k_max=K_MAX, precision=tdfe.MIXED_FP32)
+        gp = torch.from_numpy(x).cuda()
+        ksp, _ = plain.lanczos_expm(gp, tau_big, tol)
+        assert plain.krylov_soft_chunk(4) == (1, K_MAX)
+        assert all(abs(a - b) <= 1 for a, b in zip(ks, ksp))
+        assert rel(g.cpu().numpy(), gp.cpu().numpy()) < bar_big
+        plain.close()
 
 
 @pytest.mark.parametrize("steps", [1, 3])
