@@ -68,6 +68,48 @@ struct KParams {
   int64_t* groups_out;  // host pointer, set by the launcher
 };
 
+// the 6 entries of w detJ J^-1 J^-T (w: the product Gauss weight) at the
+// reference point (xa, xb, xc) of a trilinear cell with corners C[8][3]
+// (z-corner slowest, x fastest)
+__device__ __forceinline__ void metric_at(const double* C, double xa, double xb, double xc, double w, double g[6]) {
+  const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
+                          {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
+  double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
+  for (int vz = 0; vz < 2; ++vz)
+    for (int vy = 0; vy < 2; ++vy)
+      for (int vx = 0; vx < 2; ++vx) {
+        const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
+        const double sx = vx ? 0.5 : -0.5, sy = vy ? 0.5 : -0.5, sz = vz ? 0.5 : -0.5;
+        const double d0 = sx * f[vy][1] * f[vz][2];
+        const double d1 = f[vx][0] * sy * f[vz][2];
+        const double d2 = f[vx][0] * f[vy][1] * sz;
+        for (int d = 0; d < 3; ++d) {
+          J[d][0] += X3[d] * d0;
+          J[d][1] += X3[d] * d1;
+          J[d][2] += X3[d] * d2;
+        }
+      }
+  // adjugate: J^-1 = adj / det ; det J^-1 J^-T = adj adj^T / det
+  double A[3][3];
+  A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
+  A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
+  A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
+  A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
+  A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
+  A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
+  A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
+  A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
+  A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
+  const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
+  const double s = w / det;
+  g[0] = s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]);
+  g[1] = s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]);
+  g[2] = s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]);
+  g[3] = s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]);
+  g[4] = s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]);
+  g[5] = s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]);
+}
+
 template <typename T, int N, int CB, int CPB, int GEOM>
 __global__ void __launch_bounds__(CPB * N * N * CB)
     apply_kernel(KParams P) {
@@ -77,7 +119,12 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   __shared__ T sR[CPB * VOL * CB];
   __shared__ T sGY[GEOM ? CPB * VOL * CB : 1];
   __shared__ T sGZ[GEOM ? CPB * VOL * CB : 1];
-  __shared__ T sGeo[GEOM ? CPB * VOL * 6 : 1];
+  // one-column launches of curved cells (the Hartree solve's stiffness
+  // products) form each Gauss point's metric in registers at the flux step,
+  // where one thread owns the point: the LDS of the metric (48 KB for two
+  // p = 7 cells) would otherwise hold a CU to one block of two waves
+  constexpr bool GREG = GEOM && CB == 1;
+  __shared__ T sGeo[(GEOM && !GREG) ? CPB * VOL * 6 : 1];
   __shared__ T sW3[VOL];
   __shared__ double sEta[N];
   __shared__ double sCor[GEOM ? CPB * 24 : 1];
@@ -167,52 +214,17 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
   }
   __syncthreads();
   // geometry of curved cells: 6 entries of detJ w J^-1 J^-T at every Gauss point
-  if constexpr (GEOM) {
-    const T* sW3q = sW3;
+  if constexpr (GEOM && !GREG) {
     for (int it = t; it < CPB * VOL; it += S::THREADS) {
       const int sl = it / VOL, q = it % VOL;
       const int64_t ce = (int64_t)group * CPB + sl;
       if (ce >= P.n_cell) continue;
       const int a = q % N, b = (q / N) % N, c = q / (N * N);
-      const double xa = sEta[a], xb = sEta[b], xc = sEta[c];
-      const double f[2][3] = {{0.5 * (1 - xa), 0.5 * (1 - xb), 0.5 * (1 - xc)},
-                              {0.5 * (1 + xa), 0.5 * (1 + xb), 0.5 * (1 + xc)}};
-      const double* C = sCor + sl * 24;
-      double J[3][3] = {{0, 0, 0}, {0, 0, 0}, {0, 0, 0}};
-      for (int vz = 0; vz < 2; ++vz)
-        for (int vy = 0; vy < 2; ++vy)
-          for (int vx = 0; vx < 2; ++vx) {
-            const double* X3 = C + ((vz * 2 + vy) * 2 + vx) * 3;
-            const double sx = vx ? 0.5 : -0.5, sy = vy ? 0.5 : -0.5, sz = vz ? 0.5 : -0.5;
-            const double d0 = sx * f[vy][1] * f[vz][2];
-            const double d1 = f[vx][0] * sy * f[vz][2];
-            const double d2 = f[vx][0] * f[vy][1] * sz;
-            for (int d = 0; d < 3; ++d) {
-              J[d][0] += X3[d] * d0;
-              J[d][1] += X3[d] * d1;
-              J[d][2] += X3[d] * d2;
-            }
-          }
-      // adjugate: J^-1 = adj / det ; det J^-1 J^-T = adj adj^T / det
-      double A[3][3];
-      A[0][0] = J[1][1] * J[2][2] - J[1][2] * J[2][1];
-      A[0][1] = J[0][2] * J[2][1] - J[0][1] * J[2][2];
-      A[0][2] = J[0][1] * J[1][2] - J[0][2] * J[1][1];
-      A[1][0] = J[1][2] * J[2][0] - J[1][0] * J[2][2];
-      A[1][1] = J[0][0] * J[2][2] - J[0][2] * J[2][0];
-      A[1][2] = J[0][2] * J[1][0] - J[0][0] * J[1][2];
-      A[2][0] = J[1][0] * J[2][1] - J[1][1] * J[2][0];
-      A[2][1] = J[0][1] * J[2][0] - J[0][0] * J[2][1];
-      A[2][2] = J[0][0] * J[1][1] - J[0][1] * J[1][0];
-      const double det = J[0][0] * A[0][0] + J[0][1] * A[1][0] + J[0][2] * A[2][0];
-      const double s = (double)sW3q[q] / det;
+      double gd[6];
+      metric_at(sCor + sl * 24, sEta[a], sEta[b], sEta[c], (double)sW3[q], gd);
       T* g = sGeo + (sl * VOL + q) * 6;
-      g[0] = (T)(s * (A[0][0] * A[0][0] + A[0][1] * A[0][1] + A[0][2] * A[0][2]));
-      g[1] = (T)(s * (A[0][0] * A[1][0] + A[0][1] * A[1][1] + A[0][2] * A[1][2]));
-      g[2] = (T)(s * (A[0][0] * A[2][0] + A[0][1] * A[2][1] + A[0][2] * A[2][2]));
-      g[3] = (T)(s * (A[1][0] * A[1][0] + A[1][1] * A[1][1] + A[1][2] * A[1][2]));
-      g[4] = (T)(s * (A[1][0] * A[2][0] + A[1][1] * A[2][1] + A[1][2] * A[2][2]));
-      g[5] = (T)(s * (A[2][0] * A[2][0] + A[2][1] * A[2][1] + A[2][2] * A[2][2]));
+#pragma unroll
+      for (int w6 = 0; w6 < 6; ++w6) g[w6] = (T)gd[w6];
     }
   }
   __syncthreads();
@@ -402,7 +414,16 @@ __global__ void __launch_bounds__(CPB * N * N * CB)
         const int q = a + N * (b + N * c);
         const int li = lidx<N, CB>(slot, c, b, a, col);
         const T u = sU[li], dx = sR[li], dy = sGY[li], dz = sGZ[li];
-        const T* g = sGeo + (slot * VOL + q) * 6;
+        T gr[6];
+        const T* g = gr;
+        if constexpr (GREG) {
+          double gd[6] = {0, 0, 0, 0, 0, 0};
+          if (cell_ok) metric_at(sCor + slot * 24, sEta[a], sEta[b], sEta[c], (double)sW3[q], gd);
+#pragma unroll
+          for (int w6 = 0; w6 < 6; ++w6) gr[w6] = (T)gd[w6];
+        } else {
+          g = sGeo + (slot * VOL + q) * 6;
+        }
         const T k = (T)P.kin;
         const T ffx = k * (g[0] * dx + g[1] * dy + g[2] * dz);
         const T ffy = k * (g[1] * dx + g[3] * dy + g[4] * dz);
