@@ -107,6 +107,11 @@ struct tdfe_ctx {
   int* poll = nullptr;
   int flag_gen = 0;  // generation number of the Lanczos convergence flag (poll[32])
   void* blas = nullptr;        // rocBLAS handle on `stream` (fast diagonalisation along axes > 128 nodes)
+  // rocBLAS solution of each fast-diagonalisation pass [axis][transposed],
+  // chosen by timing at its first use (tuned: 0 not yet, 1 chosen)
+  int fdm_tuned[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int fdm_algo[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+  int fdm_sol[3][2] = {{0, 0}, {0, 0}, {0, 0}};
   hipEvent_t* evs = nullptr;  // [TDFE_N_EVENTS] look-ahead polling points
   int n_evs = 0;
 

@@ -18,6 +18,8 @@
 #include <algorithm>
 #include <cmath>
 
+// the solution-index queries of rocBLAS are in its beta interface
+#define ROCBLAS_BETA_FEATURES_API
 #include <rocblas/rocblas.h>
 
 #include "tdfe_internal.h"
@@ -631,23 +633,107 @@ tdfe_status blas_ready(tdfe_ctx* c) {
   return TDFE_OK;
 }
 
+// one fast-diagonalisation pass as a rocBLAS product: axis 0 and 2 one
+// DGEMM over the whole array, axis 1 a strided batch over z slabs
+struct FdmGemm {
+  rocblas_operation ta, tb;
+  int m, n, k;
+  const double* A;
+  int lda;
+  rocblas_stride sa;
+  const double* B;
+  int ldb;
+  rocblas_stride sb;
+  int ldc;
+  rocblas_stride sc;
+  int batch;  // 0: a single product
+};
+
+rocblas_status fdm_gemm(rocblas_handle h, const FdmGemm& g, double* out, rocblas_gemm_algo algo, int32_t sol) {
+  const double one = 1.0, zero = 0.0;
+  const rocblas_datatype f64 = rocblas_datatype_f64_r;
+  if (g.batch == 0)
+    return rocblas_gemm_ex(h, g.ta, g.tb, g.m, g.n, g.k, &one, g.A, f64, g.lda, g.B, f64, g.ldb, &zero, out, f64,
+                           g.ldc, out, f64, g.ldc, f64, algo, sol, 0);
+  return rocblas_gemm_strided_batched_ex(h, g.ta, g.tb, g.m, g.n, g.k, &one, g.A, f64, g.lda, g.sa, g.B, f64, g.ldb,
+                                         g.sb, &zero, out, f64, g.ldc, g.sc, out, f64, g.ldc, g.sc, g.batch, f64, algo,
+                                         sol, 0);
+}
+
+// rocBLAS's default kernel for these shapes (K = one axis, some hundreds;
+// the other dimension the rest of the grid) runs at about 10-30 TFLOP/s; at
+// a pass's first use every solution rocBLAS lists for it is timed on the
+// stream (the output is overwritten, the input is not touched) and the
+// fastest kept: 272^3 passes 228-273 -> 175-186 us, 185^3 85 -> 47 us
+void fdm_tune(tdfe_ctx* c, rocblas_handle h, const FdmGemm& g, double* out, int* algo_out, int* sol_out) {
+  *algo_out = (int)rocblas_gemm_algo_standard;
+  *sol_out = 0;
+  const double one = 1.0, zero = 0.0;
+  const rocblas_datatype f64 = rocblas_datatype_f64_r;
+  const rocblas_gemm_algo idx = rocblas_gemm_algo_solution_index;
+  rocblas_int cnt = 0;
+  auto list = [&](rocblas_int* arr) {
+    if (g.batch == 0)
+      return rocblas_gemm_ex_get_solutions(h, g.ta, g.tb, g.m, g.n, g.k, &one, g.A, f64, g.lda, g.B, f64, g.ldb, &zero,
+                                           out, f64, g.ldc, out, f64, g.ldc, f64, idx, 0, arr, &cnt);
+    return rocblas_gemm_strided_batched_ex_get_solutions(h, g.ta, g.tb, g.m, g.n, g.k, &one, g.A, f64, g.lda, g.sa, g.B,
+                                                         f64, g.ldb, g.sb, &zero, out, f64, g.ldc, g.sc, out, f64,
+                                                         g.ldc, g.sc, g.batch, f64, idx, 0, arr, &cnt);
+  };
+  if (list(nullptr) != rocblas_status_success || cnt <= 0) return;
+  std::vector<rocblas_int> sols((size_t)cnt);
+  if (list(sols.data()) != rocblas_status_success) return;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess) {
+    (void)hipGetLastError();
+    if (e0) (void)hipEventDestroy(e0);
+    return;
+  }
+  auto time_one = [&](rocblas_gemm_algo a, int32_t s) -> float {
+    if (fdm_gemm(h, g, out, a, s) != rocblas_status_success) return -1.f;  // warm-up
+    if (hipEventRecord(e0, c->stream) != hipSuccess) return -1.f;
+    for (int r = 0; r < 3; ++r)
+      if (fdm_gemm(h, g, out, a, s) != rocblas_status_success) return -1.f;
+    float ms = -1.f;
+    if (hipEventRecord(e1, c->stream) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+        hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+      return -1.f;
+    return ms;
+  };
+  float best = time_one(rocblas_gemm_algo_standard, 0);
+  for (const rocblas_int s : sols) {
+    const float t = time_one(idx, s);
+    if (t > 0.f && (best < 0.f || t < best)) {
+      best = t;
+      *algo_out = (int)idx;
+      *sol_out = s;
+    }
+  }
+  (void)hipGetLastError();
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 tdfe_status fdm_blas_pass(tdfe_ctx* c, const double* in, double* out, const double* S, int axis, int trans) {
   TDFE_TRY(blas_ready(c));
   rocblas_handle h = (rocblas_handle)c->blas;
   const int n1x = c->Nx - 2, n1y = c->Ny - 2, n1z = c->Nz - 2;
-  const double one = 1.0, zero = 0.0;
   const rocblas_operation nt = rocblas_operation_none, tr = rocblas_operation_transpose;
-  rocblas_status st;
+  FdmGemm g{};
   if (axis == 0) {
-    st = rocblas_dgemm(h, trans ? nt : tr, nt, n1x, n1y * n1z, n1x, &one, S, n1x, in, n1x, &zero, out, n1x);
+    g = FdmGemm{trans ? nt : tr, nt, n1x, n1y * n1z, n1x, S, n1x, 0, in, n1x, 0, n1x, 0, 0};
   } else if (axis == 1) {
     const rocblas_stride slab = (rocblas_stride)n1x * n1y;
-    st = rocblas_dgemm_strided_batched(h, nt, trans ? tr : nt, n1x, n1y, n1y, &one, in, n1x, slab, S, n1y, 0, &zero,
-                                       out, n1x, slab, n1z);
+    g = FdmGemm{nt, trans ? tr : nt, n1x, n1y, n1y, in, n1x, slab, S, n1y, 0, n1x, slab, n1z};
   } else {
-    st = rocblas_dgemm(h, nt, trans ? tr : nt, n1x * n1y, n1z, n1z, &one, in, n1x * n1y, S, n1z, &zero, out,
-                       n1x * n1y);
+    g = FdmGemm{nt, trans ? tr : nt, n1x * n1y, n1z, n1z, in, n1x * n1y, 0, S, n1z, 0, n1x * n1y, 0, 0};
   }
+  const int tq = trans ? 1 : 0;
+  if (!c->fdm_tuned[axis][tq]) {
+    fdm_tune(c, h, g, out, &c->fdm_algo[axis][tq], &c->fdm_sol[axis][tq]);
+    c->fdm_tuned[axis][tq] = 1;
+  }
+  const rocblas_status st = fdm_gemm(h, g, out, (rocblas_gemm_algo)c->fdm_algo[axis][tq], c->fdm_sol[axis][tq]);
   if (st != rocblas_status_success) return tdfe_fail(c, TDFE_EDEVICE, "rocBLAS DGEMM failed (status %d)", (int)st);
   return TDFE_OK;
 }
