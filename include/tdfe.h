@@ -91,7 +91,13 @@ typedef struct {
  * No device memory is touched until tdfe_bind_workspace; the free memory of
  * the current device is queried once to size the Krylov basis: orbitals are
  * processed in chunks whose basis ((k_max + 2) vectors per orbital) fits in
- * 60% of it (128 GB if the query fails).
+ * 60% of it (128 GB if the query fails); the workspace also holds the
+ * operator output of the widest soft-capped chunk (krylov_soft_chunk).
+ * Environment read here: TDFE_MAX_CHUNK_ORB=n caps every Krylov chunk at n
+ * orbitals; TDFE_BASIS_CHUNK_ORB=n caps only the basis memory at n orbitals
+ * (soft-capped chunks may still be wider), as on a device with less memory;
+ * TDFE_APPLY_VARIANT=line|pair|plane forces one operator kernel family
+ * where it applies (the default picks per mesh, order and precision).
  * hip_stream: hipStream_t (may be 0).  *out receives a new context. */
 tdfe_status tdfe_fe_mesh_setup(const tdfe_mesh_desc* d, void* hip_stream, tdfe_ctx** out);
 
