@@ -998,7 +998,25 @@ tdfe_status tdfe_lanczos_run(tdfe_ctx* c, const double* vw, const void* in, void
       TDFE_TRY(run(q0, std::min(sub, o0 + Nc - q0), c->k_max, &again));
     }
   }
-  if (slot) return TDFE_OK;
+  if (slot) {
+    // the first exponential of a context: read its Krylov dimensions back
+    // now (one wait on the device, once), so that the next exponential -- the
+    // same step's corrector -- may already run soft-capped chunks
+    if (c->k_seen == 0 && c->wide_orb > c->chunk_orb && n_orb > c->chunk_orb) {
+      const void* h = nullptr;
+      TDFE_TRY(tdfe_lanczos_enqueue_results(c, defer, &h));
+      TDFE_HIP(c, hipStreamSynchronize(c->stream));
+      const volatile double* hv = (const volatile double*)h;
+      const int nm = c->n_orb_max;
+      int kmax = 0, ok = 1;
+      for (int o = 0; o < n_orb; ++o) {
+        kmax = std::max(kmax, (int)hv[o]);
+        if ((int)hv[nm + o] != 1) ok = 0;  // only a set that converged informs the cap
+      }
+      if (ok) c->k_seen = kmax;
+    }
+    return TDFE_OK;
+  }
   int kmax = 0, ksum = 0, bad = 0, nonfinite = 0;
   double emax = 0.0;
   for (int o = 0; o < n_orb; ++o) {

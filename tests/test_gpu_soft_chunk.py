@@ -88,14 +88,18 @@ def test_soft_chunk_widens_after_first_exponential_and_restarts_past_cap(monkeyp
         plain.close()
 
 
-@pytest.mark.parametrize("steps", [1, 3])
-def test_soft_chunk_magnus_and_propagate_match_plain_chunks(monkeypatch, steps):
-    """magnus_step (host-read results) and propagate (results kept on the
-    device until the end) with soft-capped chunks, one of which restarts in
-    the corrector (tau = dt = 6), against the same steps in one chunk."""
+@pytest.mark.parametrize("steps,warm", [(1, True), (3, True), (3, False)])
+def test_soft_chunk_magnus_and_propagate_match_plain_chunks(monkeypatch, steps, warm):
+    """magnus_step and propagate (both keep the Lanczos results on the
+    device until the step ends) with soft-capped chunks against the same
+    steps in one chunk.  warm: a short exponential first, so that the steps
+    widen at once, and each restarts (tau = dt = 6, k = 56 > 49); cold: the
+    first exponential of the context reads its Krylov dimensions back (k = 9
+    at dt = 0.05) and the next steps run two-orbital chunks capped at 49."""
     cfg = _cfg()
     m, _ = oracle_mesh(cfg)
     x = _block(m, seed=21)
+    dt = 6.0 if warm else 0.05
     out = []
     for basis in ("1", None):
         if basis:
@@ -103,18 +107,20 @@ def test_soft_chunk_magnus_and_propagate_match_plain_chunks(monkeypatch, steps):
         else:
             monkeypatch.delenv("TDFE_BASIS_CHUNK_ORB", raising=False)
         ctx = gpu_context(cfg, n_orb=4, k_max=K_MAX)
-        # a short exponential first, so that the next ones may widen
-        warm = torch.from_numpy(x).cuda()
-        ctx.lanczos_expm(warm, 0.01, 1e-12)
-        if basis:
-            assert ctx.krylov_soft_chunk(4)[0] > 1
+        if warm:
+            w = torch.from_numpy(x).cuda()
+            ctx.lanczos_expm(w, 0.01, 1e-12)
+            if basis:
+                assert ctx.krylov_soft_chunk(4)[0] > 1
         g = torch.from_numpy(x).cuda()
         if steps == 1:
-            rep = ctx.magnus_step(g, 6.0, 0.0, 1e-12)
+            rep = ctx.magnus_step(g, dt, 0.0, 1e-12)
             mu = np.asarray(rep["mu"])
         else:
-            rec, _ = ctx.propagate(g, steps, 6.0, tol=1e-12)
+            rec, _ = ctx.propagate(g, steps, dt, tol=1e-12)
             mu = rec.cpu().numpy() if hasattr(rec, "cpu") else np.asarray(rec)
+        if basis and not warm:
+            assert ctx.krylov_soft_chunk(4) == (2, 49)
         out.append((g.cpu().numpy(), mu))
         ctx.close()
     (g1, mu1), (g2, mu2) = out
