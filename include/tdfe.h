@@ -169,7 +169,12 @@ typedef struct {
  * of a rectilinear stand-in mesh whose vertex coordinates along each axis are
  * the means of the true ones over the other two indices (on smoothly graded
  * meshes 20-30 iterations instead of the hundreds Jacobi needs).  Both stop at
- * the same residual test; box meshes always solve exactly. */
+ * the same residual test; box meshes always solve exactly.  Along axes of
+ * more than 128 interior nodes the fast diagonalisation's 1D transforms are
+ * rocBLAS DGEMMs; the first solve of a context times every rocBLAS solution
+ * for each transform shape and keeps the fastest (a one-time cost of about
+ * 0.1-0.5 s; two contexts may keep different solutions, which changes phi
+ * at the level of the solve's tolerance). */
 #define TDFE_PCG_FDM 0
 #define TDFE_PCG_JACOBI 1
 
